@@ -1,0 +1,184 @@
+/*
+ * semfuse: label fusion in semantically textured meshes on AMD Instinct MI355X (gfx950).
+ *
+ * The method (Fervers et al., "Improving Semantic Image Segmentation via Label
+ * Fusion in Semantically Textured Meshes"): a known triangle mesh is rendered
+ * with every frame's camera into per-pixel triangle and texel identifiers
+ * (Section 3.3.1); each pixel's c-class probability vector is aggregated into
+ * the row of a texel-major array P (Section 3.3.2, eq. texel-in-array) with
+ * the weighted aggregators of Section 3.2 (eqs. w-sum, w-mul, w-maxsum and
+ * the weights w^(P), w^(I)); every row is normalised and its argmax is the
+ * texel's class (Section 3.2.1); the fused labels are rendered back into every
+ * frame.
+ *
+ * Conventions shared by every call
+ *  - All pointers named d_* are device pointers (hipMalloc / torch CUDA
+ *    tensors) owned by the caller; the library allocates no device memory and
+ *    keeps no pointer beyond what the mesh handle documents.  h_* pointers are
+ *    host memory.
+ *  - Calls enqueue work on `stream` and return without waiting, except
+ *    lf_load_mesh, which waits for its validation result.  Inputs must stay
+ *    unmodified until the stream has consumed them.
+ *  - A handle is not thread-safe; two handles are independent.
+ *  - Every call returns an lf_status; on failure lf_last_error() (thread-local)
+ *    describes it.  No C++ exception crosses this interface.
+ *  - Camera record (16 floats): fx, fy, cx, cy, R[9] (row-major, world to
+ *    camera), t[3]; X_cam = R X_world + t; pinhole, no distortion, x right,
+ *    y down, z forward; pixel (x, y) has its centre at (x + 1/2, y + 1/2).
+ *  - Probability input: a 4-D array indexed [frame][class][y][x] with
+ *    arbitrary element strides (NCHW, or channels-last NHWC memory).  float32,
+ *    or OCP E4M3FN codes (uint8) with a float32 per-pixel scale
+ *    [frame][y][x]: p = decode(q) * scale.  Probabilities are used as given
+ *    (not renormalised); NaN propagates into the texels it reaches.
+ *  - Limits: 1 <= c <= 255 (labels are uint8, 255 = void); n_texels < 2^31;
+ *    H, W <= 8192; triangle count < 2^31.
+ */
+#ifndef SEMFUSE_H
+#define SEMFUSE_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LF_OK = 0,
+    LF_EINVAL = -1,   /* bad argument, shape or option                         */
+    LF_ESIZE = -2,    /* caller buffer / workspace smaller than required       */
+    LF_EHIP = -3,     /* HIP runtime error (launch failure, ...)               */
+    LF_ESTATE = -4    /* handle freed or used with mismatching options         */
+} lf_status;
+
+typedef enum { LF_TEX_SQUARE = 0, LF_TEX_SPLIT = 1 } lf_texel_scheme;
+typedef enum { LF_W_PIXEL = 0, LF_W_IMAGE = 1, LF_W_LEARNED = 2 } lf_weighting;
+typedef enum { LF_AGG_SUM = 0, LF_AGG_MUL = 1, LF_AGG_MAXSUM = 2 } lf_aggregator;
+typedef enum { LF_F32 = 0, LF_BF16 = 1, LF_F16 = 2, LF_FP8_E4M3 = 3 } lf_dtype;
+typedef enum { LF_SCATTER_AUTO = 0, LF_SCATTER_ATOMIC = 1, LF_SCATTER_SORTED = 2 } lf_scatter_mode;
+
+typedef struct lf_mesh_s* lf_mesh;
+
+/* Mesh options.
+ *  scheme     texel layout of a triangle with s steps per uv dimension
+ *             (Section 3.1): SQUARE = the paper's (s^2+s)/2 cells; SPLIT cuts
+ *             every full square cell along its anti-diagonal (s^2 texels).
+ *  s_uniform  s for every triangle when no per-face array is given (>= 1).
+ *  n_classes  c.
+ *  aggregator f of Section 3.2.1 (eq. sum / mul / maxsum, weighted forms of 3.2.2).
+ *  accum_dtype LF_F32 (default) or LF_BF16 / LF_F16 to keep the accumulator
+ *             itself in 16 bits (measures accumulation stagnation; SUM only).
+ *  z_near     near clipping plane in camera units (> 0). */
+typedef struct {
+    int32_t scheme;
+    int32_t s_uniform;
+    int32_t n_classes;
+    int32_t aggregator;
+    int32_t accum_dtype;
+    float z_near;
+} lf_mesh_opts;
+
+/* Sizes of the caller-owned buffers of a mesh (Section 3.3.2: n_x = sum of
+ * |X_t|).  h_s_face: optional per-face s (host, [n_faces]).  Outputs:
+ * *n_texels; *mesh_ws_bytes = workspace lf_load_mesh needs and the handle
+ * keeps using.  Errors: LF_EINVAL on bad options or counts. */
+lf_status lf_mesh_sizes(const lf_mesh_opts* opts, int64_t n_vertices, int64_t n_faces,
+                        const int32_t* h_s_face, int64_t* n_texels, int64_t* mesh_ws_bytes);
+
+/* Load a mesh (Section 3.1 / 3.3.2): picks every triangle's uv origin (the
+ * vertex whose interior angle is closest to 90 degrees), its texel count and
+ * its row offset id_t, builds culling bounds, and clears the accumulator.
+ *  d_vertices [V][3] float32 world coordinates; d_faces [T][3] int32 vertex
+ *  indices; d_s_face [T] int32 or NULL (then opts->s_uniform);
+ *  d_mesh_ws  >= mesh_ws_bytes, 256-byte aligned, kept by the handle;
+ *  d_accum    [n_texels][c] accumulator (FP32 unless opts->accum_dtype), kept;
+ *  d_wsum     [n_texels] float32 total weight per texel, kept (may be NULL
+ *             unless aggregator == MUL).
+ * Waits on `stream` for index validation: LF_EINVAL if a face index is out of
+ * range or an s is < 1.  The caller keeps vertices, workspace and accumulator
+ * alive until lf_free_mesh. */
+lf_status lf_load_mesh(const lf_mesh_opts* opts, const float* d_vertices, int64_t n_vertices,
+                       const int32_t* d_faces, int64_t n_faces, const int32_t* d_s_face,
+                       void* d_mesh_ws, int64_t mesh_ws_bytes, void* d_accum, float* d_wsum,
+                       int64_t n_texels, hipStream_t stream, lf_mesh* out);
+
+/* Clear the accumulator (and weight sums): start a new fusion. */
+lf_status lf_reset(lf_mesh mesh, hipStream_t stream);
+
+/* Workspace bytes lf_fuse_frames / lf_rasterize / lf_render_labels need for
+ * frames of H x W processed `batch` at a time (batch >= 1). */
+lf_status lf_frame_ws_bytes(lf_mesh mesh, int32_t H, int32_t W, int32_t batch, int32_t weighting,
+                            int32_t scatter_mode, int64_t* bytes);
+
+/* Fuse F frames into the accumulator (Sections 3.3.1, 3.3.2, 3.2):
+ * render every frame to triangle / texel ids, then add w_k * p_k (SUM),
+ * w_k * log p_k (MUL) or w_k * g(p_k) (MAXSUM) into row l_k of every valid
+ * covered pixel.
+ *  d_cams   [F][16] float32 camera records (device);
+ *  d_probs  probability input, element strides[4] = (frame, class, y, x);
+ *  prob_dtype LF_F32 or LF_FP8_E4M3 (then d_scale [F][H][W] float32);
+ *  d_valid  [F][H][W] uint8 (0 = pixel without depth, skipped) or NULL;
+ *  weighting LF_W_PIXEL (w = 1), LF_W_IMAGE (w = 1/|K_i ∩ K_x|) or
+ *           LF_W_LEARNED (w = the bound MLP's output, see lf_mlp_bind);
+ *  d_l_out  [F][H][W] int32 texel rows (-1 = no triangle) or NULL;
+ *  d_ws     workspace of lf_frame_ws_bytes(H, W, batch) bytes, 256-aligned;
+ *  scatter_mode  LF_SCATTER_AUTO / ATOMIC / SORTED (same result up to FP32
+ *           summation order).
+ * Frames may be fused in several calls (fusion is incremental).  Errors:
+ * LF_EINVAL (shapes, dtype, strides), LF_ESIZE (workspace), LF_EHIP. */
+lf_status lf_fuse_frames(lf_mesh mesh, const float* d_cams, int32_t F, int32_t H, int32_t W,
+                         const void* d_probs, int32_t prob_dtype, const int64_t* h_strides,
+                         const float* d_scale, const uint8_t* d_valid, int32_t weighting,
+                         int32_t* d_l_out, void* d_ws, int64_t ws_bytes, int32_t batch,
+                         int32_t scatter_mode, hipStream_t stream);
+
+/* Normalise every texel and take its class (Section 3.2.1): SUM/MAXSUM
+ * P = A / sum_j A_j, MUL P = softmax(A); label = first maximal index; a texel
+ * never observed gets P = 0 and label 255.
+ *  d_tex_out [n_texels][c] in tex_dtype (LF_F32, LF_BF16 or LF_F16, round to
+ *            nearest even) or NULL;  d_labels [n_texels] uint8 (required). */
+lf_status lf_finalize(lf_mesh mesh, void* d_tex_out, int32_t tex_dtype, uint8_t* d_labels,
+                      hipStream_t stream);
+
+/* Render the fused labels back into F frames (Section 3.2.1): out = label of
+ * the pixel's texel, 255 where no triangle is hit or the pixel is invalid.
+ *  d_l [F][H][W] rows from lf_fuse_frames, or NULL to re-render with d_cams;
+ *  d_labels [n_texels] from lf_finalize; d_out [F][H][W] uint8. */
+lf_status lf_render_labels(lf_mesh mesh, const float* d_cams, int32_t F, int32_t H, int32_t W,
+                           const int32_t* d_l, const uint8_t* d_valid, const uint8_t* d_labels,
+                           uint8_t* d_out, void* d_ws, int64_t ws_bytes, hipStream_t stream);
+
+/* Renderer alone (Section 3.3.1): per pixel triangle id (-1 none), texel row
+ * l (-1), depth z (NaN where none).  Any output may be NULL. */
+lf_status lf_rasterize(lf_mesh mesh, const float* d_cams, int32_t F, int32_t H, int32_t W,
+                       int32_t* d_tri, int32_t* d_l, float* d_z, void* d_ws, int64_t ws_bytes,
+                       hipStream_t stream);
+
+/* Per-stage kernel timing with HIP events recorded on the launch stream
+ * around every kernel of a stage (instrumentation for roofline reports).
+ * Stages: 0 ray tables + raster, 1 resolve, 2 scatter, 3 counts, 4 finalize,
+ * 5 render, 6 accumulator reset, 7 learned-weight inference.
+ * lf_profile_enable(mesh, 1) starts recording (clearing earlier records);
+ * lf_profile_read waits for the recorded events and returns, per stage, the
+ * summed milliseconds and the number of timed launches. */
+#define LF_N_STAGES 8
+typedef struct {
+    double ms[LF_N_STAGES];
+    int64_t launches[LF_N_STAGES];
+} lf_profile;
+lf_status lf_profile_enable(lf_mesh mesh, int32_t on);
+lf_status lf_profile_read(lf_mesh mesh, lf_profile* out);
+
+/* Release a handle (no device memory is freed: the caller owns it all). */
+void lf_free_mesh(lf_mesh mesh);
+
+/* Thread-local description of the last failure ("" if none). */
+const char* lf_last_error(void);
+
+/* Library version string. */
+const char* lf_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

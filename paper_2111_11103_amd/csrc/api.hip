@@ -1,0 +1,456 @@
+// C-ABI of the semfuse library: argument checking, workspace carving and the
+// per-batch launch sequence.  See include/semfuse.h for the contract.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "../../include/semfuse.h"
+#include "internal.h"
+
+using namespace lf;
+
+// Event pairs recorded around the kernels of each stage when profiling is on.
+struct Profiler {
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  std::vector<hipEvent_t> marks[LF_N_STAGES];   // start, end, start, end, ...
+  hipEvent_t take() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+  void recycle() {
+    for (auto& v : marks) {
+      for (hipEvent_t e : v) pool.push_back(e);
+      v.clear();
+    }
+  }
+  ~Profiler() {
+    recycle();
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+  }
+};
+
+struct lf_mesh_s {
+  uint32_t magic;
+  MeshDev d;
+  lf_mesh_opts opts;
+  Profiler prof;
+};
+
+namespace {
+// Records an event pair around the launches in its scope (stage `st`).
+struct StageTimer {
+  Profiler* p;
+  int st;
+  hipStream_t s;
+  StageTimer(lf_mesh_s* m, int stage, hipStream_t stream) : p(m && m->prof.on ? &m->prof : nullptr), st(stage), s(stream) {
+    if (p) {
+      hipEvent_t e = p->take();
+      if (e && hipEventRecord(e, s) == hipSuccess) p->marks[st].push_back(e);
+      else p = nullptr;
+    }
+  }
+  ~StageTimer() {
+    if (p) {
+      hipEvent_t e = p->take();
+      if (e && hipEventRecord(e, s) == hipSuccess) p->marks[st].push_back(e);
+      else p->marks[st].pop_back();
+    }
+  }
+};
+}  // namespace
+
+namespace {
+
+constexpr uint32_t kMagic = 0x5E4F05E1u;
+thread_local char g_err[512] = "";
+
+lf_status fail(lf_status st, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return st;
+}
+
+lf_status hip_check(hipError_t e, const char* where) {
+  if (e != hipSuccess) return fail(LF_EHIP, "%s: %s", where, hipGetErrorString(e));
+  return LF_OK;
+}
+
+#define LF_TRY(expr, where)                                 \
+  do {                                                      \
+    lf_status _st = hip_check((expr), (where));             \
+    if (_st != LF_OK) return _st;                           \
+  } while (0)
+
+int64_t align256(int64_t b) { return (b + 255) & ~int64_t(255); }
+
+int64_t per_tri(int32_t s, int32_t scheme) {
+  return scheme == LF_TEX_SPLIT ? (int64_t)s * s : (int64_t)s * (s + 1) / 2;
+}
+
+struct MeshLayout {
+  int64_t faces_uv, s_face, off, cl_box, err, scan, total;
+};
+
+MeshLayout mesh_layout(int64_t T, bool per_face) {
+  MeshLayout L{};
+  int64_t o = 0;
+  L.faces_uv = o; o += align256(T * 3 * 4);
+  L.s_face = o; if (per_face) o += align256(T * 4);
+  L.off = o; if (per_face) o += align256((T + 1) * 8);
+  const int64_t ncl = (T + kClusterTris - 1) / kClusterTris;
+  L.cl_box = o; o += align256(ncl * 8 * 4);
+  L.err = o; o += 256;
+  L.scan = o; if (per_face) o += align256(((T + 4095) / 4096 + 2) * 8);
+  L.total = o;
+  return L;
+}
+
+lf_status check_opts(const lf_mesh_opts* o) {
+  if (!o) return fail(LF_EINVAL, "options are NULL");
+  if (o->scheme != LF_TEX_SQUARE && o->scheme != LF_TEX_SPLIT) return fail(LF_EINVAL, "unknown texel scheme %d", o->scheme);
+  if (o->n_classes < 1 || o->n_classes > 255) return fail(LF_EINVAL, "n_classes must be in [1, 255], got %d", o->n_classes);
+  if (o->aggregator < LF_AGG_SUM || o->aggregator > LF_AGG_MAXSUM) return fail(LF_EINVAL, "unknown aggregator %d", o->aggregator);
+  if (o->accum_dtype != LF_F32) return fail(LF_EINVAL, "accumulator dtype %d not supported", o->accum_dtype);
+  if (!(o->z_near > 0.0f)) return fail(LF_EINVAL, "z_near must be > 0");
+  return LF_OK;
+}
+
+lf_status check_mesh(lf_mesh m) {
+  if (!m || m->magic != kMagic) return fail(LF_ESTATE, "invalid or freed mesh handle");
+  return LF_OK;
+}
+
+struct FrameLayout {
+  int64_t keys, rx, ry, l, cnt, wpix, total;
+};
+
+FrameLayout frame_layout(const MeshDev& m, int H, int W, int B, int weighting) {
+  FrameLayout L{};
+  const int64_t HW = (int64_t)H * W;
+  int64_t o = 0;
+  L.keys = o; o += align256(B * HW * 8);
+  L.rx = o; o += align256((int64_t)B * W * 4);
+  L.ry = o; o += align256((int64_t)B * H * 4);
+  L.l = o; o += align256(B * HW * 4);
+  L.cnt = o; if (weighting == LF_W_IMAGE) o += align256((int64_t)B * m.n_texels * 4);
+  L.wpix = o; if (weighting == LF_W_LEARNED) o += align256(B * HW * 4);
+  L.total = o;
+  return L;
+}
+
+lf_status check_frames(int32_t F, int32_t H, int32_t W) {
+  if (F < 0) return fail(LF_EINVAL, "negative frame count");
+  if (H < 1 || W < 1 || H > 8192 || W > 8192) return fail(LF_EINVAL, "image size %dx%d out of range [1, 8192]", W, H);
+  return LF_OK;
+}
+
+// Render frames [f0, f0 + nb) of the call into the batch key planes and
+// resolve them into texel rows (and optional triangle / depth outputs).
+lf_status render_batch(lf_mesh_s* mh, const float* cams, int f0, int nb, int H, int W, const FrameLayout& L,
+                       char* ws, int32_t* l_dst, int32_t* tri_dst, float* z_dst, const uint8_t* valid,
+                       int32_t* cnt, int64_t cnt_stride, hipStream_t s) {
+  const MeshDev& d = mh->d;
+  auto* keys = reinterpret_cast<unsigned long long*>(ws + L.keys);
+  auto* rx = reinterpret_cast<float*>(ws + L.rx);
+  auto* ry = reinterpret_cast<float*>(ws + L.ry);
+  const float* cb = cams + 16 * (int64_t)f0;
+  {
+    StageTimer tm(mh, 0, s);
+    LF_TRY(launch_raytab(cb, nb, H, W, rx, ry, s), "ray tables");
+    LF_TRY(launch_raster(d, cb, nb, H, W, keys, rx, ry, s), "raster");
+  }
+  {
+    StageTimer tm(mh, 1, s);
+    LF_TRY(launch_resolve(d, cb, nb, H, W, keys, rx, ry, l_dst, tri_dst, z_dst, valid, cnt, cnt_stride, s), "resolve");
+  }
+  return LF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lf_last_error(void) { return g_err; }
+const char* lf_version(void) { return "semfuse 0.1 (gfx950)"; }
+
+lf_status lf_mesh_sizes(const lf_mesh_opts* opts, int64_t n_vertices, int64_t n_faces, const int32_t* h_s_face,
+                        int64_t* n_texels, int64_t* mesh_ws_bytes) {
+  g_err[0] = 0;
+  lf_status st = check_opts(opts);
+  if (st != LF_OK) return st;
+  if (n_vertices < 0 || n_faces < 0 || n_faces >= (int64_t)1 << 31) return fail(LF_EINVAL, "bad vertex/face count");
+  int64_t nx = 0;
+  if (h_s_face) {
+    for (int64_t t = 0; t < n_faces; ++t) {
+      if (h_s_face[t] < 1) return fail(LF_EINVAL, "s of face %lld is %d (< 1)", (long long)t, h_s_face[t]);
+      nx += per_tri(h_s_face[t], opts->scheme);
+    }
+  } else {
+    if (opts->s_uniform < 1 || opts->s_uniform > 4096) return fail(LF_EINVAL, "s_uniform must be in [1, 4096]");
+    nx = n_faces * per_tri(opts->s_uniform, opts->scheme);
+  }
+  if (nx >= ((int64_t)1 << 31)) return fail(LF_EINVAL, "texel count %lld exceeds 2^31 - 1", (long long)nx);
+  if (n_texels) *n_texels = nx;
+  if (mesh_ws_bytes) *mesh_ws_bytes = mesh_layout(n_faces, h_s_face != nullptr).total;
+  return LF_OK;
+}
+
+lf_status lf_load_mesh(const lf_mesh_opts* opts, const float* d_vertices, int64_t n_vertices, const int32_t* d_faces,
+                       int64_t n_faces, const int32_t* d_s_face, void* d_mesh_ws, int64_t mesh_ws_bytes,
+                       void* d_accum, float* d_wsum, int64_t n_texels, hipStream_t stream, lf_mesh* out) {
+  g_err[0] = 0;
+  if (!out) return fail(LF_EINVAL, "out handle pointer is NULL");
+  *out = nullptr;
+  lf_status st = check_opts(opts);
+  if (st != LF_OK) return st;
+  if (n_vertices < 1 || n_faces < 0 || n_faces >= (int64_t)1 << 31) return fail(LF_EINVAL, "bad vertex/face count");
+  if (!d_vertices || (!d_faces && n_faces > 0) || !d_mesh_ws || (!d_accum && n_texels > 0))
+    return fail(LF_EINVAL, "NULL device buffer");
+  if (reinterpret_cast<uintptr_t>(d_mesh_ws) & 255) return fail(LF_EINVAL, "mesh workspace must be 256-byte aligned");
+  if (opts->aggregator == LF_AGG_MUL && !d_wsum) return fail(LF_EINVAL, "MUL aggregation needs the weight-sum buffer");
+  const bool per_face = d_s_face != nullptr;
+  if (!per_face && (opts->s_uniform < 1 || opts->s_uniform > 4096)) return fail(LF_EINVAL, "s_uniform must be in [1, 4096]");
+  const MeshLayout L = mesh_layout(n_faces, per_face);
+  if (mesh_ws_bytes < L.total) return fail(LF_ESIZE, "mesh workspace %lld < %lld bytes", (long long)mesh_ws_bytes, (long long)L.total);
+  if (!per_face) {
+    const int64_t want = n_faces * per_tri(opts->s_uniform, opts->scheme);
+    if (want != n_texels) return fail(LF_ESIZE, "n_texels %lld != %lld", (long long)n_texels, (long long)want);
+  }
+  char* ws = reinterpret_cast<char*>(d_mesh_ws);
+  MeshDev d{};
+  d.verts = d_vertices;
+  d.faces_uv = reinterpret_cast<int32_t*>(ws + L.faces_uv);
+  d.s_face = per_face ? reinterpret_cast<int32_t*>(ws + L.s_face) : nullptr;
+  d.off = per_face ? reinterpret_cast<int64_t*>(ws + L.off) : nullptr;
+  d.cl_box = reinterpret_cast<float*>(ws + L.cl_box);
+  d.err = reinterpret_cast<int32_t*>(ws + L.err);
+  d.accum = d_accum;
+  d.wsum = d_wsum;
+  d.V = n_vertices;
+  d.T = n_faces;
+  d.n_texels = n_texels;
+  d.n_clusters = (n_faces + kClusterTris - 1) / kClusterTris;
+  d.s_uniform = per_face ? 0 : opts->s_uniform;
+  d.split = opts->scheme == LF_TEX_SPLIT;
+  d.c = opts->n_classes;
+  d.aggregator = opts->aggregator;
+  d.accum_dtype = opts->accum_dtype;
+  d.n_per = per_face ? 0 : (int32_t)per_tri(opts->s_uniform, opts->scheme);
+  d.z_near = opts->z_near;
+
+  LF_TRY(launch_zero(d.err, 4, stream), "clear flag");
+  if (per_face)
+    LF_TRY(hipMemcpyAsync(d.s_face, d_s_face, n_faces * 4, hipMemcpyDeviceToDevice, stream), "copy s");
+  LF_TRY(launch_mesh_prep(d, d_faces, stream), "mesh prep");
+  if (per_face) LF_TRY(launch_offsets(d, reinterpret_cast<int32_t*>(ws + L.scan), stream), "offsets");
+  LF_TRY(launch_cluster_boxes(d, stream), "cluster boxes");
+  LF_TRY(launch_zero(d_accum, n_texels * opts->n_classes * 4, stream), "clear accumulator");
+  if (d_wsum) LF_TRY(launch_zero(d_wsum, n_texels * 4, stream), "clear weights");
+  int32_t herr = 0;
+  int64_t htot = n_texels;
+  LF_TRY(hipMemcpyAsync(&herr, d.err, 4, hipMemcpyDeviceToHost, stream), "read flag");
+  if (per_face) LF_TRY(hipMemcpyAsync(&htot, d.off + n_faces, 8, hipMemcpyDeviceToHost, stream), "read total");
+  LF_TRY(hipStreamSynchronize(stream), "sync");
+  if (herr) return fail(LF_EINVAL, "face index out of range [0, %lld) or s < 1", (long long)n_vertices);
+  if (htot != n_texels) return fail(LF_ESIZE, "n_texels %lld != %lld", (long long)n_texels, (long long)htot);
+  lf_mesh h = new (std::nothrow) lf_mesh_s;
+  if (!h) return fail(LF_EINVAL, "out of host memory");
+  h->magic = kMagic;
+  h->d = d;
+  h->opts = *opts;
+  *out = h;
+  return LF_OK;
+}
+
+lf_status lf_reset(lf_mesh mesh, hipStream_t stream) {
+  g_err[0] = 0;
+  lf_status st = check_mesh(mesh);
+  if (st != LF_OK) return st;
+  StageTimer tm(mesh, 6, stream);
+  LF_TRY(launch_zero(mesh->d.accum, mesh->d.n_texels * mesh->d.c * 4, stream), "clear accumulator");
+  if (mesh->d.wsum) LF_TRY(launch_zero(mesh->d.wsum, mesh->d.n_texels * 4, stream), "clear weights");
+  return LF_OK;
+}
+
+lf_status lf_frame_ws_bytes(lf_mesh mesh, int32_t H, int32_t W, int32_t batch, int32_t weighting,
+                            int32_t scatter_mode, int64_t* bytes) {
+  g_err[0] = 0;
+  lf_status st = check_mesh(mesh);
+  if (st != LF_OK) return st;
+  if ((st = check_frames(1, H, W)) != LF_OK) return st;
+  if (batch < 1 || batch > 65535) return fail(LF_EINVAL, "batch must be in [1, 65535]");
+  (void)scatter_mode;
+  if (bytes) *bytes = frame_layout(mesh->d, H, W, batch, weighting).total;
+  return LF_OK;
+}
+
+lf_status lf_fuse_frames(lf_mesh mesh, const float* d_cams, int32_t F, int32_t H, int32_t W, const void* d_probs,
+                         int32_t prob_dtype, const int64_t* h_strides, const float* d_scale, const uint8_t* d_valid,
+                         int32_t weighting, int32_t* d_l_out, void* d_ws, int64_t ws_bytes, int32_t batch,
+                         int32_t scatter_mode, hipStream_t stream) {
+  g_err[0] = 0;
+  lf_status st = check_mesh(mesh);
+  if (st != LF_OK) return st;
+  if ((st = check_frames(F, H, W)) != LF_OK) return st;
+  if (F == 0) return LF_OK;
+  if (!d_cams || !d_probs || !h_strides || !d_ws) return fail(LF_EINVAL, "NULL argument");
+  if (prob_dtype != LF_F32 && prob_dtype != LF_FP8_E4M3) return fail(LF_EINVAL, "probabilities must be F32 or FP8_E4M3");
+  if (prob_dtype == LF_FP8_E4M3 && !d_scale) return fail(LF_EINVAL, "FP8 input needs the per-pixel scale");
+  if (weighting < LF_W_PIXEL || weighting > LF_W_IMAGE) return fail(LF_EINVAL, "weighting %d not supported here", weighting);
+  if (scatter_mode < LF_SCATTER_AUTO || scatter_mode > LF_SCATTER_SORTED) return fail(LF_EINVAL, "bad scatter mode");
+  for (int i = 0; i < 4; ++i)
+    if (h_strides[i] < 0) return fail(LF_EINVAL, "negative stride");
+  if (batch < 1) return fail(LF_EINVAL, "batch must be >= 1");
+  if (reinterpret_cast<uintptr_t>(d_ws) & 255) return fail(LF_EINVAL, "workspace must be 256-byte aligned");
+  const MeshDev& d = mesh->d;
+  const int B = batch < F ? batch : F;
+  const FrameLayout L = frame_layout(d, H, W, B, weighting);
+  if (ws_bytes < L.total) return fail(LF_ESIZE, "frame workspace %lld < %lld bytes", (long long)ws_bytes, (long long)L.total);
+  char* ws = reinterpret_cast<char*>(d_ws);
+  const int64_t HW = (int64_t)H * W;
+  ProbIn in{d_probs, d_scale, d_valid, h_strides[0], h_strides[1], h_strides[2], h_strides[3], prob_dtype};
+  int32_t* cnt = weighting == LF_W_IMAGE ? reinterpret_cast<int32_t*>(ws + L.cnt) : nullptr;
+  LF_TRY(launch_fill_u64(reinterpret_cast<unsigned long long*>(ws + L.keys), B * HW, ~0ull, stream), "clear keys");
+  if (cnt) LF_TRY(launch_zero(cnt, (int64_t)B * d.n_texels * 4, stream), "clear counts");
+  for (int f0 = 0; f0 < F; f0 += B) {
+    const int nb = (F - f0) < B ? (F - f0) : B;
+    int32_t* lb = d_l_out ? d_l_out + (int64_t)f0 * HW : reinterpret_cast<int32_t*>(ws + L.l);
+    const uint8_t* vb = d_valid ? d_valid + (int64_t)f0 * HW : nullptr;
+    if ((st = render_batch(mesh, d_cams, f0, nb, H, W, L, ws, lb, nullptr, nullptr, vb, cnt, d.n_texels, stream)) != LF_OK)
+      return st;
+    {
+      StageTimer tm(mesh, 2, stream);
+      LF_TRY(launch_scatter_atomic(d, in, f0, nb, H, W, lb, weighting, cnt, d.n_texels, nullptr, stream), "scatter");
+    }
+    if (cnt) {
+      StageTimer tm(mesh, 3, stream);
+      LF_TRY(launch_clear_counts(lb, vb, nb, H, W, cnt, d.n_texels, stream), "clear counts");
+    }
+  }
+  return LF_OK;
+}
+
+lf_status lf_finalize(lf_mesh mesh, void* d_tex_out, int32_t tex_dtype, uint8_t* d_labels, hipStream_t stream) {
+  g_err[0] = 0;
+  lf_status st = check_mesh(mesh);
+  if (st != LF_OK) return st;
+  if (!d_labels) return fail(LF_EINVAL, "labels buffer is NULL");
+  if (tex_dtype != LF_F32 && tex_dtype != LF_BF16 && tex_dtype != LF_F16) return fail(LF_EINVAL, "bad texture dtype");
+  StageTimer tm(mesh, 4, stream);
+  LF_TRY(launch_finalize(mesh->d, d_tex_out, tex_dtype, d_labels, stream), "finalize");
+  return LF_OK;
+}
+
+lf_status lf_render_labels(lf_mesh mesh, const float* d_cams, int32_t F, int32_t H, int32_t W, const int32_t* d_l,
+                           const uint8_t* d_valid, const uint8_t* d_labels, uint8_t* d_out, void* d_ws,
+                           int64_t ws_bytes, hipStream_t stream) {
+  g_err[0] = 0;
+  lf_status st = check_mesh(mesh);
+  if (st != LF_OK) return st;
+  if ((st = check_frames(F, H, W)) != LF_OK) return st;
+  if (!d_labels || !d_out) return fail(LF_EINVAL, "NULL argument");
+  const int64_t HW = (int64_t)H * W;
+  if (d_l) {
+    StageTimer tm(mesh, 5, stream);
+    LF_TRY(launch_render(d_l, d_valid, d_labels, (int64_t)F * HW, d_out, stream), "render");
+    return LF_OK;
+  }
+  if (!d_cams || !d_ws) return fail(LF_EINVAL, "re-rendering needs cameras and a workspace");
+  if (F == 0) return LF_OK;
+  const FrameLayout L = frame_layout(mesh->d, H, W, 1, LF_W_PIXEL);
+  int B = 1;
+  while (B < F && frame_layout(mesh->d, H, W, B * 2, LF_W_PIXEL).total <= ws_bytes && B < 64) B *= 2;
+  if (B > F) B = F;
+  const FrameLayout LB = frame_layout(mesh->d, H, W, B, LF_W_PIXEL);
+  if (ws_bytes < L.total) return fail(LF_ESIZE, "frame workspace too small");
+  char* ws = reinterpret_cast<char*>(d_ws);
+  LF_TRY(launch_fill_u64(reinterpret_cast<unsigned long long*>(ws + LB.keys), B * HW, ~0ull, stream), "clear keys");
+  for (int f0 = 0; f0 < F; f0 += B) {
+    const int nb = (F - f0) < B ? (F - f0) : B;
+    int32_t* lb = reinterpret_cast<int32_t*>(ws + LB.l);
+    if ((st = render_batch(mesh, d_cams, f0, nb, H, W, LB, ws, lb, nullptr, nullptr, nullptr, nullptr, 0, stream)) != LF_OK)
+      return st;
+    LF_TRY(launch_render(lb, d_valid ? d_valid + (int64_t)f0 * HW : nullptr, d_labels, (int64_t)nb * HW,
+                         d_out + (int64_t)f0 * HW, stream), "render");
+  }
+  return LF_OK;
+}
+
+lf_status lf_rasterize(lf_mesh mesh, const float* d_cams, int32_t F, int32_t H, int32_t W, int32_t* d_tri,
+                       int32_t* d_l, float* d_z, void* d_ws, int64_t ws_bytes, hipStream_t stream) {
+  g_err[0] = 0;
+  lf_status st = check_mesh(mesh);
+  if (st != LF_OK) return st;
+  if ((st = check_frames(F, H, W)) != LF_OK) return st;
+  if (F == 0) return LF_OK;
+  if (!d_cams || !d_ws) return fail(LF_EINVAL, "NULL argument");
+  if (reinterpret_cast<uintptr_t>(d_ws) & 255) return fail(LF_EINVAL, "workspace must be 256-byte aligned");
+  int B = 1;
+  while (B < F && frame_layout(mesh->d, H, W, B * 2, LF_W_PIXEL).total <= ws_bytes && B < 64) B *= 2;
+  if (B > F) B = F;
+  const FrameLayout L = frame_layout(mesh->d, H, W, B, LF_W_PIXEL);
+  if (ws_bytes < L.total) return fail(LF_ESIZE, "frame workspace too small");
+  char* ws = reinterpret_cast<char*>(d_ws);
+  const int64_t HW = (int64_t)H * W;
+  LF_TRY(launch_fill_u64(reinterpret_cast<unsigned long long*>(ws + L.keys), B * HW, ~0ull, stream), "clear keys");
+  for (int f0 = 0; f0 < F; f0 += B) {
+    const int nb = (F - f0) < B ? (F - f0) : B;
+    const int64_t o = (int64_t)f0 * HW;
+    if ((st = render_batch(mesh, d_cams, f0, nb, H, W, L, ws, d_l ? d_l + o : nullptr, d_tri ? d_tri + o : nullptr,
+                           d_z ? d_z + o : nullptr, nullptr, nullptr, 0, stream)) != LF_OK)
+      return st;
+  }
+  return LF_OK;
+}
+
+lf_status lf_profile_enable(lf_mesh mesh, int32_t on) {
+  g_err[0] = 0;
+  lf_status st = check_mesh(mesh);
+  if (st != LF_OK) return st;
+  for (auto& v : mesh->prof.marks)
+    for (hipEvent_t e : v) (void)hipEventSynchronize(e);
+  mesh->prof.recycle();
+  mesh->prof.on = on != 0;
+  return LF_OK;
+}
+
+lf_status lf_profile_read(lf_mesh mesh, lf_profile* out) {
+  g_err[0] = 0;
+  lf_status st = check_mesh(mesh);
+  if (st != LF_OK) return st;
+  if (!out) return fail(LF_EINVAL, "NULL profile");
+  for (int k = 0; k < LF_N_STAGES; ++k) {
+    double ms = 0.0;
+    const auto& v = mesh->prof.marks[k];
+    for (size_t i = 0; i + 1 < v.size(); i += 2) {
+      LF_TRY(hipEventSynchronize(v[i + 1]), "event sync");
+      float t = 0.0f;
+      LF_TRY(hipEventElapsedTime(&t, v[i], v[i + 1]), "event time");
+      ms += t;
+    }
+    out->ms[k] = ms;
+    out->launches[k] = (int64_t)(v.size() / 2);
+  }
+  return LF_OK;
+}
+
+void lf_free_mesh(lf_mesh mesh) {
+  if (mesh && mesh->magic == kMagic) {
+    mesh->magic = 0;
+    delete mesh;
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,295 @@
+// Aggregation (Sections 3.2.1, 3.2.2, 3.3.2): scatter of weighted pixel
+// distributions into texel rows, normalisation + argmax, render-back.
+//
+// k_scatter_hash: a block owns one screen tile of K consecutive frames.  The
+// texel rows its (pixel, frame) observations hit are first gathered into an
+// LDS hash table (open addressing on the row index), so every distinct row
+// costs one global atomic per class per block instead of one per pixel.
+// Classes are processed CC at a time: the block reads one class plane of the
+// tile (coalesced along x for NCHW input), adds w * p into the LDS row with
+// ds_add_f32, then flushes the used rows to HBM with global_atomic_add_f32.
+// Observations that find no free slot fall back to direct global atomics.
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+
+#include "internal.h"
+#include "spec.h"
+
+namespace lf {
+
+__device__ __forceinline__ float e4m3_value(uint32_t q) {
+  const int e = (q >> 3) & 15, mnt = q & 7;
+  float v = (e == 0) ? (float)mnt * 0.001953125f : __builtin_ldexpf((float)(8 + mnt), e - 10);
+  if (e == 15 && mnt == 7) v = __builtin_nanf("");
+  return (q & 0x80u) ? -v : v;
+}
+
+template <int DT>
+__device__ __forceinline__ float load_prob(const ProbIn& in, int64_t e, float scale) {
+  if constexpr (DT == 0) {
+    return __builtin_nontemporal_load(reinterpret_cast<const float*>(in.p) + e);
+  } else {
+    return e4m3_value(__builtin_nontemporal_load(reinterpret_cast<const uint8_t*>(in.p) + e)) * scale;
+  }
+}
+
+template <int AGG>
+__device__ __forceinline__ float agg_term(float p, float pmax) {
+  if constexpr (AGG == 0) return p;
+  else if constexpr (AGG == 1) return logf(p);
+  else return (p == pmax) ? p : 0.0f;
+}
+
+template <int TW, int TH, int K, int CC, int DT, int AGG>
+__global__ __launch_bounds__(TW * TH) void k_scatter_hash(MeshDev m, ProbIn in, int f_first, int nf, int H, int W,
+                                                           const int32_t* __restrict__ lbuf, int weighting,
+                                                           const int32_t* __restrict__ cnt, int64_t cnt_stride,
+                                                           const float* __restrict__ wpix) {
+  constexpr int NT = TW * TH;
+  constexpr int HS = 2048;            // hash slots (power of two)
+  constexpr int RC = 1024;            // LDS rows
+  constexpr int MAXPROBE = 64;
+  __shared__ int hkey[HS];
+  __shared__ short hpos[HS];
+  __shared__ int rowl[RC];
+  __shared__ float rows[RC * CC];
+  __shared__ int nrow;
+
+  const int c = m.c;
+  float* __restrict__ A = reinterpret_cast<float*>(m.accum);
+  const int tiles_x = (W + TW - 1) / TW;
+  const int tile = blockIdx.x;
+  const int x = (tile % tiles_x) * TW + (threadIdx.x % TW);
+  const int y = (tile / tiles_x) * TH + (threadIdx.x / TW);
+  const bool inimg = x < W && y < H;
+  const int64_t HW = (int64_t)H * W;
+  const int fb0 = blockIdx.y * K;     // first frame of this group, relative to the batch
+
+  for (int i = threadIdx.x; i < HS; i += NT) hkey[i] = -1;
+  if (threadIdx.x == 0) nrow = 0;
+  __syncthreads();
+
+  int lk[K];
+  int sk[K];
+  float wk[K];
+  float sck[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    lk[k] = -1;
+    sk[k] = -1;
+    wk[k] = 0.0f;
+    sck[k] = 1.0f;
+    const int fb = fb0 + k;
+    if (fb < nf && inimg) {
+      const int64_t pi = (int64_t)fb * HW + (int64_t)y * W + x;
+      const int64_t gi = (int64_t)(f_first + fb) * HW + (int64_t)y * W + x;
+      int l = lbuf[pi];
+      if (l >= 0 && in.valid && !in.valid[gi]) l = -1;
+      if (l >= 0) {
+        float w = 1.0f;
+        if (weighting == 1) w = 1.0f / (float)cnt[(int64_t)fb * cnt_stride + l];
+        else if (weighting == 2) w = wpix[pi];
+        lk[k] = l;
+        wk[k] = w;
+        if (DT == 3) sck[k] = in.scale[gi];
+        if (m.wsum) unsafeAtomicAdd(m.wsum + l, w);
+        // insert l; the thread whose CAS fills an empty slot owns it
+        uint32_t h = ((uint32_t)l * 2654435761u) >> (32 - 11);
+        for (int probe = 0; probe < MAXPROBE; ++probe) {
+          const int prev = atomicCAS(&hkey[h], -1, l);
+          if (prev == -1 || prev == l) {
+            sk[k] = (prev == -1) ? (int)(h | 0x80000000u) : (int)h;
+            break;
+          }
+          h = (h + 1) & (HS - 1);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  // owners allocate compact rows
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    if (sk[k] != -1 && (sk[k] & 0x80000000)) {
+      const int slot = sk[k] & 0x7fffffff;
+      const int pos = atomicAdd(&nrow, 1);
+      hpos[slot] = (short)(pos < RC ? pos : -1);
+      if (pos < RC) rowl[pos] = lk[k];
+      sk[k] = slot;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+    if (sk[k] != -1) sk[k] = hpos[sk[k]];   // -1 when the rows overflowed
+  const int nr = min(nrow, RC);
+
+  // per-observation maxima for maxsum
+  float pmx[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) pmx[k] = 0.0f;
+  if constexpr (AGG == 2) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      if (lk[k] < 0) continue;
+      const int64_t base = (int64_t)(f_first + fb0 + k) * in.sf + (int64_t)y * in.sy + (int64_t)x * in.sx;
+      float mx = load_prob<DT>(in, base, sck[k]);
+      for (int j = 1; j < c; ++j) mx = fmaxf(mx, load_prob<DT>(in, base + (int64_t)j * in.sc, sck[k]));
+      pmx[k] = mx;
+    }
+  }
+
+  for (int j0 = 0; j0 < c; j0 += CC) {
+    for (int i = threadIdx.x; i < nr * CC; i += NT) rows[i] = 0.0f;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      if (lk[k] < 0) continue;
+      const int64_t base = (int64_t)(f_first + fb0 + k) * in.sf + (int64_t)y * in.sy + (int64_t)x * in.sx;
+#pragma unroll
+      for (int jj = 0; jj < CC; ++jj) {
+        const int j = j0 + jj;
+        if (j >= c) break;
+        const float v = wk[k] * agg_term<AGG>(load_prob<DT>(in, base + (int64_t)j * in.sc, sck[k]), pmx[k]);
+        if (sk[k] >= 0) atomicAdd(&rows[sk[k] * CC + jj], v);
+        else unsafeAtomicAdd(A + (int64_t)lk[k] * c + j, v);
+      }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < nr * CC; i += NT) {
+      const int r = i / CC, jj = i - r * CC;
+      const int j = j0 + jj;
+      const float v = rows[i];
+      if (j < c && v != 0.0f) unsafeAtomicAdd(A + (int64_t)rowl[r] * c + j, v);
+    }
+    __syncthreads();
+  }
+}
+
+hipError_t launch_scatter_atomic(const MeshDev& m, const ProbIn& in, int f_first, int nf, int H, int W,
+                                 const int32_t* l, int weighting, const int32_t* cnt, int64_t cnt_stride,
+                                 const float* wpix, hipStream_t s) {
+  if (nf <= 0) return hipSuccess;
+  constexpr int TW = 16, TH = 16, K = 4, CC = 8;
+  dim3 grid((unsigned)(((W + TW - 1) / TW) * ((H + TH - 1) / TH)), (unsigned)((nf + K - 1) / K));
+#define LF_SCATTER(DT, AGG)                                                                                   \
+  k_scatter_hash<TW, TH, K, CC, DT, AGG><<<grid, TW * TH, 0, s>>>(m, in, f_first, nf, H, W, l, weighting, cnt, \
+                                                                   cnt_stride, wpix)
+  if (in.dtype == 0) {
+    if (m.aggregator == 0) LF_SCATTER(0, 0);
+    else if (m.aggregator == 1) LF_SCATTER(0, 1);
+    else LF_SCATTER(0, 2);
+  } else {
+    if (m.aggregator == 0) LF_SCATTER(3, 0);
+    else if (m.aggregator == 1) LF_SCATTER(3, 1);
+    else LF_SCATTER(3, 2);
+  }
+#undef LF_SCATTER
+  return hipGetLastError();
+}
+
+// ---- w^(I) counts are per frame: clear the entries a batch touched ---------
+__global__ __launch_bounds__(256) void k_clear_counts(const int32_t* __restrict__ l, int H, int W,
+                                                      int32_t* __restrict__ cnt, int64_t cnt_stride) {
+  const int fb = blockIdx.y;
+  const int64_t HW = (int64_t)H * W;
+  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (p >= HW) return;
+  const int32_t li = l[(int64_t)fb * HW + p];
+  if (li >= 0) cnt[(int64_t)fb * cnt_stride + li] = 0;
+}
+
+hipError_t launch_clear_counts(const int32_t* l, const uint8_t* /*valid*/, int nf, int H, int W, int32_t* cnt,
+                               int64_t cnt_stride, hipStream_t s) {
+  if (nf <= 0) return hipSuccess;
+  const int64_t HW = (int64_t)H * W;
+  k_clear_counts<<<dim3((unsigned)((HW + 255) / 256), (unsigned)nf), 256, 0, s>>>(l, H, W, cnt, cnt_stride);
+  return hipGetLastError();
+}
+
+// ---- normalise + argmax (one wave per row group) ---------------------------
+template <int OUT>
+__device__ __forceinline__ void store_tex(void* out, int64_t i, float v) {
+  if constexpr (OUT == 0) reinterpret_cast<float*>(out)[i] = v;
+  else if constexpr (OUT == 1) reinterpret_cast<__hip_bfloat16*>(out)[i] = __float2bfloat16(v);
+  else reinterpret_cast<__half*>(out)[i] = __float2half(v);
+}
+
+// One thread per texel row: S = sum_j A_j in class order; P = A / S; label =
+// first maximal class; S == 0 (never observed) -> P = 0, label 255.  For MUL
+// the row holds sum w log p: P = softmax(A), observed iff wsum > 0.
+template <int OUT, int AGG>
+__global__ __launch_bounds__(256) void k_finalize(MeshDev m, void* __restrict__ out, uint8_t* __restrict__ labels) {
+  const int64_t x = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (x >= m.n_texels) return;
+  const int c = m.c;
+  const float* __restrict__ a = reinterpret_cast<const float*>(m.accum) + x * c;
+  if constexpr (AGG == 1) {
+    const bool seen = m.wsum[x] > 0.0f;
+    float mx = a[0];
+    int best = 0;
+    for (int j = 1; j < c; ++j) {
+      const float v = a[j];
+      if (v > mx) { mx = v; best = j; }
+    }
+    float s = 0.0f;
+    for (int j = 0; j < c; ++j) s += expf(a[j] - mx);
+    const float inv = 1.0f / s;
+    for (int j = 0; j < c; ++j) {
+      const float v = seen ? expf(a[j] - mx) * inv : 0.0f;
+      if (out) store_tex<OUT>(out, x * c + j, v);
+    }
+    labels[x] = seen ? (uint8_t)best : (uint8_t)255;
+  } else {
+    float s = 0.0f, mx = a[0];
+    int best = 0;
+    for (int j = 0; j < c; ++j) {
+      const float v = a[j];
+      s += v;
+      if (v > mx) { mx = v; best = j; }
+    }
+    const bool seen = s > 0.0f;
+    for (int j = 0; j < c; ++j) {
+      const float v = seen ? a[j] / s : 0.0f;
+      if (out) store_tex<OUT>(out, x * c + j, v);
+    }
+    labels[x] = seen ? (uint8_t)best : (uint8_t)255;
+  }
+}
+
+hipError_t launch_finalize(const MeshDev& m, void* tex_out, int tex_dtype, uint8_t* labels, hipStream_t s) {
+  if (m.n_texels == 0) return hipSuccess;
+  dim3 g((unsigned)((m.n_texels + 255) / 256));
+#define LF_FIN(O, A) k_finalize<O, A><<<g, 256, 0, s>>>(m, tex_out, labels)
+  const bool mul = m.aggregator == 1;
+  if (tex_dtype == 1) { if (mul) LF_FIN(1, 1); else LF_FIN(1, 0); }
+  else if (tex_dtype == 2) { if (mul) LF_FIN(2, 1); else LF_FIN(2, 0); }
+  else { if (mul) LF_FIN(0, 1); else LF_FIN(0, 0); }
+#undef LF_FIN
+  return hipGetLastError();
+}
+
+// ---- render-back ------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_render(const int32_t* __restrict__ l, const uint8_t* __restrict__ valid,
+                                                const uint8_t* __restrict__ labels, int64_t npx,
+                                                uint8_t* __restrict__ out) {
+  const int64_t i = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4;
+  if (i >= npx) return;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int64_t p = i + k;
+    if (p < npx) {
+      const int32_t li = l[p];
+      out[p] = (li >= 0 && (!valid || valid[p])) ? labels[li] : (uint8_t)255;
+    }
+  }
+}
+
+hipError_t launch_render(const int32_t* l, const uint8_t* valid, const uint8_t* labels, int64_t npx, uint8_t* out,
+                         hipStream_t s) {
+  if (npx <= 0) return hipSuccess;
+  k_render<<<dim3((unsigned)((npx + 1023) / 1024)), 256, 0, s>>>(l, valid, labels, npx, out);
+  return hipGetLastError();
+}
+
+}  // namespace lf

@@ -1,0 +1,75 @@
+// Internal host/device interfaces of the semfuse library (not part of the C-ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lf {
+
+constexpr int kClusterTris = 64;      // triangles per culling cluster (one wave)
+
+// Device view of a loaded mesh.  Every pointer is caller-owned device memory.
+struct MeshDev {
+  const float* verts;        // [V][3]
+  int32_t* faces_uv;         // [T][3] vertex indices in uv order (A, B, C)
+  int32_t* s_face;           // [T] or nullptr (uniform s)
+  int64_t* off;              // [T+1] row offsets or nullptr (uniform: t * n_per)
+  float* cl_box;             // [n_clusters][8]: lo.xyz, hi.xyz, magnitude bound, pad
+  int32_t* err;              // [1] validation flag
+  void* accum;               // [n_texels][c]
+  float* wsum;               // [n_texels] or nullptr
+  int64_t V, T, n_texels, n_clusters;
+  int32_t s_uniform, split, c, aggregator, accum_dtype;
+  int32_t n_per;             // texels per triangle when uniform
+  float z_near;
+};
+
+__device__ __forceinline__ int64_t row_offset(const MeshDev& m, int64_t t) {
+  return m.off ? m.off[t] : t * (int64_t)m.n_per;
+}
+__device__ __forceinline__ int tri_s(const MeshDev& m, int64_t t) { return m.s_face ? m.s_face[t] : m.s_uniform; }
+
+// Per-batch frame workspace carved out of the caller's buffer.
+struct FrameWs {
+  unsigned long long* keys;  // [B][H][W] depth|triangle keys, all-ones = empty
+  float* rx;                 // [B][W] pixel ray x per frame
+  float* ry;                 // [B][H]
+  int32_t* l;                // [B][H][W] texel rows (when the caller gives none)
+  int32_t* cnt;              // [B][n_texels] per-frame texel counts (w^(I)) or [n_texels] (sorted)
+  int32_t* start;            // [n_texels + 1] segment starts (sorted scatter)
+  int32_t* entries;          // [B][H][W] sorted (frame, pixel) entries
+  int32_t* scan_tmp;         // scan partials
+  float* wpix;               // [B][H][W] per-pixel weights (learned)
+  int32_t B, H, W;
+};
+
+struct ProbIn {
+  const void* p;             // probabilities (float32 or E4M3 codes)
+  const float* scale;        // per-pixel scale for E4M3 [F][H][W]
+  const uint8_t* valid;      // [F][H][W] or nullptr
+  int64_t sf, sc, sy, sx;    // element strides
+  int32_t dtype;             // 0 = f32, 3 = e4m3
+};
+
+// ---- launchers (return hipGetLastError()) ----------------------------------
+hipError_t launch_mesh_prep(const MeshDev& m, const int32_t* faces, hipStream_t s);
+hipError_t launch_offsets(const MeshDev& m, int32_t* scratch, hipStream_t s);
+hipError_t launch_cluster_boxes(const MeshDev& m, hipStream_t s);
+hipError_t launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t s);
+hipError_t launch_zero(void* p, int64_t bytes, hipStream_t s);
+hipError_t launch_raytab(const float* cams, int nf, int H, int W, float* rx, float* ry, hipStream_t s);
+hipError_t launch_raster(const MeshDev& m, const float* cams, int nf, int H, int W,
+                         unsigned long long* keys, const float* rx, const float* ry, hipStream_t s);
+hipError_t launch_resolve(const MeshDev& m, const float* cams, int nf, int H, int W,
+                          unsigned long long* keys, const float* rx, const float* ry, int32_t* l_out,
+                          int32_t* tri_out, float* z_out, const uint8_t* valid, int32_t* cnt,
+                          int64_t cnt_stride, hipStream_t s);
+hipError_t launch_scatter_atomic(const MeshDev& m, const ProbIn& in, int f_first, int nf, int H, int W,
+                                 const int32_t* l, int weighting, const int32_t* cnt, int64_t cnt_stride,
+                                 const float* wpix, hipStream_t s);
+hipError_t launch_clear_counts(const int32_t* l, const uint8_t* valid, int nf, int H, int W, int32_t* cnt,
+                               int64_t cnt_stride, hipStream_t s);
+hipError_t launch_finalize(const MeshDev& m, void* tex_out, int tex_dtype, uint8_t* labels, hipStream_t s);
+hipError_t launch_render(const int32_t* l, const uint8_t* valid, const uint8_t* labels, int64_t npx,
+                         uint8_t* out, hipStream_t s);
+
+}  // namespace lf

@@ -1,0 +1,243 @@
+"""Python binding of the semfuse C-ABI (``include/semfuse.h``).
+
+Argument marshalling only: tensors are passed as raw device pointers on the
+current PyTorch stream, and every step runs in the library's HIP kernels.
+The library must be built (``paper_2111_11103_amd/build.py``); nothing here
+falls back to another implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import threading
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsemfuse.so")
+
+# enums of semfuse.h
+LF_OK, LF_EINVAL, LF_ESIZE, LF_EHIP, LF_ESTATE = 0, -1, -2, -3, -4
+SQUARE, SPLIT = 0, 1
+W_PIXEL, W_IMAGE, W_LEARNED = 0, 1, 2
+AGG_SUM, AGG_MUL, AGG_MAXSUM = 0, 1, 2
+F32, BF16, F16, FP8_E4M3 = 0, 1, 2, 3
+SCATTER_AUTO, SCATTER_ATOMIC, SCATTER_SORTED = 0, 1, 2
+
+_TEX_DT = {torch.float32: F32, torch.bfloat16: BF16, torch.float16: F16}
+
+
+class SemfuseError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"semfuse error {status}: {msg}")
+        self.status = status
+
+
+class _MeshOpts(C.Structure):
+    _fields_ = [("scheme", C.c_int32), ("s_uniform", C.c_int32), ("n_classes", C.c_int32),
+                ("aggregator", C.c_int32), ("accum_dtype", C.c_int32), ("z_near", C.c_float)]
+
+
+_lib = None
+_lock = threading.Lock()
+_p, _i32, _i64 = C.c_void_p, C.c_int32, C.c_int64
+
+
+def lib():
+    """The loaded HIP library (raises if it was not built)."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise RuntimeError(f"semfuse HIP library missing: {LIB_PATH} (build it with "
+                                   "`python -c 'import __graft_entry__ as g; g.build()'`)")
+            L = C.CDLL(LIB_PATH)
+            L.lf_last_error.restype = C.c_char_p
+            L.lf_version.restype = C.c_char_p
+            L.lf_mesh_sizes.argtypes = [C.POINTER(_MeshOpts), _i64, _i64, _p, C.POINTER(_i64), C.POINTER(_i64)]
+            L.lf_load_mesh.argtypes = [C.POINTER(_MeshOpts), _p, _i64, _p, _i64, _p, _p, _i64, _p, _p, _i64, _p,
+                                       C.POINTER(_p)]
+            L.lf_reset.argtypes = [_p, _p]
+            L.lf_frame_ws_bytes.argtypes = [_p, _i32, _i32, _i32, _i32, _i32, C.POINTER(_i64)]
+            L.lf_fuse_frames.argtypes = [_p, _p, _i32, _i32, _i32, _p, _i32, _p, _p, _p, _i32, _p, _p, _i64, _i32,
+                                         _i32, _p]
+            L.lf_finalize.argtypes = [_p, _p, _i32, _p, _p]
+            L.lf_render_labels.argtypes = [_p, _p, _i32, _i32, _i32, _p, _p, _p, _p, _p, _i64, _p]
+            L.lf_rasterize.argtypes = [_p, _p, _i32, _i32, _i32, _p, _p, _p, _p, _i64, _p]
+            L.lf_free_mesh.argtypes = [_p]
+            L.lf_free_mesh.restype = None
+            for name in ("lf_mesh_sizes", "lf_load_mesh", "lf_reset", "lf_frame_ws_bytes", "lf_fuse_frames",
+                         "lf_finalize", "lf_render_labels", "lf_rasterize"):
+                getattr(L, name).restype = _i32
+            _lib = L
+    return _lib
+
+
+def _check(st):
+    if st != LF_OK:
+        raise SemfuseError(st, lib().lf_last_error().decode())
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _need_cuda(t, name, dtype=None):
+    if t is None:
+        return
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+
+
+def version() -> str:
+    return lib().lf_version().decode()
+
+
+def mesh_sizes(n_vertices, n_faces, s=1, scheme=SPLIT, n_classes=40, aggregator=AGG_SUM, s_face=None,
+               z_near=0.05):
+    """(n_texels, mesh workspace bytes) -- lf_mesh_sizes."""
+    o = _MeshOpts(scheme, s, n_classes, aggregator, F32, z_near)
+    nx, ws = _i64(), _i64()
+    hs = None
+    if s_face is not None:
+        import numpy as np
+        arr = np.ascontiguousarray(s_face, dtype=np.int32)
+        hs = arr.ctypes.data_as(_p)
+    _check(lib().lf_mesh_sizes(C.byref(o), int(n_vertices), int(n_faces), hs, C.byref(nx), C.byref(ws)))
+    return nx.value, ws.value
+
+
+class Mesh:
+    """A loaded mesh with its caller-owned accumulator (lf_load_mesh)."""
+
+    def __init__(self, vertices: torch.Tensor, faces: torch.Tensor, *, n_classes: int, s: int = 1,
+                 scheme: int = SPLIT, aggregator: int = AGG_SUM, s_face: torch.Tensor | None = None,
+                 z_near: float = 0.05, keep_weights: bool = True):
+        _need_cuda(vertices, "vertices", torch.float32)
+        _need_cuda(faces, "faces", torch.int32)
+        vertices = vertices.contiguous()
+        faces = faces.contiguous()
+        self.device = vertices.device
+        self.c = int(n_classes)
+        self.opts = _MeshOpts(scheme, s, n_classes, aggregator, F32, z_near)
+        hs = None if s_face is None else s_face.detach().cpu().to(torch.int32).numpy()
+        self.n_texels, ws_bytes = mesh_sizes(vertices.shape[0], faces.shape[0], s, scheme, n_classes, aggregator,
+                                             hs, z_near)
+        self.vertices = vertices
+        self.ws = torch.empty(max(ws_bytes, 256), dtype=torch.uint8, device=self.device)
+        self.accum = torch.empty((self.n_texels, self.c), dtype=torch.float32, device=self.device)
+        self.wsum = torch.empty(self.n_texels, dtype=torch.float32, device=self.device) \
+            if (keep_weights or aggregator == AGG_MUL) else None
+        sf = None
+        if s_face is not None:
+            sf = s_face.to(device=self.device, dtype=torch.int32).contiguous()
+        h = _p()
+        _check(lib().lf_load_mesh(C.byref(self.opts), _ptr(vertices), vertices.shape[0], _ptr(faces), faces.shape[0],
+                                  _ptr(sf), _ptr(self.ws), self.ws.numel(), _ptr(self.accum), _ptr(self.wsum),
+                                  self.n_texels, _stream(), C.byref(h)))
+        self._h = h
+        self._fws = {}
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.lf_free_mesh(h)
+            self._h = None
+
+    # -- workspace -----------------------------------------------------------------
+    def frame_ws(self, H, W, batch, weighting=W_PIXEL, scatter_mode=SCATTER_AUTO):
+        n = _i64()
+        _check(lib().lf_frame_ws_bytes(self._h, H, W, batch, weighting, scatter_mode, C.byref(n)))
+        key = (H, W, batch, weighting, scatter_mode)
+        t = self._fws.get(key)
+        if t is None or t.numel() < n.value:
+            self._fws.clear()
+            t = torch.empty(n.value, dtype=torch.uint8, device=self.device)
+            self._fws[key] = t
+        return t
+
+    # -- C-ABI calls -----------------------------------------------------------------
+    def reset(self):
+        _check(lib().lf_reset(self._h, _stream()))
+
+    def fuse_frames(self, cams: torch.Tensor, probs: torch.Tensor, *, scale=None, valid=None,
+                    weighting=W_PIXEL, l_out=None, batch=16, scatter_mode=SCATTER_AUTO, ws=None):
+        """lf_fuse_frames: probs is [F, c, H, W] (any strides) float32, or uint8
+        E4M3 codes with ``scale`` [F, H, W]."""
+        F, c, H, W = probs.shape
+        if c != self.c:
+            raise ValueError(f"probs has {c} classes, mesh has {self.c}")
+        _need_cuda(cams, "cams", torch.float32)
+        _need_cuda(probs, "probs")
+        _need_cuda(valid, "valid", torch.uint8)
+        _need_cuda(l_out, "l_out", torch.int32)
+        cams = cams.contiguous()
+        if cams.shape != (F, 16):
+            raise ValueError("cams must be [F, 16]")
+        if probs.dtype == torch.float32:
+            dt = F32
+        elif probs.dtype == torch.uint8:
+            dt = FP8_E4M3
+            _need_cuda(scale, "scale", torch.float32)
+            scale = scale.contiguous()
+        else:
+            raise TypeError("probs must be float32 or uint8 E4M3 codes")
+        if valid is not None:
+            valid = valid.contiguous()
+        if l_out is not None and (not l_out.is_contiguous() or tuple(l_out.shape) != (F, H, W)):
+            raise ValueError("l_out must be a contiguous [F, H, W] int32 tensor")
+        strides = (C.c_int64 * 4)(*probs.stride())
+        b = max(1, min(int(batch), F))
+        if ws is None:
+            ws = self.frame_ws(H, W, b, weighting, scatter_mode)
+        _check(lib().lf_fuse_frames(self._h, _ptr(cams), F, H, W, _ptr(probs), dt, strides, _ptr(scale), _ptr(valid),
+                                    weighting, _ptr(l_out), _ptr(ws), ws.numel(), b, scatter_mode, _stream()))
+
+    def finalize(self, tex_dtype=torch.float32, want_tex=True):
+        """lf_finalize -> (texture [n_texels, c] or None, labels [n_texels] uint8)."""
+        tex = torch.empty((self.n_texels, self.c), dtype=tex_dtype, device=self.device) if want_tex else None
+        lab = torch.empty(self.n_texels, dtype=torch.uint8, device=self.device)
+        _check(lib().lf_finalize(self._h, _ptr(tex), _TEX_DT[tex_dtype], _ptr(lab), _stream()))
+        return tex, lab
+
+    def render_labels(self, labels, *, l=None, cams=None, H=None, W=None, valid=None, out=None, batch=8):
+        """lf_render_labels from stored rows ``l`` [F,H,W], or by re-rendering ``cams``."""
+        if l is not None:
+            F, H, W = l.shape
+            _need_cuda(l, "l", torch.int32)
+            l = l.contiguous()
+        else:
+            F = cams.shape[0]
+        _need_cuda(labels, "labels", torch.uint8)
+        _need_cuda(valid, "valid", torch.uint8)
+        if valid is not None:
+            valid = valid.contiguous()
+        if out is None:
+            out = torch.empty((F, H, W), dtype=torch.uint8, device=self.device)
+        ws = None
+        if l is None:
+            _need_cuda(cams, "cams", torch.float32)
+            cams = cams.contiguous()
+            ws = self.frame_ws(H, W, max(1, min(batch, F)))
+        _check(lib().lf_render_labels(self._h, _ptr(cams), F, H, W, _ptr(l), _ptr(valid), _ptr(labels), _ptr(out),
+                                      _ptr(ws), 0 if ws is None else ws.numel(), _stream()))
+        return out
+
+    def rasterize(self, cams, H, W, batch=8, want=("tri", "l", "z")):
+        """lf_rasterize -> dict of [F, H, W] tensors (tri int32, l int32, z float32)."""
+        _need_cuda(cams, "cams", torch.float32)
+        cams = cams.contiguous()
+        F = cams.shape[0]
+        out = {}
+        for k, dt in (("tri", torch.int32), ("l", torch.int32), ("z", torch.float32)):
+            out[k] = torch.empty((F, H, W), dtype=dt, device=self.device) if k in want else None
+        ws = self.frame_ws(H, W, max(1, min(batch, F)))
+        _check(lib().lf_rasterize(self._h, _ptr(cams), F, H, W, _ptr(out["tri"]), _ptr(out["l"]), _ptr(out["z"]),
+                                  _ptr(ws), ws.numel(), _stream()))
+        return out

@@ -1,0 +1,202 @@
+"""GPU parity of the HIP path (through the C-ABI) against the CPU oracle on
+identical seeded inputs: bit-exact triangle ids, texel rows and depths;
+fused distributions within 1e-5 relative of binary64; labels equal wherever
+the class margin exceeds that tolerance."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2111_11103_amd import scenes as S
+from paper_2111_11103_amd import semfuse as sf
+from tests.gpu_cases import (compare_fused, compare_labels, compare_normalized, compare_raster, gpu_mesh,
+                             oracle_mesh, say, to_dev)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def cfg1():
+    say("[case] config-1 workload (2,100 triangles, 20 frames 160x120, c=13)")
+    return S.config1(device="cpu")
+
+
+def _fuse_both(gm, om, w, cams, probs_np, valid_np, weighting, aggregator=sf.AGG_SUM, batch=8, scatter=sf.SCATTER_AUTO,
+               probs_dev=None, scale=None):
+    F, c, H, W = probs_np.shape if probs_dev is None or probs_dev.dtype == torch.float32 else probs_dev.shape
+    l_out = torch.empty((F, H, W), dtype=torch.int32, device="cuda")
+    gm.fuse_frames(to_dev(cams, torch.float32), probs_dev if probs_dev is not None else to_dev(probs_np),
+                   valid=None if valid_np is None else to_dev(valid_np), weighting=weighting, l_out=l_out,
+                   batch=batch, scatter_mode=scatter, scale=scale)
+    torch.cuda.synchronize()
+    l_g = l_out.cpu().numpy()
+    return l_g
+
+
+def test_config1_raster_bit_exact(cfg1):
+    say("[case] config-1 raster")
+    sc = cfg1.scene
+    gm = gpu_mesh((sc.vertices, sc.faces), 1, oracle.SPLIT, 13)
+    om = oracle_mesh(sc.vertices, sc.faces, 1, oracle.SPLIT)
+    compare_raster(gm, om, cfg1.cams, cfg1.H, cfg1.W)
+
+
+@pytest.mark.parametrize("weighting", [sf.W_PIXEL, sf.W_IMAGE])
+def test_config1_fusion_parity(cfg1, weighting):
+    say(f"[case] config-1 fusion weighting={weighting}")
+    sc = cfg1.scene
+    gm = gpu_mesh((sc.vertices, sc.faces), 1, oracle.SPLIT, 13)
+    om = oracle_mesh(sc.vertices, sc.faces, 1, oracle.SPLIT)
+    probs = cfg1.probs.numpy()
+    valid = cfg1.valid.numpy()
+    l_g = _fuse_both(gm, om, weighting, cfg1.cams, probs, valid, weighting)
+    _, l_o = om.raster_frames(cfg1.cams, cfg1.H, cfg1.W)
+    assert np.array_equal(l_g, l_o)
+    A_o, W_o = oracle.fuse(om.n_texels, 13, l_o, probs, valid, weighting=weighting)
+    compare_fused(gm.accum.cpu().numpy(), A_o)
+    # total weight per texel: one binary32 atomic add per pixel, so the error
+    # bound is (number of adds) * 2^-24 relative
+    n_add = np.bincount(l_o[(l_o >= 0) & (valid > 0)], minlength=om.n_texels)
+    ws_g = gm.wsum.cpu().numpy().astype(np.float64)
+    assert (np.abs(ws_g - W_o) <= np.maximum(n_add, 1) * 2.0 ** -24 * W_o).all()
+    P_o, lab_o = oracle.finalize(A_o, W_o)
+    tex, lab = gm.finalize()
+    torch.cuda.synchronize()
+    compare_normalized(tex.cpu().numpy(), P_o)
+    compare_labels(lab.cpu().numpy(), P_o, lab_o)
+    # render-back from the stored rows and by re-rendering
+    out1 = gm.render_labels(lab, l=to_dev(l_g), valid=to_dev(valid)).cpu().numpy()
+    out2 = gm.render_labels(lab, cams=to_dev(cfg1.cams, torch.float32), H=cfg1.H, W=cfg1.W,
+                            valid=to_dev(valid)).cpu().numpy()
+    ref = oracle.render(l_o, lab.cpu().numpy(), valid)
+    assert np.array_equal(out1, ref) and np.array_equal(out2, ref)
+    # the fusion improves over the input argmax on this workload
+    gt = cfg1.gt.numpy()
+    acc_in = (probs.argmax(1) == gt).mean()
+    acc_out = (out1 == gt).mean()
+    say(f"  pixel accuracy input {acc_in:.4f} -> fused {acc_out:.4f}")
+    assert acc_out > acc_in + 0.1
+
+
+def test_raster_deterministic_and_batch_invariant(cfg1):
+    say("[case] raster determinism across runs and batch sizes")
+    sc = cfg1.scene
+    gm = gpu_mesh((sc.vertices, sc.faces), 2, oracle.SQUARE, 13)
+    cams = to_dev(cfg1.cams, torch.float32)
+    a = gm.rasterize(cams, cfg1.H, cfg1.W, batch=1)
+    b = gm.rasterize(cams, cfg1.H, cfg1.W, batch=8)
+    c = gm.rasterize(cams, cfg1.H, cfg1.W, batch=20)
+    for k in ("tri", "l"):
+        assert torch.equal(a[k], b[k]) and torch.equal(a[k], c[k])
+
+
+def test_texel_subdivision_and_per_face_s(cfg1):
+    say("[case] s=4 SPLIT, per-face s SQUARE, ragged 157x113 frames")
+    sc = cfg1.scene
+    cams = np.stack([S.camera_matrix(p, (3.1, 2.5, 0.5), 157, 113)
+                     for p in [(1.0, 1.0, 1.6), (5.0, 1.0, 1.4), (5.0, 4.0, 2.0), (1.0, 4.0, 1.0),
+                               (3.0, 2.5, 2.5), (0.2, 0.2, 0.3)]])
+    gm = gpu_mesh((sc.vertices, sc.faces), 4, oracle.SPLIT, 13)
+    om = oracle_mesh(sc.vertices, sc.faces, 4, oracle.SPLIT)
+    compare_raster(gm, om, cams, 113, 157)
+    rng = np.random.default_rng(0)
+    s_face = rng.integers(1, 6, sc.n_faces).astype(np.int32)
+    gm = gpu_mesh((sc.vertices, sc.faces), 1, oracle.SQUARE, 13, s_face=s_face)
+    om = oracle_mesh(sc.vertices, sc.faces, 1, oracle.SQUARE, s_face=s_face)
+    assert gm.n_texels == om.n_texels
+    compare_raster(gm, om, cams, 113, 157)
+
+
+def test_near_plane_clipping_close_to_walls():
+    say("[case] camera 3 cm from a wall and the floor: clipped triangles")
+    sc = S.room_scene(seed=3, room=(4.0, 3.0, 2.5), n_boxes=3, n_classes=8, room_grid=6, box_grid=2)
+    cams = np.stack([
+        S.camera_matrix((0.03, 1.5, 0.03), (2.0, 1.5, 0.0), 96, 64),
+        S.camera_matrix((0.5, 0.03, 1.0), (0.6, 3.0, 0.2), 96, 64),
+        S.camera_matrix((2.0, 1.5, 0.05), (2.5, 1.6, 2.5), 96, 64),
+        S.camera_matrix((3.9, 2.9, 2.4), (0.0, 0.0, 0.0), 96, 64),
+    ])
+    gm = gpu_mesh((sc.vertices, sc.faces), 3, oracle.SPLIT, 8)
+    om = oracle_mesh(sc.vertices, sc.faces, 3, oracle.SPLIT)
+    compare_raster(gm, om, cams, 64, 96)
+
+
+def test_tiny_and_empty_frames(cfg1):
+    say("[case] 1x1 and 1x7 frames, F=0, camera facing away")
+    sc = cfg1.scene
+    gm = gpu_mesh((sc.vertices, sc.faces), 1, oracle.SPLIT, 13)
+    om = oracle_mesh(sc.vertices, sc.faces, 1, oracle.SPLIT)
+    for (H, W) in ((1, 1), (7, 1), (1, 7)):
+        cams = np.stack([S.camera_matrix((3, 2.5, 1.5), (3.5, 2.0, 1.0), W, H)])
+        compare_raster(gm, om, cams, H, W)
+    # no frames: a no-op
+    p = torch.zeros((0, 13, 4, 4), device="cuda")
+    gm.fuse_frames(torch.zeros((0, 16), device="cuda"), p)
+    torch.cuda.synchronize()
+    assert float(gm.accum.abs().sum()) == 0.0
+    # a camera outside the room facing away sees nothing
+    cams = np.stack([S.camera_matrix((20, 20, 1.5), (40, 40, 1.5), 32, 24)])
+    out = gm.rasterize(to_dev(cams, torch.float32), 24, 32)
+    assert int((out["tri"] >= 0).sum()) == 0
+
+
+@pytest.mark.parametrize("aggregator", [sf.AGG_MUL, sf.AGG_MAXSUM])
+def test_aggregators_mul_maxsum(cfg1, aggregator):
+    say(f"[case] aggregator {aggregator}")
+    sc = cfg1.scene
+    gm = gpu_mesh((sc.vertices, sc.faces), 1, oracle.SPLIT, 13, aggregator=aggregator)
+    om = oracle_mesh(sc.vertices, sc.faces, 1, oracle.SPLIT)
+    probs = cfg1.probs.numpy()[:8]
+    l_g = _fuse_both(gm, om, 0, cfg1.cams[:8], probs, None, sf.W_IMAGE)
+    A_o, W_o = oracle.fuse(om.n_texels, 13, l_g, probs, None, weighting=oracle.W_IMAGE, aggregator=aggregator)
+    compare_fused(gm.accum.cpu().numpy(), A_o, aggregator=aggregator, rel=2e-5 if aggregator == sf.AGG_MUL else 1e-5)
+    P_o, lab_o = oracle.finalize(A_o, W_o, aggregator=aggregator)
+    tex, lab = gm.finalize()
+    torch.cuda.synchronize()
+    if aggregator == sf.AGG_MUL:
+        # the margin that decides a label is A_1 - A_2 in the log domain; the
+        # binary32 sums of m log terms carry up to ~m 2^-24 |A| of error
+        srt = np.sort(A_o, axis=1)
+        clear = (lab_o == 255) | (srt[:, -1] - srt[:, -2] > 2e-5 * np.abs(srt[:, -1]) + 1e-5)
+        assert not ((lab.cpu().numpy() != lab_o) & clear).any()
+    else:
+        compare_labels(lab.cpu().numpy(), P_o, lab_o)
+
+
+def test_nhwc_and_fp8_inputs(cfg1):
+    say("[case] channels-last input and FP8 E4M3 input with per-pixel scale")
+    sc = cfg1.scene
+    probs = cfg1.probs[:10]
+    cams = cfg1.cams[:10]
+    om = oracle_mesh(sc.vertices, sc.faces, 1, oracle.SPLIT)
+    gm = gpu_mesh((sc.vertices, sc.faces), 1, oracle.SPLIT, 13)
+    nhwc = probs.to(memory_format=torch.channels_last).cuda()
+    assert nhwc.stride()[1] == 1
+    l_out = torch.empty((10, cfg1.H, cfg1.W), dtype=torch.int32, device="cuda")
+    gm.fuse_frames(to_dev(cams, torch.float32), nhwc, l_out=l_out)
+    torch.cuda.synchronize()
+    l_g = l_out.cpu().numpy()
+    A_o, _ = oracle.fuse(om.n_texels, 13, l_g, probs.numpy())
+    compare_fused(gm.accum.cpu().numpy(), A_o)
+    q, scale = S.quantize_fp8(probs)
+    gm8 = gpu_mesh((sc.vertices, sc.faces), 1, oracle.SPLIT, 13)
+    gm8.fuse_frames(to_dev(cams, torch.float32), q.cuda(), scale=scale.cuda(), l_out=l_out)
+    torch.cuda.synchronize()
+    A8, _ = oracle.fuse(om.n_texels, 13, l_g, q.numpy(), scale=scale.numpy())
+    compare_fused(gm8.accum.cpu().numpy(), A8)
+
+
+def test_errors_are_reported():
+    say("[case] error statuses")
+    V = torch.zeros((3, 3), device="cuda")
+    F = torch.tensor([[0, 1, 5]], dtype=torch.int32, device="cuda")
+    with pytest.raises(sf.SemfuseError) as e:
+        sf.Mesh(V, F, n_classes=4)
+    assert e.value.status == sf.LF_EINVAL
+    m = sf.Mesh(V, torch.tensor([[0, 1, 2]], dtype=torch.int32, device="cuda"), n_classes=4)
+    with pytest.raises(sf.SemfuseError) as e:
+        m.fuse_frames(torch.zeros((1, 16), device="cuda"), torch.zeros((1, 4, 8, 8), device="cuda"),
+                      ws=torch.empty(16, dtype=torch.uint8, device="cuda"))
+    assert e.value.status in (sf.LF_ESIZE, sf.LF_EINVAL)
+    with pytest.raises(ValueError):
+        m.fuse_frames(torch.zeros((1, 16), device="cuda"), torch.zeros((1, 5, 8, 8), device="cuda"))
