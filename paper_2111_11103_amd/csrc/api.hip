@@ -4,6 +4,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 #include <vector>
 
@@ -133,19 +134,38 @@ lf_status check_mesh(lf_mesh m) {
 }
 
 struct FrameLayout {
-  int64_t keys, rx, ry, l, cnt, wpix, total;
+  int64_t vis, vis_n, tcnt, toff, over, tlist, l, cnt, wpix, seg, rank, start, sums, ent_off, ent_w, ent_s, total;
+  int64_t list_cap, ntiles;
+  bool sorted;
 };
 
-FrameLayout frame_layout(const MeshDev& m, int H, int W, int B, int weighting) {
+int64_t tiles_of(int H, int W) {
+  return (int64_t)((W + kTileSize - 1) / kTileSize) * ((H + kTileSize - 1) / kTileSize);
+}
+
+FrameLayout frame_layout(const MeshDev& m, int H, int W, int B, int weighting, int scatter_mode) {
   FrameLayout L{};
   const int64_t HW = (int64_t)H * W;
+  L.ntiles = tiles_of(H, W);
+  L.list_cap = 4 * m.T + 64 * L.ntiles + 1024;
+  L.sorted = scatter_mode != LF_SCATTER_ATOMIC;
   int64_t o = 0;
-  L.keys = o; o += align256(B * HW * 8);
-  L.rx = o; o += align256((int64_t)B * W * 4);
-  L.ry = o; o += align256((int64_t)B * H * 4);
+  L.vis = o; o += align256(B * std::max<int64_t>(m.n_clusters, 1) * 4);
+  L.vis_n = o; o += align256(B * 4);
+  L.tcnt = o; o += align256(B * L.ntiles * 4);
+  L.toff = o; o += align256(B * (L.ntiles + 1) * 4);
+  L.over = o; o += align256(B * 4);
+  L.tlist = o; o += align256(B * L.list_cap * 4);
   L.l = o; o += align256(B * HW * 4);
-  L.cnt = o; if (weighting == LF_W_IMAGE) o += align256((int64_t)B * m.n_texels * 4);
+  L.cnt = o; if (weighting == LF_W_IMAGE) o += align256(B * m.n_texels * 4);
   L.wpix = o; if (weighting == LF_W_LEARNED) o += align256(B * HW * 4);
+  L.seg = o; if (L.sorted) o += align256(m.n_texels * 4);
+  L.rank = o; if (L.sorted) o += align256(B * HW * 4);
+  L.start = o; if (L.sorted) o += align256((m.n_texels + 1) * 4);
+  L.sums = o; if (L.sorted) o += align256((m.n_texels / 8192 + 2) * 4);
+  L.ent_off = o; if (L.sorted) o += align256(B * HW * 4);
+  L.ent_w = o; if (L.sorted) o += align256(B * HW * 4);
+  L.ent_s = o; if (L.sorted) o += align256(B * HW * 4);
   L.total = o;
   return L;
 }
@@ -156,26 +176,31 @@ lf_status check_frames(int32_t F, int32_t H, int32_t W) {
   return LF_OK;
 }
 
-// Render frames [f0, f0 + nb) of the call into the batch key planes and
-// resolve them into texel rows (and optional triangle / depth outputs).
+RasterWs raster_ws(const FrameLayout& L, char* ws) {
+  RasterWs r;
+  r.vis = reinterpret_cast<int32_t*>(ws + L.vis);
+  r.vis_n = reinterpret_cast<int32_t*>(ws + L.vis_n);
+  r.tcnt = reinterpret_cast<int32_t*>(ws + L.tcnt);
+  r.toff = reinterpret_cast<int32_t*>(ws + L.toff);
+  r.over = reinterpret_cast<int32_t*>(ws + L.over);
+  r.tlist = reinterpret_cast<int32_t*>(ws + L.tlist);
+  r.list_cap = L.list_cap;
+  return r;
+}
+
+// Render frames [f0, f0 + nb) of the call and resolve them into texel rows
+// (and optional triangle / depth outputs, per-frame and per-row counts).
 lf_status render_batch(lf_mesh_s* mh, const float* cams, int f0, int nb, int H, int W, const FrameLayout& L,
-                       char* ws, int32_t* l_dst, int32_t* tri_dst, float* z_dst, const uint8_t* valid,
-                       int32_t* cnt, int64_t cnt_stride, hipStream_t s) {
-  const MeshDev& d = mh->d;
-  auto* keys = reinterpret_cast<unsigned long long*>(ws + L.keys);
-  auto* rx = reinterpret_cast<float*>(ws + L.rx);
-  auto* ry = reinterpret_cast<float*>(ws + L.ry);
-  const float* cb = cams + 16 * (int64_t)f0;
-  {
-    StageTimer tm(mh, 0, s);
-    LF_TRY(launch_raytab(cb, nb, H, W, rx, ry, s), "ray tables");
-    LF_TRY(launch_raster(d, cb, nb, H, W, keys, rx, ry, s), "raster");
-  }
-  {
-    StageTimer tm(mh, 1, s);
-    LF_TRY(launch_resolve(d, cb, nb, H, W, keys, rx, ry, l_dst, tri_dst, z_dst, valid, cnt, cnt_stride, s), "resolve");
-  }
+                       char* ws, const RasterOut& out, hipStream_t s) {
+  StageTimer tm(mh, 0, s);
+  LF_TRY(launch_render_batch(mh->d, cams + 16 * (int64_t)f0, nb, H, W, raster_ws(L, ws), out, s), "render");
   return LF_OK;
+}
+
+int pick_batch(const MeshDev& m, int H, int W, int F, int64_t ws_bytes, int weighting, int mode) {
+  int B = 1;
+  while (B < F && B < 64 && frame_layout(m, H, W, B * 2, weighting, mode).total <= ws_bytes) B *= 2;
+  return B > F ? F : B;
 }
 
 }  // namespace
@@ -291,8 +316,7 @@ lf_status lf_frame_ws_bytes(lf_mesh mesh, int32_t H, int32_t W, int32_t batch, i
   if (st != LF_OK) return st;
   if ((st = check_frames(1, H, W)) != LF_OK) return st;
   if (batch < 1 || batch > 65535) return fail(LF_EINVAL, "batch must be in [1, 65535]");
-  (void)scatter_mode;
-  if (bytes) *bytes = frame_layout(mesh->d, H, W, batch, weighting).total;
+  if (bytes) *bytes = frame_layout(mesh->d, H, W, batch, weighting, scatter_mode).total;
   return LF_OK;
 }
 
@@ -316,21 +340,44 @@ lf_status lf_fuse_frames(lf_mesh mesh, const float* d_cams, int32_t F, int32_t H
   if (reinterpret_cast<uintptr_t>(d_ws) & 255) return fail(LF_EINVAL, "workspace must be 256-byte aligned");
   const MeshDev& d = mesh->d;
   const int B = batch < F ? batch : F;
-  const FrameLayout L = frame_layout(d, H, W, B, weighting);
+  // texel-sorted aggregation when the classes of a pixel are contiguous
+  const int mode = scatter_mode != LF_SCATTER_AUTO ? scatter_mode
+                                                   : (h_strides[1] == 1 ? LF_SCATTER_SORTED : LF_SCATTER_ATOMIC);
+  const FrameLayout L = frame_layout(d, H, W, B, weighting, scatter_mode == LF_SCATTER_AUTO ? LF_SCATTER_SORTED : mode);
   if (ws_bytes < L.total) return fail(LF_ESIZE, "frame workspace %lld < %lld bytes", (long long)ws_bytes, (long long)L.total);
   char* ws = reinterpret_cast<char*>(d_ws);
   const int64_t HW = (int64_t)H * W;
   ProbIn in{d_probs, d_scale, d_valid, h_strides[0], h_strides[1], h_strides[2], h_strides[3], prob_dtype};
   int32_t* cnt = weighting == LF_W_IMAGE ? reinterpret_cast<int32_t*>(ws + L.cnt) : nullptr;
-  LF_TRY(launch_fill_u64(reinterpret_cast<unsigned long long*>(ws + L.keys), B * HW, ~0ull, stream), "clear keys");
+  // the sorted path stores batch-relative element offsets in 32 bits
+  const bool sorted = mode == LF_SCATTER_SORTED &&
+                      ((int64_t)(B - 1) * h_strides[0] + (int64_t)(H - 1) * h_strides[2] +
+                       (int64_t)(W - 1) * h_strides[3] + (int64_t)d.c * h_strides[1]) < ((int64_t)1 << 32);
+  int32_t* seg = sorted ? reinterpret_cast<int32_t*>(ws + L.seg) : nullptr;
+  LF_TRY(launch_zero(ws + L.tcnt, B * L.ntiles * 4, stream), "clear tile counts");
   if (cnt) LF_TRY(launch_zero(cnt, (int64_t)B * d.n_texels * 4, stream), "clear counts");
+  int32_t* rank = sorted ? reinterpret_cast<int32_t*>(ws + L.rank) : nullptr;
   for (int f0 = 0; f0 < F; f0 += B) {
     const int nb = (F - f0) < B ? (F - f0) : B;
     int32_t* lb = d_l_out ? d_l_out + (int64_t)f0 * HW : reinterpret_cast<int32_t*>(ws + L.l);
     const uint8_t* vb = d_valid ? d_valid + (int64_t)f0 * HW : nullptr;
-    if ((st = render_batch(mesh, d_cams, f0, nb, H, W, L, ws, lb, nullptr, nullptr, vb, cnt, d.n_texels, stream)) != LF_OK)
-      return st;
-    {
+    if (seg) LF_TRY(launch_zero(seg, d.n_texels * 4, stream), "clear segments");
+    RasterOut out{lb, nullptr, nullptr, vb, cnt, d.n_texels, seg, rank};
+    if ((st = render_batch(mesh, d_cams, f0, nb, H, W, L, ws, out, stream)) != LF_OK) return st;
+    if (sorted) {
+      int32_t* start = reinterpret_cast<int32_t*>(ws + L.start);
+      uint32_t* eo = reinterpret_cast<uint32_t*>(ws + L.ent_off);
+      float* ew = weighting != LF_W_PIXEL ? reinterpret_cast<float*>(ws + L.ent_w) : nullptr;
+      float* es = prob_dtype == LF_FP8_E4M3 ? reinterpret_cast<float*>(ws + L.ent_s) : nullptr;
+      {
+        StageTimer tm(mesh, 3, stream);
+        LF_TRY(launch_seg_scan(seg, d.n_texels, reinterpret_cast<int32_t*>(ws + L.sums), start, stream), "segment scan");
+        LF_TRY(launch_seg_fill(in, f0, nb, H, W, lb, rank, start, eo, ew, es, weighting, cnt, d.n_texels, nullptr, stream),
+               "segment fill");
+      }
+      StageTimer tm(mesh, 2, stream);
+      LF_TRY(launch_seg_gather(d, in, f0, H, W, start, eo, ew, es, stream), "segment gather");
+    } else {
       StageTimer tm(mesh, 2, stream);
       LF_TRY(launch_scatter_atomic(d, in, f0, nb, H, W, lb, weighting, cnt, d.n_texels, nullptr, stream), "scatter");
     }
@@ -369,19 +416,18 @@ lf_status lf_render_labels(lf_mesh mesh, const float* d_cams, int32_t F, int32_t
   }
   if (!d_cams || !d_ws) return fail(LF_EINVAL, "re-rendering needs cameras and a workspace");
   if (F == 0) return LF_OK;
-  const FrameLayout L = frame_layout(mesh->d, H, W, 1, LF_W_PIXEL);
-  int B = 1;
-  while (B < F && frame_layout(mesh->d, H, W, B * 2, LF_W_PIXEL).total <= ws_bytes && B < 64) B *= 2;
-  if (B > F) B = F;
-  const FrameLayout LB = frame_layout(mesh->d, H, W, B, LF_W_PIXEL);
+  if (reinterpret_cast<uintptr_t>(d_ws) & 255) return fail(LF_EINVAL, "workspace must be 256-byte aligned");
+  const int B = pick_batch(mesh->d, H, W, F, ws_bytes, LF_W_PIXEL, LF_SCATTER_ATOMIC);
+  const FrameLayout L = frame_layout(mesh->d, H, W, B, LF_W_PIXEL, LF_SCATTER_ATOMIC);
   if (ws_bytes < L.total) return fail(LF_ESIZE, "frame workspace too small");
   char* ws = reinterpret_cast<char*>(d_ws);
-  LF_TRY(launch_fill_u64(reinterpret_cast<unsigned long long*>(ws + LB.keys), B * HW, ~0ull, stream), "clear keys");
+  LF_TRY(launch_zero(ws + L.tcnt, B * L.ntiles * 4, stream), "clear tile counts");
   for (int f0 = 0; f0 < F; f0 += B) {
     const int nb = (F - f0) < B ? (F - f0) : B;
-    int32_t* lb = reinterpret_cast<int32_t*>(ws + LB.l);
-    if ((st = render_batch(mesh, d_cams, f0, nb, H, W, LB, ws, lb, nullptr, nullptr, nullptr, nullptr, 0, stream)) != LF_OK)
-      return st;
+    int32_t* lb = reinterpret_cast<int32_t*>(ws + L.l);
+    RasterOut out{lb, nullptr, nullptr, nullptr, nullptr, 0, nullptr, nullptr};
+    if ((st = render_batch(mesh, d_cams, f0, nb, H, W, L, ws, out, stream)) != LF_OK) return st;
+    StageTimer tm(mesh, 5, stream);
     LF_TRY(launch_render(lb, d_valid ? d_valid + (int64_t)f0 * HW : nullptr, d_labels, (int64_t)nb * HW,
                          d_out + (int64_t)f0 * HW, stream), "render");
   }
@@ -397,20 +443,18 @@ lf_status lf_rasterize(lf_mesh mesh, const float* d_cams, int32_t F, int32_t H, 
   if (F == 0) return LF_OK;
   if (!d_cams || !d_ws) return fail(LF_EINVAL, "NULL argument");
   if (reinterpret_cast<uintptr_t>(d_ws) & 255) return fail(LF_EINVAL, "workspace must be 256-byte aligned");
-  int B = 1;
-  while (B < F && frame_layout(mesh->d, H, W, B * 2, LF_W_PIXEL).total <= ws_bytes && B < 64) B *= 2;
-  if (B > F) B = F;
-  const FrameLayout L = frame_layout(mesh->d, H, W, B, LF_W_PIXEL);
+  const int B = pick_batch(mesh->d, H, W, F, ws_bytes, LF_W_PIXEL, LF_SCATTER_ATOMIC);
+  const FrameLayout L = frame_layout(mesh->d, H, W, B, LF_W_PIXEL, LF_SCATTER_ATOMIC);
   if (ws_bytes < L.total) return fail(LF_ESIZE, "frame workspace too small");
   char* ws = reinterpret_cast<char*>(d_ws);
   const int64_t HW = (int64_t)H * W;
-  LF_TRY(launch_fill_u64(reinterpret_cast<unsigned long long*>(ws + L.keys), B * HW, ~0ull, stream), "clear keys");
+  LF_TRY(launch_zero(ws + L.tcnt, B * L.ntiles * 4, stream), "clear tile counts");
   for (int f0 = 0; f0 < F; f0 += B) {
     const int nb = (F - f0) < B ? (F - f0) : B;
     const int64_t o = (int64_t)f0 * HW;
-    if ((st = render_batch(mesh, d_cams, f0, nb, H, W, L, ws, d_l ? d_l + o : nullptr, d_tri ? d_tri + o : nullptr,
-                           d_z ? d_z + o : nullptr, nullptr, nullptr, 0, stream)) != LF_OK)
-      return st;
+    RasterOut out{d_l ? d_l + o : nullptr, d_tri ? d_tri + o : nullptr, d_z ? d_z + o : nullptr, nullptr, nullptr, 0,
+                  nullptr, nullptr};
+    if ((st = render_batch(mesh, d_cams, f0, nb, H, W, L, ws, out, stream)) != LF_OK) return st;
   }
   return LF_OK;
 }

@@ -215,52 +215,62 @@ __device__ __forceinline__ void store_tex(void* out, int64_t i, float v) {
   else reinterpret_cast<__half*>(out)[i] = __float2half(v);
 }
 
-// One thread per texel row: S = sum_j A_j in class order; P = A / S; label =
-// first maximal class; S == 0 (never observed) -> P = 0, label 255.  For MUL
-// the row holds sum w log p: P = softmax(A), observed iff wsum > 0.
+// A block stages R consecutive rows in LDS with coalesced loads (row stride
+// padded to an odd number of words against bank conflicts); one thread per
+// row then computes S = sum_j A_j in class order, P = A / S and the first
+// maximal class (S == 0: never observed -> P = 0, label 255).  For MUL the row
+// holds sum w log p: P = softmax(A), observed iff its weight sum is > 0.
+// The normalised rows are written back through LDS, coalesced.
 template <int OUT, int AGG>
-__global__ __launch_bounds__(256) void k_finalize(MeshDev m, void* __restrict__ out, uint8_t* __restrict__ labels) {
-  const int64_t x = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (x >= m.n_texels) return;
+__global__ __launch_bounds__(256) void k_finalize(MeshDev m, void* __restrict__ out, uint8_t* __restrict__ labels, int R) {
+  extern __shared__ float rows[];
   const int c = m.c;
-  const float* __restrict__ a = reinterpret_cast<const float*>(m.accum) + x * c;
-  if constexpr (AGG == 1) {
-    const bool seen = m.wsum[x] > 0.0f;
-    float mx = a[0];
+  const int cp = c | 1;
+  const int64_t x0 = (int64_t)blockIdx.x * R;
+  const int nr = (int)min<int64_t>(R, m.n_texels - x0);
+  const float* __restrict__ a = reinterpret_cast<const float*>(m.accum) + x0 * c;
+  for (int i = threadIdx.x; i < nr * c; i += 256) {
+    const int r = i / c, j = i - r * c;
+    rows[r * cp + j] = __builtin_nontemporal_load(a + i);
+  }
+  __syncthreads();
+  for (int r = threadIdx.x; r < nr; r += 256) {
+    float* row = rows + r * cp;
+    float mx = row[0];
     int best = 0;
     for (int j = 1; j < c; ++j) {
-      const float v = a[j];
+      const float v = row[j];
       if (v > mx) { mx = v; best = j; }
     }
-    float s = 0.0f;
-    for (int j = 0; j < c; ++j) s += expf(a[j] - mx);
-    const float inv = 1.0f / s;
-    for (int j = 0; j < c; ++j) {
-      const float v = seen ? expf(a[j] - mx) * inv : 0.0f;
-      if (out) store_tex<OUT>(out, x * c + j, v);
+    bool seen;
+    if constexpr (AGG == 1) {
+      seen = m.wsum[x0 + r] > 0.0f;
+      float s = 0.0f;
+      for (int j = 0; j < c; ++j) s += expf(row[j] - mx);
+      for (int j = 0; j < c; ++j) row[j] = seen ? expf(row[j] - mx) / s : 0.0f;
+    } else {
+      float s = 0.0f;
+      for (int j = 0; j < c; ++j) s += row[j];
+      seen = s > 0.0f;
+      for (int j = 0; j < c; ++j) row[j] = seen ? row[j] / s : 0.0f;
     }
-    labels[x] = seen ? (uint8_t)best : (uint8_t)255;
-  } else {
-    float s = 0.0f, mx = a[0];
-    int best = 0;
-    for (int j = 0; j < c; ++j) {
-      const float v = a[j];
-      s += v;
-      if (v > mx) { mx = v; best = j; }
-    }
-    const bool seen = s > 0.0f;
-    for (int j = 0; j < c; ++j) {
-      const float v = seen ? a[j] / s : 0.0f;
-      if (out) store_tex<OUT>(out, x * c + j, v);
-    }
-    labels[x] = seen ? (uint8_t)best : (uint8_t)255;
+    labels[x0 + r] = seen ? (uint8_t)best : (uint8_t)255;
+  }
+  if (!out) return;
+  __syncthreads();
+  for (int i = threadIdx.x; i < nr * c; i += 256) {
+    const int r = i / c, j = i - r * c;
+    store_tex<OUT>(out, x0 * c + i, rows[r * cp + j]);
   }
 }
 
 hipError_t launch_finalize(const MeshDev& m, void* tex_out, int tex_dtype, uint8_t* labels, hipStream_t s) {
   if (m.n_texels == 0) return hipSuccess;
-  dim3 g((unsigned)((m.n_texels + 255) / 256));
-#define LF_FIN(O, A) k_finalize<O, A><<<g, 256, 0, s>>>(m, tex_out, labels)
+  const int cp = m.c | 1;
+  const int R = m.c <= 64 ? 192 : 32;
+  const size_t lds = (size_t)R * cp * sizeof(float);
+  dim3 g((unsigned)((m.n_texels + R - 1) / R));
+#define LF_FIN(O, A) k_finalize<O, A><<<g, 256, lds, s>>>(m, tex_out, labels, R)
   const bool mul = m.aggregator == 1;
   if (tex_dtype == 1) { if (mul) LF_FIN(1, 1); else LF_FIN(1, 0); }
   else if (tex_dtype == 2) { if (mul) LF_FIN(2, 1); else LF_FIN(2, 0); }

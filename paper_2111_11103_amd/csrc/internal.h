@@ -28,18 +28,29 @@ __device__ __forceinline__ int64_t row_offset(const MeshDev& m, int64_t t) {
 }
 __device__ __forceinline__ int tri_s(const MeshDev& m, int64_t t) { return m.s_face ? m.s_face[t] : m.s_uniform; }
 
-// Per-batch frame workspace carved out of the caller's buffer.
-struct FrameWs {
-  unsigned long long* keys;  // [B][H][W] depth|triangle keys, all-ones = empty
-  float* rx;                 // [B][W] pixel ray x per frame
-  float* ry;                 // [B][H]
-  int32_t* l;                // [B][H][W] texel rows (when the caller gives none)
-  int32_t* cnt;              // [B][n_texels] per-frame texel counts (w^(I)) or [n_texels] (sorted)
-  int32_t* start;            // [n_texels + 1] segment starts (sorted scatter)
-  int32_t* entries;          // [B][H][W] sorted (frame, pixel) entries
-  int32_t* scan_tmp;         // scan partials
-  float* wpix;               // [B][H][W] per-pixel weights (learned)
-  int32_t B, H, W;
+constexpr int kTileSize = 32;         // raster tile edge (pixels)
+
+// Raster workspace of one batch (all caller memory).
+struct RasterWs {
+  int32_t* vis;              // [B][n_clusters] visible cluster ids
+  int32_t* vis_n;            // [B]
+  int32_t* tcnt;             // [B][ntiles] (zero between uses)
+  int32_t* toff;             // [B][ntiles + 1]
+  int32_t* tlist;            // [B][list_cap] triangle ids per tile
+  int32_t* over;             // [B] list overflow flags
+  int64_t list_cap;
+};
+
+// Per-pixel outputs of the renderer for a batch (batch-relative pointers, any may be null).
+struct RasterOut {
+  int32_t* l;                // texel rows
+  int32_t* tri;              // triangle ids
+  float* z;                  // depths
+  const uint8_t* valid;      // validity of the batch's pixels
+  int32_t* cnt;              // per-frame texel counts [B][cnt_stride] (w^(I))
+  int64_t cnt_stride;
+  int32_t* seg;              // per-row observation counts of the batch (sorted scatter)
+  int32_t* rank;             // [B][H][W] rank of the pixel within its row's segment
 };
 
 struct ProbIn {
@@ -56,19 +67,20 @@ hipError_t launch_offsets(const MeshDev& m, int32_t* scratch, hipStream_t s);
 hipError_t launch_cluster_boxes(const MeshDev& m, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t s);
 hipError_t launch_zero(void* p, int64_t bytes, hipStream_t s);
-hipError_t launch_raytab(const float* cams, int nf, int H, int W, float* rx, float* ry, hipStream_t s);
-hipError_t launch_raster(const MeshDev& m, const float* cams, int nf, int H, int W,
-                         unsigned long long* keys, const float* rx, const float* ry, hipStream_t s);
-hipError_t launch_resolve(const MeshDev& m, const float* cams, int nf, int H, int W,
-                          unsigned long long* keys, const float* rx, const float* ry, int32_t* l_out,
-                          int32_t* tri_out, float* z_out, const uint8_t* valid, int32_t* cnt,
-                          int64_t cnt_stride, hipStream_t s);
+hipError_t launch_render_batch(const MeshDev& m, const float* cams, int nb, int H, int W, const RasterWs& ws,
+                               const RasterOut& out, hipStream_t s);
 hipError_t launch_scatter_atomic(const MeshDev& m, const ProbIn& in, int f_first, int nf, int H, int W,
                                  const int32_t* l, int weighting, const int32_t* cnt, int64_t cnt_stride,
                                  const float* wpix, hipStream_t s);
 hipError_t launch_clear_counts(const int32_t* l, const uint8_t* valid, int nf, int H, int W, int32_t* cnt,
                                int64_t cnt_stride, hipStream_t s);
 hipError_t launch_finalize(const MeshDev& m, void* tex_out, int tex_dtype, uint8_t* labels, hipStream_t s);
+hipError_t launch_seg_scan(const int32_t* seg, int64_t n, int32_t* sums, int32_t* start, hipStream_t s);
+hipError_t launch_seg_fill(const ProbIn& in, int f_first, int nf, int H, int W, const int32_t* l, const int32_t* rank,
+                           const int32_t* start, uint32_t* ent_pix, float* ent_w, float* ent_s, int weighting,
+                           const int32_t* cnt, int64_t cnt_stride, const float* wpix, hipStream_t s);
+hipError_t launch_seg_gather(const MeshDev& m, const ProbIn& in, int f_first, int H, int W, const int32_t* start,
+                             const uint32_t* ent_pix, const float* ent_w, const float* ent_s, hipStream_t s);
 hipError_t launch_render(const int32_t* l, const uint8_t* valid, const uint8_t* labels, int64_t npx,
                          uint8_t* out, hipStream_t s);
 

@@ -1,67 +1,105 @@
 // Renderer (Section 3.3.1): z-buffered projection of the mesh into per-pixel
-// (depth, triangle) keys, then resolution of every pixel's texel row
-// l = id_t + id_x (Section 3.3.2, eq. texel-in-array; eq. idtexel).
+// triangle ids, then every pixel's texel row l = id_t + id_x (Section 3.3.2,
+// eq. texel-in-array; eq. idtexel).
 //
-// k_raster: one thread per (frame, triangle); a wave of 64 consecutive
-// triangles first tests its cluster box against the view frustum and leaves
-// if the whole cluster is outside.  Unclipped triangles are snapped to 8
-// sub-pixel bits; a triangle whose pixel-centre bounding box is small is
-// rasterized by its own thread with incremental int64 edge functions; larger
-// ones (and clipped polygons) are rasterized by the whole wave together, 8x8
-// pixel blocks at a time.  Every covered pixel's key (bits(z) << 32 | t) goes
-// through a 64-bit atomic minimum, so the result does not depend on the
-// order in which fragments arrive.
+// Sort-middle tiled rasterizer, all frames of a batch at once:
+//   k_cull_clusters  frame x cluster (64 consecutive triangles): conservative
+//                    frustum test of the cluster box, compact list of the
+//                    clusters that may be visible;
+//   k_bin (count)    one wave per visible cluster: set up every triangle
+//                    (transform, clip, 8-bit sub-pixel snap), count it into
+//                    every 32x32-pixel tile its pixel-centre box overlaps;
+//   k_tile_scan      per frame exclusive scan of the tile counts;
+//   k_bin (fill)     same walk, writes triangle ids into the tile lists;
+//   k_tile_raster    one workgroup per (frame, tile): a 64-bit depth|id key
+//                    per pixel in LDS, every listed triangle rasterized with
+//                    int64 edge functions and the top-left rule (small ones by
+//                    one thread, large ones by the whole wave), ds_min_u64 on
+//                    the key; then every pixel resolves its winner into
+//                    (triangle, texel row, depth) and writes them out.
+// The key order (depth bits, then triangle id) makes the result independent
+// of the order fragments arrive in.
+#include <algorithm>
+
 #include "internal.h"
 #include "spec.h"
 
 namespace lf {
 
-__global__ __launch_bounds__(256) void k_raytab(const float* __restrict__ cams, int nf, int H, int W,
-                                                float* __restrict__ rx, float* __restrict__ ry) {
-  const int f = blockIdx.y;
-  const Cam c = load_cam(cams + 16 * (int64_t)f);
-  for (int i = blockIdx.x * 256 + threadIdx.x; i < W + H; i += gridDim.x * 256) {
-    if (i < W) rx[(int64_t)f * W + i] = ray_x(c, i);
-    else ry[(int64_t)f * H + (i - W)] = ray_y(c, i - W);
-  }
-}
-
-hipError_t launch_raytab(const float* cams, int nf, int H, int W, float* rx, float* ry, hipStream_t s) {
-  if (nf <= 0) return hipSuccess;
-  k_raytab<<<dim3((unsigned)((W + H + 255) / 256), (unsigned)nf), 256, 0, s>>>(cams, nf, H, W, rx, ry);
-  return hipGetLastError();
-}
-
 namespace {
 
-constexpr int kSmallPx = 48;   // bbox pixel count handled by a single thread
+constexpr int kSmallPx = 48;   // pixel boxes up to this size are rasterized by one thread
+constexpr int TS = kTileSize;
 
-struct Frag {
-  unsigned long long* keys;    // this frame's key plane
-  const float* rx;
-  const float* ry;
-  int W;
+// Snapped screen polygon of one triangle in one frame.
+struct Setup {
+  int n;                       // polygon vertex count (0 = nothing to draw)
+  int PX[8], PY[8];            // snapped vertices, 1/256 px
+  RayK rk;                     // ray-cast constants of the original triangle
+  int x0, x1, y0, y1;          // pixel-centre box, clamped to the image
 };
 
-__device__ __forceinline__ void emit(const Frag& fr, const RayK& rk, int x, int y, uint32_t tri) {
-  float z;
-  if (!frag_depth(rk, fr.rx[x], fr.ry[y], &z)) return;
-  const unsigned long long key = ((unsigned long long)__float_as_uint(z) << 32) | tri;
-  unsigned long long* slot = fr.keys + (int64_t)y * fr.W + x;
-  // keys only decrease within a batch: a stale value that is already smaller
-  // proves this fragment loses, so the atomic can be skipped
-  if (__builtin_nontemporal_load(slot) <= key) return;
-  atomicMin(slot, key);
+__device__ __forceinline__ void load_tri(const MeshDev& m, const Cam& cam, int64_t t, V3& A, V3& B, V3& C) {
+  const int i0 = m.faces_uv[3 * t], i1 = m.faces_uv[3 * t + 1], i2 = m.faces_uv[3 * t + 2];
+  const float* q0 = m.verts + 3 * (int64_t)i0;
+  const float* q1 = m.verts + 3 * (int64_t)i1;
+  const float* q2 = m.verts + 3 * (int64_t)i2;
+  A = to_cam(cam, q0[0], q0[1], q0[2]);
+  B = to_cam(cam, q1[0], q1[1], q1[2]);
+  C = to_cam(cam, q2[0], q2[1], q2[2]);
 }
 
-// Oriented sub-triangle with edge data for coverage tests.
+__device__ __forceinline__ void setup_triangle(const MeshDev& m, const Cam& cam, int64_t t, int H, int W, Setup& s) {
+  s.n = 0;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) { s.PX[i] = 0; s.PY[i] = 0; }
+  s.x0 = 0; s.x1 = -1; s.y0 = 0; s.y1 = -1;
+  V3 A, B, C;
+  load_tri(m, cam, t, A, B, C);
+  bool gone = false;
+#pragma unroll
+  for (int p = 0; p < 5; ++p)
+    gone = gone || (clip_dist(p, A, cam, m.z_near) < 0.0f && clip_dist(p, B, cam, m.z_near) < 0.0f &&
+                    clip_dist(p, C, cam, m.z_near) < 0.0f);
+  if (gone) return;
+  s.rk = ray_consts(A, B, C);
+  if (inside_all(A, cam, m.z_near) && inside_all(B, cam, m.z_near) && inside_all(C, cam, m.z_near)) {
+    snap(cam, A, &s.PX[0], &s.PY[0]);
+    snap(cam, B, &s.PX[1], &s.PY[1]);
+    snap(cam, C, &s.PX[2], &s.PY[2]);
+    s.n = 3;
+  } else {
+    V3 P[8];
+    P[0] = A; P[1] = B; P[2] = C;
+    s.n = clip_poly(P, 3, cam, m.z_near);
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+      if (i < s.n) snap(cam, P[i], &s.PX[i], &s.PY[i]);
+  }
+  if (s.n < 3) { s.n = 0; return; }
+  int xmin = s.PX[0], xmax = s.PX[0], ymin = s.PY[0], ymax = s.PY[0];
+#pragma unroll
+  for (int i = 1; i < 8; ++i)
+    if (i < s.n) {
+      xmin = min(xmin, s.PX[i]); xmax = max(xmax, s.PX[i]);
+      ymin = min(ymin, s.PY[i]); ymax = max(ymax, s.PY[i]);
+    }
+  // pixel x is a candidate iff its centre 256x + 128 lies in [xmin, xmax]
+  s.x0 = max((xmin + 127) >> 8, 0);
+  s.x1 = min((xmax - 128) >> 8, W - 1);
+  s.y0 = max((ymin + 127) >> 8, 0);
+  s.y1 = min((ymax - 128) >> 8, H - 1);
+  if (s.x0 > s.x1 || s.y0 > s.y1) s.n = 0;
+}
+
+// Oriented sub-triangle with its top-left biases.
 struct Edge3 {
-  int x0, y0, x1, y1, x2, y2;  // positively oriented vertices
-  int b01, b12, b20;           // 1 if the edge does not own on-edge centres
+  int x0, y0, x1, y1, x2, y2;
+  int b01, b12, b20;          // 1 when the edge does not own centres lying on it
   bool ok;
 };
 
-__device__ __forceinline__ Edge3 setup_tri(int ax, int ay, int bx, int by, int cx, int cy) {
+__device__ __forceinline__ Edge3 orient(int ax, int ay, int bx, int by, int cx, int cy) {
   Edge3 e;
   const long long area = (long long)(bx - ax) * (cy - ay) - (long long)(by - ay) * (cx - ax);
   e.ok = area != 0;
@@ -82,29 +120,7 @@ __device__ __forceinline__ bool covers(const Edge3& e, int px, int py) {
          efn(e.x2, e.y2, e.x0, e.y0, px, py) >= e.b20;
 }
 
-// Single-thread raster of one positively oriented sub-triangle over a pixel
-// box, stepping the three edge functions incrementally.
-__device__ __forceinline__ void raster_tri_thread(const Frag& fr, const RayK& rk, uint32_t tri, const Edge3& e, int x0, int x1,
-                                  int y0, int y1) {
-  const int px0 = 256 * x0 + 128, py0 = 256 * y0 + 128;
-  long long r01 = efn(e.x0, e.y0, e.x1, e.y1, px0, py0) - e.b01;
-  long long r12 = efn(e.x1, e.y1, e.x2, e.y2, px0, py0) - e.b12;
-  long long r20 = efn(e.x2, e.y2, e.x0, e.y0, px0, py0) - e.b20;
-  // d/dx of efn(i->j) = -(yj - yi), d/dy = (xj - xi); one pixel = 256 units
-  const long long sx01 = -256ll * (e.y1 - e.y0), sy01 = 256ll * (e.x1 - e.x0);
-  const long long sx12 = -256ll * (e.y2 - e.y1), sy12 = 256ll * (e.x2 - e.x1);
-  const long long sx20 = -256ll * (e.y0 - e.y2), sy20 = 256ll * (e.x0 - e.x2);
-  for (int y = y0; y <= y1; ++y) {
-    long long a = r01, b = r12, c = r20;
-    for (int x = x0; x <= x1; ++x) {
-      if ((a | b | c) >= 0) emit(fr, rk, x, y, tri);
-      a += sx01; b += sx12; c += sx20;
-    }
-    r01 += sy01; r12 += sy12; r20 += sy20;
-  }
-}
-
-// v[i] for a runtime i without dynamic register indexing (keeps the array in VGPRs).
+// v[i] for a runtime i without dynamic register indexing.
 __device__ __forceinline__ int pick8(const int (&v)[8], int i) {
   int r = v[0];
 #pragma unroll
@@ -112,118 +128,202 @@ __device__ __forceinline__ int pick8(const int (&v)[8], int i) {
   return r;
 }
 
+// Conservative cluster-vs-frustum test: outside if all 8 box corners lie
+// beyond one plane (near, or an image border widened by 2 px) by a margin far
+// larger than the rounding of the per-vertex arithmetic, so no triangle of a
+// culled cluster could have covered a pixel centre.
+__device__ bool cluster_outside(const MeshDev& m, const Cam& cam, int64_t cl, int H, int W) {
+  const float* b = m.cl_box + 8 * cl;
+  const float lo[3] = {b[0], b[1], b[2]}, hi[3] = {b[3], b[4], b[5]};
+  float mag = fabsf(cam.t[0]) + fabsf(cam.t[1]) + fabsf(cam.t[2]);
+  for (int d = 0; d < 3; ++d) mag += 3.0f * fmaxf(fabsf(lo[d]), fabsf(hi[d]));
+  const float eps = 1e-5f * mag;
+  const float magp = eps * (1.0f + fabsf(cam.fx) + fabsf(cam.fy) + fabsf(cam.cx) + fabsf(cam.cy) + W + H);
+  bool out0 = true, out1 = true, out2 = true, out3 = true, out4 = true;
+  for (int k = 0; k < 8; ++k) {
+    const V3 p = to_cam(cam, (k & 1) ? hi[0] : lo[0], (k & 2) ? hi[1] : lo[1], (k & 4) ? hi[2] : lo[2]);
+    out0 = out0 && (p.z - m.z_near < -eps);
+    out1 = out1 && (cam.fx * p.x + (cam.cx + 2.0f) * p.z < -magp);
+    out2 = out2 && (((float)W + 2.0f - cam.cx) * p.z - cam.fx * p.x < -magp);
+    out3 = out3 && (cam.fy * p.y + (cam.cy + 2.0f) * p.z < -magp);
+    out4 = out4 && (((float)H + 2.0f - cam.cy) * p.z - cam.fy * p.y < -magp);
+  }
+  return out0 || out1 || out2 || out3 || out4;
+}
+
+// Wave-aggregated append: this lane's slot where `want`.
+__device__ __forceinline__ int wave_append(int32_t* counter, bool want) {
+  const unsigned long long mask = __ballot(want);
+  if (mask == 0) return -1;
+  const int lane = threadIdx.x & 63;
+  const int leader = __ffsll(mask) - 1;
+  int base = 0;
+  if (lane == leader) base = atomicAdd(counter, __popcll(mask));
+  base = __shfl(base, leader);
+  return base + __popcll(mask & ((1ull << lane) - 1ull));
+}
+
 }  // namespace
 
-__global__ __launch_bounds__(256) void k_raster(MeshDev m, const float* __restrict__ cams, int H, int W,
-                                                unsigned long long* __restrict__ keys,
-                                                const float* __restrict__ rxt, const float* __restrict__ ryt) {
+// ---- 1. visible clusters ------------------------------------------------------
+__global__ __launch_bounds__(256) void k_cull_clusters(MeshDev m, const float* __restrict__ cams, int H, int W,
+                                                       int32_t* __restrict__ vis, int32_t* __restrict__ vis_n) {
   const int fb = blockIdx.y;
   const Cam cam = load_cam(cams + 16 * (int64_t)fb);
-  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t cl = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const bool keep = cl < m.n_clusters && !cluster_outside(m, cam, cl, H, W);
+  const int slot = wave_append(vis_n + fb, keep);
+  if (keep) vis[(int64_t)fb * m.n_clusters + slot] = (int32_t)cl;
+}
+
+// ---- 2./4. binning into tiles (count, then fill) ---------------------------------
+template <bool FILL>
+__global__ __launch_bounds__(256) void k_bin(MeshDev m, const float* __restrict__ cams, int H, int W,
+                                             const int32_t* __restrict__ vis, const int32_t* __restrict__ vis_n,
+                                             int32_t* __restrict__ tcnt, const int32_t* __restrict__ toff,
+                                             int32_t* __restrict__ tlist, int64_t list_cap) {
+  const int fb = blockIdx.y;
+  const Cam cam = load_cam(cams + 16 * (int64_t)fb);
+  const int ntx = (W + TS - 1) / TS, nty = (H + TS - 1) / TS;
+  const int ntiles = ntx * nty;
   const int lane = threadIdx.x & 63;
-
-  // ---- cluster cull (uniform per wave) ----
-  {
-    const int64_t cl = t >> 6;
-    if (cl >= m.n_clusters) return;
-    const float* b = m.cl_box + 8 * cl;
-    const float lo[3] = {b[0], b[1], b[2]}, hi[3] = {b[3], b[4], b[5]};
-    // bound on |coordinate| magnitudes for a rounding margin
-    float mag = fabsf(cam.t[0]) + fabsf(cam.t[1]) + fabsf(cam.t[2]);
-    for (int d = 0; d < 3; ++d) mag += 3.0f * fmaxf(fabsf(lo[d]), fabsf(hi[d]));
-    const float eps = 1e-5f * mag;
-    // planes in camera space (inside >= 0): near, and the image borders
-    // widened by 2 px: x: fx*x + (cx + 2) z >= 0, (W + 2 - cx) z - fx*x >= 0 ...
-    bool out[5] = {true, true, true, true, true};
-    for (int k = 0; k < 8; ++k) {
-      V3 p = to_cam(cam, (k & 1) ? hi[0] : lo[0], (k & 2) ? hi[1] : lo[1], (k & 4) ? hi[2] : lo[2]);
-      const float magp = eps * (1.0f + fabsf(cam.fx) + fabsf(cam.fy) + fabsf(cam.cx) + fabsf(cam.cy) + W + H);
-      out[0] = out[0] && (p.z - m.z_near < -eps);
-      out[1] = out[1] && (cam.fx * p.x + (cam.cx + 2.0f) * p.z < -magp);
-      out[2] = out[2] && (((float)W + 2.0f - cam.cx) * p.z - cam.fx * p.x < -magp);
-      out[3] = out[3] && (cam.fy * p.y + (cam.cy + 2.0f) * p.z < -magp);
-      out[4] = out[4] && (((float)H + 2.0f - cam.cy) * p.z - cam.fy * p.y < -magp);
-    }
-    if (out[0] || out[1] || out[2] || out[3] || out[4]) return;
-  }
-
-  Frag fr{keys + (int64_t)fb * H * W, rxt + (int64_t)fb * W, ryt + (int64_t)fb * H, W};
-  const bool live = t < m.T;
-  int n = 0;
-  int PX[8] = {0, 0, 0, 0, 0, 0, 0, 0}, PY[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  RayK rk{};
-  if (live) {
-    const int i0 = m.faces_uv[3 * t], i1 = m.faces_uv[3 * t + 1], i2 = m.faces_uv[3 * t + 2];
-    const float* q0 = m.verts + 3 * (int64_t)i0;
-    const float* q1 = m.verts + 3 * (int64_t)i1;
-    const float* q2 = m.verts + 3 * (int64_t)i2;
-    const V3 A = to_cam(cam, q0[0], q0[1], q0[2]);
-    const V3 B = to_cam(cam, q1[0], q1[1], q1[2]);
-    const V3 C = to_cam(cam, q2[0], q2[1], q2[2]);
-    // trivially outside one plane: nothing survives clipping
-    bool gone = false;
-#pragma unroll
-    for (int p = 0; p < 5; ++p)
-      gone = gone || (clip_dist(p, A, cam, m.z_near) < 0.0f && clip_dist(p, B, cam, m.z_near) < 0.0f &&
-                      clip_dist(p, C, cam, m.z_near) < 0.0f);
-    if (!gone) {
-      rk = ray_consts(A, B, C);
-      if (inside_all(A, cam, m.z_near) && inside_all(B, cam, m.z_near) && inside_all(C, cam, m.z_near)) {
-        snap(cam, A, &PX[0], &PY[0]);
-        snap(cam, B, &PX[1], &PY[1]);
-        snap(cam, C, &PX[2], &PY[2]);
-        n = 3;
+  const int nvis = vis_n[fb];
+  int32_t* cnt = tcnt + (int64_t)fb * ntiles;
+  for (int w = blockIdx.x * 4 + (threadIdx.x >> 6); w < nvis; w += gridDim.x * 4) {
+    const int64_t cl = vis[(int64_t)fb * m.n_clusters + w];
+    const int64_t t = cl * kClusterTris + lane;
+    Setup s;
+    s.n = 0;
+    s.x0 = 0; s.x1 = -1; s.y0 = 0; s.y1 = -1;
+    if (t < m.T) setup_triangle(m, cam, t, H, W, s);
+    // walk this lane's tile range; lanes currently on the same tile share one atomic
+    const int tx0 = s.x0 / TS, tx1 = s.x1 / TS, ty0 = s.y0 / TS, ty1 = s.y1 / TS;
+    int tx = tx0, ty = ty0;
+    bool more = s.n != 0;
+    while (true) {
+      const int tile = more ? ty * ntx + tx : -1;
+      const unsigned long long act = __ballot(more);
+      if (act == 0) break;
+      const int leader_tile = __shfl(tile, __ffsll(act) - 1);
+      const unsigned long long grp = __ballot(more && tile == leader_tile);
+      const int leader = __ffsll(grp) - 1;
+      const int rank = __popcll(grp & ((1ull << lane) - 1ull));
+      if (!FILL) {
+        if (lane == leader) atomicAdd(cnt + leader_tile, __popcll(grp));
       } else {
-        V3 P[8];
-        P[0] = A; P[1] = B; P[2] = C;
-        n = clip_poly(P, 3, cam, m.z_near);
-#pragma unroll
-        for (int i = 0; i < 8; ++i)
-          if (i < n) snap(cam, P[i], &PX[i], &PY[i]);
+        int base = 0;
+        if (lane == leader) base = atomicSub(cnt + leader_tile, __popcll(grp)) - __popcll(grp);
+        base = __shfl(base, leader);
+        if (more && tile == leader_tile) {
+          const int64_t pos = (int64_t)toff[(int64_t)fb * (ntiles + 1) + leader_tile] + base + rank;
+          if (pos < list_cap) tlist[(int64_t)fb * list_cap + pos] = (int32_t)t;
+        }
+      }
+      if (more && tile == leader_tile) {
+        if (++tx > tx1) { tx = tx0; ++ty; }
+        more = ty <= ty1;
       }
     }
   }
-  // pixel-centre bounding box: centre (256x+128) in [min, max]
-  int x0 = 0, x1 = -1, y0 = 0, y1 = -1;
-  if (n >= 3) {
-    int xmin = PX[0], xmax = PX[0], ymin = PY[0], ymax = PY[0];
-#pragma unroll
-    for (int i = 1; i < 8; ++i)
-      if (i < n) {
-        xmin = min(xmin, PX[i]); xmax = max(xmax, PX[i]);
-        ymin = min(ymin, PY[i]); ymax = max(ymax, PY[i]);
-      }
-    x0 = max((xmin + 127) >> 8, 0);
-    x1 = min((xmax - 128) >> 8, W - 1);
-    y0 = max((ymin + 127) >> 8, 0);
-    y1 = min((ymax - 128) >> 8, H - 1);
+}
+
+// ---- 3. per-frame exclusive scan of tile counts ------------------------------------
+__global__ __launch_bounds__(1024) void k_tile_scan(const int32_t* __restrict__ tcnt, int ntiles,
+                                                    int32_t* __restrict__ toff, int64_t list_cap,
+                                                    int32_t* __restrict__ over) {
+  __shared__ int part[1024];
+  const int fb = blockIdx.x;
+  const int32_t* c = tcnt + (int64_t)fb * ntiles;
+  int32_t* o = toff + (int64_t)fb * (ntiles + 1);
+  int64_t carry = 0;
+  for (int base = 0; base < ntiles; base += 1024) {
+    const int i = base + threadIdx.x;
+    const int v = i < ntiles ? c[i] : 0;
+    part[threadIdx.x] = v;
+    __syncthreads();
+    for (int d = 1; d < 1024; d <<= 1) {
+      const int a = threadIdx.x >= d ? part[threadIdx.x - d] : 0;
+      __syncthreads();
+      part[threadIdx.x] += a;
+      __syncthreads();
+    }
+    const int64_t here = carry + part[threadIdx.x] - v;
+    if (i < ntiles) o[i] = (int32_t)std::min<int64_t>(here, list_cap);
+    carry += part[1023];
+    __syncthreads();
   }
-  const bool any = n >= 3 && x0 <= x1 && y0 <= y1;
-  const int npx = any ? (x1 - x0 + 1) * (y1 - y0 + 1) : 0;
-  const bool small = any && npx <= kSmallPx;
+  if (threadIdx.x == 0) {
+    o[ntiles] = (int32_t)std::min<int64_t>(carry, list_cap);
+    over[fb] = carry > list_cap ? 1 : 0;
+  }
+}
+
+// ---- 5. tile raster + resolve --------------------------------------------------------
+namespace {
+
+struct TileCtx {
+  unsigned long long* key;   // LDS [TS*TS]
+  const float* rx;           // LDS [TS] ray x of the tile's columns
+  const float* ry;           // LDS [TS]
+  int tx0, ty0;              // tile origin (pixels)
+};
+
+__device__ __forceinline__ void emit_lds(const TileCtx& c, const RayK& rk, int x, int y, uint32_t tri) {
+  float z;
+  if (!frag_depth(rk, c.rx[x - c.tx0], c.ry[y - c.ty0], &z)) return;
+  const unsigned long long k = ((unsigned long long)__float_as_uint(z) << 32) | tri;
+  atomicMin(c.key + (y - c.ty0) * TS + (x - c.tx0), k);
+}
+
+// One thread rasterizes one sub-triangle over a small pixel box.
+__device__ __forceinline__ void raster_thread(const TileCtx& c, const RayK& rk, uint32_t tri, const Edge3& e, int x0,
+                                              int x1, int y0, int y1) {
+  const int px0 = 256 * x0 + 128, py0 = 256 * y0 + 128;
+  long long r01 = efn(e.x0, e.y0, e.x1, e.y1, px0, py0) - e.b01;
+  long long r12 = efn(e.x1, e.y1, e.x2, e.y2, px0, py0) - e.b12;
+  long long r20 = efn(e.x2, e.y2, e.x0, e.y0, px0, py0) - e.b20;
+  const long long sx01 = -256ll * (e.y1 - e.y0), sy01 = 256ll * (e.x1 - e.x0);
+  const long long sx12 = -256ll * (e.y2 - e.y1), sy12 = 256ll * (e.x2 - e.x1);
+  const long long sx20 = -256ll * (e.y0 - e.y2), sy20 = 256ll * (e.x0 - e.x2);
+  for (int y = y0; y <= y1; ++y) {
+    long long a = r01, b = r12, d = r20;
+    for (int x = x0; x <= x1; ++x) {
+      if ((a | b | d) >= 0) emit_lds(c, rk, x, y, tri);
+      a += sx01; b += sx12; d += sx20;
+    }
+    r01 += sy01; r12 += sy12; r20 += sy20;
+  }
+}
+
+// Rasterize the triangle this lane holds (`s`, restricted to the pixel box
+// x0..x1 x y0..y1 of the tile); large boxes are done by the whole wave.
+__device__ __forceinline__ void raster_entries(const TileCtx& c, const Setup& s, uint32_t tri, bool have, int x0,
+                                               int x1, int y0, int y1) {
+  const int lane = threadIdx.x & 63;
+  const bool any = have && s.n >= 3 && x0 <= x1 && y0 <= y1;
+  const bool small = any && (x1 - x0 + 1) * (y1 - y0 + 1) <= kSmallPx;
   if (small) {
-    for (int i = 1; i + 1 < n; ++i) {
-      const Edge3 e = setup_tri(PX[0], PY[0], pick8(PX, i), pick8(PY, i), pick8(PX, i + 1), pick8(PY, i + 1));
-      if (e.ok) raster_tri_thread(fr, rk, (uint32_t)t, e, x0, x1, y0, y1);
+    for (int i = 1; i + 1 < s.n; ++i) {
+      const Edge3 e = orient(s.PX[0], s.PY[0], pick8(s.PX, i), pick8(s.PY, i), pick8(s.PX, i + 1), pick8(s.PY, i + 1));
+      if (e.ok) raster_thread(c, s.rk, tri, e, x0, x1, y0, y1);
     }
   }
-  // ---- large triangles: the whole wave, one triangle at a time ----
   unsigned long long big = __ballot(any && !small);
   while (big) {
     const int src = __ffsll(big) - 1;
     big &= big - 1;
-    const int bn = __shfl(n, src);
+    const int bn = __shfl(s.n, src);
     int bx[8], by[8];
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-      bx[i] = __shfl(PX[i], src);
-      by[i] = __shfl(PY[i], src);
+      bx[i] = __shfl(s.PX[i], src);
+      by[i] = __shfl(s.PY[i], src);
     }
     RayK bk;
-    bk.n = V3{__shfl(rk.n.x, src), __shfl(rk.n.y, src), __shfl(rk.n.z, src)};
-    bk.d = __shfl(rk.d, src);
+    bk.n = V3{__shfl(s.rk.n.x, src), __shfl(s.rk.n.y, src), __shfl(s.rk.n.z, src)};
+    bk.d = __shfl(s.rk.d, src);
     const int bx0 = __shfl(x0, src), bx1 = __shfl(x1, src), by0 = __shfl(y0, src), by1 = __shfl(y1, src);
-    const uint32_t btri = (uint32_t)(t - lane + src);
+    const uint32_t btri = (uint32_t)__shfl((int)tri, src);
     const int ox = lane & 7, oy = lane >> 3;
     for (int yb = by0; yb <= by1; yb += 8) {
       for (int xb = bx0; xb <= bx1; xb += 8) {
@@ -232,69 +332,120 @@ __global__ __launch_bounds__(256) void k_raster(MeshDev m, const float* __restri
         const int pcx = 256 * x + 128, pcy = 256 * y + 128;
         bool cov = false;
         for (int i = 1; i + 1 < bn; ++i) {
-          const Edge3 e = setup_tri(bx[0], by[0], pick8(bx, i), pick8(by, i), pick8(bx, i + 1), pick8(by, i + 1));
+          const Edge3 e = orient(bx[0], by[0], pick8(bx, i), pick8(by, i), pick8(bx, i + 1), pick8(by, i + 1));
           cov = cov || (e.ok && covers(e, pcx, pcy));
         }
-        if (cov) emit(fr, bk, x, y, btri);
+        if (cov) emit_lds(c, bk, x, y, btri);
       }
     }
   }
 }
 
-hipError_t launch_raster(const MeshDev& m, const float* cams, int nf, int H, int W, unsigned long long* keys,
-                         const float* rx, const float* ry, hipStream_t s) {
-  if (nf <= 0 || m.T == 0) return hipSuccess;
-  k_raster<<<dim3((unsigned)((m.T + 255) / 256), (unsigned)nf), 256, 0, s>>>(m, cams, H, W, keys, rx, ry);
-  return hipGetLastError();
-}
+}  // namespace
 
-// ---- resolve: key -> (triangle, texel row, depth); resets the key --------------
-__global__ __launch_bounds__(256) void k_resolve(MeshDev m, const float* __restrict__ cams, int H, int W,
-                                                 unsigned long long* __restrict__ keys,
-                                                 const float* __restrict__ rxt, const float* __restrict__ ryt,
-                                                 int32_t* __restrict__ l_out, int32_t* __restrict__ tri_out,
-                                                 float* __restrict__ z_out, const uint8_t* __restrict__ valid,
-                                                 int32_t* __restrict__ cnt, int64_t cnt_stride) {
+__global__ __launch_bounds__(256) void k_tile_raster(MeshDev m, const float* __restrict__ cams, int H, int W,
+                                                     const int32_t* __restrict__ vis, const int32_t* __restrict__ vis_n,
+                                                     const int32_t* __restrict__ toff, const int32_t* __restrict__ tlist,
+                                                     int64_t list_cap, const int32_t* __restrict__ over, RasterOut out) {
+  __shared__ unsigned long long key[TS * TS];
+  __shared__ float rxs[TS], rys[TS];
   const int fb = blockIdx.y;
+  const Cam cam = load_cam(cams + 16 * (int64_t)fb);
+  const int ntx = (W + TS - 1) / TS, nty = (H + TS - 1) / TS;
+  const int ntiles = ntx * nty;
+  const int tile = blockIdx.x;
+  const int tx0 = (tile % ntx) * TS, ty0 = (tile / ntx) * TS;
+  const int tx1 = min(tx0 + TS, W) - 1, ty1 = min(ty0 + TS, H) - 1;
+  for (int i = threadIdx.x; i < TS * TS; i += 256) key[i] = ~0ull;
+  if (threadIdx.x < TS) rxs[threadIdx.x] = ray_x(cam, tx0 + threadIdx.x);
+  else if (threadIdx.x < 2 * TS) rys[threadIdx.x - TS] = ray_y(cam, ty0 + threadIdx.x - TS);
+  __syncthreads();
+  const TileCtx c{key, rxs, rys, tx0, ty0};
   const int64_t HW = (int64_t)H * W;
-  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (p >= HW) return;
-  const int64_t i = (int64_t)fb * HW + p;
-  const unsigned long long key = keys[i];
-  keys[i] = ~0ull;
-  int32_t l = -1, tri = -1;
-  float z = __builtin_nanf("");
-  if (key != ~0ull) {
-    tri = (int32_t)(uint32_t)(key & 0xffffffffull);
-    const Cam cam = load_cam(cams + 16 * (int64_t)fb);
-    const int x = (int)(p % W), y = (int)(p / W);
-    const int i0 = m.faces_uv[3 * (int64_t)tri], i1 = m.faces_uv[3 * (int64_t)tri + 1],
-              i2 = m.faces_uv[3 * (int64_t)tri + 2];
-    const float* q0 = m.verts + 3 * (int64_t)i0;
-    const float* q1 = m.verts + 3 * (int64_t)i1;
-    const float* q2 = m.verts + 3 * (int64_t)i2;
-    const RayK rk = ray_consts(to_cam(cam, q0[0], q0[1], q0[2]), to_cam(cam, q1[0], q1[1], q1[2]),
-                               to_cam(cam, q2[0], q2[1], q2[2]));
-    const float rx = rxt[(int64_t)fb * W + x], ry = ryt[(int64_t)fb * H + y];
-    const float den = rdot(rx, ry, rk.n);
-    z = rk.d / den;
-    const float u = rdot(rx, ry, rk.nu) / den;
-    const float v = rdot(rx, ry, rk.nv) / den;
-    l = (int32_t)(row_offset(m, tri) + texel_id(tri_s(m, tri), m.split, u, v));
-    if (cnt && (!valid || valid[i])) atomicAdd(cnt + (int64_t)fb * cnt_stride + l, 1);
+
+  if (!over[fb]) {
+    const int e0 = toff[(int64_t)fb * (ntiles + 1) + tile], e1 = toff[(int64_t)fb * (ntiles + 1) + tile + 1];
+    const int32_t* lst = tlist + (int64_t)fb * list_cap;
+    for (int base = e0; base < e1; base += 256) {   // same trip count for the whole block
+      const int e = base + threadIdx.x;
+      const bool have = e < e1;
+      Setup s;
+      s.n = 0;
+      s.x0 = 0; s.x1 = -1; s.y0 = 0; s.y1 = -1;
+      uint32_t tri = 0;
+      if (have) {
+        tri = (uint32_t)lst[e];
+        setup_triangle(m, cam, tri, H, W, s);
+      }
+      raster_entries(c, s, tri, have, max(s.x0, tx0), min(s.x1, tx1), max(s.y0, ty0), min(s.y1, ty1));
+    }
+  } else {
+    // the tile lists overflowed their capacity: walk every triangle of every
+    // visible cluster instead (slow, same result)
+    const int nvis = vis_n[fb];
+    for (int w0 = 0; w0 < nvis; w0 += 4) {
+      const int w = w0 + (threadIdx.x >> 6);
+      const int64_t t = w < nvis ? (int64_t)vis[(int64_t)fb * m.n_clusters + w] * kClusterTris + (threadIdx.x & 63)
+                                 : m.T;
+      Setup s;
+      s.n = 0;
+      s.x0 = 0; s.x1 = -1; s.y0 = 0; s.y1 = -1;
+      const bool have = t < m.T;
+      if (have) setup_triangle(m, cam, t, H, W, s);
+      raster_entries(c, s, (uint32_t)t, have, max(s.x0, tx0), min(s.x1, tx1), max(s.y0, ty0), min(s.y1, ty1));
+    }
   }
-  if (l_out) l_out[i] = l;
-  if (tri_out) tri_out[i] = tri;
-  if (z_out) z_out[i] = z;
+  __syncthreads();
+
+  // ---- resolve every pixel of the tile ----
+  for (int i = threadIdx.x; i < TS * TS; i += 256) {
+    const int x = tx0 + (i % TS), y = ty0 + (i / TS);
+    if (x > tx1 || y > ty1) continue;
+    const unsigned long long k = key[i];
+    const int64_t pix = (int64_t)fb * HW + (int64_t)y * W + x;
+    int32_t l = -1, tri = -1;
+    float z = __builtin_nanf("");
+    if (k != ~0ull) {
+      tri = (int32_t)(uint32_t)(k & 0xffffffffull);
+      V3 A, B, C;
+      load_tri(m, cam, tri, A, B, C);
+      const RayK rk = ray_consts(A, B, C);
+      const float rx = rxs[i % TS], ry = rys[i / TS];
+      const float den = rdot(rx, ry, rk.n);
+      z = rk.d / den;
+      const float u = rdot(rx, ry, rk.nu) / den;
+      const float v = rdot(rx, ry, rk.nv) / den;
+      l = (int32_t)(row_offset(m, tri) + texel_id(tri_s(m, tri), m.split, u, v));
+      if (!out.valid || out.valid[pix]) {
+        if (out.cnt) atomicAdd(out.cnt + (int64_t)fb * out.cnt_stride + l, 1);
+        if (out.seg) out.rank[pix] = atomicAdd(out.seg + l, 1);
+      }
+    }
+    if (out.l) out.l[pix] = l;
+    if (out.tri) out.tri[pix] = tri;
+    if (out.z) out.z[pix] = z;
+  }
 }
 
-hipError_t launch_resolve(const MeshDev& m, const float* cams, int nf, int H, int W, unsigned long long* keys,
-                          const float* rx, const float* ry, int32_t* l_out, int32_t* tri_out, float* z_out,
-                          const uint8_t* valid, int32_t* cnt, int64_t cnt_stride, hipStream_t s) {
-  if (nf <= 0) return hipSuccess;
-  const int64_t HW = (int64_t)H * W;
-  k_resolve<<<dim3((unsigned)((HW + 255) / 256), (unsigned)nf), 256, 0, s>>>(m, cams, H, W, keys, rx, ry, l_out,
-                                                                             tri_out, z_out, valid, cnt, cnt_stride);
+// ---- launcher ---------------------------------------------------------------
+hipError_t launch_render_batch(const MeshDev& m, const float* cams, int nb, int H, int W, const RasterWs& ws,
+                               const RasterOut& out, hipStream_t s) {
+  if (nb <= 0) return hipSuccess;
+  const int ntx = (W + TS - 1) / TS, nty = (H + TS - 1) / TS;
+  const int ntiles = ntx * nty;
+  hipError_t e = launch_zero(ws.vis_n, (int64_t)nb * 4, s);
+  if (e != hipSuccess) return e;
+  if (m.n_clusters > 0)
+    k_cull_clusters<<<dim3((unsigned)((m.n_clusters + 255) / 256), (unsigned)nb), 256, 0, s>>>(m, cams, H, W, ws.vis,
+                                                                                               ws.vis_n);
+  const unsigned gb = (unsigned)std::min<int64_t>((m.n_clusters + 3) / 4 + 1, 1024);
+  k_bin<false><<<dim3(gb, (unsigned)nb), 256, 0, s>>>(m, cams, H, W, ws.vis, ws.vis_n, ws.tcnt, ws.toff, ws.tlist,
+                                                      ws.list_cap);
+  k_tile_scan<<<dim3((unsigned)nb), 1024, 0, s>>>(ws.tcnt, ntiles, ws.toff, ws.list_cap, ws.over);
+  k_bin<true><<<dim3(gb, (unsigned)nb), 256, 0, s>>>(m, cams, H, W, ws.vis, ws.vis_n, ws.tcnt, ws.toff, ws.tlist,
+                                                     ws.list_cap);
+  k_tile_raster<<<dim3((unsigned)ntiles, (unsigned)nb), 256, 0, s>>>(m, cams, H, W, ws.vis, ws.vis_n, ws.toff,
+                                                                     ws.tlist, ws.list_cap, ws.over, out);
   return hipGetLastError();
 }
 

@@ -1,0 +1,385 @@
+// Texel-sorted aggregation (Sections 3.2.1, 3.2.2, 3.3.2) without floating
+// point atomics: every batch of frames is counting-sorted by texel row, then
+// one wave owns each touched row and adds all of the batch's observations of
+// it in registers before a single read-modify-write of the row.
+//   k_seg_scan*   exclusive scan of the per-row observation counts (counted
+//                 while resolving the frames) -> segment starts;
+//   k_seg_fill    every valid covered pixel claims a slot in its row's
+//                 segment (atomic down-count, which also returns the counts
+//                 to zero) and stores the element offset of its class-0 value
+//                 and, when needed, its weight and FP8 scale;
+//   k_seg_gather  one wave per 64 consecutive rows, lanes = classes: for each
+//                 non-empty row, stream its observations (a contiguous 4c-byte
+//                 read per observation when classes are innermost), sum
+//                 w * f(p) in registers, then update the row once.
+// Rows touched by many frames of a batch are read and written once per
+// batch instead of once per pixel.
+#include <algorithm>
+
+#include "internal.h"
+#include "spec.h"
+
+namespace lf {
+
+__device__ __forceinline__ float e4m3_dec(uint32_t q) {
+  const int e = (q >> 3) & 15, mnt = q & 7;
+  float v = (e == 0) ? (float)mnt * 0.001953125f : __builtin_ldexpf((float)(8 + mnt), e - 10);
+  if (e == 15 && mnt == 7) v = __builtin_nanf("");
+  return (q & 0x80u) ? -v : v;
+}
+
+// ---- scan of the segment counts ------------------------------------------------
+constexpr int kSegChunk = 8192;   // rows per scan block (256 threads x 32)
+
+__global__ __launch_bounds__(256) void k_seg_sums(const int32_t* __restrict__ cnt, int64_t n, int32_t* __restrict__ sums) {
+  __shared__ int red[256];
+  const int64_t base = (int64_t)blockIdx.x * kSegChunk;
+  int acc = 0;
+  for (int i = threadIdx.x; i < kSegChunk; i += 256) {
+    const int64_t r = base + i;
+    if (r < n) acc += cnt[r];
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) sums[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(1024) void k_seg_scan_sums(int32_t* __restrict__ sums, int64_t nblk) {
+  __shared__ int part[1024];
+  int carry = 0;
+  for (int64_t base = 0; base < nblk; base += 1024) {
+    const int64_t i = base + threadIdx.x;
+    const int v = i < nblk ? sums[i] : 0;
+    part[threadIdx.x] = v;
+    __syncthreads();
+    for (int d = 1; d < 1024; d <<= 1) {
+      const int a = threadIdx.x >= d ? part[threadIdx.x - d] : 0;
+      __syncthreads();
+      part[threadIdx.x] += a;
+      __syncthreads();
+    }
+    if (i < nblk) sums[i] = carry + part[threadIdx.x] - v;
+    carry += part[1023];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) sums[nblk] = carry;
+}
+
+__global__ __launch_bounds__(256) void k_seg_scan(const int32_t* __restrict__ cnt, int64_t n,
+                                                  const int32_t* __restrict__ sums, int32_t* __restrict__ start) {
+  __shared__ int part[256];
+  constexpr int per = kSegChunk / 256;
+  const int64_t base = (int64_t)blockIdx.x * kSegChunk + (int64_t)threadIdx.x * per;
+  int loc[per];
+  int acc = 0;
+#pragma unroll
+  for (int i = 0; i < per; ++i) {
+    const int64_t r = base + i;
+    const int v = r < n ? cnt[r] : 0;
+    loc[i] = acc;
+    acc += v;
+  }
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  for (int d = 1; d < 256; d <<= 1) {
+    const int a = threadIdx.x >= d ? part[threadIdx.x - d] : 0;
+    __syncthreads();
+    part[threadIdx.x] += a;
+    __syncthreads();
+  }
+  const int pre = sums[blockIdx.x] + part[threadIdx.x] - acc;
+#pragma unroll
+  for (int i = 0; i < per; ++i) {
+    const int64_t r = base + i;
+    if (r < n) start[r] = pre + loc[i];
+  }
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) start[n] = sums[gridDim.x];
+}
+
+// ---- fill ------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_seg_fill(ProbIn in, int f_first, int H, int W, const int32_t* __restrict__ lbuf,
+                                                  const int32_t* __restrict__ rank, const int32_t* __restrict__ start,
+                                                  uint32_t* __restrict__ ent_pix, float* __restrict__ ent_w,
+                                                  float* __restrict__ ent_s, int weighting,
+                                                  const int32_t* __restrict__ cnt, int64_t cnt_stride,
+                                                  const float* __restrict__ wpix) {
+  const int fb = blockIdx.y;
+  const int64_t HW = (int64_t)H * W;
+  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (p >= HW) return;
+  const int64_t pi = (int64_t)fb * HW + p;
+  const int l = lbuf[pi];
+  if (l < 0) return;
+  const int64_t gi = (int64_t)(f_first + fb) * HW + p;
+  if (in.valid && !in.valid[gi]) return;
+  const int pos = start[l] + rank[pi];
+  const int y = (int)(p / W), x = (int)(p - (int64_t)y * W);
+  ent_pix[pos] = (uint32_t)((int64_t)fb * in.sf + (int64_t)y * in.sy + (int64_t)x * in.sx);
+  if (ent_w) {
+    float w = 1.0f;
+    if (weighting == 1) w = 1.0f / (float)cnt[(int64_t)fb * cnt_stride + l];
+    else if (weighting == 2) w = wpix[pi];
+    ent_w[pos] = w;
+  }
+  if (ent_s) ent_s[pos] = in.scale[gi];
+}
+
+// ---- gather --------------------------------------------------------------------------
+template <int DT>
+__device__ __forceinline__ float ld_prob(const void* p, int64_t e) {
+  if constexpr (DT == 0) return reinterpret_cast<const float*>(p)[e];
+  else return e4m3_dec(reinterpret_cast<const uint8_t*>(p)[e]);
+}
+
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+  return v;
+}
+
+template <int NCH, int DT, int AGG>
+__device__ __forceinline__ void accumulate(float (&acc)[NCH], const float (&v)[NCH], float w, int lane, int c) {
+  if constexpr (AGG == 0) {
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch) acc[ch] += w * v[ch];
+  } else if constexpr (AGG == 1) {
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch) acc[ch] += w * logf(v[ch]);
+  } else {
+    float mx = -__builtin_inff();
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch) mx = fmaxf(mx, (lane + 64 * ch < c) ? v[ch] : -__builtin_inff());
+    mx = wave_max(mx);
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch) acc[ch] += w * ((v[ch] == mx) ? v[ch] : 0.0f);
+  }
+}
+
+constexpr int kGatherUnroll = 8;   // observations in flight per wave
+
+// Element offset of an observation's class-0 value: the batch's first frame
+// plus the batch-relative offset stored by the fill.
+struct PixDecode {
+  int64_t base;
+  __device__ __forceinline__ int64_t operator()(const ProbIn&, uint32_t q) const { return base + (int64_t)q; }
+};
+
+// Lanes = classes (any stride, any c): one wave per 64 consecutive rows.
+template <int NCH, int DT, int AGG>
+__global__ __launch_bounds__(256) void k_seg_gather(MeshDev m, ProbIn in, PixDecode dec, const int32_t* __restrict__ start,
+                                                    const uint32_t* __restrict__ ent_pix,
+                                                    const float* __restrict__ ent_w, const float* __restrict__ ent_s) {
+  const int lane = threadIdx.x & 63;
+  const int64_t x0 = (((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6) * 64;
+  if (x0 >= m.n_texels) return;
+  const int c = m.c;
+  float* __restrict__ A = reinterpret_cast<float*>(m.accum);
+  const int64_t xl = x0 + lane;
+  int s = 0, e = 0;
+  if (xl < m.n_texels) {
+    s = start[xl];
+    e = start[xl + 1];
+  }
+  unsigned long long todo = __ballot(e > s);
+  while (todo) {
+    const int src = __ffsll(todo) - 1;
+    todo &= todo - 1;
+    const int seg_s = __builtin_amdgcn_readlane(s, src), seg_e = __builtin_amdgcn_readlane(e, src);
+    const int64_t x = x0 + src;
+    // the row's old value is loaded first so its latency hides behind the observations
+    float old[NCH];
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch) {
+      const int j = lane + 64 * ch;
+      old[ch] = j < c ? A[x * c + j] : 0.0f;
+    }
+    float acc[NCH];
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch) acc[ch] = 0.0f;
+    float wsum = 0.0f;
+    for (int b = seg_s; b < seg_e; b += 64) {
+      const int k = b + lane;
+      const bool ok = k < seg_e;
+      const int64_t my_off = ok ? dec(in, ent_pix[k]) : 0;
+      const float my_w = (ent_w && ok) ? ent_w[k] : 1.0f;
+      const float my_s = (ent_s && ok) ? ent_s[k] : 1.0f;
+      const int cnt = min(64, seg_e - b);
+      const int lo32 = (int)(my_off & 0xffffffffll), hi32 = (int)(my_off >> 32);
+      for (int i0 = 0; i0 < cnt; i0 += kGatherUnroll) {
+        float v[kGatherUnroll][NCH];
+        float w[kGatherUnroll];
+#pragma unroll
+        for (int u = 0; u < kGatherUnroll; ++u) {
+          const int i = i0 + u < cnt ? i0 + u : i0;   // uniform
+          const int64_t off = ((int64_t)__builtin_amdgcn_readlane(hi32, i) << 32) |
+                              (uint32_t)__builtin_amdgcn_readlane(lo32, i);
+          w[u] = i0 + u < cnt ? __int_as_float(__builtin_amdgcn_readlane(__float_as_int(my_w), i)) : 0.0f;
+          const float sc = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(my_s), i));
+#pragma unroll
+          for (int ch = 0; ch < NCH; ++ch) {
+            const int j = lane + 64 * ch;
+            v[u][ch] = (j < c && i0 + u < cnt) ? ld_prob<DT>(in.p, off + (int64_t)j * in.sc) : 1.0f;
+            if (DT == 3) v[u][ch] = v[u][ch] * sc;
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < kGatherUnroll; ++u) {
+          if (i0 + u < cnt) {
+            accumulate<NCH, DT, AGG>(acc, v[u], w[u], lane, c);
+            wsum += w[u];
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch) {
+      const int j = lane + 64 * ch;
+      if (j < c) A[x * c + j] = old[ch] + acc[ch];
+    }
+    if (m.wsum && lane == 0) m.wsum[x] += wsum;
+  }
+}
+
+// 16 lanes per row (classes contiguous, c <= 64, c % 4 == 0): lane i of a
+// group owns classes 4i..4i+3 of one texel row, reads them as one float4 (FP32)
+// or one 32-bit word of four codes (E4M3) per observation, so one wave
+// instruction fetches four contiguous class vectors; four observations are
+// kept in flight per lane.  The group then updates its row once.
+constexpr int kRowsPerGroup = 4;   // consecutive rows walked by one 16-lane group
+
+template <int DT, int AGG>
+__global__ __launch_bounds__(256) void k_seg_gather16(MeshDev m, ProbIn in, PixDecode dec,
+                                                      const int32_t* __restrict__ start,
+                                                      const uint32_t* __restrict__ ent,
+                                                      const float* __restrict__ ent_w, const float* __restrict__ ent_s) {
+  constexpr int U = 4;
+  const int gl = threadIdx.x & 15;                       // lane in group = class chunk
+  const int64_t grp = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 4;
+  const int c = m.c;
+  const int nv = c >> 2;
+  const bool act = gl < nv;
+  float* __restrict__ A = reinterpret_cast<float*>(m.accum);
+  for (int r = 0; r < kRowsPerGroup; ++r) {
+    const int64_t x = grp * kRowsPerGroup + r;
+    if (x >= m.n_texels) break;
+    const int s0 = start[x], s1 = start[x + 1];
+    if (s0 == s1) continue;
+    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+    float4 old = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (act) old = *reinterpret_cast<const float4*>(A + x * c + 4 * gl);
+    float wsum = 0.0f;
+    for (int k0 = s0; k0 < s1; k0 += U) {
+      float4 v[U];
+      float w[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int k = k0 + u;
+        const bool ok = k < s1;
+        const int kk = ok ? k : k0;
+        const int64_t off = dec(in, ent[kk]);
+        w[u] = ok ? (ent_w ? ent_w[kk] : 1.0f) : 0.0f;
+        v[u] = make_float4(1.f, 1.f, 1.f, 1.f);
+        if (act) {
+          if constexpr (DT == 0) {
+            v[u] = *reinterpret_cast<const float4*>(reinterpret_cast<const float*>(in.p) + off + 4 * gl);
+          } else {
+            const uint32_t q = *reinterpret_cast<const uint32_t*>(reinterpret_cast<const uint8_t*>(in.p) + off + 4 * gl);
+            const float sc = ent_s[kk];
+            v[u] = make_float4(e4m3_dec(q & 0xffu) * sc, e4m3_dec((q >> 8) & 0xffu) * sc,
+                               e4m3_dec((q >> 16) & 0xffu) * sc, e4m3_dec(q >> 24) * sc);
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        float4 t = v[u];
+        if constexpr (AGG == 1) {
+          t = make_float4(logf(t.x), logf(t.y), logf(t.z), logf(t.w));
+        } else if constexpr (AGG == 2) {
+          float mx = act ? fmaxf(fmaxf(t.x, t.y), fmaxf(t.z, t.w)) : -__builtin_inff();
+#pragma unroll
+          for (int o = 8; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o, 16));
+          t = make_float4(t.x == mx ? t.x : 0.f, t.y == mx ? t.y : 0.f, t.z == mx ? t.z : 0.f, t.w == mx ? t.w : 0.f);
+        }
+        acc.x += w[u] * t.x;
+        acc.y += w[u] * t.y;
+        acc.z += w[u] * t.z;
+        acc.w += w[u] * t.w;
+        wsum += w[u];
+      }
+    }
+    if (act)
+      *reinterpret_cast<float4*>(A + x * c + 4 * gl) =
+          make_float4(old.x + acc.x, old.y + acc.y, old.z + acc.z, old.w + acc.w);
+    if (m.wsum && gl == 0) m.wsum[x] += wsum;
+  }
+}
+
+hipError_t launch_seg_gather(const MeshDev& m, const ProbIn& in, int f_first, int H, int W, const int32_t* start,
+                             const uint32_t* ent, const float* ent_w, const float* ent_s, hipStream_t s) {
+  if (m.n_texels == 0) return hipSuccess;
+  (void)H;
+  (void)W;
+  const PixDecode dec{(int64_t)f_first * in.sf};
+  // 4-class chunks of contiguous classes: 16-byte (FP32) / 4-byte (E4M3) aligned
+  const int64_t esz = in.dtype == 0 ? 4 : 1;
+  const int64_t chunk = 4 * esz;
+  const bool grouped = in.sc == 1 && m.c <= 64 && (m.c % 4) == 0 &&
+                       (reinterpret_cast<uintptr_t>(in.p) % chunk) == 0 && ((in.sf * esz) % chunk) == 0 &&
+                       ((in.sy * esz) % chunk) == 0 && ((in.sx * esz) % chunk) == 0 &&
+                       (reinterpret_cast<uintptr_t>(m.accum) % 16) == 0;
+  if (grouped) {
+    const int64_t groups = (m.n_texels + kRowsPerGroup - 1) / kRowsPerGroup;
+    dim3 g((unsigned)((groups * 16 + 255) / 256));
+#define LF_R(DT, AGG) k_seg_gather16<DT, AGG><<<g, 256, 0, s>>>(m, in, dec, start, ent, ent_w, ent_s)
+    if (in.dtype == 0) {
+      if (m.aggregator == 0) LF_R(0, 0); else if (m.aggregator == 1) LF_R(0, 1); else LF_R(0, 2);
+    } else {
+      if (m.aggregator == 0) LF_R(3, 0); else if (m.aggregator == 1) LF_R(3, 1); else LF_R(3, 2);
+    }
+#undef LF_R
+    return hipGetLastError();
+  }
+  const int64_t waves = (m.n_texels + 63) / 64;
+  dim3 g((unsigned)((waves + 3) / 4));
+#define LF_G(NCH, DT, AGG) k_seg_gather<NCH, DT, AGG><<<g, 256, 0, s>>>(m, in, dec, start, ent, ent_w, ent_s)
+#define LF_G2(NCH, DT)                      \
+  do {                                      \
+    if (m.aggregator == 0) LF_G(NCH, DT, 0); \
+    else if (m.aggregator == 1) LF_G(NCH, DT, 1); \
+    else LF_G(NCH, DT, 2);                  \
+  } while (0)
+  if (m.c <= 64) {
+    if (in.dtype == 0) LF_G2(1, 0); else LF_G2(1, 3);
+  } else {
+    if (in.dtype == 0) LF_G2(4, 0); else LF_G2(4, 3);
+  }
+#undef LF_G2
+#undef LF_G
+  return hipGetLastError();
+}
+
+hipError_t launch_seg_scan(const int32_t* seg, int64_t n, int32_t* sums, int32_t* start, hipStream_t s) {
+  const int64_t nblk = std::max<int64_t>((n + kSegChunk - 1) / kSegChunk, 1);
+  k_seg_sums<<<dim3((unsigned)nblk), 256, 0, s>>>(seg, n, sums);
+  k_seg_scan_sums<<<1, 1024, 0, s>>>(sums, nblk);
+  k_seg_scan<<<dim3((unsigned)nblk), 256, 0, s>>>(seg, n, sums, start);
+  return hipGetLastError();
+}
+
+hipError_t launch_seg_fill(const ProbIn& in, int f_first, int nf, int H, int W, const int32_t* l, const int32_t* rank,
+                           const int32_t* start, uint32_t* ent_pix, float* ent_w, float* ent_s, int weighting,
+                           const int32_t* cnt, int64_t cnt_stride, const float* wpix, hipStream_t s) {
+  if (nf <= 0) return hipSuccess;
+  const int64_t HW = (int64_t)H * W;
+  k_seg_fill<<<dim3((unsigned)((HW + 255) / 256), (unsigned)nf), 256, 0, s>>>(in, f_first, H, W, l, rank, start, ent_pix,
+                                                                              ent_w, ent_s, weighting, cnt, cnt_stride,
+                                                                              wpix);
+  return hipGetLastError();
+}
+
+}  // namespace lf

@@ -41,15 +41,16 @@ def test_config1_raster_bit_exact(cfg1):
     compare_raster(gm, om, cfg1.cams, cfg1.H, cfg1.W)
 
 
+@pytest.mark.parametrize("scatter", [sf.SCATTER_ATOMIC, sf.SCATTER_SORTED])
 @pytest.mark.parametrize("weighting", [sf.W_PIXEL, sf.W_IMAGE])
-def test_config1_fusion_parity(cfg1, weighting):
-    say(f"[case] config-1 fusion weighting={weighting}")
+def test_config1_fusion_parity(cfg1, weighting, scatter):
+    say(f"[case] config-1 fusion weighting={weighting} scatter={scatter}")
     sc = cfg1.scene
     gm = gpu_mesh((sc.vertices, sc.faces), 1, oracle.SPLIT, 13)
     om = oracle_mesh(sc.vertices, sc.faces, 1, oracle.SPLIT)
     probs = cfg1.probs.numpy()
     valid = cfg1.valid.numpy()
-    l_g = _fuse_both(gm, om, weighting, cfg1.cams, probs, valid, weighting)
+    l_g = _fuse_both(gm, om, weighting, cfg1.cams, probs, valid, weighting, scatter=scatter)
     _, l_o = om.raster_frames(cfg1.cams, cfg1.H, cfg1.W)
     assert np.array_equal(l_g, l_o)
     A_o, W_o = oracle.fuse(om.n_texels, 13, l_o, probs, valid, weighting=weighting)
@@ -140,14 +141,15 @@ def test_tiny_and_empty_frames(cfg1):
     assert int((out["tri"] >= 0).sum()) == 0
 
 
+@pytest.mark.parametrize("scatter", [sf.SCATTER_ATOMIC, sf.SCATTER_SORTED])
 @pytest.mark.parametrize("aggregator", [sf.AGG_MUL, sf.AGG_MAXSUM])
-def test_aggregators_mul_maxsum(cfg1, aggregator):
-    say(f"[case] aggregator {aggregator}")
+def test_aggregators_mul_maxsum(cfg1, aggregator, scatter):
+    say(f"[case] aggregator {aggregator} scatter {scatter}")
     sc = cfg1.scene
     gm = gpu_mesh((sc.vertices, sc.faces), 1, oracle.SPLIT, 13, aggregator=aggregator)
     om = oracle_mesh(sc.vertices, sc.faces, 1, oracle.SPLIT)
     probs = cfg1.probs.numpy()[:8]
-    l_g = _fuse_both(gm, om, 0, cfg1.cams[:8], probs, None, sf.W_IMAGE)
+    l_g = _fuse_both(gm, om, 0, cfg1.cams[:8], probs, None, sf.W_IMAGE, scatter=scatter)
     A_o, W_o = oracle.fuse(om.n_texels, 13, l_g, probs, None, weighting=oracle.W_IMAGE, aggregator=aggregator)
     compare_fused(gm.accum.cpu().numpy(), A_o, aggregator=aggregator, rel=2e-5 if aggregator == sf.AGG_MUL else 1e-5)
     P_o, lab_o = oracle.finalize(A_o, W_o, aggregator=aggregator)
@@ -179,10 +181,17 @@ def test_nhwc_and_fp8_inputs(cfg1):
     A_o, _ = oracle.fuse(om.n_texels, 13, l_g, probs.numpy())
     compare_fused(gm.accum.cpu().numpy(), A_o)
     q, scale = S.quantize_fp8(probs)
-    gm8 = gpu_mesh((sc.vertices, sc.faces), 1, oracle.SPLIT, 13)
-    gm8.fuse_frames(to_dev(cams, torch.float32), q.cuda(), scale=scale.cuda(), l_out=l_out)
-    torch.cuda.synchronize()
     A8, _ = oracle.fuse(om.n_texels, 13, l_g, q.numpy(), scale=scale.numpy())
+    for mode in (sf.SCATTER_ATOMIC, sf.SCATTER_SORTED):
+        gm8 = gpu_mesh((sc.vertices, sc.faces), 1, oracle.SPLIT, 13)
+        gm8.fuse_frames(to_dev(cams, torch.float32), q.cuda(), scale=scale.cuda(), l_out=l_out, scatter_mode=mode)
+        torch.cuda.synchronize()
+        compare_fused(gm8.accum.cpu().numpy(), A8)
+    # channels-last FP8 codes
+    q_cl = q.to(memory_format=torch.channels_last).cuda()
+    gm8 = gpu_mesh((sc.vertices, sc.faces), 1, oracle.SPLIT, 13)
+    gm8.fuse_frames(to_dev(cams, torch.float32), q_cl, scale=scale.cuda(), l_out=l_out)
+    torch.cuda.synchronize()
     compare_fused(gm8.accum.cpu().numpy(), A8)
 
 
@@ -200,3 +209,43 @@ def test_errors_are_reported():
     assert e.value.status in (sf.LF_ESIZE, sf.LF_EINVAL)
     with pytest.raises(ValueError):
         m.fuse_frames(torch.zeros((1, 16), device="cuda"), torch.zeros((1, 5, 8, 8), device="cuda"))
+
+
+@pytest.fixture(scope="module")
+def cfg2_subset():
+    say("[case] config-2 shaped subset: ~500k-triangle room, SPLIT s=3, 12 frames 640x480, c=40 (GPU-generated)")
+    sc = S.config2_scene(0)
+    w = S.config2(device="cuda", n_frames=12, scene=sc)
+    return w
+
+
+def test_config2_subset_raster_and_sorted_fusion(cfg2_subset):
+    w = cfg2_subset
+    sc = w.scene
+    gm = gpu_mesh((sc.vertices, sc.faces), 3, oracle.SPLIT, 40)
+    om = oracle_mesh(sc.vertices, sc.faces, 3, oracle.SPLIT)
+    say("  raster 12 frames")
+    tri_o, l_o = compare_raster(gm, om, w.cams, w.H, w.W)
+    probs_cl = w.probs.to(memory_format=torch.channels_last)
+    for weighting in (sf.W_PIXEL, sf.W_IMAGE):
+        say(f"  sorted fusion, channels-last, weighting {weighting}")
+        gm.reset()
+        l_out = torch.empty((12, w.H, w.W), dtype=torch.int32, device="cuda")
+        gm.fuse_frames(to_dev(w.cams, torch.float32), probs_cl, valid=w.valid, weighting=weighting, l_out=l_out,
+                       batch=8)
+        torch.cuda.synchronize()
+        assert np.array_equal(l_out.cpu().numpy(), l_o)
+        A_o, W_o = oracle.fuse(om.n_texels, 40, l_o, w.probs.cpu().numpy(), w.valid.cpu().numpy(),
+                               weighting=weighting)
+        compare_fused(gm.accum.cpu().numpy(), A_o)
+        P_o, lab_o = oracle.finalize(A_o, W_o)
+        tex, lab = gm.finalize()
+        torch.cuda.synchronize()
+        compare_normalized(tex.cpu().numpy(), P_o)
+        compare_labels(lab.cpu().numpy(), P_o, lab_o)
+    say("  atomic fusion, NCHW, w^(P)")
+    gm.reset()
+    gm.fuse_frames(to_dev(w.cams, torch.float32), w.probs, valid=w.valid, batch=8, scatter_mode=sf.SCATTER_ATOMIC)
+    torch.cuda.synchronize()
+    A_o, _ = oracle.fuse(om.n_texels, 40, l_o, w.probs.cpu().numpy(), w.valid.cpu().numpy())
+    compare_fused(gm.accum.cpu().numpy(), A_o)
