@@ -123,7 +123,10 @@ lf_status check_opts(const lf_mesh_opts* o) {
   if (o->scheme != LF_TEX_SQUARE && o->scheme != LF_TEX_SPLIT) return fail(LF_EINVAL, "unknown texel scheme %d", o->scheme);
   if (o->n_classes < 1 || o->n_classes > 255) return fail(LF_EINVAL, "n_classes must be in [1, 255], got %d", o->n_classes);
   if (o->aggregator < LF_AGG_SUM || o->aggregator > LF_AGG_MAXSUM) return fail(LF_EINVAL, "unknown aggregator %d", o->aggregator);
-  if (o->accum_dtype != LF_F32) return fail(LF_EINVAL, "accumulator dtype %d not supported", o->accum_dtype);
+  if (o->accum_dtype != LF_F32 && o->accum_dtype != LF_BF16 && o->accum_dtype != LF_F16)
+    return fail(LF_EINVAL, "accumulator dtype %d not supported", o->accum_dtype);
+  if (o->accum_dtype != LF_F32 && o->aggregator == LF_AGG_MUL)
+    return fail(LF_EINVAL, "MUL aggregation keeps log-probability sums and needs an FP32 accumulator");
   if (!(o->z_near > 0.0f)) return fail(LF_EINVAL, "z_near must be > 0");
   return LF_OK;
 }
@@ -134,7 +137,8 @@ lf_status check_mesh(lf_mesh m) {
 }
 
 struct FrameLayout {
-  int64_t vis, vis_n, tcnt, toff, over, tlist, l, cnt, wpix, seg, rank, start, sums, ent_off, ent_w, ent_s, total;
+  int64_t vis, vis_n, tcnt, toff, over, tlist, l, cnt, wpix, seg, rank, start, sums, rows, nrows, ent_off, ent_w,
+      ent_s, total;
   int64_t list_cap, ntiles;
   bool sorted;
 };
@@ -163,6 +167,8 @@ FrameLayout frame_layout(const MeshDev& m, int H, int W, int B, int weighting, i
   L.rank = o; if (L.sorted) o += align256(B * HW * 4);
   L.start = o; if (L.sorted) o += align256((m.n_texels + 1) * 4);
   L.sums = o; if (L.sorted) o += align256((m.n_texels / 8192 + 2) * 4);
+  L.rows = o; if (L.sorted) o += align256(m.n_texels * 4);
+  L.nrows = o; if (L.sorted) o += 256;
   L.ent_off = o; if (L.sorted) o += align256(B * HW * 4);
   L.ent_w = o; if (L.sorted) o += align256(B * HW * 4);
   L.ent_s = o; if (L.sorted) o += align256(B * HW * 4);
@@ -281,7 +287,8 @@ lf_status lf_load_mesh(const lf_mesh_opts* opts, const float* d_vertices, int64_
   LF_TRY(launch_mesh_prep(d, d_faces, stream), "mesh prep");
   if (per_face) LF_TRY(launch_offsets(d, reinterpret_cast<int32_t*>(ws + L.scan), stream), "offsets");
   LF_TRY(launch_cluster_boxes(d, stream), "cluster boxes");
-  LF_TRY(launch_zero(d_accum, n_texels * opts->n_classes * 4, stream), "clear accumulator");
+  LF_TRY(launch_zero(d_accum, n_texels * opts->n_classes * (opts->accum_dtype == LF_F32 ? 4 : 2), stream),
+         "clear accumulator");
   if (d_wsum) LF_TRY(launch_zero(d_wsum, n_texels * 4, stream), "clear weights");
   int32_t herr = 0;
   int64_t htot = n_texels;
@@ -304,7 +311,8 @@ lf_status lf_reset(lf_mesh mesh, hipStream_t stream) {
   lf_status st = check_mesh(mesh);
   if (st != LF_OK) return st;
   StageTimer tm(mesh, 6, stream);
-  LF_TRY(launch_zero(mesh->d.accum, mesh->d.n_texels * mesh->d.c * 4, stream), "clear accumulator");
+  LF_TRY(launch_zero(mesh->d.accum, mesh->d.n_texels * mesh->d.c * (mesh->d.accum_dtype == LF_F32 ? 4 : 2), stream),
+         "clear accumulator");
   if (mesh->d.wsum) LF_TRY(launch_zero(mesh->d.wsum, mesh->d.n_texels * 4, stream), "clear weights");
   return LF_OK;
 }
@@ -371,12 +379,16 @@ lf_status lf_fuse_frames(lf_mesh mesh, const float* d_cams, int32_t F, int32_t H
       float* es = prob_dtype == LF_FP8_E4M3 ? reinterpret_cast<float*>(ws + L.ent_s) : nullptr;
       {
         StageTimer tm(mesh, 3, stream);
-        LF_TRY(launch_seg_scan(seg, d.n_texels, reinterpret_cast<int32_t*>(ws + L.sums), start, stream), "segment scan");
+        LF_TRY(launch_zero(ws + L.nrows, 4, stream), "clear row count");
+        LF_TRY(launch_seg_scan(seg, d.n_texels, reinterpret_cast<int32_t*>(ws + L.sums), start,
+                               reinterpret_cast<int32_t*>(ws + L.rows), reinterpret_cast<int32_t*>(ws + L.nrows),
+                               stream), "segment scan");
         LF_TRY(launch_seg_fill(in, f0, nb, H, W, lb, rank, start, eo, ew, es, weighting, cnt, d.n_texels, nullptr, stream),
                "segment fill");
       }
       StageTimer tm(mesh, 2, stream);
-      LF_TRY(launch_seg_gather(d, in, f0, H, W, start, eo, ew, es, stream), "segment gather");
+      LF_TRY(launch_seg_gather(d, in, f0, H, W, start, reinterpret_cast<int32_t*>(ws + L.rows),
+                               reinterpret_cast<int32_t*>(ws + L.nrows), eo, ew, es, stream), "segment gather");
     } else {
       StageTimer tm(mesh, 2, stream);
       LF_TRY(launch_scatter_atomic(d, in, f0, nb, H, W, lb, weighting, cnt, d.n_texels, nullptr, stream), "scatter");

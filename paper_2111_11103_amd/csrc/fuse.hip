@@ -12,6 +12,7 @@
 #include <hip/hip_bf16.h>
 #include <hip/hip_fp16.h>
 
+#include "accum.h"
 #include "internal.h"
 #include "spec.h"
 
@@ -40,7 +41,7 @@ __device__ __forceinline__ float agg_term(float p, float pmax) {
   else return (p == pmax) ? p : 0.0f;
 }
 
-template <int TW, int TH, int K, int CC, int DT, int AGG>
+template <int TW, int TH, int K, int CC, int DT, int AGG, int AT>
 __global__ __launch_bounds__(TW * TH) void k_scatter_hash(MeshDev m, ProbIn in, int f_first, int nf, int H, int W,
                                                            const int32_t* __restrict__ lbuf, int weighting,
                                                            const int32_t* __restrict__ cnt, int64_t cnt_stride,
@@ -56,7 +57,7 @@ __global__ __launch_bounds__(TW * TH) void k_scatter_hash(MeshDev m, ProbIn in, 
   __shared__ int nrow;
 
   const int c = m.c;
-  float* __restrict__ A = reinterpret_cast<float*>(m.accum);
+  void* __restrict__ A = m.accum;
   const int tiles_x = (W + TW - 1) / TW;
   const int tile = blockIdx.x;
   const int x = (tile % tiles_x) * TW + (threadIdx.x % TW);
@@ -152,7 +153,7 @@ __global__ __launch_bounds__(TW * TH) void k_scatter_hash(MeshDev m, ProbIn in, 
         if (j >= c) break;
         const float v = wk[k] * agg_term<AGG>(load_prob<DT>(in, base + (int64_t)j * in.sc, sck[k]), pmx[k]);
         if (sk[k] >= 0) atomicAdd(&rows[sk[k] * CC + jj], v);
-        else unsafeAtomicAdd(A + (int64_t)lk[k] * c + j, v);
+        else acc_atomic_add<AT>(A, (int64_t)lk[k] * c + j, v);
       }
     }
     __syncthreads();
@@ -160,7 +161,7 @@ __global__ __launch_bounds__(TW * TH) void k_scatter_hash(MeshDev m, ProbIn in, 
       const int r = i / CC, jj = i - r * CC;
       const int j = j0 + jj;
       const float v = rows[i];
-      if (j < c && v != 0.0f) unsafeAtomicAdd(A + (int64_t)rowl[r] * c + j, v);
+      if (j < c && v != 0.0f) acc_atomic_add<AT>(A, (int64_t)rowl[r] * c + j, v);
     }
     __syncthreads();
   }
@@ -172,18 +173,19 @@ hipError_t launch_scatter_atomic(const MeshDev& m, const ProbIn& in, int f_first
   if (nf <= 0) return hipSuccess;
   constexpr int TW = 16, TH = 16, K = 4, CC = 8;
   dim3 grid((unsigned)(((W + TW - 1) / TW) * ((H + TH - 1) / TH)), (unsigned)((nf + K - 1) / K));
-#define LF_SCATTER(DT, AGG)                                                                                   \
-  k_scatter_hash<TW, TH, K, CC, DT, AGG><<<grid, TW * TH, 0, s>>>(m, in, f_first, nf, H, W, l, weighting, cnt, \
-                                                                   cnt_stride, wpix)
-  if (in.dtype == 0) {
-    if (m.aggregator == 0) LF_SCATTER(0, 0);
-    else if (m.aggregator == 1) LF_SCATTER(0, 1);
-    else LF_SCATTER(0, 2);
-  } else {
-    if (m.aggregator == 0) LF_SCATTER(3, 0);
-    else if (m.aggregator == 1) LF_SCATTER(3, 1);
-    else LF_SCATTER(3, 2);
-  }
+#define LF_SCATTER(DT, AGG, AT)                                                                     \
+  k_scatter_hash<TW, TH, K, CC, DT, AGG, AT><<<grid, TW * TH, 0, s>>>(m, in, f_first, nf, H, W, l, weighting, cnt, \
+                                                                       cnt_stride, wpix)
+#define LF_SCATTER2(DT)                                                   \
+  do {                                                                    \
+    if (m.aggregator == 1) LF_SCATTER(DT, 1, 0);                          \
+    else if (m.accum_dtype == 0) { if (m.aggregator == 0) LF_SCATTER(DT, 0, 0); else LF_SCATTER(DT, 2, 0); } \
+    else if (m.accum_dtype == 1) { if (m.aggregator == 0) LF_SCATTER(DT, 0, 1); else LF_SCATTER(DT, 2, 1); } \
+    else { if (m.aggregator == 0) LF_SCATTER(DT, 0, 2); else LF_SCATTER(DT, 2, 2); }                     \
+  } while (0)
+  if (in.dtype == 0) LF_SCATTER2(0);
+  else LF_SCATTER2(3);
+#undef LF_SCATTER2
 #undef LF_SCATTER
   return hipGetLastError();
 }
@@ -221,17 +223,25 @@ __device__ __forceinline__ void store_tex(void* out, int64_t i, float v) {
 // maximal class (S == 0: never observed -> P = 0, label 255).  For MUL the row
 // holds sum w log p: P = softmax(A), observed iff its weight sum is > 0.
 // The normalised rows are written back through LDS, coalesced.
-template <int OUT, int AGG>
+template <int OUT, int AGG, int AT>
 __global__ __launch_bounds__(256) void k_finalize(MeshDev m, void* __restrict__ out, uint8_t* __restrict__ labels, int R) {
   extern __shared__ float rows[];
   const int c = m.c;
   const int cp = c | 1;
   const int64_t x0 = (int64_t)blockIdx.x * R;
   const int nr = (int)min<int64_t>(R, m.n_texels - x0);
-  const float* __restrict__ a = reinterpret_cast<const float*>(m.accum) + x0 * c;
-  for (int i = threadIdx.x; i < nr * c; i += 256) {
-    const int r = i / c, j = i - r * c;
-    rows[r * cp + j] = __builtin_nontemporal_load(a + i);
+  const int64_t a0 = x0 * c;
+  // element i of the block's rows sits at row i / c: walk (row, class) pairs
+  // incrementally instead of dividing per element
+  {
+    int r = threadIdx.x / c, j = threadIdx.x - (threadIdx.x / c) * c;
+    const int dr = 256 / c, dj = 256 - dr * c;
+    for (int i = threadIdx.x; i < nr * c; i += 256) {
+      rows[r * cp + j] = acc_load<AT>(m.accum, a0 + i);
+      r += dr;
+      j += dj;
+      if (j >= c) { j -= c; ++r; }
+    }
   }
   __syncthreads();
   for (int r = threadIdx.x; r < nr; r += 256) {
@@ -258,9 +268,13 @@ __global__ __launch_bounds__(256) void k_finalize(MeshDev m, void* __restrict__ 
   }
   if (!out) return;
   __syncthreads();
+  int r = threadIdx.x / c, j = threadIdx.x - (threadIdx.x / c) * c;
+  const int dr = 256 / c, dj = 256 - dr * c;
   for (int i = threadIdx.x; i < nr * c; i += 256) {
-    const int r = i / c, j = i - r * c;
     store_tex<OUT>(out, x0 * c + i, rows[r * cp + j]);
+    r += dr;
+    j += dj;
+    if (j >= c) { j -= c; ++r; }
   }
 }
 
@@ -270,23 +284,49 @@ hipError_t launch_finalize(const MeshDev& m, void* tex_out, int tex_dtype, uint8
   const int R = m.c <= 64 ? 192 : 32;
   const size_t lds = (size_t)R * cp * sizeof(float);
   dim3 g((unsigned)((m.n_texels + R - 1) / R));
-#define LF_FIN(O, A) k_finalize<O, A><<<g, 256, lds, s>>>(m, tex_out, labels, R)
-  const bool mul = m.aggregator == 1;
-  if (tex_dtype == 1) { if (mul) LF_FIN(1, 1); else LF_FIN(1, 0); }
-  else if (tex_dtype == 2) { if (mul) LF_FIN(2, 1); else LF_FIN(2, 0); }
-  else { if (mul) LF_FIN(0, 1); else LF_FIN(0, 0); }
+#define LF_FIN(O, A, T) k_finalize<O, A, T><<<g, 256, lds, s>>>(m, tex_out, labels, R)
+#define LF_FIN2(O)                                              \
+  do {                                                          \
+    if (m.aggregator == 1) LF_FIN(O, 1, 0);                     \
+    else if (m.accum_dtype == 1) LF_FIN(O, 0, 1);               \
+    else if (m.accum_dtype == 2) LF_FIN(O, 0, 2);               \
+    else LF_FIN(O, 0, 0);                                       \
+  } while (0)
+  if (tex_dtype == 1) LF_FIN2(1);
+  else if (tex_dtype == 2) LF_FIN2(2);
+  else LF_FIN2(0);
+#undef LF_FIN2
 #undef LF_FIN
   return hipGetLastError();
 }
 
-// ---- render-back ------------------------------------------------------------
+// ---- render-back: 8 pixels per thread (two 16-byte loads of rows) ----------
 __global__ __launch_bounds__(256) void k_render(const int32_t* __restrict__ l, const uint8_t* __restrict__ valid,
                                                 const uint8_t* __restrict__ labels, int64_t npx,
                                                 uint8_t* __restrict__ out) {
-  const int64_t i = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4;
+  const int64_t i = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 8;
   if (i >= npx) return;
+  if (i + 8 <= npx && (reinterpret_cast<uintptr_t>(l + i) & 15) == 0 && (reinterpret_cast<uintptr_t>(out + i) & 7) == 0) {
+    const int4 a = *reinterpret_cast<const int4*>(l + i);
+    const int4 b = *reinterpret_cast<const int4*>(l + i + 4);
+    const int li[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+    uint64_t vv = ~0ull;
+    if (valid) {
+      vv = 0;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
+      for (int k = 0; k < 8; ++k) vv |= (uint64_t)(valid[i + k] ? 0xffu : 0u) << (8 * k);
+    }
+    uint64_t o = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const bool ok = li[k] >= 0 && ((vv >> (8 * k)) & 0xffu);
+      const uint64_t lab = ok ? labels[li[k]] : 255u;
+      o |= lab << (8 * k);
+    }
+    *reinterpret_cast<uint64_t*>(out + i) = o;
+    return;
+  }
+  for (int k = 0; k < 8; ++k) {
     const int64_t p = i + k;
     if (p < npx) {
       const int32_t li = l[p];
@@ -298,7 +338,7 @@ __global__ __launch_bounds__(256) void k_render(const int32_t* __restrict__ l, c
 hipError_t launch_render(const int32_t* l, const uint8_t* valid, const uint8_t* labels, int64_t npx, uint8_t* out,
                          hipStream_t s) {
   if (npx <= 0) return hipSuccess;
-  k_render<<<dim3((unsigned)((npx + 1023) / 1024)), 256, 0, s>>>(l, valid, labels, npx, out);
+  k_render<<<dim3((unsigned)((npx + 2047) / 2048)), 256, 0, s>>>(l, valid, labels, npx, out);
   return hipGetLastError();
 }
 

@@ -75,12 +75,14 @@ hipError_t launch_scatter_atomic(const MeshDev& m, const ProbIn& in, int f_first
 hipError_t launch_clear_counts(const int32_t* l, const uint8_t* valid, int nf, int H, int W, int32_t* cnt,
                                int64_t cnt_stride, hipStream_t s);
 hipError_t launch_finalize(const MeshDev& m, void* tex_out, int tex_dtype, uint8_t* labels, hipStream_t s);
-hipError_t launch_seg_scan(const int32_t* seg, int64_t n, int32_t* sums, int32_t* start, hipStream_t s);
+hipError_t launch_seg_scan(const int32_t* seg, int64_t n, int32_t* sums, int32_t* start, int32_t* rows,
+                           int32_t* nrows, hipStream_t s);
 hipError_t launch_seg_fill(const ProbIn& in, int f_first, int nf, int H, int W, const int32_t* l, const int32_t* rank,
                            const int32_t* start, uint32_t* ent_pix, float* ent_w, float* ent_s, int weighting,
                            const int32_t* cnt, int64_t cnt_stride, const float* wpix, hipStream_t s);
 hipError_t launch_seg_gather(const MeshDev& m, const ProbIn& in, int f_first, int H, int W, const int32_t* start,
-                             const uint32_t* ent_pix, const float* ent_w, const float* ent_s, hipStream_t s);
+                             const int32_t* rows, const int32_t* nrows, const uint32_t* ent_pix, const float* ent_w,
+                             const float* ent_s, hipStream_t s);
 hipError_t launch_render(const int32_t* l, const uint8_t* valid, const uint8_t* labels, int64_t npx,
                          uint8_t* out, hipStream_t s);
 

@@ -28,7 +28,6 @@ namespace lf {
 
 namespace {
 
-constexpr int kSmallPx = 48;   // pixel boxes up to this size are rasterized by one thread
 constexpr int TS = kTileSize;
 
 // Snapped screen polygon of one triangle in one frame.
@@ -275,18 +274,22 @@ __device__ __forceinline__ void emit_lds(const TileCtx& c, const RayK& rk, int x
   atomicMin(c.key + (y - c.ty0) * TS + (x - c.tx0), k);
 }
 
-// One thread rasterizes one sub-triangle over a small pixel box.
-__device__ __forceinline__ void raster_thread(const TileCtx& c, const RayK& rk, uint32_t tri, const Edge3& e, int x0,
-                                              int x1, int y0, int y1) {
+// One thread rasterizes one sub-triangle over a small pixel box, stepping
+// the three edge functions incrementally.  When every coordinate difference
+// of the snapped triangle is below 2^14 (64 px) all edge values fit in int32
+// exactly, so the narrower arithmetic gives the same decisions.
+template <typename T>
+__device__ __forceinline__ void raster_thread_t(const TileCtx& c, const RayK& rk, uint32_t tri, const Edge3& e, int x0,
+                                                int x1, int y0, int y1) {
   const int px0 = 256 * x0 + 128, py0 = 256 * y0 + 128;
-  long long r01 = efn(e.x0, e.y0, e.x1, e.y1, px0, py0) - e.b01;
-  long long r12 = efn(e.x1, e.y1, e.x2, e.y2, px0, py0) - e.b12;
-  long long r20 = efn(e.x2, e.y2, e.x0, e.y0, px0, py0) - e.b20;
-  const long long sx01 = -256ll * (e.y1 - e.y0), sy01 = 256ll * (e.x1 - e.x0);
-  const long long sx12 = -256ll * (e.y2 - e.y1), sy12 = 256ll * (e.x2 - e.x1);
-  const long long sx20 = -256ll * (e.y0 - e.y2), sy20 = 256ll * (e.x0 - e.x2);
+  T r01 = (T)(e.x1 - e.x0) * (T)(py0 - e.y0) - (T)(e.y1 - e.y0) * (T)(px0 - e.x0) - (T)e.b01;
+  T r12 = (T)(e.x2 - e.x1) * (T)(py0 - e.y1) - (T)(e.y2 - e.y1) * (T)(px0 - e.x1) - (T)e.b12;
+  T r20 = (T)(e.x0 - e.x2) * (T)(py0 - e.y2) - (T)(e.y0 - e.y2) * (T)(px0 - e.x2) - (T)e.b20;
+  const T sx01 = (T)-256 * (T)(e.y1 - e.y0), sy01 = (T)256 * (T)(e.x1 - e.x0);
+  const T sx12 = (T)-256 * (T)(e.y2 - e.y1), sy12 = (T)256 * (T)(e.x2 - e.x1);
+  const T sx20 = (T)-256 * (T)(e.y0 - e.y2), sy20 = (T)256 * (T)(e.x0 - e.x2);
   for (int y = y0; y <= y1; ++y) {
-    long long a = r01, b = r12, d = r20;
+    T a = r01, b = r12, d = r20;
     for (int x = x0; x <= x1; ++x) {
       if ((a | b | d) >= 0) emit_lds(c, rk, x, y, tri);
       a += sx01; b += sx12; d += sx20;
@@ -294,6 +297,16 @@ __device__ __forceinline__ void raster_thread(const TileCtx& c, const RayK& rk, 
     r01 += sy01; r12 += sy12; r20 += sy20;
   }
 }
+
+__device__ __forceinline__ void raster_thread(const TileCtx& c, const RayK& rk, uint32_t tri, const Edge3& e, int x0,
+                                              int x1, int y0, int y1) {
+  const int ex = max(max(e.x0, e.x1), e.x2) - min(min(e.x0, e.x1), e.x2);
+  const int ey = max(max(e.y0, e.y1), e.y2) - min(min(e.y0, e.y1), e.y2);
+  if (ex < 16384 && ey < 16384) raster_thread_t<int>(c, rk, tri, e, x0, x1, y0, y1);
+  else raster_thread_t<long long>(c, rk, tri, e, x0, x1, y0, y1);
+}
+
+constexpr int kSmallPx = 48;   // pixel boxes up to this size are rasterized by one thread
 
 // Rasterize the triangle this lane holds (`s`, restricted to the pixel box
 // x0..x1 x y0..y1 of the tile); large boxes are done by the whole wave.
@@ -397,33 +410,70 @@ __global__ __launch_bounds__(256) void k_tile_raster(MeshDev m, const float* __r
   }
   __syncthreads();
 
-  // ---- resolve every pixel of the tile ----
-  for (int i = threadIdx.x; i < TS * TS; i += 256) {
+  // ---- resolve every pixel of the tile: 4 pixels per thread, each phase
+  // issued for all 4 before the next so the memory round trips overlap ----
+  constexpr int PPT = TS * TS / 256;
+  int32_t tri[PPT], l[PPT];
+  float z[PPT];
+  int64_t pix[PPT];
+  bool in[PPT], use[PPT];
+  int fi[PPT][3];
+#pragma unroll
+  for (int r = 0; r < PPT; ++r) {
+    const int i = threadIdx.x + 256 * r;
     const int x = tx0 + (i % TS), y = ty0 + (i / TS);
-    if (x > tx1 || y > ty1) continue;
+    in[r] = x <= tx1 && y <= ty1;
+    pix[r] = (int64_t)fb * HW + (int64_t)y * W + x;
     const unsigned long long k = key[i];
-    const int64_t pix = (int64_t)fb * HW + (int64_t)y * W + x;
-    int32_t l = -1, tri = -1;
-    float z = __builtin_nanf("");
-    if (k != ~0ull) {
-      tri = (int32_t)(uint32_t)(k & 0xffffffffull);
-      V3 A, B, C;
-      load_tri(m, cam, tri, A, B, C);
-      const RayK rk = ray_consts(A, B, C);
+    tri[r] = (in[r] && k != ~0ull) ? (int32_t)(uint32_t)(k & 0xffffffffull) : -1;
+    l[r] = -1;
+    z[r] = __builtin_nanf("");
+  }
+#pragma unroll
+  for (int r = 0; r < PPT; ++r) {
+    if (tri[r] >= 0) {
+      fi[r][0] = m.faces_uv[3 * (int64_t)tri[r]];
+      fi[r][1] = m.faces_uv[3 * (int64_t)tri[r] + 1];
+      fi[r][2] = m.faces_uv[3 * (int64_t)tri[r] + 2];
+    }
+    use[r] = tri[r] >= 0 && (!out.valid || out.valid[pix[r]]);
+  }
+#pragma unroll
+  for (int r = 0; r < PPT; ++r) {
+    if (tri[r] >= 0) {
+      const int i = threadIdx.x + 256 * r;
+      const float* q0 = m.verts + 3 * (int64_t)fi[r][0];
+      const float* q1 = m.verts + 3 * (int64_t)fi[r][1];
+      const float* q2 = m.verts + 3 * (int64_t)fi[r][2];
+      const RayK rk = ray_consts(to_cam(cam, q0[0], q0[1], q0[2]), to_cam(cam, q1[0], q1[1], q1[2]),
+                                 to_cam(cam, q2[0], q2[1], q2[2]));
       const float rx = rxs[i % TS], ry = rys[i / TS];
       const float den = rdot(rx, ry, rk.n);
-      z = rk.d / den;
+      z[r] = rk.d / den;
       const float u = rdot(rx, ry, rk.nu) / den;
       const float v = rdot(rx, ry, rk.nv) / den;
-      l = (int32_t)(row_offset(m, tri) + texel_id(tri_s(m, tri), m.split, u, v));
-      if (!out.valid || out.valid[pix]) {
-        if (out.cnt) atomicAdd(out.cnt + (int64_t)fb * out.cnt_stride + l, 1);
-        if (out.seg) out.rank[pix] = atomicAdd(out.seg + l, 1);
-      }
+      l[r] = (int32_t)(row_offset(m, tri[r]) + texel_id(tri_s(m, tri[r]), m.split, u, v));
     }
-    if (out.l) out.l[pix] = l;
-    if (out.tri) out.tri[pix] = tri;
-    if (out.z) out.z[pix] = z;
+  }
+  if (out.cnt) {
+#pragma unroll
+    for (int r = 0; r < PPT; ++r)
+      if (use[r]) atomicAdd(out.cnt + (int64_t)fb * out.cnt_stride + l[r], 1);
+  }
+  if (out.seg) {
+    int rk[PPT];
+#pragma unroll
+    for (int r = 0; r < PPT; ++r) rk[r] = use[r] ? atomicAdd(out.seg + l[r], 1) : 0;
+#pragma unroll
+    for (int r = 0; r < PPT; ++r)
+      if (use[r]) out.rank[pix[r]] = rk[r];
+  }
+#pragma unroll
+  for (int r = 0; r < PPT; ++r) {
+    if (!in[r]) continue;
+    if (out.l) out.l[pix[r]] = l[r];
+    if (out.tri) out.tri[pix[r]] = tri[r];
+    if (out.z) out.z[pix[r]] = z[r];
   }
 }
 
@@ -438,7 +488,7 @@ hipError_t launch_render_batch(const MeshDev& m, const float* cams, int nb, int 
   if (m.n_clusters > 0)
     k_cull_clusters<<<dim3((unsigned)((m.n_clusters + 255) / 256), (unsigned)nb), 256, 0, s>>>(m, cams, H, W, ws.vis,
                                                                                                ws.vis_n);
-  const unsigned gb = (unsigned)std::min<int64_t>((m.n_clusters + 3) / 4 + 1, 1024);
+  const unsigned gb = (unsigned)std::min<int64_t>((m.n_clusters + 3) / 4 + 1, 256);
   k_bin<false><<<dim3(gb, (unsigned)nb), 256, 0, s>>>(m, cams, H, W, ws.vis, ws.vis_n, ws.tcnt, ws.toff, ws.tlist,
                                                       ws.list_cap);
   k_tile_scan<<<dim3((unsigned)nb), 1024, 0, s>>>(ws.tcnt, ntiles, ws.toff, ws.list_cap, ws.over);

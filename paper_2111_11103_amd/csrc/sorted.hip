@@ -16,6 +16,7 @@
 // batch instead of once per pixel.
 #include <algorithm>
 
+#include "accum.h"
 #include "internal.h"
 #include "spec.h"
 
@@ -69,63 +70,92 @@ __global__ __launch_bounds__(1024) void k_seg_scan_sums(int32_t* __restrict__ su
   if (threadIdx.x == 0) sums[nblk] = carry;
 }
 
+// Also appends every row with observations to a compact list (one global
+// atomic per block) so the gather visits only touched rows.
 __global__ __launch_bounds__(256) void k_seg_scan(const int32_t* __restrict__ cnt, int64_t n,
-                                                  const int32_t* __restrict__ sums, int32_t* __restrict__ start) {
+                                                  const int32_t* __restrict__ sums, int32_t* __restrict__ start,
+                                                  int32_t* __restrict__ rows, int32_t* __restrict__ nrows) {
   __shared__ int part[256];
+  __shared__ int zpart[256];
+  __shared__ int zbase;
   constexpr int per = kSegChunk / 256;
   const int64_t base = (int64_t)blockIdx.x * kSegChunk + (int64_t)threadIdx.x * per;
   int loc[per];
   int acc = 0;
+  int nz = 0;
 #pragma unroll
   for (int i = 0; i < per; ++i) {
     const int64_t r = base + i;
     const int v = r < n ? cnt[r] : 0;
     loc[i] = acc;
     acc += v;
+    nz += v > 0;
   }
   part[threadIdx.x] = acc;
+  zpart[threadIdx.x] = nz;
   __syncthreads();
   for (int d = 1; d < 256; d <<= 1) {
     const int a = threadIdx.x >= d ? part[threadIdx.x - d] : 0;
+    const int b = threadIdx.x >= d ? zpart[threadIdx.x - d] : 0;
     __syncthreads();
     part[threadIdx.x] += a;
+    zpart[threadIdx.x] += b;
     __syncthreads();
   }
+  if (threadIdx.x == 255) zbase = atomicAdd(nrows, zpart[255]);
+  __syncthreads();
   const int pre = sums[blockIdx.x] + part[threadIdx.x] - acc;
+  int zpos = zbase + zpart[threadIdx.x] - nz;
 #pragma unroll
   for (int i = 0; i < per; ++i) {
     const int64_t r = base + i;
-    if (r < n) start[r] = pre + loc[i];
+    if (r < n) {
+      start[r] = pre + loc[i];
+      const int v = (i + 1 < per ? loc[i + 1] : acc) - loc[i];
+      if (v > 0) rows[zpos++] = (int32_t)r;
+    }
   }
   if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) start[n] = sums[gridDim.x];
 }
 
 // ---- fill ------------------------------------------------------------------------
+// 4 pixels per thread; every phase is issued for all 4 before the next so
+// the dependent loads (row, then its segment start) overlap.
 __global__ __launch_bounds__(256) void k_seg_fill(ProbIn in, int f_first, int H, int W, const int32_t* __restrict__ lbuf,
                                                   const int32_t* __restrict__ rank, const int32_t* __restrict__ start,
                                                   uint32_t* __restrict__ ent_pix, float* __restrict__ ent_w,
                                                   float* __restrict__ ent_s, int weighting,
                                                   const int32_t* __restrict__ cnt, int64_t cnt_stride,
                                                   const float* __restrict__ wpix) {
+  constexpr int P = 4;
   const int fb = blockIdx.y;
   const int64_t HW = (int64_t)H * W;
-  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (p >= HW) return;
-  const int64_t pi = (int64_t)fb * HW + p;
-  const int l = lbuf[pi];
-  if (l < 0) return;
-  const int64_t gi = (int64_t)(f_first + fb) * HW + p;
-  if (in.valid && !in.valid[gi]) return;
-  const int pos = start[l] + rank[pi];
-  const int y = (int)(p / W), x = (int)(p - (int64_t)y * W);
-  ent_pix[pos] = (uint32_t)((int64_t)fb * in.sf + (int64_t)y * in.sy + (int64_t)x * in.sx);
-  if (ent_w) {
-    float w = 1.0f;
-    if (weighting == 1) w = 1.0f / (float)cnt[(int64_t)fb * cnt_stride + l];
-    else if (weighting == 2) w = wpix[pi];
-    ent_w[pos] = w;
+  int l[P], st[P];
+  int64_t p[P];
+  bool ok[P];
+#pragma unroll
+  for (int k = 0; k < P; ++k) {
+    p[k] = ((int64_t)blockIdx.x * P + k) * 256 + threadIdx.x;
+    ok[k] = p[k] < HW;
+    l[k] = ok[k] ? lbuf[(int64_t)fb * HW + p[k]] : -1;
+    if (l[k] >= 0 && in.valid && !in.valid[(int64_t)(f_first + fb) * HW + p[k]]) l[k] = -1;
   }
-  if (ent_s) ent_s[pos] = in.scale[gi];
+#pragma unroll
+  for (int k = 0; k < P; ++k) st[k] = l[k] >= 0 ? start[l[k]] + rank[(int64_t)fb * HW + p[k]] : 0;
+#pragma unroll
+  for (int k = 0; k < P; ++k) {
+    if (l[k] < 0) continue;
+    const int pos = st[k];
+    const int y = (int)(p[k] / W), x = (int)(p[k] - (int64_t)y * W);
+    ent_pix[pos] = (uint32_t)((int64_t)fb * in.sf + (int64_t)y * in.sy + (int64_t)x * in.sx);
+    if (ent_w) {
+      float w = 1.0f;
+      if (weighting == 1) w = 1.0f / (float)cnt[(int64_t)fb * cnt_stride + l[k]];
+      else if (weighting == 2) w = wpix[(int64_t)fb * HW + p[k]];
+      ent_w[pos] = w;
+    }
+    if (ent_s) ent_s[pos] = in.scale[(int64_t)(f_first + fb) * HW + p[k]];
+  }
 }
 
 // ---- gather --------------------------------------------------------------------------
@@ -169,7 +199,7 @@ struct PixDecode {
 };
 
 // Lanes = classes (any stride, any c): one wave per 64 consecutive rows.
-template <int NCH, int DT, int AGG>
+template <int NCH, int DT, int AGG, int AT>
 __global__ __launch_bounds__(256) void k_seg_gather(MeshDev m, ProbIn in, PixDecode dec, const int32_t* __restrict__ start,
                                                     const uint32_t* __restrict__ ent_pix,
                                                     const float* __restrict__ ent_w, const float* __restrict__ ent_s) {
@@ -177,7 +207,6 @@ __global__ __launch_bounds__(256) void k_seg_gather(MeshDev m, ProbIn in, PixDec
   const int64_t x0 = (((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6) * 64;
   if (x0 >= m.n_texels) return;
   const int c = m.c;
-  float* __restrict__ A = reinterpret_cast<float*>(m.accum);
   const int64_t xl = x0 + lane;
   int s = 0, e = 0;
   if (xl < m.n_texels) {
@@ -195,7 +224,7 @@ __global__ __launch_bounds__(256) void k_seg_gather(MeshDev m, ProbIn in, PixDec
 #pragma unroll
     for (int ch = 0; ch < NCH; ++ch) {
       const int j = lane + 64 * ch;
-      old[ch] = j < c ? A[x * c + j] : 0.0f;
+      old[ch] = j < c ? acc_load<AT>(m.accum, x * c + j) : 0.0f;
     }
     float acc[NCH];
 #pragma unroll
@@ -238,89 +267,116 @@ __global__ __launch_bounds__(256) void k_seg_gather(MeshDev m, ProbIn in, PixDec
 #pragma unroll
     for (int ch = 0; ch < NCH; ++ch) {
       const int j = lane + 64 * ch;
-      if (j < c) A[x * c + j] = old[ch] + acc[ch];
+      if (j < c) acc_store<AT>(m.accum, x * c + j, old[ch] + acc[ch]);
     }
     if (m.wsum && lane == 0) m.wsum[x] += wsum;
   }
 }
 
 // 16 lanes per row (classes contiguous, c <= 64, c % 4 == 0): lane i of a
-// group owns classes 4i..4i+3 of one texel row, reads them as one float4 (FP32)
-// or one 32-bit word of four codes (E4M3) per observation, so one wave
-// instruction fetches four contiguous class vectors; four observations are
-// kept in flight per lane.  The group then updates its row once.
-constexpr int kRowsPerGroup = 4;   // consecutive rows walked by one 16-lane group
-
-template <int DT, int AGG>
+// group owns classes 4i..4i+3 of one texel row and reads them as one float4
+// (FP32) or one 32-bit word of four codes (E4M3) per observation, so one wave
+// instruction fetches four contiguous class vectors.  The group loads 16
+// observation offsets at once (one per lane, shuffled out) and keeps 8
+// observations in flight.  Groups walk the compact list of touched rows.
+template <int DT, int AGG, int AT>
 __global__ __launch_bounds__(256) void k_seg_gather16(MeshDev m, ProbIn in, PixDecode dec,
                                                       const int32_t* __restrict__ start,
+                                                      const int32_t* __restrict__ rows,
+                                                      const int32_t* __restrict__ nrows,
                                                       const uint32_t* __restrict__ ent,
                                                       const float* __restrict__ ent_w, const float* __restrict__ ent_s) {
-  constexpr int U = 4;
+  constexpr int U = 8;
   const int gl = threadIdx.x & 15;                       // lane in group = class chunk
-  const int64_t grp = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 4;
+  const int64_t g0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 4;
+  const int64_t ng = ((int64_t)gridDim.x * 256) >> 4;
   const int c = m.c;
   const int nv = c >> 2;
   const bool act = gl < nv;
-  float* __restrict__ A = reinterpret_cast<float*>(m.accum);
-  for (int r = 0; r < kRowsPerGroup; ++r) {
-    const int64_t x = grp * kRowsPerGroup + r;
-    if (x >= m.n_texels) break;
+  const int nr = *nrows;
+  for (int64_t g = g0; g < nr; g += ng) {
+    const int64_t x = rows[g];
     const int s0 = start[x], s1 = start[x + 1];
-    if (s0 == s1) continue;
     float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
     float4 old = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (act) old = *reinterpret_cast<const float4*>(A + x * c + 4 * gl);
-    float wsum = 0.0f;
-    for (int k0 = s0; k0 < s1; k0 += U) {
-      float4 v[U];
-      float w[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int k = k0 + u;
-        const bool ok = k < s1;
-        const int kk = ok ? k : k0;
-        const int64_t off = dec(in, ent[kk]);
-        w[u] = ok ? (ent_w ? ent_w[kk] : 1.0f) : 0.0f;
-        v[u] = make_float4(1.f, 1.f, 1.f, 1.f);
-        if (act) {
-          if constexpr (DT == 0) {
-            v[u] = *reinterpret_cast<const float4*>(reinterpret_cast<const float*>(in.p) + off + 4 * gl);
-          } else {
-            const uint32_t q = *reinterpret_cast<const uint32_t*>(reinterpret_cast<const uint8_t*>(in.p) + off + 4 * gl);
-            const float sc = ent_s[kk];
-            v[u] = make_float4(e4m3_dec(q & 0xffu) * sc, e4m3_dec((q >> 8) & 0xffu) * sc,
-                               e4m3_dec((q >> 16) & 0xffu) * sc, e4m3_dec(q >> 24) * sc);
-          }
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        float4 t = v[u];
-        if constexpr (AGG == 1) {
-          t = make_float4(logf(t.x), logf(t.y), logf(t.z), logf(t.w));
-        } else if constexpr (AGG == 2) {
-          float mx = act ? fmaxf(fmaxf(t.x, t.y), fmaxf(t.z, t.w)) : -__builtin_inff();
-#pragma unroll
-          for (int o = 8; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o, 16));
-          t = make_float4(t.x == mx ? t.x : 0.f, t.y == mx ? t.y : 0.f, t.z == mx ? t.z : 0.f, t.w == mx ? t.w : 0.f);
-        }
-        acc.x += w[u] * t.x;
-        acc.y += w[u] * t.y;
-        acc.z += w[u] * t.z;
-        acc.w += w[u] * t.w;
-        wsum += w[u];
+    if (act) {
+      if constexpr (AT == 0) {
+        old = *reinterpret_cast<const float4*>(reinterpret_cast<const float*>(m.accum) + x * c + 4 * gl);
+      } else {
+        const int64_t i0 = x * c + 4 * gl;
+        old = make_float4(acc_load<AT>(m.accum, i0), acc_load<AT>(m.accum, i0 + 1), acc_load<AT>(m.accum, i0 + 2),
+                          acc_load<AT>(m.accum, i0 + 3));
       }
     }
-    if (act)
-      *reinterpret_cast<float4*>(A + x * c + 4 * gl) =
-          make_float4(old.x + acc.x, old.y + acc.y, old.z + acc.z, old.w + acc.w);
+    float wsum = 0.0f;
+    for (int k0 = s0; k0 < s1; k0 += 16) {
+      const int kk = k0 + gl;
+      const bool okl = kk < s1;
+      const uint32_t my_e = okl ? ent[kk] : 0u;
+      const float my_w = okl ? (ent_w ? ent_w[kk] : 1.0f) : 0.0f;
+      const float my_s = (DT == 3 && okl) ? ent_s[kk] : 1.0f;
+      const int cnt = min(16, s1 - k0);
+      for (int h = 0; h < cnt; h += U) {
+        float4 v[U];
+        float w[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int src = h + u;
+          const uint32_t e = __shfl(my_e, src, 16);
+          w[u] = __shfl(my_w, src, 16);            // 0 past the segment end
+          const float sc = __shfl(my_s, src, 16);
+          const int64_t off = dec(in, e);
+          v[u] = make_float4(1.f, 1.f, 1.f, 1.f);
+          if (act && src < cnt) {
+            if constexpr (DT == 0) {
+              v[u] = *reinterpret_cast<const float4*>(reinterpret_cast<const float*>(in.p) + off + 4 * gl);
+            } else {
+              const uint32_t q =
+                  *reinterpret_cast<const uint32_t*>(reinterpret_cast<const uint8_t*>(in.p) + off + 4 * gl);
+              v[u] = make_float4(e4m3_dec(q & 0xffu) * sc, e4m3_dec((q >> 8) & 0xffu) * sc,
+                                 e4m3_dec((q >> 16) & 0xffu) * sc, e4m3_dec(q >> 24) * sc);
+            }
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          float4 t = v[u];
+          if constexpr (AGG == 1) {
+            t = make_float4(logf(t.x), logf(t.y), logf(t.z), logf(t.w));
+          } else if constexpr (AGG == 2) {
+            float mx = act ? fmaxf(fmaxf(t.x, t.y), fmaxf(t.z, t.w)) : -__builtin_inff();
+#pragma unroll
+            for (int o = 8; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o, 16));
+            t = make_float4(t.x == mx ? t.x : 0.f, t.y == mx ? t.y : 0.f, t.z == mx ? t.z : 0.f,
+                            t.w == mx ? t.w : 0.f);
+          }
+          acc.x += w[u] * t.x;
+          acc.y += w[u] * t.y;
+          acc.z += w[u] * t.z;
+          acc.w += w[u] * t.w;
+          wsum += w[u];
+        }
+      }
+    }
+    if (act) {
+      const float4 nv4 = make_float4(old.x + acc.x, old.y + acc.y, old.z + acc.z, old.w + acc.w);
+      if constexpr (AT == 0) {
+        *reinterpret_cast<float4*>(reinterpret_cast<float*>(m.accum) + x * c + 4 * gl) = nv4;
+      } else {
+        const int64_t i0 = x * c + 4 * gl;
+        acc_store<AT>(m.accum, i0, nv4.x);
+        acc_store<AT>(m.accum, i0 + 1, nv4.y);
+        acc_store<AT>(m.accum, i0 + 2, nv4.z);
+        acc_store<AT>(m.accum, i0 + 3, nv4.w);
+      }
+    }
     if (m.wsum && gl == 0) m.wsum[x] += wsum;
   }
 }
 
 hipError_t launch_seg_gather(const MeshDev& m, const ProbIn& in, int f_first, int H, int W, const int32_t* start,
-                             const uint32_t* ent, const float* ent_w, const float* ent_s, hipStream_t s) {
+                             const int32_t* rows, const int32_t* nrows, const uint32_t* ent, const float* ent_w,
+                             const float* ent_s, hipStream_t s) {
   if (m.n_texels == 0) return hipSuccess;
   (void)H;
   (void)W;
@@ -333,25 +389,32 @@ hipError_t launch_seg_gather(const MeshDev& m, const ProbIn& in, int f_first, in
                        ((in.sy * esz) % chunk) == 0 && ((in.sx * esz) % chunk) == 0 &&
                        (reinterpret_cast<uintptr_t>(m.accum) % 16) == 0;
   if (grouped) {
-    const int64_t groups = (m.n_texels + kRowsPerGroup - 1) / kRowsPerGroup;
+    // enough resident groups to cover the machine; each walks the row list
+    const int64_t groups = std::min<int64_t>(m.n_texels, (int64_t)256 * 8 * 16 * 4);
     dim3 g((unsigned)((groups * 16 + 255) / 256));
-#define LF_R(DT, AGG) k_seg_gather16<DT, AGG><<<g, 256, 0, s>>>(m, in, dec, start, ent, ent_w, ent_s)
-    if (in.dtype == 0) {
-      if (m.aggregator == 0) LF_R(0, 0); else if (m.aggregator == 1) LF_R(0, 1); else LF_R(0, 2);
-    } else {
-      if (m.aggregator == 0) LF_R(3, 0); else if (m.aggregator == 1) LF_R(3, 1); else LF_R(3, 2);
-    }
+#define LF_R(DT, AGG, AT) k_seg_gather16<DT, AGG, AT><<<g, 256, 0, s>>>(m, in, dec, start, rows, nrows, ent, ent_w, ent_s)
+#define LF_R2(DT)                                                                                            \
+  do {                                                                                                       \
+    if (m.aggregator == 1) LF_R(DT, 1, 0);                                                                   \
+    else if (m.accum_dtype == 1) { if (m.aggregator == 0) LF_R(DT, 0, 1); else LF_R(DT, 2, 1); }            \
+    else if (m.accum_dtype == 2) { if (m.aggregator == 0) LF_R(DT, 0, 2); else LF_R(DT, 2, 2); }            \
+    else { if (m.aggregator == 0) LF_R(DT, 0, 0); else LF_R(DT, 2, 0); }                                     \
+  } while (0)
+    if (in.dtype == 0) LF_R2(0);
+    else LF_R2(3);
+#undef LF_R2
 #undef LF_R
     return hipGetLastError();
   }
   const int64_t waves = (m.n_texels + 63) / 64;
   dim3 g((unsigned)((waves + 3) / 4));
-#define LF_G(NCH, DT, AGG) k_seg_gather<NCH, DT, AGG><<<g, 256, 0, s>>>(m, in, dec, start, ent, ent_w, ent_s)
-#define LF_G2(NCH, DT)                      \
-  do {                                      \
-    if (m.aggregator == 0) LF_G(NCH, DT, 0); \
-    else if (m.aggregator == 1) LF_G(NCH, DT, 1); \
-    else LF_G(NCH, DT, 2);                  \
+#define LF_G(NCH, DT, AGG, AT) k_seg_gather<NCH, DT, AGG, AT><<<g, 256, 0, s>>>(m, in, dec, start, ent, ent_w, ent_s)
+#define LF_G2(NCH, DT)                                                                                       \
+  do {                                                                                                       \
+    if (m.aggregator == 1) LF_G(NCH, DT, 1, 0);                                                              \
+    else if (m.accum_dtype == 1) { if (m.aggregator == 0) LF_G(NCH, DT, 0, 1); else LF_G(NCH, DT, 2, 1); }  \
+    else if (m.accum_dtype == 2) { if (m.aggregator == 0) LF_G(NCH, DT, 0, 2); else LF_G(NCH, DT, 2, 2); }  \
+    else { if (m.aggregator == 0) LF_G(NCH, DT, 0, 0); else LF_G(NCH, DT, 2, 0); }                          \
   } while (0)
   if (m.c <= 64) {
     if (in.dtype == 0) LF_G2(1, 0); else LF_G2(1, 3);
@@ -363,11 +426,12 @@ hipError_t launch_seg_gather(const MeshDev& m, const ProbIn& in, int f_first, in
   return hipGetLastError();
 }
 
-hipError_t launch_seg_scan(const int32_t* seg, int64_t n, int32_t* sums, int32_t* start, hipStream_t s) {
+hipError_t launch_seg_scan(const int32_t* seg, int64_t n, int32_t* sums, int32_t* start, int32_t* rows,
+                           int32_t* nrows, hipStream_t s) {
   const int64_t nblk = std::max<int64_t>((n + kSegChunk - 1) / kSegChunk, 1);
   k_seg_sums<<<dim3((unsigned)nblk), 256, 0, s>>>(seg, n, sums);
   k_seg_scan_sums<<<1, 1024, 0, s>>>(sums, nblk);
-  k_seg_scan<<<dim3((unsigned)nblk), 256, 0, s>>>(seg, n, sums, start);
+  k_seg_scan<<<dim3((unsigned)nblk), 256, 0, s>>>(seg, n, sums, start, rows, nrows);
   return hipGetLastError();
 }
 
@@ -376,7 +440,7 @@ hipError_t launch_seg_fill(const ProbIn& in, int f_first, int nf, int H, int W, 
                            const int32_t* cnt, int64_t cnt_stride, const float* wpix, hipStream_t s) {
   if (nf <= 0) return hipSuccess;
   const int64_t HW = (int64_t)H * W;
-  k_seg_fill<<<dim3((unsigned)((HW + 255) / 256), (unsigned)nf), 256, 0, s>>>(in, f_first, H, W, l, rank, start, ent_pix,
+  k_seg_fill<<<dim3((unsigned)((HW + 1023) / 1024), (unsigned)nf), 256, 0, s>>>(in, f_first, H, W, l, rank, start, ent_pix,
                                                                               ent_w, ent_s, weighting, cnt, cnt_stride,
                                                                               wpix);
   return hipGetLastError();

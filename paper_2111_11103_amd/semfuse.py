@@ -118,20 +118,20 @@ class Mesh:
 
     def __init__(self, vertices: torch.Tensor, faces: torch.Tensor, *, n_classes: int, s: int = 1,
                  scheme: int = SPLIT, aggregator: int = AGG_SUM, s_face: torch.Tensor | None = None,
-                 z_near: float = 0.05, keep_weights: bool = True):
+                 z_near: float = 0.05, keep_weights: bool = True, accum_dtype=torch.float32):
         _need_cuda(vertices, "vertices", torch.float32)
         _need_cuda(faces, "faces", torch.int32)
         vertices = vertices.contiguous()
         faces = faces.contiguous()
         self.device = vertices.device
         self.c = int(n_classes)
-        self.opts = _MeshOpts(scheme, s, n_classes, aggregator, F32, z_near)
+        self.opts = _MeshOpts(scheme, s, n_classes, aggregator, _TEX_DT[accum_dtype], z_near)
         hs = None if s_face is None else s_face.detach().cpu().to(torch.int32).numpy()
         self.n_texels, ws_bytes = mesh_sizes(vertices.shape[0], faces.shape[0], s, scheme, n_classes, aggregator,
                                              hs, z_near)
         self.vertices = vertices
         self.ws = torch.empty(max(ws_bytes, 256), dtype=torch.uint8, device=self.device)
-        self.accum = torch.empty((self.n_texels, self.c), dtype=torch.float32, device=self.device)
+        self.accum = torch.empty((self.n_texels, self.c), dtype=accum_dtype, device=self.device)
         self.wsum = torch.empty(self.n_texels, dtype=torch.float32, device=self.device) \
             if (keep_weights or aggregator == AGG_MUL) else None
         sf = None
