@@ -154,10 +154,72 @@ lf_status lf_rasterize(lf_mesh mesh, const float* d_cams, int32_t F, int32_t H, 
                        int32_t* d_tri, int32_t* d_l, float* d_z, void* d_ws, int64_t ws_bytes,
                        hipStream_t stream);
 
+/* ---- Learned per-observation weight ---------------------------------------
+ * Section 3.2.2 weights every observation k of a texel by w_k, with the two
+ * fixed choices w^(P) = 1 and w^(I) = 1/|K_i ∩ K_x|.  LF_W_LEARNED takes w_k
+ * from a small network on per-observation features phi_k (8 floats):
+ *   0 |cos| of the angle between the pixel ray and the triangle normal,
+ *   1 z / (1 + z) of the depth z,  2 normalised entropy -sum p ln p / ln c,
+ *   3 top-1 probability,  4 top-1 minus top-2,
+ *   5 min(1, 3 min(u, v, 1-u-v)) (closeness to the triangle's centroid),
+ *   6 min(2, ln n / ln 64), n = the frame's pixels on the same texel,
+ *   7 |(x + 1/2 - cx, y + 1/2 - cy)| / |(cx, cy)| (radial image distance).
+ * Network: h1 = relu(W1 q(phi) + b1), h2 = relu(W2 q(h1) + b2),
+ * w = sigmoid(w3 . h2 + b3); W1 64x8, W2 64x64, w3 64; q = round to bfloat16.
+ * Master parameters are binary32 in the order W1 (row-major [64][8]), b1,
+ * W2 ([64][64]), b2, w3, b3 (n_params floats); the packed form holds W1, W2,
+ * w3 in bfloat16 and the biases in binary32 (packed_bytes, 16-byte aligned).
+ * Training target: y_k = 1 when the observation's own argmax equals the
+ * label plain fusion gives its texel; loss = mean binary cross-entropy. */
+
+/* Number of master parameters and bytes of the packed form. */
+lf_status lf_mlp_sizes(int32_t* n_params, int64_t* packed_bytes);
+
+/* Pack binary32 master parameters d_params [n_params] into d_packed
+ * (bfloat16 weights, round to nearest even). */
+lf_status lf_mlp_pack(const float* d_params, void* d_packed, hipStream_t stream);
+
+/* Bind packed weights to a mesh for LF_W_LEARNED fusion (NULL unbinds).  The
+ * handle keeps the pointer: the caller keeps the buffer alive and may repack
+ * into it between calls. */
+lf_status lf_mlp_bind(lf_mesh mesh, const void* d_packed);
+
+/* w [n] = network output for features d_phi [n][8] (float32). */
+lf_status lf_mlp_forward(const void* d_packed, const float* d_phi, int64_t n, float* d_w,
+                         hipStream_t stream);
+
+/* Mean binary cross-entropy of the network on (d_phi [n][8], d_target [n]
+ * in {0, 1}) and its gradient with respect to every master parameter, in the
+ * master order, written to d_grad [n_params] (overwritten) and *d_loss
+ * (float, may be NULL).  The rounding q is passed straight through in the
+ * backward pass; products use the bfloat16 weights of d_packed. */
+lf_status lf_mlp_grad(const void* d_packed, const float* d_phi, const float* d_target, int64_t n,
+                      float* d_grad, float* d_loss, hipStream_t stream);
+
+/* One Adam step (Kingma & Ba) on n binary32 parameters with moments d_m,
+ * d_v (caller-owned, zero before step 1): step counts from 1. */
+lf_status lf_adam_step(float* d_params, float* d_m, float* d_v, const float* d_grad, int64_t n,
+                       float lr, float beta1, float beta2, float eps, int32_t step, hipStream_t stream);
+
+/* Features of every valid covered pixel of F frames (arguments as in
+ * lf_fuse_frames), appended in unspecified order:
+ *  d_phi [cap][8] features; d_target [cap] training targets against the
+ *  fused labels d_labels [n_texels] (both may be NULL together); d_pix [cap]
+ *  int32 pixel index f*H*W + y*W + x (or NULL; needs F*H*W < 2^31);
+ *  *d_count (uint64, device) = number of observations found, which may
+ *  exceed cap: only the first cap are written.
+ *  d_ws: workspace of lf_frame_ws_bytes(H, W, batch, LF_W_LEARNED,
+ *  LF_SCATTER_ATOMIC) for some batch >= 1. */
+lf_status lf_extract_features(lf_mesh mesh, const float* d_cams, int32_t F, int32_t H, int32_t W,
+                              const void* d_probs, int32_t prob_dtype, const int64_t* h_strides,
+                              const float* d_scale, const uint8_t* d_valid, const uint8_t* d_labels,
+                              float* d_phi, float* d_target, int32_t* d_pix, int64_t cap,
+                              uint64_t* d_count, void* d_ws, int64_t ws_bytes, hipStream_t stream);
+
 /* Per-stage kernel timing with HIP events recorded on the launch stream
  * around every kernel of a stage (instrumentation for roofline reports).
  * Stages: 0 ray tables + raster, 1 resolve, 2 scatter, 3 counts, 4 finalize,
- * 5 render, 6 accumulator reset, 7 learned-weight inference.
+ * 5 render, 6 accumulator reset, 7 learned-weight inference / feature extraction.
  * lf_profile_enable(mesh, 1) starts recording (clearing earlier records);
  * lf_profile_read waits for the recorded events and returns, per stage, the
  * summed milliseconds and the number of timed launches. */

@@ -45,6 +45,7 @@ struct lf_mesh_s {
   MeshDev d;
   lf_mesh_opts opts;
   Profiler prof;
+  const void* mlp = nullptr;   // bound packed weights of the learned weighting
 };
 
 namespace {
@@ -137,7 +138,7 @@ lf_status check_mesh(lf_mesh m) {
 }
 
 struct FrameLayout {
-  int64_t vis, vis_n, tcnt, toff, over, tlist, l, cnt, wpix, seg, rank, start, sums, rows, nrows, ent_off, ent_w,
+  int64_t vis, vis_n, tcnt, toff, over, tlist, l, cnt, geo, wpix, seg, rank, start, sums, rows, nrows, ent_off, ent_w,
       ent_s, total;
   int64_t list_cap, ntiles;
   bool sorted;
@@ -161,7 +162,8 @@ FrameLayout frame_layout(const MeshDev& m, int H, int W, int B, int weighting, i
   L.over = o; o += align256(B * 4);
   L.tlist = o; o += align256(B * L.list_cap * 4);
   L.l = o; o += align256(B * HW * 4);
-  L.cnt = o; if (weighting == LF_W_IMAGE) o += align256(B * m.n_texels * 4);
+  L.cnt = o; if (weighting == LF_W_IMAGE || weighting == LF_W_LEARNED) o += align256(B * m.n_texels * 4);
+  L.geo = o; if (weighting == LF_W_LEARNED) o += align256(B * HW * 16);
   L.wpix = o; if (weighting == LF_W_LEARNED) o += align256(B * HW * 4);
   L.seg = o; if (L.sorted) o += align256(m.n_texels * 4);
   L.rank = o; if (L.sorted) o += align256(B * HW * 4);
@@ -340,7 +342,8 @@ lf_status lf_fuse_frames(lf_mesh mesh, const float* d_cams, int32_t F, int32_t H
   if (!d_cams || !d_probs || !h_strides || !d_ws) return fail(LF_EINVAL, "NULL argument");
   if (prob_dtype != LF_F32 && prob_dtype != LF_FP8_E4M3) return fail(LF_EINVAL, "probabilities must be F32 or FP8_E4M3");
   if (prob_dtype == LF_FP8_E4M3 && !d_scale) return fail(LF_EINVAL, "FP8 input needs the per-pixel scale");
-  if (weighting < LF_W_PIXEL || weighting > LF_W_IMAGE) return fail(LF_EINVAL, "weighting %d not supported here", weighting);
+  if (weighting < LF_W_PIXEL || weighting > LF_W_LEARNED) return fail(LF_EINVAL, "unknown weighting %d", weighting);
+  if (weighting == LF_W_LEARNED && !mesh->mlp) return fail(LF_ESTATE, "learned weighting needs weights bound by lf_mlp_bind");
   if (scatter_mode < LF_SCATTER_AUTO || scatter_mode > LF_SCATTER_SORTED) return fail(LF_EINVAL, "bad scatter mode");
   for (int i = 0; i < 4; ++i)
     if (h_strides[i] < 0) return fail(LF_EINVAL, "negative stride");
@@ -356,7 +359,10 @@ lf_status lf_fuse_frames(lf_mesh mesh, const float* d_cams, int32_t F, int32_t H
   char* ws = reinterpret_cast<char*>(d_ws);
   const int64_t HW = (int64_t)H * W;
   ProbIn in{d_probs, d_scale, d_valid, h_strides[0], h_strides[1], h_strides[2], h_strides[3], prob_dtype};
-  int32_t* cnt = weighting == LF_W_IMAGE ? reinterpret_cast<int32_t*>(ws + L.cnt) : nullptr;
+  const bool learned = weighting == LF_W_LEARNED;
+  int32_t* cnt = weighting != LF_W_PIXEL ? reinterpret_cast<int32_t*>(ws + L.cnt) : nullptr;
+  float4* geo = learned ? reinterpret_cast<float4*>(ws + L.geo) : nullptr;
+  float* wpix = learned ? reinterpret_cast<float*>(ws + L.wpix) : nullptr;
   // the sorted path stores batch-relative element offsets in 32 bits
   const bool sorted = mode == LF_SCATTER_SORTED &&
                       ((int64_t)(B - 1) * h_strides[0] + (int64_t)(H - 1) * h_strides[2] +
@@ -370,8 +376,13 @@ lf_status lf_fuse_frames(lf_mesh mesh, const float* d_cams, int32_t F, int32_t H
     int32_t* lb = d_l_out ? d_l_out + (int64_t)f0 * HW : reinterpret_cast<int32_t*>(ws + L.l);
     const uint8_t* vb = d_valid ? d_valid + (int64_t)f0 * HW : nullptr;
     if (seg) LF_TRY(launch_zero(seg, d.n_texels * 4, stream), "clear segments");
-    RasterOut out{lb, nullptr, nullptr, vb, cnt, d.n_texels, seg, rank};
+    RasterOut out{lb, nullptr, nullptr, vb, cnt, d.n_texels, seg, rank, geo};
     if ((st = render_batch(mesh, d_cams, f0, nb, H, W, L, ws, out, stream)) != LF_OK) return st;
+    if (learned) {
+      StageTimer tm(mesh, 7, stream);
+      LF_TRY(launch_mlp_weights(mesh->mlp, in, f0, nb, H, W, d_cams, lb, geo, cnt, d.n_texels, d.c, wpix, stream),
+             "learned weights");
+    }
     if (sorted) {
       int32_t* start = reinterpret_cast<int32_t*>(ws + L.start);
       uint32_t* eo = reinterpret_cast<uint32_t*>(ws + L.ent_off);
@@ -383,7 +394,7 @@ lf_status lf_fuse_frames(lf_mesh mesh, const float* d_cams, int32_t F, int32_t H
         LF_TRY(launch_seg_scan(seg, d.n_texels, reinterpret_cast<int32_t*>(ws + L.sums), start,
                                reinterpret_cast<int32_t*>(ws + L.rows), reinterpret_cast<int32_t*>(ws + L.nrows),
                                stream), "segment scan");
-        LF_TRY(launch_seg_fill(in, f0, nb, H, W, lb, rank, start, eo, ew, es, weighting, cnt, d.n_texels, nullptr, stream),
+        LF_TRY(launch_seg_fill(in, f0, nb, H, W, lb, rank, start, eo, ew, es, weighting, cnt, d.n_texels, wpix, stream),
                "segment fill");
       }
       StageTimer tm(mesh, 2, stream);
@@ -391,7 +402,7 @@ lf_status lf_fuse_frames(lf_mesh mesh, const float* d_cams, int32_t F, int32_t H
                                reinterpret_cast<int32_t*>(ws + L.nrows), eo, ew, es, stream), "segment gather");
     } else {
       StageTimer tm(mesh, 2, stream);
-      LF_TRY(launch_scatter_atomic(d, in, f0, nb, H, W, lb, weighting, cnt, d.n_texels, nullptr, stream), "scatter");
+      LF_TRY(launch_scatter_atomic(d, in, f0, nb, H, W, lb, weighting, cnt, d.n_texels, wpix, stream), "scatter");
     }
     if (cnt) {
       StageTimer tm(mesh, 3, stream);
@@ -437,7 +448,7 @@ lf_status lf_render_labels(lf_mesh mesh, const float* d_cams, int32_t F, int32_t
   for (int f0 = 0; f0 < F; f0 += B) {
     const int nb = (F - f0) < B ? (F - f0) : B;
     int32_t* lb = reinterpret_cast<int32_t*>(ws + L.l);
-    RasterOut out{lb, nullptr, nullptr, nullptr, nullptr, 0, nullptr, nullptr};
+    RasterOut out{lb, nullptr, nullptr, nullptr, nullptr, 0, nullptr, nullptr, nullptr};
     if ((st = render_batch(mesh, d_cams, f0, nb, H, W, L, ws, out, stream)) != LF_OK) return st;
     StageTimer tm(mesh, 5, stream);
     LF_TRY(launch_render(lb, d_valid ? d_valid + (int64_t)f0 * HW : nullptr, d_labels, (int64_t)nb * HW,
@@ -465,7 +476,7 @@ lf_status lf_rasterize(lf_mesh mesh, const float* d_cams, int32_t F, int32_t H, 
     const int nb = (F - f0) < B ? (F - f0) : B;
     const int64_t o = (int64_t)f0 * HW;
     RasterOut out{d_l ? d_l + o : nullptr, d_tri ? d_tri + o : nullptr, d_z ? d_z + o : nullptr, nullptr, nullptr, 0,
-                  nullptr, nullptr};
+                  nullptr, nullptr, nullptr};
     if ((st = render_batch(mesh, d_cams, f0, nb, H, W, L, ws, out, stream)) != LF_OK) return st;
   }
   return LF_OK;
@@ -498,6 +509,116 @@ lf_status lf_profile_read(lf_mesh mesh, lf_profile* out) {
     }
     out->ms[k] = ms;
     out->launches[k] = (int64_t)(v.size() / 2);
+  }
+  return LF_OK;
+}
+
+// ---- learned per-observation weight --------------------------------------------
+
+lf_status lf_mlp_sizes(int32_t* n_params, int64_t* packed_bytes) {
+  g_err[0] = 0;
+  if (n_params) *n_params = mlp_nparam();
+  if (packed_bytes) *packed_bytes = mlp_packed_bytes();
+  return LF_OK;
+}
+
+lf_status lf_mlp_pack(const float* d_params, void* d_packed, hipStream_t stream) {
+  g_err[0] = 0;
+  if (!d_params || !d_packed) return fail(LF_EINVAL, "NULL argument");
+  if (reinterpret_cast<uintptr_t>(d_packed) & 15) return fail(LF_EINVAL, "packed weights must be 16-byte aligned");
+  LF_TRY(launch_mlp_pack(d_params, d_packed, stream), "pack");
+  return LF_OK;
+}
+
+lf_status lf_mlp_bind(lf_mesh mesh, const void* d_packed) {
+  g_err[0] = 0;
+  lf_status st = check_mesh(mesh);
+  if (st != LF_OK) return st;
+  if (d_packed && (reinterpret_cast<uintptr_t>(d_packed) & 15))
+    return fail(LF_EINVAL, "packed weights must be 16-byte aligned");
+  mesh->mlp = d_packed;
+  return LF_OK;
+}
+
+lf_status lf_mlp_forward(const void* d_packed, const float* d_phi, int64_t n, float* d_w, hipStream_t stream) {
+  g_err[0] = 0;
+  if (n < 0) return fail(LF_EINVAL, "negative count");
+  if (n == 0) return LF_OK;
+  if (!d_packed || !d_phi || !d_w) return fail(LF_EINVAL, "NULL argument");
+  if (n > ((int64_t)1 << 40)) return fail(LF_EINVAL, "too many observations");
+  LF_TRY(launch_mlp_forward(d_packed, d_phi, n, d_w, stream), "forward");
+  return LF_OK;
+}
+
+lf_status lf_mlp_grad(const void* d_packed, const float* d_phi, const float* d_target, int64_t n, float* d_grad,
+                      float* d_loss, hipStream_t stream) {
+  g_err[0] = 0;
+  if (n < 0) return fail(LF_EINVAL, "negative count");
+  if (!d_grad) return fail(LF_EINVAL, "NULL gradient buffer");
+  LF_TRY(launch_zero(d_grad, (int64_t)mlp_nparam() * 4, stream), "clear gradient");
+  if (d_loss) LF_TRY(launch_zero(d_loss, 4, stream), "clear loss");
+  if (n == 0) return LF_OK;
+  if (!d_packed || !d_phi || !d_target) return fail(LF_EINVAL, "NULL argument");
+  if (n > ((int64_t)1 << 40)) return fail(LF_EINVAL, "too many observations");
+  LF_TRY(launch_mlp_grad(d_packed, d_phi, d_target, n, (float)(1.0 / (double)n), d_grad, d_loss, stream), "gradient");
+  return LF_OK;
+}
+
+lf_status lf_adam_step(float* d_params, float* d_m, float* d_v, const float* d_grad, int64_t n, float lr,
+                       float beta1, float beta2, float eps, int32_t step, hipStream_t stream) {
+  g_err[0] = 0;
+  if (n < 0) return fail(LF_EINVAL, "negative count");
+  if (step < 1) return fail(LF_EINVAL, "Adam step counts from 1");
+  if (!(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f))
+    return fail(LF_EINVAL, "Adam needs 0 <= beta < 1 and eps > 0");
+  if (n == 0) return LF_OK;
+  if (!d_params || !d_m || !d_v || !d_grad) return fail(LF_EINVAL, "NULL argument");
+  LF_TRY(launch_adam(d_params, d_m, d_v, d_grad, n, lr, beta1, beta2, eps, step, stream), "adam");
+  return LF_OK;
+}
+
+lf_status lf_extract_features(lf_mesh mesh, const float* d_cams, int32_t F, int32_t H, int32_t W, const void* d_probs,
+                              int32_t prob_dtype, const int64_t* h_strides, const float* d_scale,
+                              const uint8_t* d_valid, const uint8_t* d_labels, float* d_phi, float* d_target,
+                              int32_t* d_pix, int64_t cap, uint64_t* d_count, void* d_ws, int64_t ws_bytes,
+                              hipStream_t stream) {
+  g_err[0] = 0;
+  lf_status st = check_mesh(mesh);
+  if (st != LF_OK) return st;
+  if ((st = check_frames(F, H, W)) != LF_OK) return st;
+  if (!d_count) return fail(LF_EINVAL, "NULL count");
+  LF_TRY(launch_zero(d_count, 8, stream), "clear count");
+  if (F == 0) return LF_OK;
+  if (!d_cams || !d_probs || !h_strides || !d_ws || !d_phi) return fail(LF_EINVAL, "NULL argument");
+  if (d_target && !d_labels) return fail(LF_EINVAL, "targets need the fused labels");
+  if (cap < 0) return fail(LF_EINVAL, "negative capacity");
+  if (prob_dtype != LF_F32 && prob_dtype != LF_FP8_E4M3) return fail(LF_EINVAL, "probabilities must be F32 or FP8_E4M3");
+  if (prob_dtype == LF_FP8_E4M3 && !d_scale) return fail(LF_EINVAL, "FP8 input needs the per-pixel scale");
+  for (int i = 0; i < 4; ++i)
+    if (h_strides[i] < 0) return fail(LF_EINVAL, "negative stride");
+  const int64_t HW = (int64_t)H * W;
+  if (d_pix && (int64_t)F * HW >= ((int64_t)1 << 31)) return fail(LF_EINVAL, "pixel indices exceed int32");
+  if (reinterpret_cast<uintptr_t>(d_ws) & 255) return fail(LF_EINVAL, "workspace must be 256-byte aligned");
+  const MeshDev& d = mesh->d;
+  const int B = pick_batch(d, H, W, F, ws_bytes, LF_W_LEARNED, LF_SCATTER_ATOMIC);
+  const FrameLayout L = frame_layout(d, H, W, B, LF_W_LEARNED, LF_SCATTER_ATOMIC);
+  if (ws_bytes < L.total) return fail(LF_ESIZE, "frame workspace %lld < %lld bytes", (long long)ws_bytes, (long long)L.total);
+  char* ws = reinterpret_cast<char*>(d_ws);
+  ProbIn in{d_probs, d_scale, d_valid, h_strides[0], h_strides[1], h_strides[2], h_strides[3], prob_dtype};
+  int32_t* cnt = reinterpret_cast<int32_t*>(ws + L.cnt);
+  float4* geo = reinterpret_cast<float4*>(ws + L.geo);
+  int32_t* lb = reinterpret_cast<int32_t*>(ws + L.l);
+  LF_TRY(launch_zero(ws + L.tcnt, B * L.ntiles * 4, stream), "clear tile counts");
+  LF_TRY(launch_zero(cnt, (int64_t)B * d.n_texels * 4, stream), "clear counts");
+  for (int f0 = 0; f0 < F; f0 += B) {
+    const int nb = (F - f0) < B ? (F - f0) : B;
+    const uint8_t* vb = d_valid ? d_valid + (int64_t)f0 * HW : nullptr;
+    RasterOut out{lb, nullptr, nullptr, vb, cnt, d.n_texels, nullptr, nullptr, geo};
+    if ((st = render_batch(mesh, d_cams, f0, nb, H, W, L, ws, out, stream)) != LF_OK) return st;
+    StageTimer tm(mesh, 7, stream);
+    LF_TRY(launch_extract(in, f0, nb, H, W, d_cams, lb, geo, cnt, d.n_texels, d.c, d_labels, d_phi, d_target, d_pix,
+                          cap, reinterpret_cast<unsigned long long*>(d_count), stream), "extract");
+    LF_TRY(launch_clear_counts(lb, vb, nb, H, W, cnt, d.n_texels, stream), "clear counts");
   }
   return LF_OK;
 }

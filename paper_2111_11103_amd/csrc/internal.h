@@ -51,6 +51,8 @@ struct RasterOut {
   int64_t cnt_stride;
   int32_t* seg;              // per-row observation counts of the batch (sorted scatter)
   int32_t* rank;             // [B][H][W] rank of the pixel within its row's segment
+  float4* geo;               // [B][H][W] learned-weight geometry: cos of the viewing angle,
+                             // z / (1 + z), centroid closeness, 0 (zeros where no triangle)
 };
 
 struct ProbIn {
@@ -85,5 +87,21 @@ hipError_t launch_seg_gather(const MeshDev& m, const ProbIn& in, int f_first, in
                              const float* ent_s, hipStream_t s);
 hipError_t launch_render(const int32_t* l, const uint8_t* valid, const uint8_t* labels, int64_t npx,
                          uint8_t* out, hipStream_t s);
+
+// learned per-observation weight (mlp.hip)
+int mlp_nparam();
+int mlp_packed_bytes();
+hipError_t launch_mlp_pack(const float* params, void* packed, hipStream_t s);
+hipError_t launch_adam(float* p, float* m, float* v, const float* g, int64_t n, float lr, float b1, float b2, float eps,
+                       int step, hipStream_t s);
+hipError_t launch_mlp_forward(const void* packed, const float* phi, int64_t n, float* w, hipStream_t s);
+hipError_t launch_mlp_grad(const void* packed, const float* phi, const float* tgt, int64_t n, float inv_total,
+                           float* grad, float* loss, hipStream_t s);
+hipError_t launch_mlp_weights(const void* packed, const ProbIn& in, int f_first, int nf, int H, int W,
+                              const float* cams, const int32_t* l, const float4* geo, const int32_t* cnt,
+                              int64_t cnt_stride, int c, float* wpix, hipStream_t s);
+hipError_t launch_extract(const ProbIn& in, int f_first, int nf, int H, int W, const float* cams, const int32_t* l,
+                          const float4* geo, const int32_t* cnt, int64_t cnt_stride, int c, const uint8_t* labels,
+                          float* phi, float* tgt, int32_t* pix, int64_t cap, unsigned long long* count, hipStream_t s);
 
 }  // namespace lf

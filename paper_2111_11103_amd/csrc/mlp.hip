@@ -1,0 +1,483 @@
+// Learned per-observation fusion weight: w_k = MLP(phi_k), a generalisation
+// of the fixed weights w^(P), w^(I) of Section 3.2.2.
+//
+//   h1 = relu(W1 q(phi) + b1)   (64 x 8)
+//   h2 = relu(W2 q(h1) + b2)    (64 x 64)
+//   w  = sigmoid(w3 . h2 + b3)
+// q = round to bfloat16; W1, W2, w3 are bfloat16, biases and accumulation
+// binary32.  Inference runs both matrix products on the matrix cores
+// (v_mfma_f32_16x16x16_bf16): a wave evaluates 64 observations as four
+// 16-row tiles, staging q(phi) and q(h1) through LDS between the layers.
+// Training gradients are accumulated on the vector ALUs in binary32 (one
+// wave per chunk of observations, one lane per hidden unit) and applied
+// with Adam on binary32 master parameters.
+#include <hip/hip_bf16.h>
+
+#include "internal.h"
+#include "spec.h"
+
+namespace lf {
+
+typedef short s4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+constexpr int NI = 8, NH = 64;
+// master (binary32) layout
+constexpr int OW1 = 0, OB1 = OW1 + NH * NI, OW2 = OB1 + NH, OB2 = OW2 + NH * NH, OW3 = OB2 + NH, OB3 = OW3 + NH;
+constexpr int NPARAM = OB3 + 1;
+// packed compute layout (bytes)
+constexpr int PW1 = 0, PW2 = PW1 + NH * NI * 2, PW3 = PW2 + NH * NH * 2, PB1 = PW3 + NH * 2, PB2 = PB1 + NH * 4,
+              PB3 = PB2 + NH * 4, PACKED_BYTES = 10240;
+static_assert(PB3 + 4 <= PACKED_BYTES, "packed layout");
+
+__device__ __forceinline__ uint16_t bf16_bits(float x) {
+  const __hip_bfloat16 b = __float2bfloat16(x);   // round to nearest even
+  return *reinterpret_cast<const uint16_t*>(&b);
+}
+__device__ __forceinline__ float bf16_val(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+struct MlpW {
+  const uint16_t* W1;
+  const uint16_t* W2;
+  const uint16_t* w3;
+  const float* b1;
+  const float* b2;
+  const float* b3;
+};
+
+__host__ __device__ inline MlpW mlp_view(const void* packed) {
+  const char* p = reinterpret_cast<const char*>(packed);
+  return MlpW{reinterpret_cast<const uint16_t*>(p + PW1), reinterpret_cast<const uint16_t*>(p + PW2),
+              reinterpret_cast<const uint16_t*>(p + PW3), reinterpret_cast<const float*>(p + PB1),
+              reinterpret_cast<const float*>(p + PB2), reinterpret_cast<const float*>(p + PB3)};
+}
+
+// ---- packing and Adam ---------------------------------------------------------
+__global__ __launch_bounds__(256) void k_mlp_pack(const float* __restrict__ prm, char* __restrict__ out) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= NPARAM) return;
+  if (i < OB1) reinterpret_cast<uint16_t*>(out + PW1)[i - OW1] = bf16_bits(prm[i]);
+  else if (i < OW2) reinterpret_cast<float*>(out + PB1)[i - OB1] = prm[i];
+  else if (i < OB2) reinterpret_cast<uint16_t*>(out + PW2)[i - OW2] = bf16_bits(prm[i]);
+  else if (i < OW3) reinterpret_cast<float*>(out + PB2)[i - OB2] = prm[i];
+  else if (i < OB3) reinterpret_cast<uint16_t*>(out + PW3)[i - OW3] = bf16_bits(prm[i]);
+  else reinterpret_cast<float*>(out + PB3)[0] = prm[i];
+}
+
+// Adam (Kingma & Ba 2015) in binary32: bias-corrected first and second moments.
+__global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, float* __restrict__ m, float* __restrict__ v,
+                                              const float* __restrict__ g, int64_t n, float lr, float b1, float b2,
+                                              float eps, float c1, float c2) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.0f - b1) * gi;
+  const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// ---- inference on the matrix cores ---------------------------------------------
+constexpr int H1S = 68;   // LDS row stride of q(h1) in halfwords (conflict-free fragment reads)
+
+struct WaveLds {
+  uint16_t* phi;   // [64][8]
+  uint16_t* h1;    // [64][H1S]
+  float* logit;    // [64]
+};
+
+// Evaluate the network for the 64 observations of a wave (lane = observation).
+// Must be reached by every thread of the block (it synchronises the block
+// around the LDS exchanges between lanes).
+__device__ float mlp_wave(const float (&phi)[NI], const MlpW& W, const WaveLds& L) {
+  const int lane = threadIdx.x & 63;
+  const int col = lane & 15, grp = lane >> 4;
+#pragma unroll
+  for (int k = 0; k < NI; ++k) L.phi[lane * NI + k] = bf16_bits(phi[k]);
+  // B fragments: lane holds B[k = 4*grp + r][j = col] of each 16x16 tile
+  s4 bw1[4];
+#pragma unroll
+  for (int n = 0; n < 4; ++n) {
+    s4 t = {0, 0, 0, 0};
+    if (grp < 2) {
+      const uint16_t* w = W.W1 + (n * 16 + col) * NI + 4 * grp;
+      t = s4{(short)w[0], (short)w[1], (short)w[2], (short)w[3]};
+    }
+    bw1[n] = t;
+  }
+  __syncthreads();
+  // layer 1: h1[sample][unit] for 4 sample tiles x 4 unit tiles
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    s4 a = {0, 0, 0, 0};
+    if (grp < 2) {
+      const uint16_t* x = L.phi + (t * 16 + col) * NI + 4 * grp;
+      a = s4{(short)x[0], (short)x[1], (short)x[2], (short)x[3]};
+    }
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+      f4 d = {0.f, 0.f, 0.f, 0.f};
+      d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bw1[n], d, 0, 0, 0);
+      const float bias = W.b1[n * 16 + col];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const float h = fmaxf(d[r] + bias, 0.0f);
+        L.h1[(t * 16 + 4 * grp + r) * H1S + n * 16 + col] = bf16_bits(h);
+      }
+    }
+  }
+  __syncthreads();
+  // layer 2 + output layer
+  float part[4][4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) part[t][r] = 0.0f;
+#pragma unroll
+  for (int n = 0; n < 4; ++n) {
+    s4 bw2[4];
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      const uint16_t* w = W.W2 + (n * 16 + col) * NH + ks * 16 + 4 * grp;
+      bw2[ks] = s4{(short)w[0], (short)w[1], (short)w[2], (short)w[3]};
+    }
+    const float bias = W.b2[n * 16 + col];
+    const float w3 = bf16_val(W.w3[n * 16 + col]);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      f4 d = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks) {
+        const uint16_t* x = L.h1 + (t * 16 + col) * H1S + ks * 16 + 4 * grp;
+        const s4 a = s4{(short)x[0], (short)x[1], (short)x[2], (short)x[3]};
+        d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bw2[ks], d, 0, 0, 0);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) part[t][r] += w3 * fmaxf(d[r] + bias, 0.0f);
+    }
+  }
+  // sum over the 16 units a lane group holds, per sample row
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      float v = part[t][r];
+#pragma unroll
+      for (int o = 8; o > 0; o >>= 1) v += __shfl_xor(v, o, 16);
+      if (col == 0) L.logit[t * 16 + 4 * grp + r] = v + W.b3[0];
+    }
+  __syncthreads();
+  const float z = L.logit[lane];
+  return 1.0f / (1.0f + expf(-z));
+}
+
+__global__ __launch_bounds__(256) void k_mlp_forward(const void* __restrict__ packed, const float* __restrict__ phi,
+                                                     int64_t n, float* __restrict__ w_out) {
+  __shared__ uint16_t sphi[4][64 * NI];
+  __shared__ uint16_t sh1[4][64 * H1S];
+  __shared__ float slog[4][64];
+  const int wv = threadIdx.x >> 6;
+  const WaveLds L{sphi[wv], sh1[wv], slog[wv]};
+  const MlpW W = mlp_view(packed);
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  float x[NI];
+#pragma unroll
+  for (int k = 0; k < NI; ++k) x[k] = i < n ? phi[i * NI + k] : 0.0f;
+  const float w = mlp_wave(x, W, L);
+  if (i < n) w_out[i] = w;
+}
+
+// ---- features ---------------------------------------------------------------------
+// Probability features of pixel (frame f, y, x): normalised entropy, top-1,
+// top-1 minus top-2.  Also returns the first maximal class.
+template <int DT>
+__device__ __forceinline__ void prob_features(const ProbIn& in, int64_t base, float scale, int c, float& ent, float& p1,
+                                              float& p2, int& best) {
+  float h = 0.0f;
+  p1 = -__builtin_inff();
+  p2 = -__builtin_inff();
+  best = 0;
+  for (int j = 0; j < c; ++j) {
+    float p;
+    if constexpr (DT == 0) {
+      p = reinterpret_cast<const float*>(in.p)[base + (int64_t)j * in.sc];
+    } else {
+      const uint32_t q = reinterpret_cast<const uint8_t*>(in.p)[base + (int64_t)j * in.sc];
+      const int e = (q >> 3) & 15, mn = q & 7;
+      float v = (e == 0) ? (float)mn * 0.001953125f : __builtin_ldexpf((float)(8 + mn), e - 10);
+      if (e == 15 && mn == 7) v = __builtin_nanf("");
+      p = ((q & 0x80u) ? -v : v) * scale;
+    }
+    if (p > 0.0f) h -= p * logf(p);
+    if (p > p1) { p2 = p1; p1 = p; best = j; }
+    else if (p > p2) p2 = p;
+  }
+  if (c < 2) p2 = 0.0f;
+  ent = c > 1 ? h / logf((float)c) : 0.0f;
+}
+
+// phi of one observation from the renderer's per-pixel geometry (cos of the
+// viewing angle, z/(1+z), centroid closeness), its frame count, its pixel
+// position and its probabilities.
+template <int DT>
+__device__ __forceinline__ void observation_features(const ProbIn& in, int64_t base, float scale, int c, float4 geo,
+                                                     int n_same, int x, int y, const float* cam, float (&phi)[NI],
+                                                     int& best) {
+  float ent, p1, p2;
+  prob_features<DT>(in, base, scale, c, ent, p1, p2, best);
+  phi[0] = geo.x;
+  phi[1] = geo.y;
+  phi[2] = ent;
+  phi[3] = p1;
+  phi[4] = p1 - p2;
+  phi[5] = geo.z;
+  phi[6] = fminf(logf((float)max(n_same, 1)) / logf(64.0f), 2.0f);
+  const float cx = cam[2], cy = cam[3];
+  const float dx = (float)x + 0.5f - cx, dy = (float)y + 0.5f - cy;
+  phi[7] = sqrtf(dx * dx + dy * dy) / sqrtf(cx * cx + cy * cy);
+}
+
+// Fused inference during fusion: weight of every valid covered pixel of the
+// batch (0 elsewhere).
+template <int DT>
+__global__ __launch_bounds__(256) void k_mlp_weights(const void* __restrict__ packed, ProbIn in, int f_first, int H,
+                                                     int W, const float* __restrict__ cams,
+                                                     const int32_t* __restrict__ lbuf, const float4* __restrict__ geo,
+                                                     const int32_t* __restrict__ cnt, int64_t cnt_stride, int c,
+                                                     float* __restrict__ wpix) {
+  __shared__ uint16_t sphi[4][64 * NI];
+  __shared__ uint16_t sh1[4][64 * H1S];
+  __shared__ float slog[4][64];
+  const int wv = threadIdx.x >> 6;
+  const WaveLds L{sphi[wv], sh1[wv], slog[wv]};
+  const MlpW Wt = mlp_view(packed);
+  const int fb = blockIdx.y;
+  const int64_t HW = (int64_t)H * W;
+  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t pi = (int64_t)fb * HW + p;
+  const int64_t gi = (int64_t)(f_first + fb) * HW + p;
+  float x[NI];
+#pragma unroll
+  for (int k = 0; k < NI; ++k) x[k] = 0.0f;
+  bool use = false;
+  if (p < HW) {
+    const int l = lbuf[pi];
+    use = l >= 0 && (!in.valid || in.valid[gi]);
+    if (use) {
+      const int y = (int)(p / W), xx = (int)(p - (int64_t)y * W);
+      const int64_t base = (int64_t)(f_first + fb) * in.sf + (int64_t)y * in.sy + (int64_t)xx * in.sx;
+      const float sc = DT == 3 ? in.scale[gi] : 1.0f;
+      int best;
+      observation_features<DT>(in, base, sc, c, geo[pi], cnt[(int64_t)fb * cnt_stride + l], xx, y,
+                               cams + 16 * (int64_t)(f_first + fb), x, best);
+    }
+  }
+  const float w = mlp_wave(x, Wt, L);
+  if (p < HW) wpix[pi] = use ? w : 0.0f;
+}
+
+// Training data: features and targets (own argmax == the texel's fused label)
+// of every valid covered pixel of the batch, appended in arbitrary order.
+template <int DT>
+__global__ __launch_bounds__(256) void k_extract(ProbIn in, int f_first, int H, int W, const float* __restrict__ cams,
+                                                 const int32_t* __restrict__ lbuf, const float4* __restrict__ geo,
+                                                 const int32_t* __restrict__ cnt, int64_t cnt_stride, int c,
+                                                 const uint8_t* __restrict__ labels, float* __restrict__ phi_out,
+                                                 float* __restrict__ tgt_out, int32_t* __restrict__ pix_out,
+                                                 int64_t cap, unsigned long long* __restrict__ count) {
+  const int fb = blockIdx.y;
+  const int64_t HW = (int64_t)H * W;
+  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t pi = (int64_t)fb * HW + p;
+  const int64_t gi = (int64_t)(f_first + fb) * HW + p;
+  bool use = false;
+  int l = -1;
+  if (p < HW) {
+    l = lbuf[pi];
+    use = l >= 0 && (!in.valid || in.valid[gi]);
+  }
+  const unsigned long long mask = __ballot(use);
+  if (mask == 0) return;
+  const int lane = threadIdx.x & 63;
+  const int leader = __ffsll(mask) - 1;
+  unsigned long long base = 0;
+  if (lane == leader) base = atomicAdd(count, (unsigned long long)__popcll(mask));
+  base = __shfl(base, leader);
+  if (!use) return;
+  const unsigned long long slot = base + __popcll(mask & ((1ull << lane) - 1ull));
+  if ((int64_t)slot >= cap) return;
+  const int y = (int)(p / W), xx = (int)(p - (int64_t)y * W);
+  const int64_t pb = (int64_t)(f_first + fb) * in.sf + (int64_t)y * in.sy + (int64_t)xx * in.sx;
+  const float sc = DT == 3 ? in.scale[gi] : 1.0f;
+  float x[NI];
+  int best;
+  observation_features<DT>(in, pb, sc, c, geo[pi], cnt[(int64_t)fb * cnt_stride + l], xx, y,
+                           cams + 16 * (int64_t)(f_first + fb), x, best);
+#pragma unroll
+  for (int k = 0; k < NI; ++k) phi_out[slot * NI + k] = x[k];
+  if (tgt_out) tgt_out[slot] = (labels && labels[l] != 255 && labels[l] == best) ? 1.0f : 0.0f;
+  if (pix_out) pix_out[slot] = (int32_t)((int64_t)(f_first + fb) * HW + p);
+}
+
+// ---- training gradients (vector ALU, binary32) --------------------------------------
+// One 64-lane block walks `chunks` chunks of 64 observations; lane o owns
+// hidden unit o of both layers.  Straight-through rounding: the backward pass
+// uses the bfloat16 weights and q(h1), q(phi) of the forward pass.
+__global__ __launch_bounds__(64) void k_mlp_grad(const void* __restrict__ packed, const float* __restrict__ phi,
+                                                 const float* __restrict__ tgt, int64_t n, int chunks,
+                                                 float inv_total, float* __restrict__ grad, float* __restrict__ loss) {
+  __shared__ float sx[64][NI];          // q(phi) of the chunk's samples
+  __shared__ float sh1[64][NH + 1];     // q(h1)[sample][unit]
+  __shared__ float sh2[64][NH + 1];     // relu(h2)[sample][unit]
+  __shared__ float sd[64][NH + 1];      // w3*h2, then d(loss)/d(h2 pre-activation)
+  __shared__ uint16_t sw2[NH][NH + 2];  // W2 (bfloat16)
+  __shared__ float sdz[64];
+  const MlpW W = mlp_view(packed);
+  const int o = threadIdx.x;
+  float w1[NI], w2[NH];
+#pragma unroll
+  for (int k = 0; k < NI; ++k) w1[k] = bf16_val(W.W1[o * NI + k]);
+#pragma unroll
+  for (int i = 0; i < NH; ++i) {
+    w2[i] = bf16_val(W.W2[o * NH + i]);
+    sw2[o][i] = W.W2[o * NH + i];
+  }
+  const float b1 = W.b1[o], b2 = W.b2[o], w3 = bf16_val(W.w3[o]), b3 = W.b3[0];
+  float gW1[NI], gW2[NH];
+#pragma unroll
+  for (int k = 0; k < NI; ++k) gW1[k] = 0.0f;
+#pragma unroll
+  for (int i = 0; i < NH; ++i) gW2[i] = 0.0f;
+  float gb1 = 0.0f, gb2 = 0.0f, gw3 = 0.0f, gb3 = 0.0f, lsum = 0.0f;
+  __syncthreads();
+  for (int ch = 0; ch < chunks; ++ch) {
+    const int64_t s0 = ((int64_t)blockIdx.x * chunks + ch) * 64;
+    if (s0 >= n) break;
+    const int64_t si = s0 + o;
+    const bool live = si < n;
+#pragma unroll
+    for (int k = 0; k < NI; ++k) sx[o][k] = live ? bf16_val(bf16_bits(phi[si * NI + k])) : 0.0f;
+    const float y = live ? tgt[si] : 0.0f;
+    __syncthreads();
+    uint64_t m1 = 0, m2 = 0;   // relu masks of unit o over the chunk's samples
+    for (int s = 0; s < 64; ++s) {
+      float a = b1;
+#pragma unroll
+      for (int k = 0; k < NI; ++k) a += w1[k] * sx[s][k];
+      if (a > 0.0f) m1 |= 1ull << s;
+      sh1[s][o] = bf16_val(bf16_bits(fmaxf(a, 0.0f)));
+    }
+    __syncthreads();
+    for (int s = 0; s < 64; ++s) {
+      float a = b2;
+#pragma unroll
+      for (int i = 0; i < NH; ++i) a += w2[i] * sh1[s][i];
+      if (a > 0.0f) m2 |= 1ull << s;
+      const float h = fmaxf(a, 0.0f);
+      sh2[s][o] = h;
+      sd[s][o] = w3 * h;
+    }
+    __syncthreads();
+    {
+      float z = b3;
+      for (int i = 0; i < NH; ++i) z += sd[o][i];
+      const float sg = 1.0f / (1.0f + expf(-z));
+      // binary cross-entropy with logits, stable form
+      const float l = (z > 0.0f ? z + log1pf(expf(-z)) : log1pf(expf(z))) - y * z;
+      sdz[o] = live ? (sg - y) * inv_total : 0.0f;
+      if (live) lsum += l * inv_total;
+    }
+    __syncthreads();
+    for (int s = 0; s < 64; ++s) {
+      const float dz = sdz[s];
+      gw3 += dz * sh2[s][o];
+      if (o == 0) gb3 += dz;
+      const float d2 = ((m2 >> s) & 1ull) ? dz * w3 : 0.0f;
+      gb2 += d2;
+#pragma unroll
+      for (int i = 0; i < NH; ++i) gW2[i] += d2 * sh1[s][i];
+      sd[s][o] = d2;
+    }
+    __syncthreads();
+    for (int s = 0; s < 64; ++s) {
+      float a = 0.0f;
+      for (int q = 0; q < NH; ++q) a += sd[s][q] * bf16_val(sw2[q][o]);
+      const float d1 = ((m1 >> s) & 1ull) ? a : 0.0f;
+      gb1 += d1;
+#pragma unroll
+      for (int k = 0; k < NI; ++k) gW1[k] += d1 * sx[s][k];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int k = 0; k < NI; ++k) atomicAdd(grad + OW1 + o * NI + k, gW1[k]);
+  atomicAdd(grad + OB1 + o, gb1);
+#pragma unroll
+  for (int i = 0; i < NH; ++i) atomicAdd(grad + OW2 + o * NH + i, gW2[i]);
+  atomicAdd(grad + OB2 + o, gb2);
+  atomicAdd(grad + OW3 + o, gw3);
+  if (o == 0) atomicAdd(grad + OB3, gb3);
+  float v = lsum;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  if (o == 0 && loss) atomicAdd(loss, v);
+}
+
+// ---- launchers --------------------------------------------------------------------
+int mlp_nparam() { return NPARAM; }
+int mlp_packed_bytes() { return PACKED_BYTES; }
+
+hipError_t launch_mlp_pack(const float* params, void* packed, hipStream_t s) {
+  k_mlp_pack<<<dim3((NPARAM + 255) / 256), 256, 0, s>>>(params, reinterpret_cast<char*>(packed));
+  return hipGetLastError();
+}
+
+hipError_t launch_adam(float* p, float* m, float* v, const float* g, int64_t n, float lr, float b1, float b2, float eps,
+                       int step, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const float c1 = 1.0f - powf(b1, (float)step), c2 = 1.0f - powf(b2, (float)step);
+  k_adam<<<dim3((unsigned)((n + 255) / 256)), 256, 0, s>>>(p, m, v, g, n, lr, b1, b2, eps, c1, c2);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_forward(const void* packed, const float* phi, int64_t n, float* w, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  k_mlp_forward<<<dim3((unsigned)((n + 255) / 256)), 256, 0, s>>>(packed, phi, n, w);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_grad(const void* packed, const float* phi, const float* tgt, int64_t n, float inv_total,
+                           float* grad, float* loss, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  constexpr int chunks = 4;
+  const int64_t blocks = (n + 64 * chunks - 1) / (64 * chunks);
+  k_mlp_grad<<<dim3((unsigned)blocks), 64, 0, s>>>(packed, phi, tgt, n, chunks, inv_total, grad, loss);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_weights(const void* packed, const ProbIn& in, int f_first, int nf, int H, int W,
+                              const float* cams, const int32_t* l, const float4* g4, const int32_t* cnt,
+                              int64_t cnt_stride, int c, float* wpix, hipStream_t s) {
+  if (nf <= 0) return hipSuccess;
+  const int64_t HW = (int64_t)H * W;
+  dim3 g((unsigned)((HW + 255) / 256), (unsigned)nf);
+  if (in.dtype == 0) k_mlp_weights<0><<<g, 256, 0, s>>>(packed, in, f_first, H, W, cams, l, g4, cnt, cnt_stride, c, wpix);
+  else k_mlp_weights<3><<<g, 256, 0, s>>>(packed, in, f_first, H, W, cams, l, g4, cnt, cnt_stride, c, wpix);
+  return hipGetLastError();
+}
+
+hipError_t launch_extract(const ProbIn& in, int f_first, int nf, int H, int W, const float* cams, const int32_t* l,
+                          const float4* g4, const int32_t* cnt, int64_t cnt_stride, int c, const uint8_t* labels,
+                          float* phi, float* tgt, int32_t* pix, int64_t cap, unsigned long long* count, hipStream_t s) {
+  if (nf <= 0) return hipSuccess;
+  const int64_t HW = (int64_t)H * W;
+  dim3 g((unsigned)((HW + 255) / 256), (unsigned)nf);
+  if (in.dtype == 0)
+    k_extract<0><<<g, 256, 0, s>>>(in, f_first, H, W, cams, l, g4, cnt, cnt_stride, c, labels, phi, tgt, pix, cap, count);
+  else
+    k_extract<3><<<g, 256, 0, s>>>(in, f_first, H, W, cams, l, g4, cnt, cnt_stride, c, labels, phi, tgt, pix, cap, count);
+  return hipGetLastError();
+}
+
+}  // namespace lf

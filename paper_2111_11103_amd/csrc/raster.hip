@@ -418,8 +418,10 @@ __global__ __launch_bounds__(256) void k_tile_raster(MeshDev m, const float* __r
   int64_t pix[PPT];
   bool in[PPT], use[PPT];
   int fi[PPT][3];
+  float4 geo[PPT];
 #pragma unroll
   for (int r = 0; r < PPT; ++r) {
+    geo[r] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     const int i = threadIdx.x + 256 * r;
     const int x = tx0 + (i % TS), y = ty0 + (i / TS);
     in[r] = x <= tx1 && y <= ty1;
@@ -453,6 +455,15 @@ __global__ __launch_bounds__(256) void k_tile_raster(MeshDev m, const float* __r
       const float u = rdot(rx, ry, rk.nu) / den;
       const float v = rdot(rx, ry, rk.nv) / den;
       l[r] = (int32_t)(row_offset(m, tri[r]) + texel_id(tri_s(m, tri[r]), m.split, u, v));
+      if (out.geo) {
+        // |cos| of the angle between the ray and the triangle normal, depth
+        // squashed to [0, 1), 3 * smallest barycentric clamped to [0, 1]
+        const float rl = sqrtf(rx * rx + ry * ry + 1.0f);
+        const float nl = sqrtf(rk.n.x * rk.n.x + rk.n.y * rk.n.y + rk.n.z * rk.n.z);
+        const float cs = nl > 0.0f ? fabsf(den) / (rl * nl) : 0.0f;
+        const float b = 3.0f * fminf(fminf(u, v), 1.0f - u - v);
+        geo[r] = make_float4(cs, z[r] / (1.0f + z[r]), fminf(fmaxf(b, 0.0f), 1.0f), 0.0f);
+      }
     }
   }
   if (out.cnt) {
@@ -474,6 +485,7 @@ __global__ __launch_bounds__(256) void k_tile_raster(MeshDev m, const float* __r
     if (out.l) out.l[pix[r]] = l[r];
     if (out.tri) out.tri[pix[r]] = tri[r];
     if (out.z) out.z[pix[r]] = z[r];
+    if (out.geo) out.geo[pix[r]] = geo[r];
   }
 }
 

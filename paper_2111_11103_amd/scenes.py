@@ -227,9 +227,11 @@ def random_walk_cameras(scene: Scene, n_frames: int, W: int, H: int, seed: int =
 
 # --------------------------------------------------------------------------- ground truth
 
-def ground_truth(scene: Scene, cams, H: int, W: int, device="cpu"):
+def ground_truth(scene: Scene, cams, H: int, W: int, device="cpu", geometry=False):
     """Class of the first surface hit by each pixel-centre ray, by an analytic
-    ray cast against the room's boxes.  Returns int64 [F,H,W]."""
+    ray cast against the room's boxes.  Returns int64 [F,H,W]; with
+    ``geometry`` also the depth z and |cos| of the viewing angle of the hit
+    (float32 [F,H,W] each)."""
     import torch
     cams_t = torch.as_tensor(np.asarray(cams, np.float64), device=device)
     F = cams_t.shape[0]
@@ -261,6 +263,7 @@ def ground_truth(scene: Scene, cams, H: int, W: int, device="cpu"):
     face_of_axis = torch.tensor([[4, 5], [2, 3], [0, 1]], device=device)
     face = face_of_axis[axis, pos_side.long()]
     cls = face % scene.n_classes
+    hit_axis = axis.clone()
     for b in scene.boxes:
         blo = torch.as_tensor(b.lo, device=device)
         bhi = torch.as_tensor(b.hi, device=device)
@@ -275,17 +278,28 @@ def ground_truth(scene: Scene, cams, H: int, W: int, device="cpu"):
         hit = (tn <= tf) & (tn > 0) & (tn < best_t)
         best_t = torch.where(hit, tn, best_t)
         cls = torch.where(hit, torch.full_like(cls, b.cls), cls)
-    return cls
+        hit_axis = torch.where(hit, tmin.argmax(-1), hit_axis)
+    if not geometry:
+        return cls
+    # the camera-space ray is (dx, dy, 1), so the ray parameter is the depth
+    dn = torch.gather(d, -1, hit_axis[..., None])[..., 0].abs() / d.norm(dim=-1)
+    return cls, best_t.to(torch.float32), dn.to(torch.float32)
 
 
 # --------------------------------------------------------------------------- probabilities
 
 def make_probs(gt, n_classes: int, margin: float, sigma: float, blob_frac: float,
-               seed: int = 0, out=None, blob_r=(0.03, 0.12)):
+               seed: int = 0, out=None, blob_r=(0.03, 0.12), quality=None, shift_px: int = 0):
     """Synthetic network output [F,c,H,W] float32 (NCHW).
 
     ``gt`` is an int64 tensor [F,H,W] on the generating device.  ``out`` may be a
     preallocated float32 tensor of the right shape (filled in place).
+    ``quality`` (optional float32 [F,H,W] in [0, 1]) makes the noise depend
+    on the view: a pixel of quality q gets the margin * (0.5 + 0.5 q) and the
+    noise sigma * (1.3 - 0.3 q), and a mislabel disc relabels only its
+    pixels whose quality is below a threshold drawn from U(0.4, 0.8).
+    ``shift_px`` > 0 shifts each frame's label map by an integer offset drawn
+    from [-shift_px, shift_px]^2 before the noise is added.
     """
     import torch
     device = gt.device
@@ -293,6 +307,15 @@ def make_probs(gt, n_classes: int, margin: float, sigma: float, blob_frac: float
     g = torch.Generator(device=device)
     g.manual_seed(int(seed) * 1000003 + 17)
     lab = gt.clone()
+    if shift_px > 0:
+        # misregistration: the network sees the image under a slightly wrong
+        # pose, so its labels are the ground truth moved by up to shift_px
+        # pixels (edge pixels repeated)
+        for f in range(F):
+            d = torch.randint(-shift_px, shift_px + 1, (2,), generator=g, device=device)
+            ys = (torch.arange(H, device=device) - d[1]).clamp(0, H - 1)
+            xs = (torch.arange(W, device=device) - d[0]).clamp(0, W - 1)
+            lab[f] = gt[f][ys][:, xs]
     yy = torch.arange(H, device=device, dtype=torch.float32)[:, None]
     xx = torch.arange(W, device=device, dtype=torch.float32)[None, :]
     mn = min(H, W)
@@ -306,14 +329,25 @@ def make_probs(gt, n_classes: int, margin: float, sigma: float, blob_frac: float
             cxy = torch.rand(2, generator=g, device=device) * torch.tensor([W, H], device=device, dtype=torch.float32)
             delta = torch.randint(1, n_classes, (), generator=g, device=device)
             disc = (xx + 0.5 - cxy[0]) ** 2 + (yy + 0.5 - cxy[1]) ** 2 <= r * r
+            if quality is not None:
+                # view-dependent mislabels: only the disc's low-quality pixels
+                qt = 0.4 + 0.4 * torch.rand((), generator=g, device=device)
+                disc &= quality[f].to(device) < qt
             newpix = disc & ~covered
             lab[f] = torch.where(newpix, (gt[f] + delta) % n_classes, lab[f])
             covered |= disc
     if out is None:
         out = torch.empty((F, n_classes, H, W), dtype=torch.float32, device=device)
     for f in range(F):
-        logits = torch.randn((n_classes, H, W), generator=g, device=device, dtype=torch.float32) * sigma
-        logits.scatter_add_(0, lab[f][None], torch.full((1, H, W), float(margin), device=device))
+        logits = torch.randn((n_classes, H, W), generator=g, device=device, dtype=torch.float32)
+        if quality is None:
+            logits *= sigma
+            add = torch.full((1, H, W), float(margin), device=device)
+        else:
+            q = quality[f].to(device=device, dtype=torch.float32).clamp(0.0, 1.0)
+            logits *= (sigma * (1.3 - 0.3 * q))[None]
+            add = (margin * (0.5 + 0.5 * q))[None]
+        logits.scatter_add_(0, lab[f][None], add)
         out[f] = torch.softmax(logits, dim=0)
     return out
 
@@ -346,8 +380,14 @@ class FrameInputs:
     scheme: int = 1       # 0 = SQUARE (paper), 1 = SPLIT
 
 
+def view_quality(z, cosv, z_ref=4.0):
+    """Per-pixel view quality in [0, 1]: half from the viewing angle, half
+    from the distance (1 at the camera, 1/2 at z_ref)."""
+    return 0.5 * cosv + 0.5 / (1.0 + (z / z_ref) ** 2)
+
+
 def frame_inputs(scene, cams, H, W, margin, sigma, blob_frac, invalid_frac, seed, device="cpu",
-                 chunk=None):
+                 chunk=None, structured=False):
     import torch
     F = cams.shape[0]
     c = scene.n_classes
@@ -357,8 +397,13 @@ def frame_inputs(scene, cams, H, W, margin, sigma, blob_frac, invalid_frac, seed
     gts = torch.empty((F, H, W), dtype=torch.int64, device=device) if F * H * W <= 50_000_000 else None
     for f0 in range(0, F, chunk):
         f1 = min(F, f0 + chunk)
-        gt = ground_truth(scene, cams[f0:f1], H, W, device=device)
-        make_probs(gt, c, margin, sigma, blob_frac, seed=seed * 100003 + f0, out=probs[f0:f1])
+        if structured:
+            gt, z, cv = ground_truth(scene, cams[f0:f1], H, W, device=device, geometry=True)
+            qual = view_quality(z, cv)
+        else:
+            gt, qual = ground_truth(scene, cams[f0:f1], H, W, device=device), None
+        make_probs(gt, c, margin, sigma, blob_frac, seed=seed * 100003 + f0, out=probs[f0:f1], quality=qual,
+                   shift_px=2 if structured else 0)
         g = torch.Generator(device=device)
         g.manual_seed(seed * 31337 + f0)
         if invalid_frac > 0:
@@ -370,12 +415,14 @@ def frame_inputs(scene, cams, H, W, margin, sigma, blob_frac, invalid_frac, seed
     return probs, valid, gts
 
 
-def config1(device="cpu", seed=0, n_frames=20, H=120, W=160):
-    """Plain FP32 parity workload: 2,100-triangle room, c = 13, 20 frames at 160x120."""
+def config1(device="cpu", seed=0, n_frames=20, H=120, W=160, structured=False):
+    """Plain FP32 parity workload: 2,100-triangle room, c = 13, 20 frames at
+    160x120.  ``structured`` makes the probability noise depend on the view
+    (see make_probs); the learned weighting trains and is judged on both."""
     sc = room_scene(seed=seed, room=(6.0, 5.0, 3.0), n_boxes=6, n_classes=13, room_grid=13, box_grid=1)
     cams = circle_cameras(sc, n_frames, W, H)
     probs, valid, gt = frame_inputs(sc, cams, H, W, margin=4.0, sigma=1.5, blob_frac=0.10,
-                                    invalid_frac=0.0, seed=seed, device=device)
+                                    invalid_frac=0.0, seed=seed, device=device, structured=structured)
     return FrameInputs(sc, cams, H, W, probs, valid, gt, s=1, scheme=1)
 
 

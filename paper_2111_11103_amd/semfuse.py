@@ -66,8 +66,20 @@ def lib():
             L.lf_rasterize.argtypes = [_p, _p, _i32, _i32, _i32, _p, _p, _p, _p, _i64, _p]
             L.lf_free_mesh.argtypes = [_p]
             L.lf_free_mesh.restype = None
+            L.lf_profile_enable.argtypes = [_p, _i32]
+            L.lf_profile_read.argtypes = [_p, _p]
+            L.lf_mlp_sizes.argtypes = [C.POINTER(_i32), C.POINTER(_i64)]
+            L.lf_mlp_pack.argtypes = [_p, _p, _p]
+            L.lf_mlp_bind.argtypes = [_p, _p]
+            L.lf_mlp_forward.argtypes = [_p, _p, _i64, _p, _p]
+            L.lf_mlp_grad.argtypes = [_p, _p, _p, _i64, _p, _p, _p]
+            L.lf_adam_step.argtypes = [_p, _p, _p, _p, _i64, C.c_float, C.c_float, C.c_float, C.c_float, _i32, _p]
+            L.lf_extract_features.argtypes = [_p, _p, _i32, _i32, _i32, _p, _i32, _p, _p, _p, _p, _p, _p, _p, _i64,
+                                              _p, _p, _i64, _p]
             for name in ("lf_mesh_sizes", "lf_load_mesh", "lf_reset", "lf_frame_ws_bytes", "lf_fuse_frames",
-                         "lf_finalize", "lf_render_labels", "lf_rasterize"):
+                         "lf_finalize", "lf_render_labels", "lf_rasterize", "lf_profile_enable", "lf_profile_read",
+                         "lf_mlp_sizes", "lf_mlp_pack", "lf_mlp_bind", "lf_mlp_forward", "lf_mlp_grad",
+                         "lf_adam_step", "lf_extract_features"):
                 getattr(L, name).restype = _i32
             _lib = L
     return _lib
@@ -93,6 +105,20 @@ def _need_cuda(t, name, dtype=None):
         raise ValueError(f"{name} must be a device tensor")
     if dtype is not None and t.dtype != dtype:
         raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+
+
+def _probs_arg(probs, scale):
+    """(dtype enum, strides array, scale) of a probability tensor [F, c, H, W]."""
+    _need_cuda(probs, "probs")
+    if probs.dtype == torch.float32:
+        dt = F32
+    elif probs.dtype == torch.uint8:
+        dt = FP8_E4M3
+        _need_cuda(scale, "scale", torch.float32)
+        scale = scale.contiguous()
+    else:
+        raise TypeError("probs must be float32 or uint8 E4M3 codes")
+    return dt, (C.c_int64 * 4)(*probs.stride()), scale
 
 
 def version() -> str:
@@ -180,19 +206,11 @@ class Mesh:
         cams = cams.contiguous()
         if cams.shape != (F, 16):
             raise ValueError("cams must be [F, 16]")
-        if probs.dtype == torch.float32:
-            dt = F32
-        elif probs.dtype == torch.uint8:
-            dt = FP8_E4M3
-            _need_cuda(scale, "scale", torch.float32)
-            scale = scale.contiguous()
-        else:
-            raise TypeError("probs must be float32 or uint8 E4M3 codes")
+        dt, strides, scale = _probs_arg(probs, scale)
         if valid is not None:
             valid = valid.contiguous()
         if l_out is not None and (not l_out.is_contiguous() or tuple(l_out.shape) != (F, H, W)):
             raise ValueError("l_out must be a contiguous [F, H, W] int32 tensor")
-        strides = (C.c_int64 * 4)(*probs.stride())
         b = max(1, min(int(batch), F))
         if ws is None:
             ws = self.frame_ws(H, W, b, weighting, scatter_mode)
@@ -241,3 +259,108 @@ class Mesh:
         _check(lib().lf_rasterize(self._h, _ptr(cams), F, H, W, _ptr(out["tri"]), _ptr(out["l"]), _ptr(out["z"]),
                                   _ptr(ws), ws.numel(), _stream()))
         return out
+
+    # -- learned weighting ------------------------------------------------------------
+    def bind_mlp(self, mlp):
+        """lf_mlp_bind: fuse with ``weighting=W_LEARNED`` using ``mlp`` (a WeightMLP
+        or a packed uint8 tensor; None unbinds).  The mesh keeps a reference."""
+        packed = None if mlp is None else (mlp.packed if hasattr(mlp, "packed") else mlp)
+        _check(lib().lf_mlp_bind(self._h, _ptr(packed)))
+        self._mlp = packed
+
+    def extract_features(self, cams, probs, *, scale=None, valid=None, labels=None, cap=None, want_pix=True,
+                         batch=8):
+        """lf_extract_features -> (phi [n, 8], target [n] or None, pix [n] or None);
+        observations come in unspecified order."""
+        F, c, H, W = probs.shape
+        if c != self.c:
+            raise ValueError(f"probs has {c} classes, mesh has {self.c}")
+        _need_cuda(cams, "cams", torch.float32)
+        _need_cuda(valid, "valid", torch.uint8)
+        _need_cuda(labels, "labels", torch.uint8)
+        cams = cams.contiguous()
+        dt, strides, scale = _probs_arg(probs, scale)
+        if valid is not None:
+            valid = valid.contiguous()
+        cap = F * H * W if cap is None else int(cap)
+        phi = torch.empty((max(cap, 1), 8), dtype=torch.float32, device=self.device)
+        tgt = torch.empty(max(cap, 1), dtype=torch.float32, device=self.device) if labels is not None else None
+        pix = torch.empty(max(cap, 1), dtype=torch.int32, device=self.device) if want_pix else None
+        count = torch.zeros(1, dtype=torch.int64, device=self.device)
+        ws = self.frame_ws(H, W, max(1, min(batch, F)), W_LEARNED, SCATTER_ATOMIC)
+        _check(lib().lf_extract_features(self._h, _ptr(cams), F, H, W, _ptr(probs), dt, strides, _ptr(scale),
+                                         _ptr(valid), _ptr(labels), _ptr(phi), _ptr(tgt), _ptr(pix), cap, _ptr(count),
+                                         _ptr(ws), ws.numel(), _stream()))
+        n = min(int(count.item()), cap)
+        return phi[:n], (tgt[:n] if tgt is not None else None), (pix[:n] if pix is not None else None)
+
+
+def mlp_sizes():
+    """(number of binary32 master parameters, bytes of the packed form)."""
+    n, b = _i32(), _i64()
+    _check(lib().lf_mlp_sizes(C.byref(n), C.byref(b)))
+    return n.value, b.value
+
+
+class WeightMLP:
+    """Parameters of the learned weight network on one device: binary32 master
+    copy, Adam moments and the packed bfloat16 form the kernels read."""
+
+    def __init__(self, device="cuda", params: torch.Tensor | None = None, seed: int = 0):
+        n, nb = mlp_sizes()
+        self.n_params = n
+        self.device = torch.device(device)
+        if params is None:
+            params = init_params(seed)
+        params = torch.as_tensor(params, dtype=torch.float32)
+        if params.numel() != n:
+            raise ValueError(f"expected {n} parameters, got {params.numel()}")
+        self.params = params.reshape(-1).to(self.device).contiguous()
+        self.m = torch.zeros(n, dtype=torch.float32, device=self.device)
+        self.v = torch.zeros(n, dtype=torch.float32, device=self.device)
+        self.grad_buf = torch.empty(n, dtype=torch.float32, device=self.device)
+        self.loss_buf = torch.empty(1, dtype=torch.float32, device=self.device)
+        self.packed = torch.empty(nb, dtype=torch.uint8, device=self.device)
+        self.t = 0
+        self.pack()
+
+    def pack(self):
+        _check(lib().lf_mlp_pack(_ptr(self.params), _ptr(self.packed), _stream()))
+
+    def forward(self, phi: torch.Tensor) -> torch.Tensor:
+        _need_cuda(phi, "phi", torch.float32)
+        phi = phi.contiguous()
+        w = torch.empty(phi.shape[0], dtype=torch.float32, device=self.device)
+        _check(lib().lf_mlp_forward(_ptr(self.packed), _ptr(phi), phi.shape[0], _ptr(w), _stream()))
+        return w
+
+    def loss_grad(self, phi: torch.Tensor, target: torch.Tensor):
+        """(loss [1] tensor, gradient [n_params] tensor) -- views of internal buffers."""
+        _need_cuda(phi, "phi", torch.float32)
+        _need_cuda(target, "target", torch.float32)
+        phi, target = phi.contiguous(), target.contiguous()
+        _check(lib().lf_mlp_grad(_ptr(self.packed), _ptr(phi), _ptr(target), phi.shape[0], _ptr(self.grad_buf),
+                                 _ptr(self.loss_buf), _stream()))
+        return self.loss_buf, self.grad_buf
+
+    def adam(self, grad: torch.Tensor, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        """One Adam step on the master parameters, then repack."""
+        self.t += 1
+        _check(lib().lf_adam_step(_ptr(self.params), _ptr(self.m), _ptr(self.v), _ptr(grad), self.n_params, lr, beta1,
+                                  beta2, eps, self.t, _stream()))
+        self.pack()
+
+
+def init_params(seed: int = 0) -> torch.Tensor:
+    """He-normal weights, zero biases (host float32 [n_params])."""
+    n, _ = mlp_sizes()
+    g = torch.Generator().manual_seed(int(seed))
+    NI, NH = 8, 64
+    p = torch.zeros(n, dtype=torch.float32)
+    o = 0
+    p[o:o + NH * NI] = torch.randn(NH * NI, generator=g) * (2.0 / NI) ** 0.5
+    o += NH * NI + NH
+    p[o:o + NH * NH] = torch.randn(NH * NH, generator=g) * (2.0 / NH) ** 0.5
+    o += NH * NH + NH
+    p[o:o + NH] = torch.randn(NH, generator=g) * (1.0 / NH) ** 0.5
+    return p
