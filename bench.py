@@ -1,23 +1,26 @@
 #!/usr/bin/env python3
 """Benchmark of the label-fusion hot path on one MI355X.
 
-Workload (default): a procedural room of ~500k triangles, SPLIT s = 3
-(~4.5M texels), 300 frames of 640x480 along a smooth random walk, c = 40,
-FP32 probabilities in HBM (NCHW), 15 % wrong-class blobs, 5 % pixels without
-depth.  One step = clear the accumulator, fuse all 300 frames (render to
-triangle/texel ids, scatter-accumulate), normalise + argmax every texel,
-render the labels back into all 300 frames.
+Workload (default): a procedural room of 501,908 triangles, SPLIT s = 3
+(4,517,172 texels), 300 frames of 640x480 along a smooth random walk, c = 40,
+FP32 probabilities resident in HBM in channels-last layout, 15 % wrong-class
+blobs, 5 % pixels without depth.  One step = clear the accumulator, fuse all
+300 frames (render to triangle/texel ids, sort by texel, gather-accumulate),
+normalise + argmax every texel, render the labels back into all 300 frames.
 
-Prints one JSON line: fused pixels/s, the scatter kernel's fraction of the
-HBM roofline (algorithmic bytes / its HIP-event-timed duration), and the CPU
-oracle's rate on a bounded sample.
+Prints one JSON line: fused pixels/s, the dominant kernel's fraction of the
+HBM roofline (algorithmic bytes / its HIP-event-timed launch duration), the
+CPU oracle's rate on a bounded sample, the other input forms' throughput
+(NCHW, FP8, w^(I), learned weight) and the label accuracy of the plain,
+reduced-precision and learned forms on held-out small scenes.
 """
 from __future__ import annotations
 
 import argparse
+import ctypes as C
+import hashlib
 import json
 import os
-import subprocess
 import sys
 import time
 
@@ -26,16 +29,42 @@ sys.path.insert(0, ROOT)
 
 METRIC = "fused pixels/sec (c=40, 640×480) + % HBM roofline; learned/BF16 vs plain at label acc"
 HBM_PEAK_GBS = 8000.0
+STAGES = ["raster", "resolve", "scatter", "counts", "finalize", "render", "reset", "mlp"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_seg_gather16_room500k_640x480_c40.json")
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+class Prof(C.Structure):
+    _fields_ = [("ms", C.c_double * 8), ("launches", C.c_int64 * 8)]
+
+
+def kernel_source_digest():
+    h = hashlib.sha256()
+    for f in ("sorted.hip", "internal.h", "accum.h"):
+        with open(os.path.join(ROOT, "paper_2111_11103_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(batch):
+    """HBM bytes per gather launch from the committed counter summary, or
+    None when the kernel's sources or the batch differ from those measured."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_digest") != kernel_source_digest() or t.get("batch") != batch:
+        return None
+    return t.get("bytes_per_launch")
+
+
 def cpu_baseline(work, n_frames: int):
-    """The CPU oracle (raster on all host cores, binary64 fusion) on the first
-    ``n_frames`` frames of the same workload; fused pixels/s."""
-    import numpy as np
+    """The CPU oracle (raster on the host's cores, binary64 fusion) on the
+    first ``n_frames`` frames of the same workload; fused pixels/s."""
     import oracle
     sc = work.scene
     threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
@@ -46,12 +75,106 @@ def cpu_baseline(work, n_frames: int):
     t0 = time.perf_counter()
     om = oracle.Mesh(sc.vertices, sc.faces, s=work.s, scheme=work.scheme)
     _, l = om.raster_frames(cams, work.H, work.W, threads=threads)
-    A, Ws = oracle.fuse(om.n_texels, sc.n_classes, l, probs, valid)
+    oracle.fuse(om.n_texels, sc.n_classes, l, probs, valid)
     dt = time.perf_counter() - t0
     px = n_frames * work.H * work.W
     return {"value": px / dt, "unit": "fused pixels/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {n_frames} of {len(work.cams)} frames, raster on {threads} threads, "
-                      f"binary64 fusion on 1 thread, {dt:.1f} s"}
+            "sample": f"first {n_frames} of {len(work.cams)} frames of the same workload (raster on {threads} "
+                      f"threads, binary64 fusion on 1 thread), {dt:.1f} s"}
+
+
+def accuracy_report(log_fn):
+    """Pixel accuracy of the fusion forms on held-out small scenes (2,100
+    triangles, c = 13, 20 frames 160x120, view-dependent noise, seeds
+    200-209); the learned weight is first trained on seeds 100-149."""
+    import numpy as np
+    import torch
+    from paper_2111_11103_amd import learned as LR
+    from paper_2111_11103_amd import scenes as S
+    from paper_2111_11103_amd import semfuse as sf
+    t0 = time.time()
+    phi, tgt = LR.training_set(range(100, 150), device="cuda", structured=True)
+    mlp = sf.WeightMLP("cuda", seed=0)
+    LR.train(mlp, phi, tgt, steps=1500, batch=32768, lr=2e-3)
+    del phi, tgt
+    acc = {k: [] for k in ("input", "pixel", "image", "learned", "bf16_texture", "fp16_texture", "fp8_input")}
+    for sd in range(200, 210):
+        w = S.config1(device="cuda", seed=sd, structured=True)
+        r = LR.evaluate(w, mlp)
+        for k in ("input", "pixel", "image", "learned"):
+            acc[k].append(r[k])
+        cams = torch.as_tensor(w.cams, dtype=torch.float32, device="cuda")
+        l_rows = torch.empty((len(w.cams), w.H, w.W), dtype=torch.int32, device="cuda")
+        seen = None
+        for name, dt, fp8 in (("bf16_texture", torch.bfloat16, False), ("fp16_texture", torch.float16, False),
+                              ("fp8_input", torch.float32, True)):
+            mesh = LR.scene_mesh(w, "cuda")
+            if fp8:
+                q, scale = S.quantize_fp8(w.probs)
+                mesh.fuse_frames(cams, q, scale=scale, valid=w.valid, l_out=l_rows)
+            else:
+                mesh.fuse_frames(cams, w.probs, valid=w.valid, l_out=l_rows)
+            _, lab = mesh.finalize(dt)
+            out = mesh.render_labels(lab, l=l_rows, valid=w.valid)
+            seen = (l_rows >= 0) & (w.valid != 0)
+            acc[name].append(float((out[seen].long() == w.gt[seen]).float().mean()))
+    res = {k: float(np.mean(v)) for k, v in acc.items()}
+    log_fn(f"[bench] accuracy report in {time.time() - t0:.1f} s: {res}")
+    res["workload"] = ("held-out rooms (2,100 triangles, c=13, 20 frames 160x120, view-dependent noise, seeds "
+                       "200-209); learned weight trained on seeds 100-149 by the library's kernels")
+    return res
+
+
+def batched_report(log_fn, steps=2, scale=1.0):
+    """Batched form: 16 rooms of uneven size (50k-2M triangles, SPLIT s = 1-4,
+    100-1000 frames each at 640x480 or 1296x968, c = 40, cycled input pools),
+    each scene's launch parameters chosen by the autotuner, the whole job
+    (clear, fuse, normalise, render back, for every scene) captured as one HIP
+    graph and replayed."""
+    import torch
+    from paper_2111_11103_amd import scenes as S
+    from paper_2111_11103_amd import semfuse as sf
+    from paper_2111_11103_amd import tune
+    t0 = time.time()
+    jobs, choices = [], []
+    n_px = n_frames = n_tex = 0
+    for i, p in enumerate(S.config4(device="cuda", scale=scale)):
+        dev = p.probs.device
+        mesh = sf.Mesh(torch.as_tensor(p.scene.vertices, device=dev), torch.as_tensor(p.scene.faces, device=dev),
+                       n_classes=p.scene.n_classes, s=p.s, scheme=sf.SPLIT, keep_weights=False)
+        probs = p.probs.to(memory_format=torch.channels_last)
+        cams = torch.as_tensor(p.cams, device=dev)
+        best = tune.autotune(mesh, cams[:p.pool], probs, valid=p.valid, probe_frames=p.pool)
+        choices.append({k: best[k] for k in ("tile", "gather_unroll", "batch", "scatter_mode", "cached")})
+        jobs.append(mesh.job(cams, probs, valid=p.valid, pool=p.pool, batch=best["batch"],
+                             scatter_mode=best["scatter_mode"], images=True))
+        F = len(p.cams)
+        n_frames += F
+        n_px += F * p.H * p.W
+        n_tex += mesh.n_texels
+        log_fn(f"[bench] batched scene {i}: T={p.scene.n_faces} s={p.s} texels={mesh.n_texels} {F} frames "
+               f"{p.W}x{p.H} tuned {choices[-1]} ({time.time() - t0:.0f} s)")
+    ws = sf.batch_ws(jobs)
+    torch.cuda.synchronize()
+    te = time.perf_counter()
+    sf.fuse_batch(jobs, ws)
+    torch.cuda.synchronize()
+    eager_s = time.perf_counter() - te
+    log_fn(f"[bench] batched eager pass {eager_s * 1e3:.1f} ms")
+    g = sf.Graph(jobs, ws)
+    g.launch()
+    torch.cuda.synchronize()
+    tg = time.perf_counter()
+    for _ in range(steps):
+        g.launch()
+    torch.cuda.synchronize()
+    graph_s = (time.perf_counter() - tg) / steps
+    log_fn(f"[bench] batched graph replay {graph_s * 1e3:.1f} ms ({n_px / graph_s / 1e9:.2f} G px/s)")
+    return {"value": n_px / graph_s, "unit": "fused pixels/s", "ms_per_replay": graph_s * 1e3,
+            "eager_ms": eager_s * 1e3, "replays": steps, "scenes": len(jobs), "frames": n_frames, "pixels": n_px,
+            "texels": n_tex, "workspace_bytes": ws.numel(), "tuning": choices,
+            "workload": "16 rooms (seed 1000+i, T=50k*40^(i/15), SPLIT s=1+i%4, 100+60i frames, 640x480 even i / "
+                        "1296x968 odd i, c=40, input pools of 16 / 8 frames), one captured graph"}
 
 
 def main():
@@ -60,12 +183,17 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--frames", type=int, default=300)
-    ap.add_argument("--batch", type=int, default=16)
+    ap.add_argument("--batch", type=int, default=32)
     ap.add_argument("--scatter", type=int, default=0, help="0 auto, 1 atomic, 2 sorted")
     ap.add_argument("--weighting", type=int, default=0, help="0 w^(P), 1 w^(I)")
-    ap.add_argument("--layout", default="nchw", choices=["nchw", "nhwc"])
-    ap.add_argument("--cpu-frames", type=int, default=96)
+    ap.add_argument("--layout", default="nhwc", choices=["nchw", "nhwc"])
+    ap.add_argument("--cpu-frames", type=int, default=200)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-forms", action="store_true", help="skip the NCHW / FP8 / w^(I) / learned throughput legs")
+    ap.add_argument("--no-accuracy", action="store_true", help="skip the label-accuracy report")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 16-scene batched graph leg")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU frame sharding is a design "
@@ -79,14 +207,21 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "launches": 3}), flush=True)
+        return
     t0 = time.time()
     log(f"[bench] generating workload: {args.frames} frames 640x480 c=40 on {torch.cuda.get_device_name(0)}")
     work = S.config2(device="cuda", n_frames=args.frames)
     sc = work.scene
-    probs = work.probs
-    if args.layout == "nhwc":
-        probs = probs.to(memory_format=torch.channels_last)
-        work.probs = probs
+    probs_nchw = work.probs
+    probs = probs_nchw.to(memory_format=torch.channels_last) if args.layout == "nhwc" else probs_nchw
     torch.cuda.synchronize()
     log(f"[bench] workload ready in {time.time() - t0:.1f} s: T={sc.n_faces} V={sc.vertices.shape[0]}")
     F, c, H, W = probs.shape
@@ -98,48 +233,65 @@ def main():
     tex = torch.empty((mesh.n_texels, c), dtype=torch.float32, device=dev)
     lab = torch.empty(mesh.n_texels, dtype=torch.uint8, device=dev)
     valid = work.valid
-    ws = mesh.frame_ws(H, W, args.batch, args.weighting, args.scatter)
     L = sf.lib()
 
-    def step():
-        mesh.reset()
-        mesh.fuse_frames(cams, probs, valid=valid, weighting=args.weighting, l_out=l_out, batch=args.batch,
-                         scatter_mode=args.scatter, ws=ws)
-        sf._check(L.lf_finalize(mesh._h, sf._ptr(tex), sf.F32, sf._ptr(lab), sf._stream()))
-        mesh.render_labels(lab, l=l_out, valid=valid, out=labels_img)
+    def make_step(p, weighting, scale=None, batch=args.batch, scatter=args.scatter):
+        ws = mesh.frame_ws(H, W, batch, weighting, scatter)
 
-    for i in range(args.warmup):
-        step()
+        def step():
+            mesh.reset()
+            mesh.fuse_frames(cams, p, scale=scale, valid=valid, weighting=weighting, l_out=l_out, batch=batch,
+                             scatter_mode=scatter, ws=ws)
+            sf._check(L.lf_finalize(mesh._h, sf._ptr(tex), sf.F32, sf._ptr(lab), sf._stream()))
+            mesh.render_labels(lab, l=l_out, valid=valid, out=labels_img)
+        return step, ws
+
+    def timed(step, steps, warmup, tag):
+        for i in range(warmup):
+            step()
+            torch.cuda.synchronize()
+            log(f"[bench] {tag}: warmup {i + 1}/{warmup} done")
+        prof = Prof()
+        sf._check(L.lf_profile_enable(mesh._h, 1))
         torch.cuda.synchronize()
-        log(f"[bench] warmup {i + 1}/{args.warmup} done")
-    import ctypes as C
-    prof = type("P", (C.Structure,), {"_fields_": [("ms", C.c_double * 8), ("launches", C.c_int64 * 8)]})()
-    sf._check(L.lf_profile_enable(mesh._h, 1))
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    for i in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    t_total = time.perf_counter() - t_start
-    sf._check(L.lf_profile_read(mesh._h, C.byref(prof)))
-    sf._check(L.lf_profile_enable(mesh._h, 0))
+        t_start = time.perf_counter()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        t_total = time.perf_counter() - t_start
+        sf._check(L.lf_profile_read(mesh._h, C.byref(prof)))
+        sf._check(L.lf_profile_enable(mesh._h, 0))
+        log(f"[bench] {tag}: {steps} steps, {1000 * t_total / steps:.3f} ms/step")
+        return t_total, prof
+
+    step, ws = make_step(probs, args.weighting)
+    t_total, prof = timed(step, args.steps, args.warmup, "headline")
     ms_step = 1000.0 * t_total / args.steps
     npx = F * H * W
     value = npx / (t_total / args.steps)
-    stages = ["raster", "resolve", "scatter", "counts", "finalize", "render", "reset", "mlp"]
-    stage_ms = {stages[k]: prof.ms[k] / args.steps for k in range(8) if prof.launches[k]}
-    log(f"[bench] {args.steps} steps in {t_total:.3f} s: {ms_step:.3f} ms/step; per stage ms/step {stage_ms}")
-    # roofline of the dominant kernel (scatter): algorithmic bytes = every
-    # pixel's c class values + its valid byte; duration from the HIP events
+    stage_ms = {STAGES[k]: prof.ms[k] / args.steps for k in range(8) if prof.launches[k]}
+    log(f"[bench] {value / 1e9:.3f} G px/s; per stage ms/step {stage_ms}")
+
+    # roofline of the dominant kernel (the gather, stage 2): algorithmic bytes
+    # = every pixel's c class values + its valid byte, per launch (one launch
+    # per batch of frames); duration = mean of the HIP-event-timed launches
     in_bytes = {torch.float32: 4, torch.uint8: 1}[probs.dtype]
     per_px = c * in_bytes + 1
-    scat_launches = prof.launches[2] / args.steps
-    scat_ms = prof.ms[2] / prof.launches[2]
-    px_per_launch = npx / scat_launches
+    launches = prof.launches[2]
+    scat_ms = prof.ms[2] / launches
+    px_per_launch = npx * args.steps / launches
     achieved = px_per_launch * per_px / (scat_ms * 1e-3) / 1e9
-    # whole-step bytes: compulsory traffic B_min over the measured step time
+    # texel rows each launch reads and writes back once (distinct valid rows per batch)
+    rows = 0
+    for f0 in range(0, F, args.batch):
+        lb = l_out[f0:f0 + args.batch]
+        rows += int(torch.unique(lb[(lb >= 0) & (valid[f0:f0 + args.batch] != 0)]).numel())
+    n_batches = (F + args.batch - 1) // args.batch
+    rows_per_launch = rows / n_batches
+    rmw_bytes = rows_per_launch * 2 * c * 4
     b_min = npx * per_px + mesh.n_texels * c * 4
-    log(f"[bench] B_min {b_min / 1e9:.2f} GB -> {b_min / (t_total / args.steps) / 1e9:.0f} GB/s whole step")
+    log(f"[bench] gather {scat_ms:.3f} ms/launch; {rows_per_launch:.0f} rows per launch; "
+        f"B_min {b_min / 1e9:.2f} GB -> {b_min / (t_total / args.steps) / 1e9:.0f} GB/s whole step")
     result = {
         "metric": METRIC,
         "value": value,
@@ -157,18 +309,63 @@ def main():
                                f"{F} frames {W}x{H}, c={c}, FP32 {args.layout.upper()} probabilities, "
                                f"weighting {'w^(I)' if args.weighting else 'w^(P)'}",
                    "frames": F, "H": H, "W": W, "classes": c, "triangles": sc.n_faces, "texels": mesh.n_texels,
-                   "batch": args.batch, "scatter_mode": args.scatter},
+                   "batch": args.batch, "scatter_mode": args.scatter, "frame_ws_bytes": ws.numel()},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "scatter", "kernel_ms": scat_ms, "bytes_per_px": per_px},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.batch),
+                     "kernel": "k_seg_gather16", "kernel_ms": scat_ms, "launches": launches,
+                     "bytes_per_px": per_px, "px_per_launch": px_per_launch,
+                     "row_rmw_bytes_per_launch": rmw_bytes,
+                     "achieved_incl_row_rmw": (px_per_launch * per_px + rmw_bytes) / (scat_ms * 1e-3) / 1e9},
         "step_hbm_frac": b_min / (t_total / args.steps) / 1e9 / HBM_PEAK_GBS,
         "stage_ms_per_step": stage_ms,
     }
+
+    if not args.no_forms:
+        forms = {}
+        legs = [("nchw_atomic", lambda: make_step(probs_nchw, 0, scatter=0)[0], None)]
+        legs.append(("w_image", lambda: make_step(probs, 1)[0], None))
+        mlp_holder = {}
+
+        def learned_step():
+            mlp_holder["mlp"] = sf.WeightMLP("cuda", seed=0)
+            mesh.bind_mlp(mlp_holder["mlp"])
+            return make_step(probs, sf.W_LEARNED)[0]
+        legs.append(("learned", learned_step, None))
+        for name, mk, _ in legs:
+            st = mk()
+            tt, pr = timed(st, 2, 1, name)
+            forms[name] = {"value": 2 * npx / tt, "ms_per_step": 1000 * tt / 2,
+                           "stage_ms_per_step": {STAGES[k]: pr.ms[k] / 2 for k in range(8) if pr.launches[k]}}
+        mesh.bind_mlp(None)
+        # FP8 E4M3 input with a per-pixel scale (quantised in chunks, channels-last)
+        q = torch.empty((F, c, H, W), dtype=torch.uint8, device=dev).to(memory_format=torch.channels_last)
+        qs = torch.empty((F, H, W), dtype=torch.float32, device=dev)
+        for f0 in range(0, F, 50):
+            qq, ss = S.quantize_fp8(probs[f0:f0 + 50])
+            q[f0:f0 + 50] = qq
+            qs[f0:f0 + 50] = ss
+        del qq, ss
+        st = make_step(q, 0, scale=qs)[0]
+        tt, pr = timed(st, 2, 1, "fp8")
+        forms["fp8_input"] = {"value": 2 * npx / tt, "ms_per_step": 1000 * tt / 2,
+                              "stage_ms_per_step": {STAGES[k]: pr.ms[k] / 2 for k in range(8) if pr.launches[k]}}
+        del q, qs
+        result["forms"] = forms
+        log(f"[bench] forms: " + ", ".join(f"{k} {v['value'] / 1e9:.2f} G px/s" for k, v in forms.items()))
+
     if not args.no_cpu:
         log(f"[bench] CPU oracle on {args.cpu_frames} frames ...")
-        result["cpu_baseline"] = cpu_baseline(work, args.cpu_frames)
+        result["cpu_baseline"] = cpu_baseline(work, min(args.cpu_frames, F))
     else:
         result["cpu_baseline"] = None
+
+    if not args.no_accuracy:
+        result["accuracy"] = accuracy_report(log)
+
+    if not args.no_batched:
+        torch.cuda.empty_cache()
+        result["batched"] = batched_report(log)
+
     print(json.dumps(result), flush=True)
 
 

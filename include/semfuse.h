@@ -154,6 +154,71 @@ lf_status lf_rasterize(lf_mesh mesh, const float* d_cams, int32_t F, int32_t H, 
                        int32_t* d_tri, int32_t* d_l, float* d_z, void* d_ws, int64_t ws_bytes,
                        hipStream_t stream);
 
+/* ---- Tuning ------------------------------------------------------------------
+ * Launch parameters of a mesh's kernels that do not change results: the
+ * raster tile edge (16 or 32 pixels; default 32) and the number of
+ * observations each row keeps in flight in the texel-sorted gather (4 or 8;
+ * default 8).  Frame batch size and scatter mode are per-call arguments.
+ * lf_frame_ws_bytes depends on the tile: query it after lf_set_tuning. */
+typedef struct {
+    int32_t tile;
+    int32_t gather_unroll;
+} lf_tuning;
+lf_status lf_set_tuning(lf_mesh mesh, const lf_tuning* tuning);
+lf_status lf_get_tuning(lf_mesh mesh, lf_tuning* tuning);
+
+/* ---- Many scenes in one call, and as one captured graph ---------------------
+ * One job = one complete fusion of a scene (Sections 3.2 and 3.3): clear its
+ * accumulator, fuse its F frames (as lf_fuse_frames), normalise every texel
+ * (as lf_finalize) and optionally render the labels back (as
+ * lf_render_labels from the stored rows).
+ *  pool      0: frame f reads input frame f; > 0: frame f reads input frame
+ *            f % pool of d_probs / d_scale / d_valid (a cycled input pool;
+ *            cameras, rows and images stay per frame);
+ *  d_l_out   [F][H][W] rows or NULL (required when d_images is set);
+ *  d_tex_out [n_texels][c] in tex_dtype or NULL;  d_labels [n_texels]
+ *            (required);  d_images [F][H][W] uint8 or NULL.
+ * Jobs run one after another on `stream` and share one frame workspace of
+ * lf_batch_ws_bytes bytes (the largest any job needs). */
+typedef struct {
+    lf_mesh mesh;
+    const float* d_cams;
+    int32_t F, H, W;
+    const void* d_probs;
+    int32_t prob_dtype;
+    int64_t strides[4];
+    const float* d_scale;
+    const uint8_t* d_valid;
+    int32_t pool;
+    int32_t weighting;
+    int32_t batch;
+    int32_t scatter_mode;
+    int32_t* d_l_out;
+    void* d_tex_out;
+    int32_t tex_dtype;
+    uint8_t* d_labels;
+    uint8_t* d_images;
+} lf_scene_job;
+
+lf_status lf_batch_ws_bytes(const lf_scene_job* jobs, int32_t n_jobs, int64_t* bytes);
+
+/* Run the jobs.  Every job is checked before anything is enqueued. */
+lf_status lf_fuse_batch(const lf_scene_job* jobs, int32_t n_jobs, void* d_ws, int64_t ws_bytes,
+                        hipStream_t stream);
+
+/* Capture the jobs' whole launch sequence on `stream` (not the legacy
+ * default stream) into an executable HIP graph; lf_graph_launch replays it
+ * on any stream.  The sequence holds kernels only (buffers are cleared by
+ * kernels, no host synchronisation, no allocation), so replays are
+ * independent.  Every buffer the jobs name is baked into the graph: keep them
+ * alive and in place while the graph exists; new input values in those
+ * buffers are picked up by the next replay.  Profiling must be off. */
+typedef struct lf_graph_s* lf_graph;
+lf_status lf_graph_capture_batch(const lf_scene_job* jobs, int32_t n_jobs, void* d_ws, int64_t ws_bytes,
+                                 hipStream_t stream, lf_graph* out);
+lf_status lf_graph_launch(lf_graph graph, hipStream_t stream);
+void lf_graph_free(lf_graph graph);
+
 /* ---- Learned per-observation weight ---------------------------------------
  * Section 3.2.2 weights every observation k of a texel by w_k, with the two
  * fixed choices w^(P) = 1 and w^(I) = 1/|K_i ∩ K_x|.  LF_W_LEARNED takes w_k

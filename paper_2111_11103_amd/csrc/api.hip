@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "../../include/semfuse.h"
@@ -144,14 +145,14 @@ struct FrameLayout {
   bool sorted;
 };
 
-int64_t tiles_of(int H, int W) {
-  return (int64_t)((W + kTileSize - 1) / kTileSize) * ((H + kTileSize - 1) / kTileSize);
+int64_t tiles_of(int H, int W, int ts) {
+  return (int64_t)((W + ts - 1) / ts) * ((H + ts - 1) / ts);
 }
 
 FrameLayout frame_layout(const MeshDev& m, int H, int W, int B, int weighting, int scatter_mode) {
   FrameLayout L{};
   const int64_t HW = (int64_t)H * W;
-  L.ntiles = tiles_of(H, W);
+  L.ntiles = tiles_of(H, W, m.tile);
   L.list_cap = 4 * m.T + 64 * L.ntiles + 1024;
   L.sorted = scatter_mode != LF_SCATTER_ATOMIC;
   int64_t o = 0;
@@ -282,6 +283,8 @@ lf_status lf_load_mesh(const lf_mesh_opts* opts, const float* d_vertices, int64_
   d.accum_dtype = opts->accum_dtype;
   d.n_per = per_face ? 0 : (int32_t)per_tri(opts->s_uniform, opts->scheme);
   d.z_near = opts->z_near;
+  d.tile = kTileSize;
+  d.gather_unroll = 8;
 
   LF_TRY(launch_zero(d.err, 4, stream), "clear flag");
   if (per_face)
@@ -330,86 +333,280 @@ lf_status lf_frame_ws_bytes(lf_mesh mesh, int32_t H, int32_t W, int32_t batch, i
   return LF_OK;
 }
 
-lf_status lf_fuse_frames(lf_mesh mesh, const float* d_cams, int32_t F, int32_t H, int32_t W, const void* d_probs,
-                         int32_t prob_dtype, const int64_t* h_strides, const float* d_scale, const uint8_t* d_valid,
-                         int32_t weighting, int32_t* d_l_out, void* d_ws, int64_t ws_bytes, int32_t batch,
-                         int32_t scatter_mode, hipStream_t stream) {
-  g_err[0] = 0;
-  lf_status st = check_mesh(mesh);
+}  // extern "C"
+
+namespace {
+
+// Everything lf_fuse_frames checks, plus the input pool (0 = none).
+struct FuseArgs {
+  lf_mesh mesh;
+  const float* cams;
+  int32_t F, H, W;
+  const void* probs;
+  int32_t dtype;
+  const int64_t* strides;
+  const float* scale;
+  const uint8_t* valid;
+  int32_t pool;
+  int32_t weighting;
+  int32_t* l_out;
+  int32_t batch, scatter_mode;
+};
+
+// Resolved scatter mode (AUTO -> SORTED iff classes are contiguous) and the
+// frame layout the call needs.
+int resolve_mode(const FuseArgs& a) {
+  return a.scatter_mode != LF_SCATTER_AUTO ? a.scatter_mode
+                                           : (a.strides[1] == 1 ? LF_SCATTER_SORTED : LF_SCATTER_ATOMIC);
+}
+
+FrameLayout fuse_layout(const FuseArgs& a) {
+  const int B = a.batch < a.F ? a.batch : a.F;
+  return frame_layout(a.mesh->d, a.H, a.W, B > 0 ? B : 1, a.weighting,
+                      a.scatter_mode == LF_SCATTER_AUTO ? LF_SCATTER_SORTED : resolve_mode(a));
+}
+
+lf_status check_fuse(const FuseArgs& a, const void* ws, int64_t ws_bytes) {
+  lf_status st = check_mesh(a.mesh);
   if (st != LF_OK) return st;
-  if ((st = check_frames(F, H, W)) != LF_OK) return st;
-  if (F == 0) return LF_OK;
-  if (!d_cams || !d_probs || !h_strides || !d_ws) return fail(LF_EINVAL, "NULL argument");
-  if (prob_dtype != LF_F32 && prob_dtype != LF_FP8_E4M3) return fail(LF_EINVAL, "probabilities must be F32 or FP8_E4M3");
-  if (prob_dtype == LF_FP8_E4M3 && !d_scale) return fail(LF_EINVAL, "FP8 input needs the per-pixel scale");
-  if (weighting < LF_W_PIXEL || weighting > LF_W_LEARNED) return fail(LF_EINVAL, "unknown weighting %d", weighting);
-  if (weighting == LF_W_LEARNED && !mesh->mlp) return fail(LF_ESTATE, "learned weighting needs weights bound by lf_mlp_bind");
-  if (scatter_mode < LF_SCATTER_AUTO || scatter_mode > LF_SCATTER_SORTED) return fail(LF_EINVAL, "bad scatter mode");
+  if ((st = check_frames(a.F, a.H, a.W)) != LF_OK) return st;
+  if (a.F == 0) return LF_OK;
+  if (!a.cams || !a.probs || !a.strides || !ws) return fail(LF_EINVAL, "NULL argument");
+  if (a.dtype != LF_F32 && a.dtype != LF_FP8_E4M3) return fail(LF_EINVAL, "probabilities must be F32 or FP8_E4M3");
+  if (a.dtype == LF_FP8_E4M3 && !a.scale) return fail(LF_EINVAL, "FP8 input needs the per-pixel scale");
+  if (a.weighting < LF_W_PIXEL || a.weighting > LF_W_LEARNED) return fail(LF_EINVAL, "unknown weighting %d", a.weighting);
+  if (a.weighting == LF_W_LEARNED && !a.mesh->mlp)
+    return fail(LF_ESTATE, "learned weighting needs weights bound by lf_mlp_bind");
+  if (a.scatter_mode < LF_SCATTER_AUTO || a.scatter_mode > LF_SCATTER_SORTED) return fail(LF_EINVAL, "bad scatter mode");
   for (int i = 0; i < 4; ++i)
-    if (h_strides[i] < 0) return fail(LF_EINVAL, "negative stride");
-  if (batch < 1) return fail(LF_EINVAL, "batch must be >= 1");
-  if (reinterpret_cast<uintptr_t>(d_ws) & 255) return fail(LF_EINVAL, "workspace must be 256-byte aligned");
-  const MeshDev& d = mesh->d;
-  const int B = batch < F ? batch : F;
-  // texel-sorted aggregation when the classes of a pixel are contiguous
-  const int mode = scatter_mode != LF_SCATTER_AUTO ? scatter_mode
-                                                   : (h_strides[1] == 1 ? LF_SCATTER_SORTED : LF_SCATTER_ATOMIC);
-  const FrameLayout L = frame_layout(d, H, W, B, weighting, scatter_mode == LF_SCATTER_AUTO ? LF_SCATTER_SORTED : mode);
+    if (a.strides[i] < 0) return fail(LF_EINVAL, "negative stride");
+  if (a.batch < 1) return fail(LF_EINVAL, "batch must be >= 1");
+  if (a.pool < 0) return fail(LF_EINVAL, "negative input pool");
+  if (reinterpret_cast<uintptr_t>(ws) & 255) return fail(LF_EINVAL, "workspace must be 256-byte aligned");
+  const FrameLayout L = fuse_layout(a);
   if (ws_bytes < L.total) return fail(LF_ESIZE, "frame workspace %lld < %lld bytes", (long long)ws_bytes, (long long)L.total);
+  return LF_OK;
+}
+
+// The per-batch launch sequence of a checked call.  With an input pool,
+// frame f reads input frame f % pool (cameras and outputs stay per frame);
+// batches never straddle the end of the pool.
+lf_status fuse_impl(const FuseArgs& a, void* d_ws, hipStream_t stream) {
+  if (a.F == 0) return LF_OK;
+  lf_mesh mesh = a.mesh;
+  const MeshDev& d = mesh->d;
+  const int B = a.batch < a.F ? a.batch : a.F;
+  const int mode = resolve_mode(a);
+  const FrameLayout L = fuse_layout(a);
   char* ws = reinterpret_cast<char*>(d_ws);
-  const int64_t HW = (int64_t)H * W;
-  ProbIn in{d_probs, d_scale, d_valid, h_strides[0], h_strides[1], h_strides[2], h_strides[3], prob_dtype};
-  const bool learned = weighting == LF_W_LEARNED;
-  int32_t* cnt = weighting != LF_W_PIXEL ? reinterpret_cast<int32_t*>(ws + L.cnt) : nullptr;
+  const int64_t HW = (int64_t)a.H * a.W;
+  const int H = a.H, W = a.W;
+  const int64_t* st = a.strides;
+  ProbIn in{a.probs, a.scale, a.valid, st[0], st[1], st[2], st[3], a.dtype};
+  const bool learned = a.weighting == LF_W_LEARNED;
+  int32_t* cnt = a.weighting != LF_W_PIXEL ? reinterpret_cast<int32_t*>(ws + L.cnt) : nullptr;
   float4* geo = learned ? reinterpret_cast<float4*>(ws + L.geo) : nullptr;
   float* wpix = learned ? reinterpret_cast<float*>(ws + L.wpix) : nullptr;
   // the sorted path stores batch-relative element offsets in 32 bits
   const bool sorted = mode == LF_SCATTER_SORTED &&
-                      ((int64_t)(B - 1) * h_strides[0] + (int64_t)(H - 1) * h_strides[2] +
-                       (int64_t)(W - 1) * h_strides[3] + (int64_t)d.c * h_strides[1]) < ((int64_t)1 << 32);
+                      ((int64_t)(B - 1) * st[0] + (int64_t)(H - 1) * st[2] + (int64_t)(W - 1) * st[3] +
+                       (int64_t)d.c * st[1]) < ((int64_t)1 << 32);
   int32_t* seg = sorted ? reinterpret_cast<int32_t*>(ws + L.seg) : nullptr;
   LF_TRY(launch_zero(ws + L.tcnt, B * L.ntiles * 4, stream), "clear tile counts");
   if (cnt) LF_TRY(launch_zero(cnt, (int64_t)B * d.n_texels * 4, stream), "clear counts");
   int32_t* rank = sorted ? reinterpret_cast<int32_t*>(ws + L.rank) : nullptr;
-  for (int f0 = 0; f0 < F; f0 += B) {
-    const int nb = (F - f0) < B ? (F - f0) : B;
-    int32_t* lb = d_l_out ? d_l_out + (int64_t)f0 * HW : reinterpret_cast<int32_t*>(ws + L.l);
-    const uint8_t* vb = d_valid ? d_valid + (int64_t)f0 * HW : nullptr;
+  lf_status status;
+  for (int f0 = 0; f0 < a.F;) {
+    int nb = (a.F - f0) < B ? (a.F - f0) : B;
+    const int fi = a.pool > 0 ? f0 % a.pool : f0;     // input frame of the batch's first frame
+    if (a.pool > 0 && nb > a.pool - fi) nb = a.pool - fi;
+    const float* cams_in = a.cams + 16 * (int64_t)(f0 - fi);  // camera of input index fi + k is f0 + k
+    int32_t* lb = a.l_out ? a.l_out + (int64_t)f0 * HW : reinterpret_cast<int32_t*>(ws + L.l);
+    const uint8_t* vb = a.valid ? a.valid + (int64_t)fi * HW : nullptr;
     if (seg) LF_TRY(launch_zero(seg, d.n_texels * 4, stream), "clear segments");
     RasterOut out{lb, nullptr, nullptr, vb, cnt, d.n_texels, seg, rank, geo};
-    if ((st = render_batch(mesh, d_cams, f0, nb, H, W, L, ws, out, stream)) != LF_OK) return st;
+    if ((status = render_batch(mesh, a.cams, f0, nb, H, W, L, ws, out, stream)) != LF_OK) return status;
     if (learned) {
       StageTimer tm(mesh, 7, stream);
-      LF_TRY(launch_mlp_weights(mesh->mlp, in, f0, nb, H, W, d_cams, lb, geo, cnt, d.n_texels, d.c, wpix, stream),
+      LF_TRY(launch_mlp_weights(mesh->mlp, in, fi, nb, H, W, cams_in, lb, geo, cnt, d.n_texels, d.c, wpix, stream),
              "learned weights");
     }
     if (sorted) {
       int32_t* start = reinterpret_cast<int32_t*>(ws + L.start);
       uint32_t* eo = reinterpret_cast<uint32_t*>(ws + L.ent_off);
-      float* ew = weighting != LF_W_PIXEL ? reinterpret_cast<float*>(ws + L.ent_w) : nullptr;
-      float* es = prob_dtype == LF_FP8_E4M3 ? reinterpret_cast<float*>(ws + L.ent_s) : nullptr;
+      float* ew = a.weighting != LF_W_PIXEL ? reinterpret_cast<float*>(ws + L.ent_w) : nullptr;
+      float* es = a.dtype == LF_FP8_E4M3 ? reinterpret_cast<float*>(ws + L.ent_s) : nullptr;
       {
         StageTimer tm(mesh, 3, stream);
         LF_TRY(launch_zero(ws + L.nrows, 4, stream), "clear row count");
         LF_TRY(launch_seg_scan(seg, d.n_texels, reinterpret_cast<int32_t*>(ws + L.sums), start,
                                reinterpret_cast<int32_t*>(ws + L.rows), reinterpret_cast<int32_t*>(ws + L.nrows),
                                stream), "segment scan");
-        LF_TRY(launch_seg_fill(in, f0, nb, H, W, lb, rank, start, eo, ew, es, weighting, cnt, d.n_texels, wpix, stream),
-               "segment fill");
+        LF_TRY(launch_seg_fill(in, fi, nb, H, W, lb, rank, start, eo, ew, es, a.weighting, cnt, d.n_texels, wpix,
+                               stream), "segment fill");
       }
       StageTimer tm(mesh, 2, stream);
-      LF_TRY(launch_seg_gather(d, in, f0, H, W, start, reinterpret_cast<int32_t*>(ws + L.rows),
+      LF_TRY(launch_seg_gather(d, in, fi, H, W, start, reinterpret_cast<int32_t*>(ws + L.rows),
                                reinterpret_cast<int32_t*>(ws + L.nrows), eo, ew, es, stream), "segment gather");
     } else {
       StageTimer tm(mesh, 2, stream);
-      LF_TRY(launch_scatter_atomic(d, in, f0, nb, H, W, lb, weighting, cnt, d.n_texels, wpix, stream), "scatter");
+      LF_TRY(launch_scatter_atomic(d, in, fi, nb, H, W, lb, a.weighting, cnt, d.n_texels, wpix, stream), "scatter");
     }
     if (cnt) {
       StageTimer tm(mesh, 3, stream);
       LF_TRY(launch_clear_counts(lb, vb, nb, H, W, cnt, d.n_texels, stream), "clear counts");
     }
+    f0 += nb;
   }
   return LF_OK;
+}
+
+FuseArgs job_args(const lf_scene_job& j) {
+  return FuseArgs{j.mesh, j.d_cams, j.F, j.H, j.W, j.d_probs, j.prob_dtype, j.strides, j.d_scale, j.d_valid,
+                  j.pool, j.weighting, j.d_l_out, j.batch, j.scatter_mode};
+}
+
+lf_status check_jobs(const lf_scene_job* jobs, int32_t n, const void* ws, int64_t ws_bytes) {
+  if (n < 0) return fail(LF_EINVAL, "negative job count");
+  if (n > 0 && !jobs) return fail(LF_EINVAL, "NULL jobs");
+  for (int i = 0; i < n; ++i) {
+    const lf_scene_job& j = jobs[i];
+    lf_status st = check_fuse(job_args(j), ws, ws_bytes);
+    if (st != LF_OK) return fail(st, "job %d: %s", i, std::string(g_err).c_str());
+    if (!j.d_labels) return fail(LF_EINVAL, "job %d: labels buffer is NULL", i);
+    if (j.d_tex_out && j.tex_dtype != LF_F32 && j.tex_dtype != LF_BF16 && j.tex_dtype != LF_F16)
+      return fail(LF_EINVAL, "job %d: bad texture dtype", i);
+    if (j.d_images && !j.d_l_out) return fail(LF_EINVAL, "job %d: label images need d_l_out", i);
+  }
+  return LF_OK;
+}
+
+lf_status run_jobs(const lf_scene_job* jobs, int32_t n, void* d_ws, hipStream_t stream) {
+  for (int i = 0; i < n; ++i) {
+    const lf_scene_job& j = jobs[i];
+    lf_mesh m = j.mesh;
+    {
+      StageTimer tm(m, 6, stream);
+      LF_TRY(launch_zero(m->d.accum, m->d.n_texels * m->d.c * (m->d.accum_dtype == LF_F32 ? 4 : 2), stream),
+             "clear accumulator");
+      if (m->d.wsum) LF_TRY(launch_zero(m->d.wsum, m->d.n_texels * 4, stream), "clear weights");
+    }
+    lf_status st = fuse_impl(job_args(j), d_ws, stream);
+    if (st != LF_OK) return st;
+    {
+      StageTimer tm(m, 4, stream);
+      LF_TRY(launch_finalize(m->d, j.d_tex_out, j.tex_dtype, j.d_labels, stream), "finalize");
+    }
+    if (j.d_images) {
+      StageTimer tm(m, 5, stream);
+      const int64_t HW = (int64_t)j.H * j.W;
+      // with an input pool, frame f's validity is input frame f % pool's
+      const int chunk = j.pool > 0 ? j.pool : j.F;
+      for (int f0 = 0; f0 < j.F; f0 += chunk) {
+        const int nf = std::min(chunk, j.F - f0);
+        LF_TRY(launch_render(j.d_l_out + f0 * HW, j.d_valid, j.d_labels, nf * HW, j.d_images + f0 * HW, stream),
+               "render");
+      }
+    }
+  }
+  return LF_OK;
+}
+
+}  // namespace
+
+struct lf_graph_s {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+extern "C" {
+
+lf_status lf_fuse_frames(lf_mesh mesh, const float* d_cams, int32_t F, int32_t H, int32_t W, const void* d_probs,
+                         int32_t prob_dtype, const int64_t* h_strides, const float* d_scale, const uint8_t* d_valid,
+                         int32_t weighting, int32_t* d_l_out, void* d_ws, int64_t ws_bytes, int32_t batch,
+                         int32_t scatter_mode, hipStream_t stream) {
+  g_err[0] = 0;
+  const FuseArgs a{mesh, d_cams, F, H, W, d_probs, prob_dtype, h_strides, d_scale, d_valid, 0, weighting, d_l_out,
+                   batch, scatter_mode};
+  lf_status st = check_fuse(a, d_ws, ws_bytes);
+  if (st != LF_OK) return st;
+  return fuse_impl(a, d_ws, stream);
+}
+
+lf_status lf_batch_ws_bytes(const lf_scene_job* jobs, int32_t n, int64_t* bytes) {
+  g_err[0] = 0;
+  if (n < 0 || (n > 0 && !jobs)) return fail(LF_EINVAL, "bad job list");
+  int64_t mx = 256;
+  for (int i = 0; i < n; ++i) {
+    lf_status st = check_mesh(jobs[i].mesh);
+    if (st != LF_OK) return fail(st, "job %d: invalid mesh handle", i);
+    if ((st = check_frames(jobs[i].F, jobs[i].H, jobs[i].W)) != LF_OK) return st;
+    if (jobs[i].batch < 1) return fail(LF_EINVAL, "job %d: batch must be >= 1", i);
+    mx = std::max(mx, fuse_layout(job_args(jobs[i])).total);
+  }
+  if (bytes) *bytes = mx;
+  return LF_OK;
+}
+
+lf_status lf_fuse_batch(const lf_scene_job* jobs, int32_t n, void* d_ws, int64_t ws_bytes, hipStream_t stream) {
+  g_err[0] = 0;
+  lf_status st = check_jobs(jobs, n, d_ws, ws_bytes);
+  if (st != LF_OK) return st;
+  return run_jobs(jobs, n, d_ws, stream);
+}
+
+lf_status lf_graph_capture_batch(const lf_scene_job* jobs, int32_t n, void* d_ws, int64_t ws_bytes,
+                                 hipStream_t stream, lf_graph* out) {
+  g_err[0] = 0;
+  if (!out) return fail(LF_EINVAL, "NULL graph handle pointer");
+  *out = nullptr;
+  if (!stream) return fail(LF_EINVAL, "capture needs a non-default stream");
+  lf_status st = check_jobs(jobs, n, d_ws, ws_bytes);
+  if (st != LF_OK) return st;
+  for (int i = 0; i < n; ++i)
+    if (jobs[i].mesh->prof.on) return fail(LF_ESTATE, "job %d: turn profiling off before capturing", i);
+  LF_TRY(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal), "begin capture");
+  st = run_jobs(jobs, n, d_ws, stream);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(stream, &g);
+  if (st != LF_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return st;
+  }
+  if (e != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return fail(LF_EHIP, "end capture: %s", hipGetErrorString(e));
+  }
+  hipGraphExec_t x = nullptr;
+  const hipError_t ei = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+  if (ei != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return fail(LF_EHIP, "instantiate: %s", hipGetErrorString(ei));
+  }
+  lf_graph h = new (std::nothrow) lf_graph_s;
+  if (!h) {
+    (void)hipGraphExecDestroy(x);
+    (void)hipGraphDestroy(g);
+    return fail(LF_EINVAL, "out of host memory");
+  }
+  h->graph = g;
+  h->exec = x;
+  *out = h;
+  return LF_OK;
+}
+
+lf_status lf_graph_launch(lf_graph g, hipStream_t stream) {
+  g_err[0] = 0;
+  if (!g || !g->exec) return fail(LF_ESTATE, "invalid graph handle");
+  LF_TRY(hipGraphLaunch(g->exec, stream), "graph launch");
+  return LF_OK;
+}
+
+void lf_graph_free(lf_graph g) {
+  if (!g) return;
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  delete g;
 }
 
 lf_status lf_finalize(lf_mesh mesh, void* d_tex_out, int32_t tex_dtype, uint8_t* d_labels, hipStream_t stream) {
@@ -510,6 +707,29 @@ lf_status lf_profile_read(lf_mesh mesh, lf_profile* out) {
     out->ms[k] = ms;
     out->launches[k] = (int64_t)(v.size() / 2);
   }
+  return LF_OK;
+}
+
+lf_status lf_set_tuning(lf_mesh mesh, const lf_tuning* t) {
+  g_err[0] = 0;
+  lf_status st = check_mesh(mesh);
+  if (st != LF_OK) return st;
+  if (!t) return fail(LF_EINVAL, "NULL tuning");
+  if (t->tile != 16 && t->tile != 32) return fail(LF_EINVAL, "tile must be 16 or 32, got %d", t->tile);
+  if (t->gather_unroll != 4 && t->gather_unroll != 8)
+    return fail(LF_EINVAL, "gather_unroll must be 4 or 8, got %d", t->gather_unroll);
+  mesh->d.tile = t->tile;
+  mesh->d.gather_unroll = t->gather_unroll;
+  return LF_OK;
+}
+
+lf_status lf_get_tuning(lf_mesh mesh, lf_tuning* t) {
+  g_err[0] = 0;
+  lf_status st = check_mesh(mesh);
+  if (st != LF_OK) return st;
+  if (!t) return fail(LF_EINVAL, "NULL tuning");
+  t->tile = mesh->d.tile;
+  t->gather_unroll = mesh->d.gather_unroll;
   return LF_OK;
 }
 

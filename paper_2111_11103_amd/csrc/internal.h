@@ -21,6 +21,8 @@ struct MeshDev {
   int32_t s_uniform, split, c, aggregator, accum_dtype;
   int32_t n_per;             // texels per triangle when uniform
   float z_near;
+  int32_t tile;              // raster tile edge: 16 or 32 pixels
+  int32_t gather_unroll;     // observations in flight per row in the sorted gather: 4 or 8
 };
 
 __device__ __forceinline__ int64_t row_offset(const MeshDev& m, int64_t t) {
@@ -28,7 +30,7 @@ __device__ __forceinline__ int64_t row_offset(const MeshDev& m, int64_t t) {
 }
 __device__ __forceinline__ int tri_s(const MeshDev& m, int64_t t) { return m.s_face ? m.s_face[t] : m.s_uniform; }
 
-constexpr int kTileSize = 32;         // raster tile edge (pixels)
+constexpr int kTileSize = 32;         // default raster tile edge (pixels)
 
 // Raster workspace of one batch (all caller memory).
 struct RasterWs {

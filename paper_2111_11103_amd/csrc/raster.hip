@@ -8,7 +8,8 @@
 //                    clusters that may be visible;
 //   k_bin (count)    one wave per visible cluster: set up every triangle
 //                    (transform, clip, 8-bit sub-pixel snap), count it into
-//                    every 32x32-pixel tile its pixel-centre box overlaps;
+//                    every tile (16x16 or 32x32 pixels, a tuning knob) its
+//                    pixel-centre box overlaps;
 //   k_tile_scan      per frame exclusive scan of the tile counts;
 //   k_bin (fill)     same walk, writes triangle ids into the tile lists;
 //   k_tile_raster    one workgroup per (frame, tile): a 64-bit depth|id key
@@ -28,7 +29,6 @@ namespace lf {
 
 namespace {
 
-constexpr int TS = kTileSize;
 
 // Snapped screen polygon of one triangle in one frame.
 struct Setup {
@@ -176,7 +176,7 @@ __global__ __launch_bounds__(256) void k_cull_clusters(MeshDev m, const float* _
 }
 
 // ---- 2./4. binning into tiles (count, then fill) ---------------------------------
-template <bool FILL>
+template <bool FILL, int TS>
 __global__ __launch_bounds__(256) void k_bin(MeshDev m, const float* __restrict__ cams, int H, int W,
                                              const int32_t* __restrict__ vis, const int32_t* __restrict__ vis_n,
                                              int32_t* __restrict__ tcnt, const int32_t* __restrict__ toff,
@@ -261,17 +261,18 @@ __global__ __launch_bounds__(1024) void k_tile_scan(const int32_t* __restrict__ 
 namespace {
 
 struct TileCtx {
-  unsigned long long* key;   // LDS [TS*TS]
-  const float* rx;           // LDS [TS] ray x of the tile's columns
-  const float* ry;           // LDS [TS]
+  unsigned long long* key;   // LDS [ts*ts]
+  const float* rx;           // LDS [ts] ray x of the tile's columns
+  const float* ry;           // LDS [ts]
   int tx0, ty0;              // tile origin (pixels)
+  int ts;                    // tile edge
 };
 
 __device__ __forceinline__ void emit_lds(const TileCtx& c, const RayK& rk, int x, int y, uint32_t tri) {
   float z;
   if (!frag_depth(rk, c.rx[x - c.tx0], c.ry[y - c.ty0], &z)) return;
   const unsigned long long k = ((unsigned long long)__float_as_uint(z) << 32) | tri;
-  atomicMin(c.key + (y - c.ty0) * TS + (x - c.tx0), k);
+  atomicMin(c.key + (y - c.ty0) * c.ts + (x - c.tx0), k);
 }
 
 // One thread rasterizes one sub-triangle over a small pixel box, stepping
@@ -356,6 +357,7 @@ __device__ __forceinline__ void raster_entries(const TileCtx& c, const Setup& s,
 
 }  // namespace
 
+template <int TS>
 __global__ __launch_bounds__(256) void k_tile_raster(MeshDev m, const float* __restrict__ cams, int H, int W,
                                                      const int32_t* __restrict__ vis, const int32_t* __restrict__ vis_n,
                                                      const int32_t* __restrict__ toff, const int32_t* __restrict__ tlist,
@@ -373,7 +375,7 @@ __global__ __launch_bounds__(256) void k_tile_raster(MeshDev m, const float* __r
   if (threadIdx.x < TS) rxs[threadIdx.x] = ray_x(cam, tx0 + threadIdx.x);
   else if (threadIdx.x < 2 * TS) rys[threadIdx.x - TS] = ray_y(cam, ty0 + threadIdx.x - TS);
   __syncthreads();
-  const TileCtx c{key, rxs, rys, tx0, ty0};
+  const TileCtx c{key, rxs, rys, tx0, ty0, TS};
   const int64_t HW = (int64_t)H * W;
 
   if (!over[fb]) {
@@ -490,9 +492,9 @@ __global__ __launch_bounds__(256) void k_tile_raster(MeshDev m, const float* __r
 }
 
 // ---- launcher ---------------------------------------------------------------
-hipError_t launch_render_batch(const MeshDev& m, const float* cams, int nb, int H, int W, const RasterWs& ws,
-                               const RasterOut& out, hipStream_t s) {
-  if (nb <= 0) return hipSuccess;
+template <int TS>
+hipError_t render_batch_ts(const MeshDev& m, const float* cams, int nb, int H, int W, const RasterWs& ws,
+                           const RasterOut& out, hipStream_t s) {
   const int ntx = (W + TS - 1) / TS, nty = (H + TS - 1) / TS;
   const int ntiles = ntx * nty;
   hipError_t e = launch_zero(ws.vis_n, (int64_t)nb * 4, s);
@@ -501,14 +503,21 @@ hipError_t launch_render_batch(const MeshDev& m, const float* cams, int nb, int 
     k_cull_clusters<<<dim3((unsigned)((m.n_clusters + 255) / 256), (unsigned)nb), 256, 0, s>>>(m, cams, H, W, ws.vis,
                                                                                                ws.vis_n);
   const unsigned gb = (unsigned)std::min<int64_t>((m.n_clusters + 3) / 4 + 1, 256);
-  k_bin<false><<<dim3(gb, (unsigned)nb), 256, 0, s>>>(m, cams, H, W, ws.vis, ws.vis_n, ws.tcnt, ws.toff, ws.tlist,
+  k_bin<false, TS><<<dim3(gb, (unsigned)nb), 256, 0, s>>>(m, cams, H, W, ws.vis, ws.vis_n, ws.tcnt, ws.toff, ws.tlist,
                                                       ws.list_cap);
   k_tile_scan<<<dim3((unsigned)nb), 1024, 0, s>>>(ws.tcnt, ntiles, ws.toff, ws.list_cap, ws.over);
-  k_bin<true><<<dim3(gb, (unsigned)nb), 256, 0, s>>>(m, cams, H, W, ws.vis, ws.vis_n, ws.tcnt, ws.toff, ws.tlist,
+  k_bin<true, TS><<<dim3(gb, (unsigned)nb), 256, 0, s>>>(m, cams, H, W, ws.vis, ws.vis_n, ws.tcnt, ws.toff, ws.tlist,
                                                      ws.list_cap);
-  k_tile_raster<<<dim3((unsigned)ntiles, (unsigned)nb), 256, 0, s>>>(m, cams, H, W, ws.vis, ws.vis_n, ws.toff,
-                                                                     ws.tlist, ws.list_cap, ws.over, out);
+  k_tile_raster<TS><<<dim3((unsigned)ntiles, (unsigned)nb), 256, 0, s>>>(m, cams, H, W, ws.vis, ws.vis_n, ws.toff,
+                                                                         ws.tlist, ws.list_cap, ws.over, out);
   return hipGetLastError();
+}
+
+hipError_t launch_render_batch(const MeshDev& m, const float* cams, int nb, int H, int W, const RasterWs& ws,
+                               const RasterOut& out, hipStream_t s) {
+  if (nb <= 0) return hipSuccess;
+  return m.tile == 16 ? render_batch_ts<16>(m, cams, nb, H, W, ws, out, s)
+                      : render_batch_ts<32>(m, cams, nb, H, W, ws, out, s);
 }
 
 }  // namespace lf

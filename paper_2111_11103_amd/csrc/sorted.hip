@@ -277,16 +277,15 @@ __global__ __launch_bounds__(256) void k_seg_gather(MeshDev m, ProbIn in, PixDec
 // group owns classes 4i..4i+3 of one texel row and reads them as one float4
 // (FP32) or one 32-bit word of four codes (E4M3) per observation, so one wave
 // instruction fetches four contiguous class vectors.  The group loads 16
-// observation offsets at once (one per lane, shuffled out) and keeps 8
-// observations in flight.  Groups walk the compact list of touched rows.
-template <int DT, int AGG, int AT>
+// observation offsets at once (one per lane, shuffled out) and keeps U (4 or
+// 8) observations in flight.  Groups walk the compact list of touched rows.
+template <int DT, int AGG, int AT, int U>
 __global__ __launch_bounds__(256) void k_seg_gather16(MeshDev m, ProbIn in, PixDecode dec,
                                                       const int32_t* __restrict__ start,
                                                       const int32_t* __restrict__ rows,
                                                       const int32_t* __restrict__ nrows,
                                                       const uint32_t* __restrict__ ent,
                                                       const float* __restrict__ ent_w, const float* __restrict__ ent_s) {
-  constexpr int U = 8;
   const int gl = threadIdx.x & 15;                       // lane in group = class chunk
   const int64_t g0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 4;
   const int64_t ng = ((int64_t)gridDim.x * 256) >> 4;
@@ -392,7 +391,13 @@ hipError_t launch_seg_gather(const MeshDev& m, const ProbIn& in, int f_first, in
     // enough resident groups to cover the machine; each walks the row list
     const int64_t groups = std::min<int64_t>(m.n_texels, (int64_t)256 * 8 * 16 * 4);
     dim3 g((unsigned)((groups * 16 + 255) / 256));
-#define LF_R(DT, AGG, AT) k_seg_gather16<DT, AGG, AT><<<g, 256, 0, s>>>(m, in, dec, start, rows, nrows, ent, ent_w, ent_s)
+#define LF_R(DT, AGG, AT)                                                                                    \
+  do {                                                                                                       \
+    if (m.gather_unroll == 4)                                                                                \
+      k_seg_gather16<DT, AGG, AT, 4><<<g, 256, 0, s>>>(m, in, dec, start, rows, nrows, ent, ent_w, ent_s);   \
+    else                                                                                                     \
+      k_seg_gather16<DT, AGG, AT, 8><<<g, 256, 0, s>>>(m, in, dec, start, rows, nrows, ent, ent_w, ent_s);   \
+  } while (0)
 #define LF_R2(DT)                                                                                            \
   do {                                                                                                       \
     if (m.aggregator == 1) LF_R(DT, 1, 0);                                                                   \

@@ -446,3 +446,37 @@ def config2(device="cpu", seed=0, n_frames=300, H=480, W=640, chunk=50, scene=No
     probs, valid, gt = frame_inputs(sc, cams, H, W, margin=3.0, sigma=2.0, blob_frac=0.15,
                                     invalid_frac=0.05, seed=seed, device=device, chunk=chunk)
     return FrameInputs(sc, cams, H, W, probs, valid, gt, s=3, scheme=1)
+
+
+@dataclass
+class PooledScene:
+    scene: Scene
+    cams: np.ndarray      # [F,16] float32, one camera per frame
+    H: int
+    W: int
+    s: int
+    pool: int             # frame f reads input frame f % pool
+    probs: object         # torch float32 [pool,c,H,W]
+    valid: object         # torch uint8 [pool,H,W]
+
+
+def config4(device="cpu", n_scenes=16, scale=1.0, seed0=1000):
+    """Batched workload: scenes i = 0..n-1 (seed 1000 + i) of uneven size,
+    T_i = 50k * 40^(i/15) triangles (times ``scale``), SPLIT s_i = 1 + i mod 4,
+    F_i = 100 + 60 i frames, 640x480 for even i and 1296x968 for odd i,
+    c = 40.  Each scene's inputs are a pool of 16 (640x480) or 8 (1296x968)
+    frames cycled by frame index, generated like the large single-scene
+    workload (m = 3, sigma = 2, 15 % blobs, 5 % invalid)."""
+    out = []
+    for i in range(n_scenes):
+        T = int(round(50_000 * 40 ** (i / 15) * scale))
+        sc = config2_scene(seed=seed0 + i, target_tris=max(T, 2_000))
+        s = 1 + i % 4
+        F = 100 + 60 * i
+        H, W = (480, 640) if i % 2 == 0 else (968, 1296)
+        pool = 16 if i % 2 == 0 else 8
+        cams = random_walk_cameras(sc, F, W, H, seed=seed0 + i)
+        probs, valid, _ = frame_inputs(sc, cams[:pool], H, W, margin=3.0, sigma=2.0, blob_frac=0.15,
+                                       invalid_frac=0.05, seed=seed0 + i, device=device)
+        out.append(PooledScene(sc, cams, H, W, s, pool, probs, valid))
+    return out

@@ -38,6 +38,18 @@ class _MeshOpts(C.Structure):
                 ("aggregator", C.c_int32), ("accum_dtype", C.c_int32), ("z_near", C.c_float)]
 
 
+class _Tuning(C.Structure):
+    _fields_ = [("tile", C.c_int32), ("gather_unroll", C.c_int32)]
+
+
+class _SceneJob(C.Structure):
+    _fields_ = [("mesh", C.c_void_p), ("d_cams", C.c_void_p), ("F", C.c_int32), ("H", C.c_int32), ("W", C.c_int32),
+                ("d_probs", C.c_void_p), ("prob_dtype", C.c_int32), ("strides", C.c_int64 * 4),
+                ("d_scale", C.c_void_p), ("d_valid", C.c_void_p), ("pool", C.c_int32), ("weighting", C.c_int32),
+                ("batch", C.c_int32), ("scatter_mode", C.c_int32), ("d_l_out", C.c_void_p), ("d_tex_out", C.c_void_p),
+                ("tex_dtype", C.c_int32), ("d_labels", C.c_void_p), ("d_images", C.c_void_p)]
+
+
 _lib = None
 _lock = threading.Lock()
 _p, _i32, _i64 = C.c_void_p, C.c_int32, C.c_int64
@@ -76,10 +88,19 @@ def lib():
             L.lf_adam_step.argtypes = [_p, _p, _p, _p, _i64, C.c_float, C.c_float, C.c_float, C.c_float, _i32, _p]
             L.lf_extract_features.argtypes = [_p, _p, _i32, _i32, _i32, _p, _i32, _p, _p, _p, _p, _p, _p, _p, _i64,
                                               _p, _p, _i64, _p]
+            L.lf_set_tuning.argtypes = [_p, C.POINTER(_Tuning)]
+            L.lf_get_tuning.argtypes = [_p, C.POINTER(_Tuning)]
+            L.lf_batch_ws_bytes.argtypes = [C.POINTER(_SceneJob), _i32, C.POINTER(_i64)]
+            L.lf_fuse_batch.argtypes = [C.POINTER(_SceneJob), _i32, _p, _i64, _p]
+            L.lf_graph_capture_batch.argtypes = [C.POINTER(_SceneJob), _i32, _p, _i64, _p, C.POINTER(_p)]
+            L.lf_graph_launch.argtypes = [_p, _p]
+            L.lf_graph_free.argtypes = [_p]
+            L.lf_graph_free.restype = None
             for name in ("lf_mesh_sizes", "lf_load_mesh", "lf_reset", "lf_frame_ws_bytes", "lf_fuse_frames",
                          "lf_finalize", "lf_render_labels", "lf_rasterize", "lf_profile_enable", "lf_profile_read",
                          "lf_mlp_sizes", "lf_mlp_pack", "lf_mlp_bind", "lf_mlp_forward", "lf_mlp_grad",
-                         "lf_adam_step", "lf_extract_features"):
+                         "lf_adam_step", "lf_extract_features", "lf_set_tuning", "lf_get_tuning",
+                         "lf_batch_ws_bytes", "lf_fuse_batch", "lf_graph_capture_batch", "lf_graph_launch"):
                 getattr(L, name).restype = _i32
             _lib = L
     return _lib
@@ -156,6 +177,7 @@ class Mesh:
         self.n_texels, ws_bytes = mesh_sizes(vertices.shape[0], faces.shape[0], s, scheme, n_classes, aggregator,
                                              hs, z_near)
         self.vertices = vertices
+        self.n_faces = int(faces.shape[0])
         self.ws = torch.empty(max(ws_bytes, 256), dtype=torch.uint8, device=self.device)
         self.accum = torch.empty((self.n_texels, self.c), dtype=accum_dtype, device=self.device)
         self.wsum = torch.empty(self.n_texels, dtype=torch.float32, device=self.device) \
@@ -259,6 +281,50 @@ class Mesh:
         _check(lib().lf_rasterize(self._h, _ptr(cams), F, H, W, _ptr(out["tri"]), _ptr(out["l"]), _ptr(out["z"]),
                                   _ptr(ws), ws.numel(), _stream()))
         return out
+
+    # -- tuning and jobs ----------------------------------------------------------------
+    def set_tuning(self, tile=32, gather_unroll=8):
+        """lf_set_tuning (results do not depend on it)."""
+        _check(lib().lf_set_tuning(self._h, C.byref(_Tuning(tile, gather_unroll))))
+        self._fws.clear()
+
+    def get_tuning(self):
+        t = _Tuning()
+        _check(lib().lf_get_tuning(self._h, C.byref(t)))
+        return {"tile": t.tile, "gather_unroll": t.gather_unroll}
+
+    def job(self, cams, probs, *, scale=None, valid=None, pool=0, weighting=W_PIXEL, batch=16,
+            scatter_mode=SCATTER_AUTO, l_out=None, tex_dtype=None, images=False):
+        """A complete fusion of this mesh for fuse_batch / Graph: returns a
+        SceneJob whose outputs (``labels``, ``tex``, ``images``, ``l``) are
+        allocated here.  With ``pool`` > 0, ``probs`` / ``scale`` / ``valid``
+        hold ``pool`` input frames and frame f reads input frame f % pool."""
+        F = cams.shape[0]
+        Fi, c, H, W = probs.shape
+        if c != self.c:
+            raise ValueError(f"probs has {c} classes, mesh has {self.c}")
+        if pool == 0 and Fi != F:
+            raise ValueError("without a pool, probs needs one frame per camera")
+        if pool > 0 and Fi < pool:
+            raise ValueError("probs holds fewer frames than the pool")
+        _need_cuda(cams, "cams", torch.float32)
+        _need_cuda(valid, "valid", torch.uint8)
+        cams = cams.contiguous()
+        dt, strides, scale = _probs_arg(probs, scale)
+        if valid is not None:
+            valid = valid.contiguous()
+        if images and l_out is None:
+            l_out = torch.empty((F, H, W), dtype=torch.int32, device=self.device)
+        tex = torch.empty((self.n_texels, self.c), dtype=tex_dtype, device=self.device) if tex_dtype else None
+        labels = torch.empty(self.n_texels, dtype=torch.uint8, device=self.device)
+        imgs = torch.empty((F, H, W), dtype=torch.uint8, device=self.device) if images else None
+        st = _SceneJob(self._h.value, cams.data_ptr(), F, H, W, probs.data_ptr(), dt, strides,
+                       None if scale is None else scale.data_ptr(), None if valid is None else valid.data_ptr(),
+                       int(pool), int(weighting), int(batch), int(scatter_mode),
+                       None if l_out is None else l_out.data_ptr(), None if tex is None else tex.data_ptr(),
+                       _TEX_DT[tex_dtype] if tex_dtype else F32, labels.data_ptr(),
+                       None if imgs is None else imgs.data_ptr())
+        return SceneJob(self, st, (cams, probs, scale, valid), l_out, tex, labels, imgs)
 
     # -- learned weighting ------------------------------------------------------------
     def bind_mlp(self, mlp):
@@ -364,3 +430,60 @@ def init_params(seed: int = 0) -> torch.Tensor:
     o += NH * NH + NH
     p[o:o + NH] = torch.randn(NH, generator=g) * (1.0 / NH) ** 0.5
     return p
+
+
+class SceneJob:
+    """One scene's complete fusion (an lf_scene_job) with the tensors it uses."""
+
+    def __init__(self, mesh, st, inputs, l, tex, labels, images):
+        self.mesh, self.st, self.inputs = mesh, st, inputs
+        self.l, self.tex, self.labels, self.images = l, tex, labels, images
+
+
+def _job_array(jobs):
+    arr = (_SceneJob * max(1, len(jobs)))()
+    for i, j in enumerate(jobs):
+        arr[i] = j.st
+    return arr
+
+
+def batch_ws(jobs, device="cuda"):
+    """Workspace tensor sized by lf_batch_ws_bytes for these jobs."""
+    n = _i64()
+    _check(lib().lf_batch_ws_bytes(_job_array(jobs), len(jobs), C.byref(n)))
+    return torch.empty(n.value, dtype=torch.uint8, device=device)
+
+
+def fuse_batch(jobs, ws=None):
+    """lf_fuse_batch on the current stream."""
+    if ws is None:
+        ws = batch_ws(jobs)
+    _check(lib().lf_fuse_batch(_job_array(jobs), len(jobs), _ptr(ws), ws.numel(), _stream()))
+    return ws
+
+
+class Graph:
+    """lf_graph_capture_batch / lf_graph_launch: the jobs' whole launch
+    sequence as one executable HIP graph.  Captured on a private stream
+    (default priority); the graph keeps the jobs and workspace alive."""
+
+    def __init__(self, jobs, ws=None):
+        self.jobs = list(jobs)
+        self.ws = batch_ws(self.jobs) if ws is None else ws
+        self.stream = torch.cuda.Stream()
+        self.stream.wait_stream(torch.cuda.current_stream())
+        h = _p()
+        with torch.cuda.stream(self.stream):
+            _check(lib().lf_graph_capture_batch(_job_array(self.jobs), len(self.jobs), _ptr(self.ws), self.ws.numel(),
+                                                C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self._h = h
+
+    def launch(self):
+        """Replay on the current stream."""
+        _check(lib().lf_graph_launch(self._h, _stream()))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.lf_graph_free(h)
+            self._h = None

@@ -1,0 +1,135 @@
+"""Autotuner of the fusion's launch parameters.
+
+For one (device, image size, class count, input dtype and layout, mesh size,
+weighting) it times every candidate of: raster tile edge (16, 32), sorted
+gather unroll (4, 8), frames per batch (8, 16, 32, 64) and scatter mode
+(texel-sorted when the classes of a pixel are contiguous, LDS-hash atomic
+always) on the first frames of the caller's own input, keeps the fastest and
+caches it in a JSON file keyed by that tuple.  Results never depend on the
+choice; only speed does.  Timing uses HIP events on the stream the library
+launches on; the mesh's accumulator is cleared afterwards.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import itertools
+import json
+import math
+import os
+import threading
+
+import torch
+
+from . import semfuse as sf
+
+TILES = (16, 32)
+UNROLLS = (4, 8)
+BATCHES = (8, 16, 32, 64)
+_lock = threading.Lock()
+
+
+def default_cache_path() -> str:
+    return os.environ.get("SEMFUSE_TUNE_CACHE",
+                          os.path.join(os.path.expanduser("~"), ".cache", "semfuse", "tune.json"))
+
+
+def cache_key(mesh: sf.Mesh, H: int, W: int, probs: torch.Tensor, weighting: int) -> str:
+    props = torch.cuda.get_device_properties(mesh.device)
+    arch = getattr(props, "gcnArchName", props.name)
+    layout = "cl" if probs.stride(1) == 1 else "planar"
+    tris = int(mesh.n_faces)
+    return (f"{arch}|{W}x{H}|c{mesh.c}|{str(probs.dtype)[6:]}|{layout}|T2^{round(math.log2(max(tris, 1)))}"
+            f"|x{round(mesh.n_texels / max(tris, 1))}|w{weighting}|agg{mesh.opts.aggregator}")
+
+
+def _load(path):
+    try:
+        with open(path) as fh:
+            return json.load(fh)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store(path, table):
+    os.makedirs(os.path.dirname(path) or ".", exist_ok=True)
+    tmp = path + f".tmp{os.getpid()}"
+    with open(tmp, "w") as fh:
+        json.dump(table, fh, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def candidates(probs: torch.Tensor, max_frames: int):
+    modes = [sf.SCATTER_ATOMIC]
+    if probs.stride(1) == 1:
+        modes.insert(0, sf.SCATTER_SORTED)
+    for tile, unroll, batch, mode in itertools.product(TILES, UNROLLS, BATCHES, modes):
+        if batch > max_frames:
+            continue
+        if mode == sf.SCATTER_ATOMIC and unroll != UNROLLS[-1]:
+            continue          # the unroll only affects the sorted gather
+        yield {"tile": tile, "gather_unroll": unroll, "batch": batch, "scatter_mode": mode}
+
+
+def autotune(mesh: sf.Mesh, cams: torch.Tensor, probs: torch.Tensor, *, scale=None, valid=None,
+             weighting=sf.W_PIXEL, probe_frames=64, cache_path=None, force=False, ws_budget=8 << 30,
+             repeats=2, log=None):
+    """Best {tile, gather_unroll, batch, scatter_mode, ms_per_frame} for this
+    mesh and input; applies the tuning to ``mesh`` and returns it."""
+    F, c, H, W = probs.shape
+    path = cache_path or default_cache_path()
+    key = cache_key(mesh, H, W, probs, weighting)
+    with _lock:
+        table = _load(path)
+    if not force and key in table:
+        best = table[key]
+        mesh.set_tuning(best["tile"], best["gather_unroll"])
+        if log:
+            log(f"[tune] cache hit {key}: {best}")
+        return dict(best, cached=True)
+    nf = max(1, min(F, probe_frames))
+    cams_p, probs_p = cams[:nf], probs[:nf]
+    scale_p = None if scale is None else scale[:nf]
+    valid_p = None if valid is None else valid[:nf]
+    best = None
+    results = []
+    for cand in candidates(probs, nf):
+        mesh.set_tuning(cand["tile"], cand["gather_unroll"])
+        b = min(cand["batch"], nf)
+        n = _ws_bytes(mesh, H, W, b, weighting, cand["scatter_mode"])
+        if n > ws_budget:
+            continue
+        ws = mesh.frame_ws(H, W, b, weighting, cand["scatter_mode"])
+
+        def run():
+            mesh.fuse_frames(cams_p, probs_p, scale=scale_p, valid=valid_p, weighting=weighting, batch=b,
+                             scatter_mode=cand["scatter_mode"], ws=ws)
+        run()                                   # warm-up (first-touch of the workspace, code load)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(repeats):
+            run()
+        ev1.record()
+        ev1.synchronize()
+        ms = ev0.elapsed_time(ev1) / (repeats * nf)
+        results.append((ms, cand))
+        if best is None or ms < best[0]:
+            best = (ms, cand)
+    mesh.reset()
+    mesh._fws.clear()
+    if best is None:
+        raise RuntimeError("no tuning candidate fits the workspace budget")
+    choice = dict(best[1], ms_per_frame=best[0], probe_frames=nf, n_candidates=len(results))
+    mesh.set_tuning(choice["tile"], choice["gather_unroll"])
+    with _lock:
+        table = _load(path)
+        table[key] = choice
+        _store(path, table)
+    if log:
+        log(f"[tune] {key}: {len(results)} candidates, best {choice}")
+    return dict(choice, cached=False)
+
+
+def _ws_bytes(mesh, H, W, batch, weighting, mode):
+    n = C.c_int64()
+    sf._check(sf.lib().lf_frame_ws_bytes(mesh._h, H, W, batch, weighting, mode, C.byref(n)))
+    return n.value
