@@ -30,7 +30,7 @@ sys.path.insert(0, ROOT)
 METRIC = "fused pixels/sec (c=40, 640×480) + % HBM roofline; learned/BF16 vs plain at label acc"
 HBM_PEAK_GBS = 8000.0
 STAGES = ["raster", "resolve", "scatter", "counts", "finalize", "render", "reset", "mlp"]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_seg_gather16_room500k_640x480_c40.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_seg_gather16_room500k_640x480_c40.txt")
 
 
 def log(*a):
@@ -49,15 +49,16 @@ def kernel_source_digest():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(batch):
+def measured_traffic(launch):
     """HBM bytes per gather launch from the committed counter summary, or
-    None when the kernel's sources or the batch differ from those measured."""
+    None when the kernel's sources or the launch configuration differ from
+    those measured."""
     try:
         with open(TRAFFIC_FILE) as fh:
-            t = json.load(fh)
+            t = json.loads(fh.readline())       # first line: the figures; the rest: how they were taken
     except (OSError, ValueError):
         return None
-    if t.get("source_digest") != kernel_source_digest() or t.get("batch") != batch:
+    if t.get("source_digest") != kernel_source_digest() or any(t.get(k) != v for k, v in launch.items()):
         return None
     return t.get("bytes_per_launch")
 
@@ -183,8 +184,11 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--frames", type=int, default=300)
-    ap.add_argument("--batch", type=int, default=32)
-    ap.add_argument("--scatter", type=int, default=0, help="0 auto, 1 atomic, 2 sorted")
+    ap.add_argument("--batch", type=int, default=0, help="frames per batch; 0 = autotune batch, scatter mode, "
+                                                        "tile and gather unroll on the first 64 frames")
+    ap.add_argument("--scatter", type=int, default=0, help="0 auto, 1 atomic, 2 sorted, 3 staged")
+    ap.add_argument("--tile", type=int, default=32, help="raster tile edge (with an explicit --batch)")
+    ap.add_argument("--unroll", type=int, default=8, help="sorted-gather unroll (with an explicit --batch)")
     ap.add_argument("--weighting", type=int, default=0, help="0 w^(P), 1 w^(I)")
     ap.add_argument("--layout", default="nhwc", choices=["nchw", "nhwc"])
     ap.add_argument("--cpu-frames", type=int, default=200)
@@ -234,9 +238,16 @@ def main():
     lab = torch.empty(mesh.n_texels, dtype=torch.uint8, device=dev)
     valid = work.valid
     L = sf.lib()
+    tuning = None
+    if args.batch <= 0:
+        from paper_2111_11103_amd import tune
+        tuning = tune.autotune(mesh, cams, probs, valid=valid, weighting=args.weighting, probe_frames=64, log=log)
+        args.batch, args.scatter = int(tuning["batch"]), int(tuning["scatter_mode"])
+    else:
+        mesh.set_tuning(args.tile, args.unroll)
 
     def make_step(p, weighting, scale=None, batch=args.batch, scatter=args.scatter):
-        ws = mesh.frame_ws(H, W, batch, weighting, scatter)
+        ws = mesh.frame_ws(H, W, batch, weighting, scatter, probs=p)
 
         def step():
             mesh.reset()
@@ -309,9 +320,11 @@ def main():
                                f"{F} frames {W}x{H}, c={c}, FP32 {args.layout.upper()} probabilities, "
                                f"weighting {'w^(I)' if args.weighting else 'w^(P)'}",
                    "frames": F, "H": H, "W": W, "classes": c, "triangles": sc.n_faces, "texels": mesh.n_texels,
-                   "batch": args.batch, "scatter_mode": args.scatter, "frame_ws_bytes": ws.numel()},
+                   "batch": args.batch, "scatter_mode": args.scatter, "frame_ws_bytes": ws.numel(),
+                   "tuning": mesh.get_tuning(), "autotuned": tuning is not None},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.batch),
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(
+                         {"batch": args.batch, "scatter_mode": args.scatter, **mesh.get_tuning()}),
                      "kernel": "k_seg_gather16", "kernel_ms": scat_ms, "launches": launches,
                      "bytes_per_px": per_px, "px_per_launch": px_per_launch,
                      "row_rmw_bytes_per_launch": rmw_bytes,
@@ -322,7 +335,7 @@ def main():
 
     if not args.no_forms:
         forms = {}
-        legs = [("nchw_atomic", lambda: make_step(probs_nchw, 0, scatter=0)[0], None)]
+        legs = [("nchw", lambda: make_step(probs_nchw, 0, scatter=0)[0], None)]
         legs.append(("w_image", lambda: make_step(probs, 1)[0], None))
         mlp_holder = {}
 

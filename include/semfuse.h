@@ -55,7 +55,13 @@ typedef enum { LF_TEX_SQUARE = 0, LF_TEX_SPLIT = 1 } lf_texel_scheme;
 typedef enum { LF_W_PIXEL = 0, LF_W_IMAGE = 1, LF_W_LEARNED = 2 } lf_weighting;
 typedef enum { LF_AGG_SUM = 0, LF_AGG_MUL = 1, LF_AGG_MAXSUM = 2 } lf_aggregator;
 typedef enum { LF_F32 = 0, LF_BF16 = 1, LF_F16 = 2, LF_FP8_E4M3 = 3 } lf_dtype;
-typedef enum { LF_SCATTER_AUTO = 0, LF_SCATTER_ATOMIC = 1, LF_SCATTER_SORTED = 2 } lf_scatter_mode;
+typedef enum {
+    LF_SCATTER_AUTO = 0,     /* SORTED when a pixel's classes are contiguous, else STAGED when allowed, else ATOMIC */
+    LF_SCATTER_ATOMIC = 1,   /* LDS-hash pre-reduction, then FP32 atomics (any strides, any dtype) */
+    LF_SCATTER_SORTED = 2,   /* texel-sorted gather reading each pixel's classes in place */
+    LF_SCATTER_STAGED = 3    /* texel-sorted gather of class vectors first copied to their sorted slots
+                                (planar inputs; FP32, c % 4 == 0, c <= 60) */
+} lf_scatter_mode;
 
 typedef struct lf_mesh_s* lf_mesh;
 
@@ -110,6 +116,11 @@ lf_status lf_reset(lf_mesh mesh, hipStream_t stream);
 lf_status lf_frame_ws_bytes(lf_mesh mesh, int32_t H, int32_t W, int32_t batch, int32_t weighting,
                             int32_t scatter_mode, int64_t* bytes);
 
+/* Exact workspace bytes of an lf_fuse_frames call with this input dtype and
+ * these strides (AUTO resolved as the call resolves it). */
+lf_status lf_fuse_ws_bytes(lf_mesh mesh, int32_t H, int32_t W, int32_t batch, int32_t weighting,
+                           int32_t scatter_mode, int32_t prob_dtype, const int64_t* h_strides, int64_t* bytes);
+
 /* Fuse F frames into the accumulator (Sections 3.3.1, 3.3.2, 3.2):
  * render every frame to triangle / texel ids, then add w_k * p_k (SUM),
  * w_k * log p_k (MUL) or w_k * g(p_k) (MAXSUM) into row l_k of every valid
@@ -122,8 +133,8 @@ lf_status lf_frame_ws_bytes(lf_mesh mesh, int32_t H, int32_t W, int32_t batch, i
  *           LF_W_LEARNED (w = the bound MLP's output, see lf_mlp_bind);
  *  d_l_out  [F][H][W] int32 texel rows (-1 = no triangle) or NULL;
  *  d_ws     workspace of lf_frame_ws_bytes(H, W, batch) bytes, 256-aligned;
- *  scatter_mode  LF_SCATTER_AUTO / ATOMIC / SORTED (same result up to FP32
- *           summation order).
+ *  scatter_mode  LF_SCATTER_AUTO / ATOMIC / SORTED / STAGED (same result up
+ *           to FP32 summation order).
  * Frames may be fused in several calls (fusion is incremental).  Errors:
  * LF_EINVAL (shapes, dtype, strides), LF_ESIZE (workspace), LF_EHIP. */
 lf_status lf_fuse_frames(lf_mesh mesh, const float* d_cams, int32_t F, int32_t H, int32_t W,

@@ -139,8 +139,8 @@ lf_status check_mesh(lf_mesh m) {
 }
 
 struct FrameLayout {
-  int64_t vis, vis_n, tcnt, toff, over, tlist, l, cnt, geo, wpix, seg, rank, start, sums, rows, nrows, ent_off, ent_w,
-      ent_s, total;
+  int64_t vis, vis_n, tcnt, toff, over, tlist, rec, l, cnt, geo, wpix, seg, rank, start, sums, rows, nrows, ent_off, ent_w,
+      ent_s, stage, total;
   int64_t list_cap, ntiles;
   bool sorted;
 };
@@ -162,6 +162,7 @@ FrameLayout frame_layout(const MeshDev& m, int H, int W, int B, int weighting, i
   L.toff = o; o += align256(B * (L.ntiles + 1) * 4);
   L.over = o; o += align256(B * 4);
   L.tlist = o; o += align256(B * L.list_cap * 4);
+  L.rec = o; o += align256(B * std::max<int64_t>(m.n_clusters, 1) * kClusterTris * 64);
   L.l = o; o += align256(B * HW * 4);
   L.cnt = o; if (weighting == LF_W_IMAGE || weighting == LF_W_LEARNED) o += align256(B * m.n_texels * 4);
   L.geo = o; if (weighting == LF_W_LEARNED) o += align256(B * HW * 16);
@@ -175,6 +176,10 @@ FrameLayout frame_layout(const MeshDev& m, int H, int W, int B, int weighting, i
   L.ent_off = o; if (L.sorted) o += align256(B * HW * 4);
   L.ent_w = o; if (L.sorted) o += align256(B * HW * 4);
   L.ent_s = o; if (L.sorted) o += align256(B * HW * 4);
+  // AUTO may pick the staged form for planar inputs: size for it too
+  const bool staged = scatter_mode == LF_SCATTER_STAGED ||
+                      (scatter_mode == LF_SCATTER_AUTO && m.c % 4 == 0 && m.c <= 60);
+  L.stage = o; if (staged) o += align256(B * HW * m.c * 4);
   L.total = o;
   return L;
 }
@@ -193,6 +198,7 @@ RasterWs raster_ws(const FrameLayout& L, char* ws) {
   r.toff = reinterpret_cast<int32_t*>(ws + L.toff);
   r.over = reinterpret_cast<int32_t*>(ws + L.over);
   r.tlist = reinterpret_cast<int32_t*>(ws + L.tlist);
+  r.rec = reinterpret_cast<int4*>(ws + L.rec);
   r.list_cap = L.list_cap;
   return r;
 }
@@ -355,15 +361,17 @@ struct FuseArgs {
 
 // Resolved scatter mode (AUTO -> SORTED iff classes are contiguous) and the
 // frame layout the call needs.
+bool stage_ok(const MeshDev& d, int32_t dtype) { return dtype == LF_F32 && d.c % 4 == 0 && d.c <= 60; }
+
 int resolve_mode(const FuseArgs& a) {
-  return a.scatter_mode != LF_SCATTER_AUTO ? a.scatter_mode
-                                           : (a.strides[1] == 1 ? LF_SCATTER_SORTED : LF_SCATTER_ATOMIC);
+  if (a.scatter_mode != LF_SCATTER_AUTO) return a.scatter_mode;
+  if (a.strides[1] == 1) return LF_SCATTER_SORTED;
+  return stage_ok(a.mesh->d, a.dtype) ? LF_SCATTER_STAGED : LF_SCATTER_ATOMIC;
 }
 
 FrameLayout fuse_layout(const FuseArgs& a) {
   const int B = a.batch < a.F ? a.batch : a.F;
-  return frame_layout(a.mesh->d, a.H, a.W, B > 0 ? B : 1, a.weighting,
-                      a.scatter_mode == LF_SCATTER_AUTO ? LF_SCATTER_SORTED : resolve_mode(a));
+  return frame_layout(a.mesh->d, a.H, a.W, B > 0 ? B : 1, a.weighting, resolve_mode(a));
 }
 
 lf_status check_fuse(const FuseArgs& a, const void* ws, int64_t ws_bytes) {
@@ -377,7 +385,9 @@ lf_status check_fuse(const FuseArgs& a, const void* ws, int64_t ws_bytes) {
   if (a.weighting < LF_W_PIXEL || a.weighting > LF_W_LEARNED) return fail(LF_EINVAL, "unknown weighting %d", a.weighting);
   if (a.weighting == LF_W_LEARNED && !a.mesh->mlp)
     return fail(LF_ESTATE, "learned weighting needs weights bound by lf_mlp_bind");
-  if (a.scatter_mode < LF_SCATTER_AUTO || a.scatter_mode > LF_SCATTER_SORTED) return fail(LF_EINVAL, "bad scatter mode");
+  if (a.scatter_mode < LF_SCATTER_AUTO || a.scatter_mode > LF_SCATTER_STAGED) return fail(LF_EINVAL, "bad scatter mode");
+  if (a.scatter_mode == LF_SCATTER_STAGED && !stage_ok(a.mesh->d, a.dtype))
+    return fail(LF_EINVAL, "the staged scatter needs FP32 input, c %% 4 == 0 and c <= 60");
   for (int i = 0; i < 4; ++i)
     if (a.strides[i] < 0) return fail(LF_EINVAL, "negative stride");
   if (a.batch < 1) return fail(LF_EINVAL, "batch must be >= 1");
@@ -408,9 +418,10 @@ lf_status fuse_impl(const FuseArgs& a, void* d_ws, hipStream_t stream) {
   float4* geo = learned ? reinterpret_cast<float4*>(ws + L.geo) : nullptr;
   float* wpix = learned ? reinterpret_cast<float*>(ws + L.wpix) : nullptr;
   // the sorted path stores batch-relative element offsets in 32 bits
-  const bool sorted = mode == LF_SCATTER_SORTED &&
-                      ((int64_t)(B - 1) * st[0] + (int64_t)(H - 1) * st[2] + (int64_t)(W - 1) * st[3] +
-                       (int64_t)d.c * st[1]) < ((int64_t)1 << 32);
+  const bool staged = mode == LF_SCATTER_STAGED && (int64_t)B * HW * d.c < ((int64_t)1 << 32);
+  const bool sorted = staged || (mode == LF_SCATTER_SORTED &&
+                                 ((int64_t)(B - 1) * st[0] + (int64_t)(H - 1) * st[2] + (int64_t)(W - 1) * st[3] +
+                                  (int64_t)d.c * st[1]) < ((int64_t)1 << 32));
   int32_t* seg = sorted ? reinterpret_cast<int32_t*>(ws + L.seg) : nullptr;
   LF_TRY(launch_zero(ws + L.tcnt, B * L.ntiles * 4, stream), "clear tile counts");
   if (cnt) LF_TRY(launch_zero(cnt, (int64_t)B * d.n_texels * 4, stream), "clear counts");
@@ -442,11 +453,17 @@ lf_status fuse_impl(const FuseArgs& a, void* d_ws, hipStream_t stream) {
         LF_TRY(launch_seg_scan(seg, d.n_texels, reinterpret_cast<int32_t*>(ws + L.sums), start,
                                reinterpret_cast<int32_t*>(ws + L.rows), reinterpret_cast<int32_t*>(ws + L.nrows),
                                stream), "segment scan");
-        LF_TRY(launch_seg_fill(in, fi, nb, H, W, lb, rank, start, eo, ew, es, a.weighting, cnt, d.n_texels, wpix,
-                               stream), "segment fill");
+        if (staged)
+          LF_TRY(launch_seg_stage(in, fi, nb, H, W, d.c, lb, rank, start, eo, ew, reinterpret_cast<float*>(ws + L.stage),
+                                  a.weighting, cnt, d.n_texels, wpix, stream), "segment stage");
+        else
+          LF_TRY(launch_seg_fill(in, fi, nb, H, W, lb, rank, start, eo, ew, es, a.weighting, cnt, d.n_texels, wpix,
+                                 stream), "segment fill");
       }
       StageTimer tm(mesh, 2, stream);
-      LF_TRY(launch_seg_gather(d, in, fi, H, W, start, reinterpret_cast<int32_t*>(ws + L.rows),
+      // staged observations: contiguous class vectors at element offset slot * c
+      const ProbIn gin = staged ? ProbIn{ws + L.stage, nullptr, nullptr, 0, 1, 0, 0, LF_F32} : in;
+      LF_TRY(launch_seg_gather(d, gin, staged ? 0 : fi, H, W, start, reinterpret_cast<int32_t*>(ws + L.rows),
                                reinterpret_cast<int32_t*>(ws + L.nrows), eo, ew, es, stream), "segment gather");
     } else {
       StageTimer tm(mesh, 2, stream);
@@ -531,6 +548,20 @@ lf_status lf_fuse_frames(lf_mesh mesh, const float* d_cams, int32_t F, int32_t H
   lf_status st = check_fuse(a, d_ws, ws_bytes);
   if (st != LF_OK) return st;
   return fuse_impl(a, d_ws, stream);
+}
+
+lf_status lf_fuse_ws_bytes(lf_mesh mesh, int32_t H, int32_t W, int32_t batch, int32_t weighting,
+                           int32_t scatter_mode, int32_t prob_dtype, const int64_t* h_strides, int64_t* bytes) {
+  g_err[0] = 0;
+  lf_status st = check_mesh(mesh);
+  if (st != LF_OK) return st;
+  if ((st = check_frames(1, H, W)) != LF_OK) return st;
+  if (batch < 1 || batch > 65535) return fail(LF_EINVAL, "batch must be in [1, 65535]");
+  if (!h_strides) return fail(LF_EINVAL, "NULL strides");
+  const FuseArgs a{mesh, nullptr, batch, H, W, nullptr, prob_dtype, h_strides, nullptr, nullptr, 0, weighting,
+                   nullptr, batch, scatter_mode};
+  if (bytes) *bytes = fuse_layout(a).total;
+  return LF_OK;
 }
 
 lf_status lf_batch_ws_bytes(const lf_scene_job* jobs, int32_t n, int64_t* bytes) {

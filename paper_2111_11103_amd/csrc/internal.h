@@ -38,8 +38,9 @@ struct RasterWs {
   int32_t* vis_n;            // [B]
   int32_t* tcnt;             // [B][ntiles] (zero between uses)
   int32_t* toff;             // [B][ntiles + 1]
-  int32_t* tlist;            // [B][list_cap] triangle ids per tile
+  int32_t* tlist;            // [B][list_cap] setup-record indices per tile
   int32_t* over;             // [B] list overflow flags
+  int4* rec;                 // [B][n_clusters * 64][4] triangle setup records (by visible slot)
   int64_t list_cap;
 };
 
@@ -84,6 +85,9 @@ hipError_t launch_seg_scan(const int32_t* seg, int64_t n, int32_t* sums, int32_t
 hipError_t launch_seg_fill(const ProbIn& in, int f_first, int nf, int H, int W, const int32_t* l, const int32_t* rank,
                            const int32_t* start, uint32_t* ent_pix, float* ent_w, float* ent_s, int weighting,
                            const int32_t* cnt, int64_t cnt_stride, const float* wpix, hipStream_t s);
+hipError_t launch_seg_stage(const ProbIn& in, int f_first, int nf, int H, int W, int c, const int32_t* l,
+                            const int32_t* rank, const int32_t* start, uint32_t* ent_pix, float* ent_w, float* staging,
+                            int weighting, const int32_t* cnt, int64_t cnt_stride, const float* wpix, hipStream_t s);
 hipError_t launch_seg_gather(const MeshDev& m, const ProbIn& in, int f_first, int H, int W, const int32_t* start,
                              const int32_t* rows, const int32_t* nrows, const uint32_t* ent_pix, const float* ent_w,
                              const float* ent_s, hipStream_t s);

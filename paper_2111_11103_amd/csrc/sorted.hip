@@ -158,6 +158,64 @@ __global__ __launch_bounds__(256) void k_seg_fill(ProbIn in, int f_first, int H,
   }
 }
 
+// ---- staged fill (planar inputs) ----------------------------------------------------------
+// For inputs whose classes are far apart in memory (NCHW), the fill also
+// moves every observation's class vector to its slot of a staging array, so
+// the gather then reads each texel's observations as one contiguous run.
+// A block takes 256 consecutive pixels of one frame: each class plane is read
+// coalesced into LDS (padded rows, no bank conflicts), then the rows are
+// written out as float4 runs (c % 4 == 0, c <= 60, FP32; LDS sized by c).
+constexpr int kStageMaxC = 60;
+constexpr int kStageRow = 257;     // padded LDS row of one class (256 pixels)
+
+__global__ __launch_bounds__(256) void k_seg_stage(ProbIn in, int f_first, int H, int W, int c,
+                                                   const int32_t* __restrict__ lbuf, const int32_t* __restrict__ rank,
+                                                   const int32_t* __restrict__ start, uint32_t* __restrict__ ent_pix,
+                                                   float* __restrict__ ent_w, float* __restrict__ staging,
+                                                   int weighting, const int32_t* __restrict__ cnt, int64_t cnt_stride,
+                                                   const float* __restrict__ wpix) {
+  extern __shared__ float stage_lds[];
+  int* spos = reinterpret_cast<int*>(stage_lds);            // [256]
+  float* sv = stage_lds + 256;                              // [c][kStageRow]
+  const int fb = blockIdx.y;
+  const int64_t HW = (int64_t)H * W;
+  const int t = threadIdx.x;
+  const int64_t p = (int64_t)blockIdx.x * 256 + t;
+  int l = -1;
+  if (p < HW) {
+    l = lbuf[(int64_t)fb * HW + p];
+    if (l >= 0 && in.valid && !in.valid[(int64_t)(f_first + fb) * HW + p]) l = -1;
+  }
+  int pos = -1;
+  if (l >= 0) {
+    pos = start[l] + rank[(int64_t)fb * HW + p];
+    ent_pix[pos] = (uint32_t)pos * (uint32_t)c;
+    if (ent_w) {
+      float w = 1.0f;
+      if (weighting == 1) w = 1.0f / (float)cnt[(int64_t)fb * cnt_stride + l];
+      else if (weighting == 2) w = wpix[(int64_t)fb * HW + p];
+      ent_w[pos] = w;
+    }
+  }
+  spos[t] = pos;
+  if (p < HW) {
+    const int y = (int)(p / W), x = (int)(p - (int64_t)y * W);
+    const float* src = reinterpret_cast<const float*>(in.p) + (int64_t)(f_first + fb) * in.sf + (int64_t)y * in.sy +
+                       (int64_t)x * in.sx;
+    for (int j = 0; j < c; ++j) sv[j * kStageRow + t] = src[(int64_t)j * in.sc];
+  }
+  __syncthreads();
+  const int nq = c >> 2;
+  for (int i = t; i < 256 * nq; i += 256) {
+    const int row = i / nq, q = i - row * nq;
+    const int ps = spos[row];
+    if (ps < 0) continue;
+    const float* col = sv + 4 * q * kStageRow + row;
+    const float4 v = make_float4(col[0], col[kStageRow], col[2 * kStageRow], col[3 * kStageRow]);
+    *reinterpret_cast<float4*>(staging + (int64_t)ps * c + 4 * q) = v;
+  }
+}
+
 // ---- gather --------------------------------------------------------------------------
 template <int DT>
 __device__ __forceinline__ float ld_prob(const void* p, int64_t e) {
@@ -437,6 +495,19 @@ hipError_t launch_seg_scan(const int32_t* seg, int64_t n, int32_t* sums, int32_t
   k_seg_sums<<<dim3((unsigned)nblk), 256, 0, s>>>(seg, n, sums);
   k_seg_scan_sums<<<1, 1024, 0, s>>>(sums, nblk);
   k_seg_scan<<<dim3((unsigned)nblk), 256, 0, s>>>(seg, n, sums, start, rows, nrows);
+  return hipGetLastError();
+}
+
+hipError_t launch_seg_stage(const ProbIn& in, int f_first, int nf, int H, int W, int c, const int32_t* l,
+                            const int32_t* rank, const int32_t* start, uint32_t* ent_pix, float* ent_w, float* staging,
+                            int weighting, const int32_t* cnt, int64_t cnt_stride, const float* wpix, hipStream_t s) {
+  if (nf <= 0) return hipSuccess;
+  if (c > kStageMaxC || (c & 3) || in.dtype != 0) return hipErrorInvalidValue;
+  const int64_t HW = (int64_t)H * W;
+  const size_t lds = (size_t)(256 + c * kStageRow) * 4;
+  k_seg_stage<<<dim3((unsigned)((HW + 255) / 256), (unsigned)nf), 256, lds, s>>>(in, f_first, H, W, c, l, rank, start,
+                                                                                 ent_pix, ent_w, staging, weighting,
+                                                                                 cnt, cnt_stride, wpix);
   return hipGetLastError();
 }
 

@@ -22,7 +22,7 @@ SQUARE, SPLIT = 0, 1
 W_PIXEL, W_IMAGE, W_LEARNED = 0, 1, 2
 AGG_SUM, AGG_MUL, AGG_MAXSUM = 0, 1, 2
 F32, BF16, F16, FP8_E4M3 = 0, 1, 2, 3
-SCATTER_AUTO, SCATTER_ATOMIC, SCATTER_SORTED = 0, 1, 2
+SCATTER_AUTO, SCATTER_ATOMIC, SCATTER_SORTED, SCATTER_STAGED = 0, 1, 2, 3
 
 _TEX_DT = {torch.float32: F32, torch.bfloat16: BF16, torch.float16: F16}
 
@@ -88,6 +88,7 @@ def lib():
             L.lf_adam_step.argtypes = [_p, _p, _p, _p, _i64, C.c_float, C.c_float, C.c_float, C.c_float, _i32, _p]
             L.lf_extract_features.argtypes = [_p, _p, _i32, _i32, _i32, _p, _i32, _p, _p, _p, _p, _p, _p, _p, _i64,
                                               _p, _p, _i64, _p]
+            L.lf_fuse_ws_bytes.argtypes = [_p, _i32, _i32, _i32, _i32, _i32, _i32, _p, C.POINTER(_i64)]
             L.lf_set_tuning.argtypes = [_p, C.POINTER(_Tuning)]
             L.lf_get_tuning.argtypes = [_p, C.POINTER(_Tuning)]
             L.lf_batch_ws_bytes.argtypes = [C.POINTER(_SceneJob), _i32, C.POINTER(_i64)]
@@ -100,7 +101,8 @@ def lib():
                          "lf_finalize", "lf_render_labels", "lf_rasterize", "lf_profile_enable", "lf_profile_read",
                          "lf_mlp_sizes", "lf_mlp_pack", "lf_mlp_bind", "lf_mlp_forward", "lf_mlp_grad",
                          "lf_adam_step", "lf_extract_features", "lf_set_tuning", "lf_get_tuning",
-                         "lf_batch_ws_bytes", "lf_fuse_batch", "lf_graph_capture_batch", "lf_graph_launch"):
+                         "lf_batch_ws_bytes", "lf_fuse_batch", "lf_graph_capture_batch", "lf_graph_launch",
+                         "lf_fuse_ws_bytes"):
                 getattr(L, name).restype = _i32
             _lib = L
     return _lib
@@ -199,10 +201,18 @@ class Mesh:
             self._h = None
 
     # -- workspace -----------------------------------------------------------------
-    def frame_ws(self, H, W, batch, weighting=W_PIXEL, scatter_mode=SCATTER_AUTO):
+    def frame_ws(self, H, W, batch, weighting=W_PIXEL, scatter_mode=SCATTER_AUTO, probs=None):
+        """Workspace tensor for frames of H x W processed ``batch`` at a time
+        (exact for ``probs``' dtype and layout when given)."""
         n = _i64()
-        _check(lib().lf_frame_ws_bytes(self._h, H, W, batch, weighting, scatter_mode, C.byref(n)))
-        key = (H, W, batch, weighting, scatter_mode)
+        if probs is not None:
+            dt = F32 if probs.dtype == torch.float32 else FP8_E4M3
+            strides = (C.c_int64 * 4)(*probs.stride())
+            _check(lib().lf_fuse_ws_bytes(self._h, H, W, batch, weighting, scatter_mode, dt, strides, C.byref(n)))
+            key = (H, W, batch, weighting, scatter_mode, dt, tuple(probs.stride()))
+        else:
+            _check(lib().lf_frame_ws_bytes(self._h, H, W, batch, weighting, scatter_mode, C.byref(n)))
+            key = (H, W, batch, weighting, scatter_mode)
         t = self._fws.get(key)
         if t is None or t.numel() < n.value:
             self._fws.clear()
@@ -235,7 +245,7 @@ class Mesh:
             raise ValueError("l_out must be a contiguous [F, H, W] int32 tensor")
         b = max(1, min(int(batch), F))
         if ws is None:
-            ws = self.frame_ws(H, W, b, weighting, scatter_mode)
+            ws = self.frame_ws(H, W, b, weighting, scatter_mode, probs=probs)
         _check(lib().lf_fuse_frames(self._h, _ptr(cams), F, H, W, _ptr(probs), dt, strides, _ptr(scale), _ptr(valid),
                                     weighting, _ptr(l_out), _ptr(ws), ws.numel(), b, scatter_mode, _stream()))
 

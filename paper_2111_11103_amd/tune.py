@@ -3,8 +3,8 @@
 For one (device, image size, class count, input dtype and layout, mesh size,
 weighting) it times every candidate of: raster tile edge (16, 32), sorted
 gather unroll (4, 8), frames per batch (8, 16, 32, 64) and scatter mode
-(texel-sorted when the classes of a pixel are contiguous, LDS-hash atomic
-always) on the first frames of the caller's own input, keeps the fastest and
+(texel-sorted when the classes of a pixel are contiguous, staged texel-sorted
+for planar FP32 inputs, LDS-hash atomic always) on the first frames of the caller's own input, keeps the fastest and
 caches it in a JSON file keyed by that tuple.  Results never depend on the
 choice; only speed does.  Timing uses HIP events on the stream the library
 launches on; the mesh's accumulator is cleared afterwards.
@@ -59,9 +59,12 @@ def _store(path, table):
 
 
 def candidates(probs: torch.Tensor, max_frames: int):
+    c = probs.shape[1]
     modes = [sf.SCATTER_ATOMIC]
     if probs.stride(1) == 1:
         modes.insert(0, sf.SCATTER_SORTED)
+    elif probs.dtype == torch.float32 and c % 4 == 0 and c <= 60:
+        modes.insert(0, sf.SCATTER_STAGED)
     for tile, unroll, batch, mode in itertools.product(TILES, UNROLLS, BATCHES, modes):
         if batch > max_frames:
             continue
@@ -95,10 +98,10 @@ def autotune(mesh: sf.Mesh, cams: torch.Tensor, probs: torch.Tensor, *, scale=No
     for cand in candidates(probs, nf):
         mesh.set_tuning(cand["tile"], cand["gather_unroll"])
         b = min(cand["batch"], nf)
-        n = _ws_bytes(mesh, H, W, b, weighting, cand["scatter_mode"])
+        n = _ws_bytes(mesh, H, W, b, weighting, cand["scatter_mode"], probs)
         if n > ws_budget:
             continue
-        ws = mesh.frame_ws(H, W, b, weighting, cand["scatter_mode"])
+        ws = mesh.frame_ws(H, W, b, weighting, cand["scatter_mode"], probs=probs_p)
 
         def run():
             mesh.fuse_frames(cams_p, probs_p, scale=scale_p, valid=valid_p, weighting=weighting, batch=b,
@@ -129,7 +132,9 @@ def autotune(mesh: sf.Mesh, cams: torch.Tensor, probs: torch.Tensor, *, scale=No
     return dict(choice, cached=False)
 
 
-def _ws_bytes(mesh, H, W, batch, weighting, mode):
+def _ws_bytes(mesh, H, W, batch, weighting, mode, probs):
     n = C.c_int64()
-    sf._check(sf.lib().lf_frame_ws_bytes(mesh._h, H, W, batch, weighting, mode, C.byref(n)))
+    dt = sf.F32 if probs.dtype == torch.float32 else sf.FP8_E4M3
+    strides = (C.c_int64 * 4)(*probs.stride())
+    sf._check(sf.lib().lf_fuse_ws_bytes(mesh._h, H, W, batch, weighting, mode, dt, strides, C.byref(n)))
     return n.value

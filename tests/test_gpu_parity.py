@@ -249,3 +249,37 @@ def test_config2_subset_raster_and_sorted_fusion(cfg2_subset):
     torch.cuda.synchronize()
     A_o, _ = oracle.fuse(om.n_texels, 40, l_o, w.probs.cpu().numpy(), w.valid.cpu().numpy())
     compare_fused(gm.accum.cpu().numpy(), A_o)
+
+
+@pytest.mark.parametrize("weighting", [sf.W_PIXEL, sf.W_IMAGE])
+def test_config2_subset_staged_planar_fusion(cfg2_subset, weighting):
+    """Planar (NCHW) FP32 input through the staged texel-sorted path (AUTO's
+    choice for it), c = 40, ragged last batch (12 frames in batches of 5)."""
+    w = cfg2_subset
+    sc = w.scene
+    gm = gpu_mesh((sc.vertices, sc.faces), 3, oracle.SPLIT, 40)
+    om = oracle_mesh(sc.vertices, sc.faces, 3, oracle.SPLIT)
+    _, l_o = om.raster_frames(w.cams, w.H, w.W)
+    A_o, W_o = oracle.fuse(om.n_texels, 40, l_o, w.probs.cpu().numpy(), w.valid.cpu().numpy(), weighting=weighting)
+    for mode in (sf.SCATTER_STAGED, sf.SCATTER_AUTO):
+        say(f"  staged fusion, NCHW, weighting {weighting}, mode {mode}")
+        gm.reset()
+        gm.fuse_frames(to_dev(w.cams, torch.float32), w.probs, valid=w.valid, weighting=weighting, batch=5,
+                       scatter_mode=mode)
+        torch.cuda.synchronize()
+        compare_fused(gm.accum.cpu().numpy(), A_o)
+    P_o, lab_o = oracle.finalize(A_o, W_o)
+    tex, lab = gm.finalize()
+    torch.cuda.synchronize()
+    compare_normalized(tex.cpu().numpy(), P_o)
+    compare_labels(lab.cpu().numpy(), P_o, lab_o)
+
+
+def test_staged_mode_rejects_unsupported_inputs(cfg1):
+    """c = 13 is not a multiple of 4: an explicit staged request is an error,
+    AUTO falls back to the atomic path."""
+    w = cfg1
+    sc = w.scene
+    gm = gpu_mesh((sc.vertices, sc.faces), 1, oracle.SPLIT, 13)
+    with pytest.raises(sf.SemfuseError):
+        gm.fuse_frames(to_dev(w.cams[:2], torch.float32), w.probs[:2].cuda(), scatter_mode=sf.SCATTER_STAGED)
