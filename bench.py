@@ -50,9 +50,9 @@ def kernel_source_digest():
 
 
 def measured_traffic(launch):
-    """HBM bytes per gather launch from the committed counter summary, or
-    None when the kernel's sources or the launch configuration differ from
-    those measured."""
+    """HBM bytes per fused pixel of the gather from the committed counter
+    summary, or None when the kernel's sources or the launch configuration
+    differ from those measured."""
     try:
         with open(TRAFFIC_FILE) as fh:
             t = json.loads(fh.readline())       # first line: the figures; the rest: how they were taken
@@ -60,7 +60,7 @@ def measured_traffic(launch):
         return None
     if t.get("source_digest") != kernel_source_digest() or any(t.get(k) != v for k, v in launch.items()):
         return None
-    return t.get("bytes_per_launch")
+    return t.get("bytes_per_px")
 
 
 def cpu_baseline(work, n_frames: int):
@@ -123,6 +123,55 @@ def accuracy_report(log_fn):
     log_fn(f"[bench] accuracy report in {time.time() - t0:.1f} s: {res}")
     res["workload"] = ("held-out rooms (2,100 triangles, c=13, 20 frames 160x120, view-dependent noise, seeds "
                        "200-209); learned weight trained on seeds 100-149 by the library's kernels")
+    return res, mlp
+
+
+def learned_scale_report(mlp, log_fn, n_frames=1000, pool=16):
+    """Learned weight at scale: a 2M-triangle room, SPLIT s = 4 (32M texels),
+    1000 frames of 1296x968 (inputs cycled from a pool of 16), c = 40.
+    Throughput of plain w^(P) vs the learned weight (inference fused into the
+    fusion pass), and pixel accuracy of both on the pool's own 16 frames."""
+    import torch
+    from paper_2111_11103_amd import scenes as S
+    from paper_2111_11103_amd import semfuse as sf
+    t0 = time.time()
+    sc = S.config2_scene(seed=0, target_tris=2_000_000)
+    H, W = 968, 1296
+    cams_np = S.random_walk_cameras(sc, n_frames, W, H, seed=0)
+    probs, valid, gt = S.frame_inputs(sc, cams_np[:pool], H, W, margin=3.0, sigma=2.0, blob_frac=0.15,
+                                      invalid_frac=0.05, seed=0, device="cuda")
+    probs = probs.to(memory_format=torch.channels_last)
+    dev = probs.device
+    cams = torch.as_tensor(cams_np, device=dev)
+    mesh = sf.Mesh(torch.as_tensor(sc.vertices, device=dev), torch.as_tensor(sc.faces, device=dev), n_classes=40,
+                   s=4, scheme=sf.SPLIT, keep_weights=False)
+    mesh.bind_mlp(mlp)
+    log_fn(f"[bench] learned at scale: T={sc.n_faces} texels={mesh.n_texels} ready in {time.time() - t0:.0f} s")
+    res = {"workload": f"room mesh {sc.n_faces} triangles, SPLIT s=4 ({mesh.n_texels} texels), {n_frames} frames "
+                       f"{W}x{H} (input pool of {pool}), c=40"}
+    for name, wt in (("plain", sf.W_PIXEL), ("learned", sf.W_LEARNED)):
+        job = mesh.job(cams, probs, valid=valid, pool=pool, weighting=wt, batch=pool, scatter_mode=sf.SCATTER_SORTED)
+        ws = sf.batch_ws([job])
+        sf.fuse_batch([job], ws)
+        torch.cuda.synchronize()
+        tt = time.perf_counter()
+        sf.fuse_batch([job], ws)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - tt
+        res[f"{name}_value"] = n_frames * H * W / dt
+        res[f"{name}_ms"] = dt * 1e3
+        # accuracy on the pool's own frames (their cameras, their ground truth)
+        acc_job = mesh.job(cams[:pool], probs, valid=valid, weighting=wt, batch=pool, images=True)
+        sf.fuse_batch([acc_job])
+        torch.cuda.synchronize()
+        seen = (acc_job.l >= 0) & (valid != 0)
+        res[f"{name}_pixel_acc"] = float((acc_job.images[seen].long() == gt[seen]).float().mean())
+        if "input_pixel_acc" not in res:
+            res["input_pixel_acc"] = float((probs.argmax(1)[seen] == gt[seen]).float().mean())
+        del job, acc_job, ws
+        torch.cuda.empty_cache()
+    mesh.bind_mlp(None)
+    log_fn(f"[bench] learned at scale: {res}")
     return res
 
 
@@ -146,7 +195,7 @@ def batched_report(log_fn, steps=2, scale=1.0):
         probs = p.probs.to(memory_format=torch.channels_last)
         cams = torch.as_tensor(p.cams, device=dev)
         best = tune.autotune(mesh, cams[:p.pool], probs, valid=p.valid, probe_frames=p.pool)
-        choices.append({k: best[k] for k in ("tile", "gather_unroll", "batch", "scatter_mode", "cached")})
+        choices.append({k: best[k] for k in ("tile", "gather_unroll", "small_px", "batch", "scatter_mode", "cached")})
         jobs.append(mesh.job(cams, probs, valid=p.valid, pool=p.pool, batch=best["batch"],
                              scatter_mode=best["scatter_mode"], images=True))
         F = len(p.cams)
@@ -189,6 +238,7 @@ def main():
     ap.add_argument("--scatter", type=int, default=0, help="0 auto, 1 atomic, 2 sorted, 3 staged")
     ap.add_argument("--tile", type=int, default=32, help="raster tile edge (with an explicit --batch)")
     ap.add_argument("--unroll", type=int, default=8, help="sorted-gather unroll (with an explicit --batch)")
+    ap.add_argument("--small", type=int, default=48, help="single-lane triangle box area (with an explicit --batch)")
     ap.add_argument("--weighting", type=int, default=0, help="0 w^(P), 1 w^(I)")
     ap.add_argument("--layout", default="nhwc", choices=["nchw", "nhwc"])
     ap.add_argument("--cpu-frames", type=int, default=200)
@@ -244,7 +294,7 @@ def main():
         tuning = tune.autotune(mesh, cams, probs, valid=valid, weighting=args.weighting, probe_frames=64, log=log)
         args.batch, args.scatter = int(tuning["batch"]), int(tuning["scatter_mode"])
     else:
-        mesh.set_tuning(args.tile, args.unroll)
+        mesh.set_tuning(args.tile, args.unroll, args.small)
 
     def make_step(p, weighting, scale=None, batch=args.batch, scatter=args.scatter):
         ws = mesh.frame_ws(H, W, batch, weighting, scatter, probs=p)
@@ -300,6 +350,8 @@ def main():
     n_batches = (F + args.batch - 1) // args.batch
     rows_per_launch = rows / n_batches
     rmw_bytes = rows_per_launch * 2 * c * 4
+    tpx = measured_traffic({"batch": args.batch, "scatter_mode": args.scatter, **mesh.get_tuning()})
+    traffic = None if tpx is None else tpx * px_per_launch     # HBM bytes per launch (counters, calibrated)
     b_min = npx * per_px + mesh.n_texels * c * 4
     log(f"[bench] gather {scat_ms:.3f} ms/launch; {rows_per_launch:.0f} rows per launch; "
         f"B_min {b_min / 1e9:.2f} GB -> {b_min / (t_total / args.steps) / 1e9:.0f} GB/s whole step")
@@ -323,8 +375,7 @@ def main():
                    "batch": args.batch, "scatter_mode": args.scatter, "frame_ws_bytes": ws.numel(),
                    "tuning": mesh.get_tuning(), "autotuned": tuning is not None},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(
-                         {"batch": args.batch, "scatter_mode": args.scatter, **mesh.get_tuning()}),
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_seg_gather16", "kernel_ms": scat_ms, "launches": launches,
                      "bytes_per_px": per_px, "px_per_launch": px_per_launch,
                      "row_rmw_bytes_per_launch": rmw_bytes,
@@ -373,7 +424,9 @@ def main():
         result["cpu_baseline"] = None
 
     if not args.no_accuracy:
-        result["accuracy"] = accuracy_report(log)
+        result["accuracy"], mlp = accuracy_report(log)
+        result["learned_at_scale"] = learned_scale_report(mlp, log)
+        del mlp
 
     if not args.no_batched:
         torch.cuda.empty_cache()

@@ -167,13 +167,16 @@ lf_status lf_rasterize(lf_mesh mesh, const float* d_cams, int32_t F, int32_t H, 
 
 /* ---- Tuning ------------------------------------------------------------------
  * Launch parameters of a mesh's kernels that do not change results: the
- * raster tile edge (16 or 32 pixels; default 32) and the number of
+ * raster tile edge (16 or 32 pixels; default 32), the number of
  * observations each row keeps in flight in the texel-sorted gather (4 or 8;
- * default 8).  Frame batch size and scatter mode are per-call arguments.
+ * default 8) and the largest pixel-box area a triangle may have to be
+ * rasterized by a single lane rather than a whole wave (1..1024; default
+ * 48).  Frame batch size and scatter mode are per-call arguments.
  * lf_frame_ws_bytes depends on the tile: query it after lf_set_tuning. */
 typedef struct {
     int32_t tile;
     int32_t gather_unroll;
+    int32_t small_px;
 } lf_tuning;
 lf_status lf_set_tuning(lf_mesh mesh, const lf_tuning* tuning);
 lf_status lf_get_tuning(lf_mesh mesh, lf_tuning* tuning);

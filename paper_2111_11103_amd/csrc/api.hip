@@ -291,6 +291,7 @@ lf_status lf_load_mesh(const lf_mesh_opts* opts, const float* d_vertices, int64_
   d.z_near = opts->z_near;
   d.tile = kTileSize;
   d.gather_unroll = 8;
+  d.small_px = 48;
 
   LF_TRY(launch_zero(d.err, 4, stream), "clear flag");
   if (per_face)
@@ -749,6 +750,8 @@ lf_status lf_set_tuning(lf_mesh mesh, const lf_tuning* t) {
   if (t->tile != 16 && t->tile != 32) return fail(LF_EINVAL, "tile must be 16 or 32, got %d", t->tile);
   if (t->gather_unroll != 4 && t->gather_unroll != 8)
     return fail(LF_EINVAL, "gather_unroll must be 4 or 8, got %d", t->gather_unroll);
+  if (t->small_px < 1 || t->small_px > 1024) return fail(LF_EINVAL, "small_px must be in [1, 1024], got %d", t->small_px);
+  mesh->d.small_px = t->small_px;
   mesh->d.tile = t->tile;
   mesh->d.gather_unroll = t->gather_unroll;
   return LF_OK;
@@ -761,6 +764,7 @@ lf_status lf_get_tuning(lf_mesh mesh, lf_tuning* t) {
   if (!t) return fail(LF_EINVAL, "NULL tuning");
   t->tile = mesh->d.tile;
   t->gather_unroll = mesh->d.gather_unroll;
+  t->small_px = mesh->d.small_px;
   return LF_OK;
 }
 

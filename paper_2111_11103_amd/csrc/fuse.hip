@@ -13,6 +13,8 @@
 #include <hip/hip_fp16.h>
 
 #include "accum.h"
+#include <algorithm>
+
 #include "internal.h"
 #include "spec.h"
 
@@ -233,7 +235,21 @@ __global__ __launch_bounds__(256) void k_finalize(MeshDev m, void* __restrict__ 
   const int64_t a0 = x0 * c;
   // element i of the block's rows sits at row i / c: walk (row, class) pairs
   // incrementally instead of dividing per element
-  {
+  if (AT == 0 && (c & 3) == 0 && (reinterpret_cast<uintptr_t>(m.accum) & 15) == 0) {
+    // four classes per load (rows of c % 4 == 0 floats stay 16-byte aligned)
+    const float4* src = reinterpret_cast<const float4*>(reinterpret_cast<const float*>(m.accum) + a0);
+    const int c4 = c >> 2;
+    int r = threadIdx.x / c4, j = 4 * (threadIdx.x - r * c4);
+    const int dr = 256 / c4, dj = 4 * (256 - dr * c4);
+    for (int i = threadIdx.x; i < nr * c4; i += 256) {
+      const float4 v = src[i];
+      float* d = rows + r * cp + j;
+      d[0] = v.x; d[1] = v.y; d[2] = v.z; d[3] = v.w;
+      r += dr;
+      j += dj;
+      if (j >= c) { j -= c; ++r; }
+    }
+  } else {
     int r = threadIdx.x / c, j = threadIdx.x - (threadIdx.x / c) * c;
     const int dr = 256 / c, dj = 256 - dr * c;
     for (int i = threadIdx.x; i < nr * c; i += 256) {
@@ -281,7 +297,8 @@ __global__ __launch_bounds__(256) void k_finalize(MeshDev m, void* __restrict__ 
 hipError_t launch_finalize(const MeshDev& m, void* tex_out, int tex_dtype, uint8_t* labels, hipStream_t s) {
   if (m.n_texels == 0) return hipSuccess;
   const int cp = m.c | 1;
-  const int R = m.c <= 64 ? 192 : 32;
+  // rows per block: up to 256, within 64 KB of LDS
+  const int R = std::max(1, std::min(256, 16384 / cp));
   const size_t lds = (size_t)R * cp * sizeof(float);
   dim3 g((unsigned)((m.n_texels + R - 1) / R));
 #define LF_FIN(O, A, T) k_finalize<O, A, T><<<g, 256, lds, s>>>(m, tex_out, labels, R)

@@ -23,6 +23,7 @@ struct MeshDev {
   float z_near;
   int32_t tile;              // raster tile edge: 16 or 32 pixels
   int32_t gather_unroll;     // observations in flight per row in the sorted gather: 4 or 8
+  int32_t small_px;          // pixel boxes up to this area are rasterized by one lane
 };
 
 __device__ __forceinline__ int64_t row_offset(const MeshDev& m, int64_t t) {

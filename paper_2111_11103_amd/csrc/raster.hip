@@ -321,6 +321,7 @@ struct TileCtx {
   const float* ry;           // LDS [ts]
   int tx0, ty0;              // tile origin (pixels)
   int ts;                    // tile edge
+  int small_px;              // boxes up to this area: one lane per triangle
 };
 
 __device__ __forceinline__ void emit_lds(const TileCtx& c, const RayK& rk, int x, int y, uint32_t tri) {
@@ -362,15 +363,13 @@ __device__ __forceinline__ void raster_thread(const TileCtx& c, const RayK& rk, 
   else raster_thread_t<long long>(c, rk, tri, e, x0, x1, y0, y1);
 }
 
-constexpr int kSmallPx = 48;   // pixel boxes up to this size are rasterized by one thread
-
 // Rasterize the triangle this lane holds (`s`, restricted to the pixel box
 // x0..x1 x y0..y1 of the tile); large boxes are done by the whole wave.
 __device__ __forceinline__ void raster_entries(const TileCtx& c, const Setup& s, uint32_t tri, bool have, int x0,
                                                int x1, int y0, int y1) {
   const int lane = threadIdx.x & 63;
   const bool any = have && s.n >= 3 && x0 <= x1 && y0 <= y1;
-  const bool small = any && (x1 - x0 + 1) * (y1 - y0 + 1) <= kSmallPx;
+  const bool small = any && (x1 - x0 + 1) * (y1 - y0 + 1) <= c.small_px;
   if (small) {
     for (int i = 1; i + 1 < s.n; ++i) {
       const Edge3 e = orient(s.PX[0], s.PY[0], pick8(s.PX, i), pick8(s.PY, i), pick8(s.PX, i + 1), pick8(s.PY, i + 1));
@@ -431,7 +430,7 @@ __global__ __launch_bounds__(256) void k_tile_raster(MeshDev m, const float* __r
   if (threadIdx.x < TS) rxs[threadIdx.x] = ray_x(cam, tx0 + threadIdx.x);
   else if (threadIdx.x < 2 * TS) rys[threadIdx.x - TS] = ray_y(cam, ty0 + threadIdx.x - TS);
   __syncthreads();
-  const TileCtx c{key, rxs, rys, tx0, ty0, TS};
+  const TileCtx c{key, rxs, rys, tx0, ty0, TS, m.small_px};
   const int64_t HW = (int64_t)H * W;
   const int4* frec = rec + (int64_t)fb * m.n_clusters * kClusterTris * 4;
 

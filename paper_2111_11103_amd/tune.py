@@ -1,18 +1,21 @@
 """Autotuner of the fusion's launch parameters.
 
 For one (device, image size, class count, input dtype and layout, mesh size,
-weighting) it times every candidate of: raster tile edge (16, 32), sorted
-gather unroll (4, 8), frames per batch (8, 16, 32, 64) and scatter mode
-(texel-sorted when the classes of a pixel are contiguous, staged texel-sorted
-for planar FP32 inputs, LDS-hash atomic always) on the first frames of the caller's own input, keeps the fastest and
-caches it in a JSON file keyed by that tuple.  Results never depend on the
-choice; only speed does.  Timing uses HIP events on the stream the library
-launches on; the mesh's accumulator is cleared afterwards.
+weighting) it times candidates of five knobs on the first frames of the
+caller's own input: frames per batch (8, 16, 32, 64), scatter mode
+(texel-sorted when a pixel's classes are contiguous, staged texel-sorted for
+planar FP32 inputs, LDS-hash atomic always), raster tile edge (16, 32), the
+largest triangle box rasterized by one lane (12, 24, 48, 96 pixels) and the
+sorted gather's unroll (4, 8).  The search is coordinate descent from the
+library defaults: each knob in turn is swept with the others held, and the
+fastest value kept.  The choice is cached in a JSON file keyed by that
+tuple.  Results never depend on the choice; only speed does.  Timing uses
+events on the stream the library launches on; the mesh's accumulator is
+cleared afterwards.
 """
 from __future__ import annotations
 
 import ctypes as C
-import itertools
 import json
 import math
 import os
@@ -22,9 +25,10 @@ import torch
 
 from . import semfuse as sf
 
-TILES = (16, 32)
-UNROLLS = (4, 8)
 BATCHES = (8, 16, 32, 64)
+TILES = (16, 32)
+SMALL = (12, 24, 48, 96)
+UNROLLS = (4, 8)
 _lock = threading.Lock()
 
 
@@ -58,78 +62,14 @@ def _store(path, table):
     os.replace(tmp, path)
 
 
-def candidates(probs: torch.Tensor, max_frames: int):
+def scatter_modes(probs: torch.Tensor):
     c = probs.shape[1]
     modes = [sf.SCATTER_ATOMIC]
     if probs.stride(1) == 1:
         modes.insert(0, sf.SCATTER_SORTED)
     elif probs.dtype == torch.float32 and c % 4 == 0 and c <= 60:
         modes.insert(0, sf.SCATTER_STAGED)
-    for tile, unroll, batch, mode in itertools.product(TILES, UNROLLS, BATCHES, modes):
-        if batch > max_frames:
-            continue
-        if mode == sf.SCATTER_ATOMIC and unroll != UNROLLS[-1]:
-            continue          # the unroll only affects the sorted gather
-        yield {"tile": tile, "gather_unroll": unroll, "batch": batch, "scatter_mode": mode}
-
-
-def autotune(mesh: sf.Mesh, cams: torch.Tensor, probs: torch.Tensor, *, scale=None, valid=None,
-             weighting=sf.W_PIXEL, probe_frames=64, cache_path=None, force=False, ws_budget=8 << 30,
-             repeats=2, log=None):
-    """Best {tile, gather_unroll, batch, scatter_mode, ms_per_frame} for this
-    mesh and input; applies the tuning to ``mesh`` and returns it."""
-    F, c, H, W = probs.shape
-    path = cache_path or default_cache_path()
-    key = cache_key(mesh, H, W, probs, weighting)
-    with _lock:
-        table = _load(path)
-    if not force and key in table:
-        best = table[key]
-        mesh.set_tuning(best["tile"], best["gather_unroll"])
-        if log:
-            log(f"[tune] cache hit {key}: {best}")
-        return dict(best, cached=True)
-    nf = max(1, min(F, probe_frames))
-    cams_p, probs_p = cams[:nf], probs[:nf]
-    scale_p = None if scale is None else scale[:nf]
-    valid_p = None if valid is None else valid[:nf]
-    best = None
-    results = []
-    for cand in candidates(probs, nf):
-        mesh.set_tuning(cand["tile"], cand["gather_unroll"])
-        b = min(cand["batch"], nf)
-        n = _ws_bytes(mesh, H, W, b, weighting, cand["scatter_mode"], probs)
-        if n > ws_budget:
-            continue
-        ws = mesh.frame_ws(H, W, b, weighting, cand["scatter_mode"], probs=probs_p)
-
-        def run():
-            mesh.fuse_frames(cams_p, probs_p, scale=scale_p, valid=valid_p, weighting=weighting, batch=b,
-                             scatter_mode=cand["scatter_mode"], ws=ws)
-        run()                                   # warm-up (first-touch of the workspace, code load)
-        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        ev0.record()
-        for _ in range(repeats):
-            run()
-        ev1.record()
-        ev1.synchronize()
-        ms = ev0.elapsed_time(ev1) / (repeats * nf)
-        results.append((ms, cand))
-        if best is None or ms < best[0]:
-            best = (ms, cand)
-    mesh.reset()
-    mesh._fws.clear()
-    if best is None:
-        raise RuntimeError("no tuning candidate fits the workspace budget")
-    choice = dict(best[1], ms_per_frame=best[0], probe_frames=nf, n_candidates=len(results))
-    mesh.set_tuning(choice["tile"], choice["gather_unroll"])
-    with _lock:
-        table = _load(path)
-        table[key] = choice
-        _store(path, table)
-    if log:
-        log(f"[tune] {key}: {len(results)} candidates, best {choice}")
-    return dict(choice, cached=False)
+    return modes
 
 
 def _ws_bytes(mesh, H, W, batch, weighting, mode, probs):
@@ -138,3 +78,83 @@ def _ws_bytes(mesh, H, W, batch, weighting, mode, probs):
     strides = (C.c_int64 * 4)(*probs.stride())
     sf._check(sf.lib().lf_fuse_ws_bytes(mesh._h, H, W, batch, weighting, mode, dt, strides, C.byref(n)))
     return n.value
+
+
+def _apply(mesh, cfg):
+    mesh.set_tuning(cfg["tile"], cfg["gather_unroll"], cfg["small_px"])
+
+
+def autotune(mesh: sf.Mesh, cams: torch.Tensor, probs: torch.Tensor, *, scale=None, valid=None,
+             weighting=sf.W_PIXEL, probe_frames=64, cache_path=None, force=False, ws_budget=8 << 30,
+             repeats=2, log=None):
+    """Best {batch, scatter_mode, tile, small_px, gather_unroll, ms_per_frame}
+    for this mesh and input; applies the tuning to ``mesh`` and returns it."""
+    F, c, H, W = probs.shape
+    path = cache_path or default_cache_path()
+    key = cache_key(mesh, H, W, probs, weighting)
+    with _lock:
+        table = _load(path)
+    if not force and key in table:
+        best = table[key]
+        _apply(mesh, best)
+        if log:
+            log(f"[tune] cache hit {key}: {best}")
+        return dict(best, cached=True)
+    nf = max(1, min(F, probe_frames))
+    cams_p, probs_p = cams[:nf], probs[:nf]
+    scale_p = None if scale is None else scale[:nf]
+    valid_p = None if valid is None else valid[:nf]
+    timings = {}
+
+    def trial(cfg):
+        k = tuple(sorted(cfg.items()))
+        if k in timings:
+            return timings[k]
+        b = min(cfg["batch"], nf)
+        _apply(mesh, cfg)
+        if _ws_bytes(mesh, H, W, b, weighting, cfg["scatter_mode"], probs_p) > ws_budget:
+            timings[k] = math.inf
+            return math.inf
+        ws = mesh.frame_ws(H, W, b, weighting, cfg["scatter_mode"], probs=probs_p)
+
+        def run():
+            mesh.fuse_frames(cams_p, probs_p, scale=scale_p, valid=valid_p, weighting=weighting, batch=b,
+                             scatter_mode=cfg["scatter_mode"], ws=ws)
+        run()                                   # warm-up (first touch of the workspace, code load)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(repeats):
+            run()
+        ev1.record()
+        ev1.synchronize()
+        timings[k] = ev0.elapsed_time(ev1) / (repeats * nf)
+        return timings[k]
+
+    modes = scatter_modes(probs)
+    batches = [b for b in BATCHES if b <= max(nf, BATCHES[0])]
+    best = {"batch": min(32, batches[-1]), "scatter_mode": modes[0], "tile": 32, "small_px": 48,
+            "gather_unroll": 8}
+    best_ms = trial(best)
+    sweeps = [("batch", batches), ("scatter_mode", modes), ("tile", TILES), ("small_px", SMALL),
+              ("gather_unroll", UNROLLS)]
+    for knob, values in sweeps:
+        if knob == "gather_unroll" and best["scatter_mode"] == sf.SCATTER_ATOMIC:
+            continue                            # the unroll only affects the sorted gather
+        for v in values:
+            cand = dict(best, **{knob: v})
+            ms = trial(cand)
+            if ms < best_ms:
+                best, best_ms = cand, ms
+    mesh.reset()
+    mesh._fws.clear()
+    if not math.isfinite(best_ms):
+        raise RuntimeError("no tuning candidate fits the workspace budget")
+    choice = dict(best, ms_per_frame=best_ms, probe_frames=nf, n_candidates=len(timings))
+    _apply(mesh, choice)
+    with _lock:
+        table = _load(path)
+        table[key] = choice
+        _store(path, table)
+    if log:
+        log(f"[tune] {key}: {len(timings)} candidates, best {choice}")
+    return dict(choice, cached=False)

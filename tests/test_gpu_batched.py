@@ -86,15 +86,18 @@ def test_fuse_batch_matches_oracle(scenes):
 
 def test_tunings_do_not_change_results(scenes):
     d = scenes[0]
-    for tile, unroll in ((16, 4), (16, 8), (32, 4)):
-        jobs, meshes = _jobs(scenes[:1], tunings=[{"tile": tile, "gather_unroll": unroll}])
-        assert meshes[0].get_tuning() == {"tile": tile, "gather_unroll": unroll}
+    for tile, unroll, small in ((16, 4, 12), (16, 8, 1), (32, 4, 96)):
+        t = {"tile": tile, "gather_unroll": unroll, "small_px": small}
+        jobs, meshes = _jobs(scenes[:1], tunings=[t])
+        assert meshes[0].get_tuning() == t
         sf.fuse_batch(jobs)
         _check(jobs, scenes[:1], f"tile {tile} unroll {unroll}")
         r = meshes[0].rasterize(to_dev(d["cams"], torch.float32), d["H"], d["W"])
         assert np.array_equal(r["l"].cpu().numpy(), d["l_o"])
     with pytest.raises(sf.SemfuseError):
         meshes[0].set_tuning(24, 8)
+    with pytest.raises(sf.SemfuseError):
+        meshes[0].set_tuning(32, 8, 0)
 
 
 def test_graph_replays_match_oracle(scenes):
@@ -125,13 +128,13 @@ def test_autotuner_picks_and_caches(scenes, tmp_path):
     path = str(tmp_path / "tune.json")
     r1 = tune.autotune(m, cams, probs, valid=d["valid"].cuda(), probe_frames=8, cache_path=path, log=say)
     assert not r1["cached"] and r1["n_candidates"] >= 6
-    assert m.get_tuning() == {"tile": r1["tile"], "gather_unroll": r1["gather_unroll"]}
+    assert m.get_tuning() == {k: r1[k] for k in ("tile", "gather_unroll", "small_px")}
     with open(path) as fh:
         table = json.load(fh)
     assert len(table) == 1
     r2 = tune.autotune(m, cams, probs, valid=d["valid"].cuda(), probe_frames=8, cache_path=path)
-    assert r2["cached"] and {k: r2[k] for k in ("tile", "gather_unroll", "batch", "scatter_mode")} == \
-        {k: r1[k] for k in ("tile", "gather_unroll", "batch", "scatter_mode")}
+    knobs = ("tile", "gather_unroll", "small_px", "batch", "scatter_mode")
+    assert r2["cached"] and {k: r2[k] for k in knobs} == {k: r1[k] for k in knobs}
     # the accumulator is left clear
     assert float(m.accum.abs().max()) == 0.0
 
