@@ -139,7 +139,7 @@ lf_status check_mesh(lf_mesh m) {
 }
 
 struct FrameLayout {
-  int64_t vis, vis_n, tcnt, toff, over, tlist, rec, l, cnt, geo, wpix, seg, rank, start, sums, rows, nrows, ent_off, ent_w,
+  int64_t vis, vis_n, tcnt, toff, over, tlist, l, cnt, geo, wpix, seg, rank, start, sums, rows, nrows, ent_off, ent_w,
       ent_s, stage, total;
   int64_t list_cap, ntiles;
   bool sorted;
@@ -162,7 +162,6 @@ FrameLayout frame_layout(const MeshDev& m, int H, int W, int B, int weighting, i
   L.toff = o; o += align256(B * (L.ntiles + 1) * 4);
   L.over = o; o += align256(B * 4);
   L.tlist = o; o += align256(B * L.list_cap * 4);
-  L.rec = o; o += align256(B * std::max<int64_t>(m.n_clusters, 1) * kClusterTris * 64);
   L.l = o; o += align256(B * HW * 4);
   L.cnt = o; if (weighting == LF_W_IMAGE || weighting == LF_W_LEARNED) o += align256(B * m.n_texels * 4);
   L.geo = o; if (weighting == LF_W_LEARNED) o += align256(B * HW * 16);
@@ -198,7 +197,6 @@ RasterWs raster_ws(const FrameLayout& L, char* ws) {
   r.toff = reinterpret_cast<int32_t*>(ws + L.toff);
   r.over = reinterpret_cast<int32_t*>(ws + L.over);
   r.tlist = reinterpret_cast<int32_t*>(ws + L.tlist);
-  r.rec = reinterpret_cast<int4*>(ws + L.rec);
   r.list_cap = L.list_cap;
   return r;
 }

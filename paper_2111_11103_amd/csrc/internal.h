@@ -39,9 +39,8 @@ struct RasterWs {
   int32_t* vis_n;            // [B]
   int32_t* tcnt;             // [B][ntiles] (zero between uses)
   int32_t* toff;             // [B][ntiles + 1]
-  int32_t* tlist;            // [B][list_cap] setup-record indices per tile
+  int32_t* tlist;            // [B][list_cap] triangle ids per tile
   int32_t* over;             // [B] list overflow flags
-  int4* rec;                 // [B][n_clusters * 64][4] triangle setup records (by visible slot)
   int64_t list_cap;
 };
 

@@ -191,6 +191,20 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const void* __restrict__ pa
 // ---- features ---------------------------------------------------------------------
 // Probability features of pixel (frame f, y, x): normalised entropy, top-1,
 // top-1 minus top-2.  Also returns the first maximal class.
+__device__ __forceinline__ float e4m3_code(uint32_t q) {
+  const int e = (q >> 3) & 15, mn = q & 7;
+  float v = (e == 0) ? (float)mn * 0.001953125f : __builtin_ldexpf((float)(8 + mn), e - 10);
+  if (e == 15 && mn == 7) v = __builtin_nanf("");
+  return (q & 0x80u) ? -v : v;
+}
+
+// Running entropy / top-2 / first-argmax update with class j's probability.
+__device__ __forceinline__ void prob_step(float p, int j, float& h, float& p1, float& p2, int& best) {
+  if (p > 0.0f) h -= p * logf(p);
+  if (p > p1) { p2 = p1; p1 = p; best = j; }
+  else if (p > p2) p2 = p;
+}
+
 template <int DT>
 __device__ __forceinline__ void prob_features(const ProbIn& in, int64_t base, float scale, int c, float& ent, float& p1,
                                               float& p2, int& best) {
@@ -198,20 +212,48 @@ __device__ __forceinline__ void prob_features(const ProbIn& in, int64_t base, fl
   p1 = -__builtin_inff();
   p2 = -__builtin_inff();
   best = 0;
-  for (int j = 0; j < c; ++j) {
-    float p;
+  const int64_t esz = DT == 0 ? 4 : 1;
+  const bool vec = in.sc == 1 && (c & 3) == 0 && c <= 64 &&
+                   ((reinterpret_cast<uintptr_t>(in.p) + base * esz) & (4 * esz - 1)) == 0;
+  if (vec) {
+    // contiguous classes: issue every load of the vector first, then reduce
     if constexpr (DT == 0) {
-      p = reinterpret_cast<const float*>(in.p)[base + (int64_t)j * in.sc];
+      const float4* src = reinterpret_cast<const float4*>(reinterpret_cast<const float*>(in.p) + base);
+      float4 v[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q)
+        if (4 * q < c) v[q] = src[q];
+#pragma unroll
+      for (int q = 0; q < 16; ++q)
+        if (4 * q < c) {
+          prob_step(v[q].x, 4 * q, h, p1, p2, best);
+          prob_step(v[q].y, 4 * q + 1, h, p1, p2, best);
+          prob_step(v[q].z, 4 * q + 2, h, p1, p2, best);
+          prob_step(v[q].w, 4 * q + 3, h, p1, p2, best);
+        }
     } else {
-      const uint32_t q = reinterpret_cast<const uint8_t*>(in.p)[base + (int64_t)j * in.sc];
-      const int e = (q >> 3) & 15, mn = q & 7;
-      float v = (e == 0) ? (float)mn * 0.001953125f : __builtin_ldexpf((float)(8 + mn), e - 10);
-      if (e == 15 && mn == 7) v = __builtin_nanf("");
-      p = ((q & 0x80u) ? -v : v) * scale;
+      const uint32_t* src = reinterpret_cast<const uint32_t*>(reinterpret_cast<const uint8_t*>(in.p) + base);
+      uint32_t v[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q)
+        if (4 * q < c) v[q] = src[q];
+#pragma unroll
+      for (int q = 0; q < 16; ++q)
+        if (4 * q < c) {
+#pragma unroll
+          for (int k = 0; k < 4; ++k) prob_step(e4m3_code((v[q] >> (8 * k)) & 0xffu) * scale, 4 * q + k, h, p1, p2, best);
+        }
     }
-    if (p > 0.0f) h -= p * logf(p);
-    if (p > p1) { p2 = p1; p1 = p; best = j; }
-    else if (p > p2) p2 = p;
+  } else {
+    for (int j = 0; j < c; ++j) {
+      float p;
+      if constexpr (DT == 0) {
+        p = reinterpret_cast<const float*>(in.p)[base + (int64_t)j * in.sc];
+      } else {
+        p = e4m3_code(reinterpret_cast<const uint8_t*>(in.p)[base + (int64_t)j * in.sc]) * scale;
+      }
+      prob_step(p, j, h, p1, p2, best);
+    }
   }
   if (c < 2) p2 = 0.0f;
   ent = c > 1 ? h / logf((float)c) : 0.0f;

@@ -91,52 +91,6 @@ __device__ __forceinline__ void setup_triangle(const MeshDev& m, const Cam& cam,
   if (s.x0 > s.x1 || s.y0 > s.y1) s.n = 0;
 }
 
-// Setup record of one (frame, triangle): written once by the counting pass
-// of the binning, read by the fill pass and by every tile the triangle
-// touches.  Four int4: (PX0, PY0, PX1, PY1), (PX2, PY2, x0 | x1 << 16,
-// y0 | y1 << 16), (n.x, n.y, n.z, d) as float bits, (tri, n, 0, 0).  A
-// clipped polygon (n > 3) keeps only its box and is set up again where it is
-// rasterized.
-__device__ __forceinline__ void store_rec(int4* r, const Setup& s, uint32_t tri) {
-  if (s.n >= 3) {
-    r[0] = make_int4(s.PX[0], s.PY[0], s.PX[1], s.PY[1]);
-    r[1] = make_int4(s.PX[2], s.PY[2], (s.x0 & 0xffff) | (s.x1 << 16), (s.y0 & 0xffff) | (s.y1 << 16));
-    r[2] = make_int4(__float_as_int(s.rk.n.x), __float_as_int(s.rk.n.y), __float_as_int(s.rk.n.z),
-                     __float_as_int(s.rk.d));
-  }
-  r[3] = make_int4((int)tri, s.n, 0, 0);
-}
-
-__device__ __forceinline__ void rec_box(const int4& q1, Setup& s) {
-  s.x0 = q1.z & 0xffff;
-  s.x1 = q1.z >> 16;
-  s.y0 = q1.w & 0xffff;
-  s.y1 = q1.w >> 16;
-}
-
-// Setup of a record: unclipped triangles from the record, clipped polygons
-// recomputed.
-__device__ __forceinline__ void load_rec(const MeshDev& m, const Cam& cam, const int4* r, int H, int W, Setup& s,
-                                         uint32_t& tri) {
-  const int4 q3 = r[3];
-  tri = (uint32_t)q3.x;
-  s.n = q3.y;
-  if (s.n == 3) {
-    const int4 q0 = r[0], q1 = r[1], q2 = r[2];
-    s.PX[0] = q0.x; s.PY[0] = q0.y; s.PX[1] = q0.z; s.PY[1] = q0.w; s.PX[2] = q1.x; s.PY[2] = q1.y;
-#pragma unroll
-    for (int i = 3; i < 8; ++i) { s.PX[i] = 0; s.PY[i] = 0; }
-    rec_box(q1, s);
-    s.rk.n = V3{__int_as_float(q2.x), __int_as_float(q2.y), __int_as_float(q2.z)};
-    s.rk.d = __int_as_float(q2.w);
-  } else if (s.n > 3) {
-    setup_triangle(m, cam, tri, H, W, s);
-  } else {
-    s.n = 0;
-    s.x0 = 0; s.x1 = -1; s.y0 = 0; s.y1 = -1;
-  }
-}
-
 // Oriented sub-triangle with its top-left biases.
 struct Edge3 {
   int x0, y0, x1, y1, x2, y2;
@@ -226,7 +180,7 @@ template <bool FILL, int TS>
 __global__ __launch_bounds__(256) void k_bin(MeshDev m, const float* __restrict__ cams, int H, int W,
                                              const int32_t* __restrict__ vis, const int32_t* __restrict__ vis_n,
                                              int32_t* __restrict__ tcnt, const int32_t* __restrict__ toff,
-                                             int32_t* __restrict__ tlist, int64_t list_cap, int4* __restrict__ rec) {
+                                             int32_t* __restrict__ tlist, int64_t list_cap) {
   const int fb = blockIdx.y;
   const Cam cam = load_cam(cams + 16 * (int64_t)fb);
   const int ntx = (W + TS - 1) / TS, nty = (H + TS - 1) / TS;
@@ -237,19 +191,10 @@ __global__ __launch_bounds__(256) void k_bin(MeshDev m, const float* __restrict_
   for (int w = blockIdx.x * 4 + (threadIdx.x >> 6); w < nvis; w += gridDim.x * 4) {
     const int64_t cl = vis[(int64_t)fb * m.n_clusters + w];
     const int64_t t = cl * kClusterTris + lane;
-    const int64_t ri = (int64_t)w * kClusterTris + lane;           // record index within the frame
-    int4* r = rec + ((int64_t)fb * m.n_clusters * kClusterTris + ri) * 4;
     Setup s;
     s.n = 0;
     s.x0 = 0; s.x1 = -1; s.y0 = 0; s.y1 = -1;
-    if (!FILL) {
-      if (t < m.T) setup_triangle(m, cam, t, H, W, s);
-      store_rec(r, s, (uint32_t)(t < m.T ? t : 0));
-    } else {
-      const int4 q3 = r[3];
-      s.n = q3.y;
-      if (s.n >= 3) rec_box(r[1], s);
-    }
+    if (t < m.T) setup_triangle(m, cam, t, H, W, s);
     // walk this lane's tile range; lanes currently on the same tile share one atomic
     const int tx0 = s.x0 / TS, tx1 = s.x1 / TS, ty0 = s.y0 / TS, ty1 = s.y1 / TS;
     int tx = tx0, ty = ty0;
@@ -270,7 +215,7 @@ __global__ __launch_bounds__(256) void k_bin(MeshDev m, const float* __restrict_
         base = __shfl(base, leader);
         if (more && tile == leader_tile) {
           const int64_t pos = (int64_t)toff[(int64_t)fb * (ntiles + 1) + leader_tile] + base + rank;
-          if (pos < list_cap) tlist[(int64_t)fb * list_cap + pos] = (int32_t)ri;
+          if (pos < list_cap) tlist[(int64_t)fb * list_cap + pos] = (int32_t)t;
         }
       }
       if (more && tile == leader_tile) {
@@ -363,6 +308,7 @@ __device__ __forceinline__ void raster_thread(const TileCtx& c, const RayK& rk, 
   else raster_thread_t<long long>(c, rk, tri, e, x0, x1, y0, y1);
 }
 
+
 // Rasterize the triangle this lane holds (`s`, restricted to the pixel box
 // x0..x1 x y0..y1 of the tile); large boxes are done by the whole wave.
 __device__ __forceinline__ void raster_entries(const TileCtx& c, const Setup& s, uint32_t tri, bool have, int x0,
@@ -415,8 +361,7 @@ template <int TS>
 __global__ __launch_bounds__(256) void k_tile_raster(MeshDev m, const float* __restrict__ cams, int H, int W,
                                                      const int32_t* __restrict__ vis, const int32_t* __restrict__ vis_n,
                                                      const int32_t* __restrict__ toff, const int32_t* __restrict__ tlist,
-                                                     int64_t list_cap, const int32_t* __restrict__ over,
-                                                     const int4* __restrict__ rec, RasterOut out) {
+                                                     int64_t list_cap, const int32_t* __restrict__ over, RasterOut out) {
   __shared__ unsigned long long key[TS * TS];
   __shared__ float rxs[TS], rys[TS];
   const int fb = blockIdx.y;
@@ -432,7 +377,6 @@ __global__ __launch_bounds__(256) void k_tile_raster(MeshDev m, const float* __r
   __syncthreads();
   const TileCtx c{key, rxs, rys, tx0, ty0, TS, m.small_px};
   const int64_t HW = (int64_t)H * W;
-  const int4* frec = rec + (int64_t)fb * m.n_clusters * kClusterTris * 4;
 
   if (!over[fb]) {
     const int e0 = toff[(int64_t)fb * (ntiles + 1) + tile], e1 = toff[(int64_t)fb * (ntiles + 1) + tile + 1];
@@ -444,7 +388,10 @@ __global__ __launch_bounds__(256) void k_tile_raster(MeshDev m, const float* __r
       s.n = 0;
       s.x0 = 0; s.x1 = -1; s.y0 = 0; s.y1 = -1;
       uint32_t tri = 0;
-      if (have) load_rec(m, cam, frec + 4 * (int64_t)lst[e], H, W, s, tri);
+      if (have) {
+        tri = (uint32_t)lst[e];
+        setup_triangle(m, cam, tri, H, W, s);
+      }
       raster_entries(c, s, tri, have, max(s.x0, tx0), min(s.x1, tx1), max(s.y0, ty0), min(s.y1, ty1));
     }
   } else {
@@ -453,13 +400,14 @@ __global__ __launch_bounds__(256) void k_tile_raster(MeshDev m, const float* __r
     const int nvis = vis_n[fb];
     for (int w0 = 0; w0 < nvis; w0 += 4) {
       const int w = w0 + (threadIdx.x >> 6);
+      const int64_t t = w < nvis ? (int64_t)vis[(int64_t)fb * m.n_clusters + w] * kClusterTris + (threadIdx.x & 63)
+                                 : m.T;
       Setup s;
       s.n = 0;
       s.x0 = 0; s.x1 = -1; s.y0 = 0; s.y1 = -1;
-      uint32_t tri = 0;
-      const bool have = w < nvis;
-      if (have) load_rec(m, cam, frec + 4 * ((int64_t)w * kClusterTris + (threadIdx.x & 63)), H, W, s, tri);
-      raster_entries(c, s, tri, have, max(s.x0, tx0), min(s.x1, tx1), max(s.y0, ty0), min(s.y1, ty1));
+      const bool have = t < m.T;
+      if (have) setup_triangle(m, cam, t, H, W, s);
+      raster_entries(c, s, (uint32_t)t, have, max(s.x0, tx0), min(s.x1, tx1), max(s.y0, ty0), min(s.y1, ty1));
     }
   }
   __syncthreads();
@@ -556,12 +504,12 @@ hipError_t render_batch_ts(const MeshDev& m, const float* cams, int nb, int H, i
                                                                                                ws.vis_n);
   const unsigned gb = (unsigned)std::min<int64_t>((m.n_clusters + 3) / 4 + 1, 256);
   k_bin<false, TS><<<dim3(gb, (unsigned)nb), 256, 0, s>>>(m, cams, H, W, ws.vis, ws.vis_n, ws.tcnt, ws.toff, ws.tlist,
-                                                          ws.list_cap, ws.rec);
+                                                      ws.list_cap);
   k_tile_scan<<<dim3((unsigned)nb), 1024, 0, s>>>(ws.tcnt, ntiles, ws.toff, ws.list_cap, ws.over);
   k_bin<true, TS><<<dim3(gb, (unsigned)nb), 256, 0, s>>>(m, cams, H, W, ws.vis, ws.vis_n, ws.tcnt, ws.toff, ws.tlist,
-                                                         ws.list_cap, ws.rec);
+                                                     ws.list_cap);
   k_tile_raster<TS><<<dim3((unsigned)ntiles, (unsigned)nb), 256, 0, s>>>(m, cams, H, W, ws.vis, ws.vis_n, ws.toff,
-                                                                         ws.tlist, ws.list_cap, ws.over, ws.rec, out);
+                                                                         ws.tlist, ws.list_cap, ws.over, out);
   return hipGetLastError();
 }
 
