@@ -195,7 +195,8 @@ def batched_report(log_fn, steps=2, scale=1.0):
         probs = p.probs.to(memory_format=torch.channels_last)
         cams = torch.as_tensor(p.cams, device=dev)
         best = tune.autotune(mesh, cams[:p.pool], probs, valid=p.valid, probe_frames=p.pool)
-        choices.append({k: best[k] for k in ("tile", "gather_unroll", "small_px", "batch", "scatter_mode", "cached")})
+        choices.append({k: best[k] for k in ("tile", "gather_unroll", "small_px", "gather_waves", "batch",
+                                             "scatter_mode", "cached")})
         jobs.append(mesh.job(cams, probs, valid=p.valid, pool=p.pool, batch=best["batch"],
                              scatter_mode=best["scatter_mode"], images=True))
         F = len(p.cams)
@@ -239,6 +240,7 @@ def main():
     ap.add_argument("--tile", type=int, default=32, help="raster tile edge (with an explicit --batch)")
     ap.add_argument("--unroll", type=int, default=8, help="sorted-gather unroll (with an explicit --batch)")
     ap.add_argument("--small", type=int, default=48, help="single-lane triangle box area (with an explicit --batch)")
+    ap.add_argument("--gwaves", type=int, default=32, help="gather grid waves per CU (with an explicit --batch)")
     ap.add_argument("--weighting", type=int, default=0, help="0 w^(P), 1 w^(I)")
     ap.add_argument("--layout", default="nhwc", choices=["nchw", "nhwc"])
     ap.add_argument("--cpu-frames", type=int, default=200)
@@ -294,7 +296,7 @@ def main():
         tuning = tune.autotune(mesh, cams, probs, valid=valid, weighting=args.weighting, probe_frames=64, log=log)
         args.batch, args.scatter = int(tuning["batch"]), int(tuning["scatter_mode"])
     else:
-        mesh.set_tuning(args.tile, args.unroll, args.small)
+        mesh.set_tuning(args.tile, args.unroll, args.small, args.gwaves)
 
     def make_step(p, weighting, scale=None, batch=args.batch, scatter=args.scatter):
         ws = mesh.frame_ws(H, W, batch, weighting, scatter, probs=p)

@@ -171,12 +171,16 @@ lf_status lf_rasterize(lf_mesh mesh, const float* d_cams, int32_t F, int32_t H, 
  * observations each row keeps in flight in the texel-sorted gather (4 or 8;
  * default 8) and the largest pixel-box area a triangle may have to be
  * rasterized by a single lane rather than a whole wave (1..1024; default
- * 48).  Frame batch size and scatter mode are per-call arguments.
+ * 48), and the resident waves per compute unit the gather's grid is sized
+ * for (1..32; default 32: fewer leave room for the next batch's raster,
+ * which runs concurrently on a second stream).  Frame batch size and scatter
+ * mode are per-call arguments.
  * lf_frame_ws_bytes depends on the tile: query it after lf_set_tuning. */
 typedef struct {
     int32_t tile;
     int32_t gather_unroll;
     int32_t small_px;
+    int32_t gather_waves;
 } lf_tuning;
 lf_status lf_set_tuning(lf_mesh mesh, const lf_tuning* tuning);
 lf_status lf_get_tuning(lf_mesh mesh, lf_tuning* tuning);

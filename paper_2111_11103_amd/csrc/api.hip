@@ -47,6 +47,18 @@ struct lf_mesh_s {
   lf_mesh_opts opts;
   Profiler prof;
   const void* mlp = nullptr;   // bound packed weights of the learned weighting
+  // Second stream of the sorted path: the gather of batch k runs on it while
+  // the caller's stream renders and sorts batch k + 1 (events order them).
+  hipStream_t side = nullptr;
+  hipEvent_t sorted_ev[2] = {nullptr, nullptr};    // batch's entries are ready (caller's stream)
+  hipEvent_t gathered_ev[2] = {nullptr, nullptr};  // batch's gather is done (side stream)
+  ~lf_mesh_s() {
+    for (int i = 0; i < 2; ++i) {
+      if (sorted_ev[i]) (void)hipEventDestroy(sorted_ev[i]);
+      if (gathered_ev[i]) (void)hipEventDestroy(gathered_ev[i]);
+    }
+    if (side) (void)hipStreamDestroy(side);
+  }
 };
 
 namespace {
@@ -139,8 +151,9 @@ lf_status check_mesh(lf_mesh m) {
 }
 
 struct FrameLayout {
-  int64_t vis, vis_n, tcnt, toff, over, tlist, l, cnt, geo, wpix, seg, rank, start, sums, rows, nrows, ent_off, ent_w,
-      ent_s, stage, total;
+  int64_t vis, vis_n, tcnt, toff, over, tlist, l, cnt, geo, wpix, seg, rank, sums, total;
+  // what the gather reads, twice: batch k uses set k % 2
+  int64_t start[2], rows[2], nrows[2], ent_off[2], ent_w[2], ent_s[2], stage[2];
   int64_t list_cap, ntiles;
   bool sorted;
 };
@@ -168,17 +181,19 @@ FrameLayout frame_layout(const MeshDev& m, int H, int W, int B, int weighting, i
   L.wpix = o; if (weighting == LF_W_LEARNED) o += align256(B * HW * 4);
   L.seg = o; if (L.sorted) o += align256(m.n_texels * 4);
   L.rank = o; if (L.sorted) o += align256(B * HW * 4);
-  L.start = o; if (L.sorted) o += align256((m.n_texels + 1) * 4);
   L.sums = o; if (L.sorted) o += align256((m.n_texels / 8192 + 2) * 4);
-  L.rows = o; if (L.sorted) o += align256(m.n_texels * 4);
-  L.nrows = o; if (L.sorted) o += 256;
-  L.ent_off = o; if (L.sorted) o += align256(B * HW * 4);
-  L.ent_w = o; if (L.sorted) o += align256(B * HW * 4);
-  L.ent_s = o; if (L.sorted) o += align256(B * HW * 4);
   // AUTO may pick the staged form for planar inputs: size for it too
   const bool staged = scatter_mode == LF_SCATTER_STAGED ||
                       (scatter_mode == LF_SCATTER_AUTO && m.c % 4 == 0 && m.c <= 60);
-  L.stage = o; if (staged) o += align256(B * HW * m.c * 4);
+  for (int k = 0; k < 2; ++k) {
+    L.start[k] = o; if (L.sorted) o += align256((m.n_texels + 1) * 4);
+    L.rows[k] = o; if (L.sorted) o += align256(m.n_texels * 4);
+    L.nrows[k] = o; if (L.sorted) o += 256;
+    L.ent_off[k] = o; if (L.sorted) o += align256(B * HW * 4);
+    L.ent_w[k] = o; if (L.sorted && weighting != LF_W_PIXEL) o += align256(B * HW * 4);
+    L.ent_s[k] = o; if (L.sorted) o += align256(B * HW * 4);
+    L.stage[k] = o; if (staged) o += align256(B * HW * m.c * 4);
+  }
   L.total = o;
   return L;
 }
@@ -290,6 +305,7 @@ lf_status lf_load_mesh(const lf_mesh_opts* opts, const float* d_vertices, int64_
   d.tile = kTileSize;
   d.gather_unroll = 8;
   d.small_px = 48;
+  d.gather_waves = 32;
 
   LF_TRY(launch_zero(d.err, 4, stream), "clear flag");
   if (per_face)
@@ -309,6 +325,15 @@ lf_status lf_load_mesh(const lf_mesh_opts* opts, const float* d_vertices, int64_
   if (htot != n_texels) return fail(LF_ESIZE, "n_texels %lld != %lld", (long long)n_texels, (long long)htot);
   lf_mesh h = new (std::nothrow) lf_mesh_s;
   if (!h) return fail(LF_EINVAL, "out of host memory");
+  hipError_t he = hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking);
+  for (int i = 0; i < 2 && he == hipSuccess; ++i) {
+    he = hipEventCreateWithFlags(&h->sorted_ev[i], hipEventDisableTiming);
+    if (he == hipSuccess) he = hipEventCreateWithFlags(&h->gathered_ev[i], hipEventDisableTiming);
+  }
+  if (he != hipSuccess) {
+    delete h;
+    return fail(LF_EHIP, "stream/event creation: %s", hipGetErrorString(he));
+  }
   h->magic = kMagic;
   h->d = d;
   h->opts = *opts;
@@ -426,6 +451,7 @@ lf_status fuse_impl(const FuseArgs& a, void* d_ws, hipStream_t stream) {
   if (cnt) LF_TRY(launch_zero(cnt, (int64_t)B * d.n_texels * 4, stream), "clear counts");
   int32_t* rank = sorted ? reinterpret_cast<int32_t*>(ws + L.rank) : nullptr;
   lf_status status;
+  int nbatch = 0;      // sorted batches issued: batch k's gather runs on mesh->side
   for (int f0 = 0; f0 < a.F;) {
     int nb = (a.F - f0) < B ? (a.F - f0) : B;
     const int fi = a.pool > 0 ? f0 % a.pool : f0;     // input frame of the batch's first frame
@@ -442,28 +468,39 @@ lf_status fuse_impl(const FuseArgs& a, void* d_ws, hipStream_t stream) {
              "learned weights");
     }
     if (sorted) {
-      int32_t* start = reinterpret_cast<int32_t*>(ws + L.start);
-      uint32_t* eo = reinterpret_cast<uint32_t*>(ws + L.ent_off);
-      float* ew = a.weighting != LF_W_PIXEL ? reinterpret_cast<float*>(ws + L.ent_w) : nullptr;
-      float* es = a.dtype == LF_FP8_E4M3 ? reinterpret_cast<float*>(ws + L.ent_s) : nullptr;
+      const int k = nbatch & 1;
+      int32_t* start = reinterpret_cast<int32_t*>(ws + L.start[k]);
+      int32_t* rows = reinterpret_cast<int32_t*>(ws + L.rows[k]);
+      int32_t* nrows = reinterpret_cast<int32_t*>(ws + L.nrows[k]);
+      uint32_t* eo = reinterpret_cast<uint32_t*>(ws + L.ent_off[k]);
+      float* ew = a.weighting != LF_W_PIXEL ? reinterpret_cast<float*>(ws + L.ent_w[k]) : nullptr;
+      float* es = a.dtype == LF_FP8_E4M3 ? reinterpret_cast<float*>(ws + L.ent_s[k]) : nullptr;
+      float* stg = staged ? reinterpret_cast<float*>(ws + L.stage[k]) : nullptr;
+      // set k was last read by the gather two batches ago
+      if (nbatch >= 2) LF_TRY(hipStreamWaitEvent(stream, mesh->gathered_ev[k], 0), "wait for gather");
       {
         StageTimer tm(mesh, 3, stream);
-        LF_TRY(launch_zero(ws + L.nrows, 4, stream), "clear row count");
-        LF_TRY(launch_seg_scan(seg, d.n_texels, reinterpret_cast<int32_t*>(ws + L.sums), start,
-                               reinterpret_cast<int32_t*>(ws + L.rows), reinterpret_cast<int32_t*>(ws + L.nrows),
-                               stream), "segment scan");
+        LF_TRY(launch_zero(nrows, 4, stream), "clear row count");
+        LF_TRY(launch_seg_scan(seg, d.n_texels, reinterpret_cast<int32_t*>(ws + L.sums), start, rows, nrows, stream),
+               "segment scan");
         if (staged)
-          LF_TRY(launch_seg_stage(in, fi, nb, H, W, d.c, lb, rank, start, eo, ew, reinterpret_cast<float*>(ws + L.stage),
-                                  a.weighting, cnt, d.n_texels, wpix, stream), "segment stage");
+          LF_TRY(launch_seg_stage(in, fi, nb, H, W, d.c, lb, rank, start, eo, ew, stg, a.weighting, cnt, d.n_texels,
+                                  wpix, stream), "segment stage");
         else
           LF_TRY(launch_seg_fill(in, fi, nb, H, W, lb, rank, start, eo, ew, es, a.weighting, cnt, d.n_texels, wpix,
                                  stream), "segment fill");
       }
-      StageTimer tm(mesh, 2, stream);
-      // staged observations: contiguous class vectors at element offset slot * c
-      const ProbIn gin = staged ? ProbIn{ws + L.stage, nullptr, nullptr, 0, 1, 0, 0, LF_F32} : in;
-      LF_TRY(launch_seg_gather(d, gin, staged ? 0 : fi, H, W, start, reinterpret_cast<int32_t*>(ws + L.rows),
-                               reinterpret_cast<int32_t*>(ws + L.nrows), eo, ew, es, stream), "segment gather");
+      LF_TRY(hipEventRecord(mesh->sorted_ev[k], stream), "record sorted");
+      LF_TRY(hipStreamWaitEvent(mesh->side, mesh->sorted_ev[k], 0), "wait for sort");
+      {
+        StageTimer tm(mesh, 2, mesh->side);
+        // staged observations: contiguous class vectors at element offset slot * c
+        const ProbIn gin = staged ? ProbIn{stg, nullptr, nullptr, 0, 1, 0, 0, LF_F32} : in;
+        LF_TRY(launch_seg_gather(d, gin, staged ? 0 : fi, H, W, start, rows, nrows, eo, ew, es, mesh->side),
+               "segment gather");
+      }
+      LF_TRY(hipEventRecord(mesh->gathered_ev[k], mesh->side), "record gathered");
+      ++nbatch;
     } else {
       StageTimer tm(mesh, 2, stream);
       LF_TRY(launch_scatter_atomic(d, in, fi, nb, H, W, lb, a.weighting, cnt, d.n_texels, wpix, stream), "scatter");
@@ -474,6 +511,8 @@ lf_status fuse_impl(const FuseArgs& a, void* d_ws, hipStream_t stream) {
     }
     f0 += nb;
   }
+  // the call is complete on the caller's stream once the last gather is
+  if (nbatch > 0) LF_TRY(hipStreamWaitEvent(stream, mesh->gathered_ev[(nbatch - 1) & 1], 0), "join gathers");
   return LF_OK;
 }
 
@@ -749,7 +788,10 @@ lf_status lf_set_tuning(lf_mesh mesh, const lf_tuning* t) {
   if (t->gather_unroll != 4 && t->gather_unroll != 8)
     return fail(LF_EINVAL, "gather_unroll must be 4 or 8, got %d", t->gather_unroll);
   if (t->small_px < 1 || t->small_px > 1024) return fail(LF_EINVAL, "small_px must be in [1, 1024], got %d", t->small_px);
+  if (t->gather_waves < 1 || t->gather_waves > 32)
+    return fail(LF_EINVAL, "gather_waves must be in [1, 32], got %d", t->gather_waves);
   mesh->d.small_px = t->small_px;
+  mesh->d.gather_waves = t->gather_waves;
   mesh->d.tile = t->tile;
   mesh->d.gather_unroll = t->gather_unroll;
   return LF_OK;
@@ -763,6 +805,7 @@ lf_status lf_get_tuning(lf_mesh mesh, lf_tuning* t) {
   t->tile = mesh->d.tile;
   t->gather_unroll = mesh->d.gather_unroll;
   t->small_px = mesh->d.small_px;
+  t->gather_waves = mesh->d.gather_waves;
   return LF_OK;
 }
 

@@ -24,6 +24,7 @@ struct MeshDev {
   int32_t tile;              // raster tile edge: 16 or 32 pixels
   int32_t gather_unroll;     // observations in flight per row in the sorted gather: 4 or 8
   int32_t small_px;          // pixel boxes up to this area are rasterized by one lane
+  int32_t gather_waves;      // resident waves per CU the sorted gather's grid is sized for
 };
 
 __device__ __forceinline__ int64_t row_offset(const MeshDev& m, int64_t t) {

@@ -447,7 +447,8 @@ hipError_t launch_seg_gather(const MeshDev& m, const ProbIn& in, int f_first, in
                        (reinterpret_cast<uintptr_t>(m.accum) % 16) == 0;
   if (grouped) {
     // enough resident groups to cover the machine; each walks the row list
-    const int64_t groups = std::min<int64_t>(m.n_texels, (int64_t)256 * 8 * 16 * 4);
+    // grid: gather_waves resident waves (4 row groups each) on each of the 256 CUs
+    const int64_t groups = std::min<int64_t>(m.n_texels, (int64_t)256 * m.gather_waves * 4);
     dim3 g((unsigned)((groups * 16 + 255) / 256));
 #define LF_R(DT, AGG, AT)                                                                                    \
   do {                                                                                                       \

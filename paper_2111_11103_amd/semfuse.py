@@ -39,7 +39,8 @@ class _MeshOpts(C.Structure):
 
 
 class _Tuning(C.Structure):
-    _fields_ = [("tile", C.c_int32), ("gather_unroll", C.c_int32), ("small_px", C.c_int32)]
+    _fields_ = [("tile", C.c_int32), ("gather_unroll", C.c_int32), ("small_px", C.c_int32),
+                ("gather_waves", C.c_int32)]
 
 
 class _SceneJob(C.Structure):
@@ -293,15 +294,16 @@ class Mesh:
         return out
 
     # -- tuning and jobs ----------------------------------------------------------------
-    def set_tuning(self, tile=32, gather_unroll=8, small_px=48):
+    def set_tuning(self, tile=32, gather_unroll=8, small_px=48, gather_waves=32):
         """lf_set_tuning (results do not depend on it)."""
-        _check(lib().lf_set_tuning(self._h, C.byref(_Tuning(tile, gather_unroll, small_px))))
+        _check(lib().lf_set_tuning(self._h, C.byref(_Tuning(tile, gather_unroll, small_px, gather_waves))))
         self._fws.clear()
 
     def get_tuning(self):
         t = _Tuning()
         _check(lib().lf_get_tuning(self._h, C.byref(t)))
-        return {"tile": t.tile, "gather_unroll": t.gather_unroll, "small_px": t.small_px}
+        return {"tile": t.tile, "gather_unroll": t.gather_unroll, "small_px": t.small_px,
+                "gather_waves": t.gather_waves}
 
     def job(self, cams, probs, *, scale=None, valid=None, pool=0, weighting=W_PIXEL, batch=16,
             scatter_mode=SCATTER_AUTO, l_out=None, tex_dtype=None, images=False):

@@ -1,17 +1,19 @@
 """Autotuner of the fusion's launch parameters.
 
 For one (device, image size, class count, input dtype and layout, mesh size,
-weighting) it times candidates of five knobs on the first frames of the
-caller's own input: frames per batch (8, 16, 32, 64), scatter mode
-(texel-sorted when a pixel's classes are contiguous, staged texel-sorted for
-planar FP32 inputs, LDS-hash atomic always), raster tile edge (16, 32), the
-largest triangle box rasterized by one lane (12, 24, 48, 96 pixels) and the
-sorted gather's unroll (4, 8).  The search is coordinate descent from the
-library defaults: each knob in turn is swept with the others held, and the
-fastest value kept.  The choice is cached in a JSON file keyed by that
-tuple.  Results never depend on the choice; only speed does.  Timing uses
-events on the stream the library launches on; the mesh's accumulator is
-cleared afterwards.
+weighting) it times candidates of six knobs on the first frames of the
+caller's own input (at least three batches of them, so that the overlap of
+one batch's gather with the next batch's raster is part of the timing):
+frames per batch (8 to 128), scatter mode (texel-sorted when a pixel's
+classes are contiguous, staged texel-sorted for planar FP32 inputs, LDS-hash
+atomic always), raster tile edge (16, 32), the largest triangle box
+rasterized by one lane (12, 24, 48, 96 pixels), the sorted gather's unroll
+(4, 8) and the resident waves per CU its grid is sized for (8, 16, 32).  The
+search is coordinate descent from the library defaults: each knob in turn is
+swept with the others held, and the fastest value kept.  The choice is
+cached in a JSON file keyed by that tuple.  Results never depend on the
+choice; only speed does.  Timing uses events on the stream the library
+launches on; the mesh's accumulator is cleared afterwards.
 """
 from __future__ import annotations
 
@@ -25,10 +27,11 @@ import torch
 
 from . import semfuse as sf
 
-BATCHES = (8, 16, 32, 64)
+BATCHES = (8, 16, 32, 64, 128)
 TILES = (16, 32)
 SMALL = (12, 24, 48, 96)
 UNROLLS = (4, 8)
+GATHER_WAVES = (8, 16, 32)
 _lock = threading.Lock()
 
 
@@ -81,13 +84,13 @@ def _ws_bytes(mesh, H, W, batch, weighting, mode, probs):
 
 
 def _apply(mesh, cfg):
-    mesh.set_tuning(cfg["tile"], cfg["gather_unroll"], cfg["small_px"])
+    mesh.set_tuning(cfg["tile"], cfg["gather_unroll"], cfg["small_px"], cfg["gather_waves"])
 
 
 def autotune(mesh: sf.Mesh, cams: torch.Tensor, probs: torch.Tensor, *, scale=None, valid=None,
              weighting=sf.W_PIXEL, probe_frames=64, cache_path=None, force=False, ws_budget=8 << 30,
              repeats=2, log=None):
-    """Best {batch, scatter_mode, tile, small_px, gather_unroll, ms_per_frame}
+    """Best {batch, scatter_mode, tile, small_px, gather_unroll, gather_waves, ms_per_frame}
     for this mesh and input; applies the tuning to ``mesh`` and returns it."""
     F, c, H, W = probs.shape
     path = cache_path or default_cache_path()
@@ -101,9 +104,6 @@ def autotune(mesh: sf.Mesh, cams: torch.Tensor, probs: torch.Tensor, *, scale=No
             log(f"[tune] cache hit {key}: {best}")
         return dict(best, cached=True)
     nf = max(1, min(F, probe_frames))
-    cams_p, probs_p = cams[:nf], probs[:nf]
-    scale_p = None if scale is None else scale[:nf]
-    valid_p = None if valid is None else valid[:nf]
     timings = {}
 
     def trial(cfg):
@@ -111,6 +111,10 @@ def autotune(mesh: sf.Mesh, cams: torch.Tensor, probs: torch.Tensor, *, scale=No
         if k in timings:
             return timings[k]
         b = min(cfg["batch"], nf)
+        n = min(F, max(nf, 3 * b))
+        cams_p, probs_p = cams[:n], probs[:n]
+        scale_p = None if scale is None else scale[:n]
+        valid_p = None if valid is None else valid[:n]
         _apply(mesh, cfg)
         if _ws_bytes(mesh, H, W, b, weighting, cfg["scatter_mode"], probs_p) > ws_budget:
             timings[k] = math.inf
@@ -127,19 +131,19 @@ def autotune(mesh: sf.Mesh, cams: torch.Tensor, probs: torch.Tensor, *, scale=No
             run()
         ev1.record()
         ev1.synchronize()
-        timings[k] = ev0.elapsed_time(ev1) / (repeats * nf)
+        timings[k] = ev0.elapsed_time(ev1) / (repeats * n)
         return timings[k]
 
     modes = scatter_modes(probs)
     batches = [b for b in BATCHES if b <= max(nf, BATCHES[0])]
     best = {"batch": min(32, batches[-1]), "scatter_mode": modes[0], "tile": 32, "small_px": 48,
-            "gather_unroll": 8}
+            "gather_unroll": 8, "gather_waves": 32}
     best_ms = trial(best)
     sweeps = [("batch", batches), ("scatter_mode", modes), ("tile", TILES), ("small_px", SMALL),
-              ("gather_unroll", UNROLLS)]
+              ("gather_unroll", UNROLLS), ("gather_waves", GATHER_WAVES)]
     for knob, values in sweeps:
-        if knob == "gather_unroll" and best["scatter_mode"] == sf.SCATTER_ATOMIC:
-            continue                            # the unroll only affects the sorted gather
+        if knob in ("gather_unroll", "gather_waves") and best["scatter_mode"] == sf.SCATTER_ATOMIC:
+            continue                            # these only affect the sorted gather
         for v in values:
             cand = dict(best, **{knob: v})
             ms = trial(cand)

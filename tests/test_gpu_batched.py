@@ -86,8 +86,8 @@ def test_fuse_batch_matches_oracle(scenes):
 
 def test_tunings_do_not_change_results(scenes):
     d = scenes[0]
-    for tile, unroll, small in ((16, 4, 12), (16, 8, 1), (32, 4, 96)):
-        t = {"tile": tile, "gather_unroll": unroll, "small_px": small}
+    for tile, unroll, small, gw in ((16, 4, 12, 8), (16, 8, 1, 1), (32, 4, 96, 32)):
+        t = {"tile": tile, "gather_unroll": unroll, "small_px": small, "gather_waves": gw}
         jobs, meshes = _jobs(scenes[:1], tunings=[t])
         assert meshes[0].get_tuning() == t
         sf.fuse_batch(jobs)
@@ -128,12 +128,12 @@ def test_autotuner_picks_and_caches(scenes, tmp_path):
     path = str(tmp_path / "tune.json")
     r1 = tune.autotune(m, cams, probs, valid=d["valid"].cuda(), probe_frames=8, cache_path=path, log=say)
     assert not r1["cached"] and r1["n_candidates"] >= 6
-    assert m.get_tuning() == {k: r1[k] for k in ("tile", "gather_unroll", "small_px")}
+    assert m.get_tuning() == {k: r1[k] for k in ("tile", "gather_unroll", "small_px", "gather_waves")}
     with open(path) as fh:
         table = json.load(fh)
     assert len(table) == 1
     r2 = tune.autotune(m, cams, probs, valid=d["valid"].cuda(), probe_frames=8, cache_path=path)
-    knobs = ("tile", "gather_unroll", "small_px", "batch", "scatter_mode")
+    knobs = ("tile", "gather_unroll", "small_px", "gather_waves", "batch", "scatter_mode")
     assert r2["cached"] and {k: r2[k] for k in knobs} == {k: r1[k] for k in knobs}
     # the accumulator is left clear
     assert float(m.accum.abs().max()) == 0.0

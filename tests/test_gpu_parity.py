@@ -283,3 +283,30 @@ def test_staged_mode_rejects_unsupported_inputs(cfg1):
     gm = gpu_mesh((sc.vertices, sc.faces), 1, oracle.SPLIT, 13)
     with pytest.raises(sf.SemfuseError):
         gm.fuse_frames(to_dev(w.cams[:2], torch.float32), w.probs[:2].cuda(), scatter_mode=sf.SCATTER_STAGED)
+
+
+def test_sorted_pipeline_many_small_batches(cfg1):
+    """One frame per batch (20 batches): the gather of batch k runs on the
+    library's second stream while batch k + 1 is rendered and sorted, over
+    two alternating buffer sets; the result equals the oracle, also across
+    two calls in a row (incremental fusion)."""
+    w = cfg1
+    sc = w.scene
+    gm = gpu_mesh((sc.vertices, sc.faces), 1, oracle.SPLIT, 13)
+    om = oracle_mesh(sc.vertices, sc.faces, 1, oracle.SPLIT)
+    _, l_o = om.raster_frames(w.cams, w.H, w.W)
+    probs_cl = w.probs.to(memory_format=torch.channels_last).cuda()
+    cams = to_dev(w.cams, torch.float32)
+    for weighting in (sf.W_PIXEL, sf.W_IMAGE):
+        gm.reset()
+        gm.fuse_frames(cams[:7], probs_cl[:7], valid=w.valid[:7].cuda(), weighting=weighting, batch=1,
+                       scatter_mode=sf.SCATTER_SORTED)
+        gm.fuse_frames(cams[7:], probs_cl[7:], valid=w.valid[7:].cuda(), weighting=weighting, batch=2,
+                       scatter_mode=sf.SCATTER_SORTED)
+        tex, lab = gm.finalize()
+        torch.cuda.synchronize()
+        A_o, W_o = oracle.fuse(om.n_texels, 13, l_o, w.probs.numpy(), w.valid.numpy(), weighting=weighting)
+        compare_fused(gm.accum.cpu().numpy(), A_o)
+        P_o, lab_o = oracle.finalize(A_o, W_o)
+        compare_normalized(tex.cpu().numpy(), P_o)
+        compare_labels(lab.cpu().numpy(), P_o, lab_o)
