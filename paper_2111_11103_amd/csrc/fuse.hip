@@ -20,19 +20,12 @@
 
 namespace lf {
 
-__device__ __forceinline__ float e4m3_value(uint32_t q) {
-  const int e = (q >> 3) & 15, mnt = q & 7;
-  float v = (e == 0) ? (float)mnt * 0.001953125f : __builtin_ldexpf((float)(8 + mnt), e - 10);
-  if (e == 15 && mnt == 7) v = __builtin_nanf("");
-  return (q & 0x80u) ? -v : v;
-}
-
 template <int DT>
 __device__ __forceinline__ float load_prob(const ProbIn& in, int64_t e, float scale) {
   if constexpr (DT == 0) {
     return __builtin_nontemporal_load(reinterpret_cast<const float*>(in.p) + e);
   } else {
-    return e4m3_value(__builtin_nontemporal_load(reinterpret_cast<const uint8_t*>(in.p) + e)) * scale;
+    return fp8_e4m3(__builtin_nontemporal_load(reinterpret_cast<const uint8_t*>(in.p) + e)) * scale;
   }
 }
 
@@ -330,8 +323,14 @@ __global__ __launch_bounds__(256) void k_render(const int32_t* __restrict__ l, c
     uint64_t vv = ~0ull;
     if (valid) {
       vv = 0;
+      if ((reinterpret_cast<uintptr_t>(valid + i) & 7) == 0) {
+        const uint64_t raw = *reinterpret_cast<const uint64_t*>(valid + i);
 #pragma unroll
-      for (int k = 0; k < 8; ++k) vv |= (uint64_t)(valid[i + k] ? 0xffu : 0u) << (8 * k);
+        for (int k = 0; k < 8; ++k) vv |= (uint64_t)(((raw >> (8 * k)) & 0xffu) ? 0xffu : 0u) << (8 * k);
+      } else {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) vv |= (uint64_t)(valid[i + k] ? 0xffu : 0u) << (8 * k);
+      }
     }
     uint64_t o = 0;
 #pragma unroll

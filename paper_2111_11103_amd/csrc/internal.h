@@ -67,6 +67,15 @@ struct ProbIn {
   int32_t dtype;             // 0 = f32, 3 = e4m3
 };
 
+// OCP E4M3FN code (sign, 4 exponent bits with bias 7, 3 mantissa bits; 0x7f /
+// 0xff are NaN, no infinities) to binary32, exactly, by the gfx950 FP8
+// conversion instruction: byte K of a packed word, or a single code.
+template <int K>
+__device__ __forceinline__ float fp8_e4m3_byte(uint32_t w) {
+  return __builtin_amdgcn_cvt_f32_fp8((int)w, K);
+}
+__device__ __forceinline__ float fp8_e4m3(uint32_t code) { return __builtin_amdgcn_cvt_f32_fp8((int)code, 0); }
+
 // ---- launchers (return hipGetLastError()) ----------------------------------
 hipError_t launch_mesh_prep(const MeshDev& m, const int32_t* faces, hipStream_t s);
 hipError_t launch_offsets(const MeshDev& m, int32_t* scratch, hipStream_t s);

@@ -191,13 +191,6 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const void* __restrict__ pa
 // ---- features ---------------------------------------------------------------------
 // Probability features of pixel (frame f, y, x): normalised entropy, top-1,
 // top-1 minus top-2.  Also returns the first maximal class.
-__device__ __forceinline__ float e4m3_code(uint32_t q) {
-  const int e = (q >> 3) & 15, mn = q & 7;
-  float v = (e == 0) ? (float)mn * 0.001953125f : __builtin_ldexpf((float)(8 + mn), e - 10);
-  if (e == 15 && mn == 7) v = __builtin_nanf("");
-  return (q & 0x80u) ? -v : v;
-}
-
 // Running entropy / top-2 / first-argmax update with class j's probability.
 __device__ __forceinline__ void prob_step(float p, int j, float& h, float& p1, float& p2, int& best) {
   if (p > 0.0f) h -= p * logf(p);
@@ -240,8 +233,10 @@ __device__ __forceinline__ void prob_features(const ProbIn& in, int64_t base, fl
 #pragma unroll
       for (int q = 0; q < 16; ++q)
         if (4 * q < c) {
-#pragma unroll
-          for (int k = 0; k < 4; ++k) prob_step(e4m3_code((v[q] >> (8 * k)) & 0xffu) * scale, 4 * q + k, h, p1, p2, best);
+          prob_step(fp8_e4m3_byte<0>(v[q]) * scale, 4 * q, h, p1, p2, best);
+          prob_step(fp8_e4m3_byte<1>(v[q]) * scale, 4 * q + 1, h, p1, p2, best);
+          prob_step(fp8_e4m3_byte<2>(v[q]) * scale, 4 * q + 2, h, p1, p2, best);
+          prob_step(fp8_e4m3_byte<3>(v[q]) * scale, 4 * q + 3, h, p1, p2, best);
         }
     }
   } else {
@@ -250,7 +245,7 @@ __device__ __forceinline__ void prob_features(const ProbIn& in, int64_t base, fl
       if constexpr (DT == 0) {
         p = reinterpret_cast<const float*>(in.p)[base + (int64_t)j * in.sc];
       } else {
-        p = e4m3_code(reinterpret_cast<const uint8_t*>(in.p)[base + (int64_t)j * in.sc]) * scale;
+        p = fp8_e4m3(reinterpret_cast<const uint8_t*>(in.p)[base + (int64_t)j * in.sc]) * scale;
       }
       prob_step(p, j, h, p1, p2, best);
     }

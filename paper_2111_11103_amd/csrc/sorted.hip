@@ -22,13 +22,6 @@
 
 namespace lf {
 
-__device__ __forceinline__ float e4m3_dec(uint32_t q) {
-  const int e = (q >> 3) & 15, mnt = q & 7;
-  float v = (e == 0) ? (float)mnt * 0.001953125f : __builtin_ldexpf((float)(8 + mnt), e - 10);
-  if (e == 15 && mnt == 7) v = __builtin_nanf("");
-  return (q & 0x80u) ? -v : v;
-}
-
 // ---- scan of the segment counts ------------------------------------------------
 constexpr int kSegChunk = 8192;   // rows per scan block (256 threads x 32)
 
@@ -202,17 +195,28 @@ __global__ __launch_bounds__(256) void k_seg_stage(ProbIn in, int f_first, int H
     const int y = (int)(p / W), x = (int)(p - (int64_t)y * W);
     const float* src = reinterpret_cast<const float*>(in.p) + (int64_t)(f_first + fb) * in.sf + (int64_t)y * in.sy +
                        (int64_t)x * in.sx;
-    for (int j = 0; j < c; ++j) sv[j * kStageRow + t] = src[(int64_t)j * in.sc];
+    float* dst = sv + t;
+#pragma unroll 4
+    for (int j = 0; j < c; ++j) {
+      dst[j * kStageRow] = *src;
+      src += in.sc;
+    }
   }
   __syncthreads();
+  // output element i (in float4 units) of the block is (row, q) = (i / nq, i % nq): walk it incrementally
   const int nq = c >> 2;
+  const int drow = 256 / nq, dq = 256 - drow * nq;
+  int row = t / nq, q = t - (t / nq) * nq;
   for (int i = t; i < 256 * nq; i += 256) {
-    const int row = i / nq, q = i - row * nq;
     const int ps = spos[row];
-    if (ps < 0) continue;
-    const float* col = sv + 4 * q * kStageRow + row;
-    const float4 v = make_float4(col[0], col[kStageRow], col[2 * kStageRow], col[3 * kStageRow]);
-    *reinterpret_cast<float4*>(staging + (int64_t)ps * c + 4 * q) = v;
+    if (ps >= 0) {
+      const float* col = sv + 4 * q * kStageRow + row;
+      const float4 v = make_float4(col[0], col[kStageRow], col[2 * kStageRow], col[3 * kStageRow]);
+      *reinterpret_cast<float4*>(staging + (int64_t)ps * c + 4 * q) = v;
+    }
+    row += drow;
+    q += dq;
+    if (q >= nq) { q -= nq; ++row; }
   }
 }
 
@@ -220,7 +224,7 @@ __global__ __launch_bounds__(256) void k_seg_stage(ProbIn in, int f_first, int H
 template <int DT>
 __device__ __forceinline__ float ld_prob(const void* p, int64_t e) {
   if constexpr (DT == 0) return reinterpret_cast<const float*>(p)[e];
-  else return e4m3_dec(reinterpret_cast<const uint8_t*>(p)[e]);
+  else return fp8_e4m3(reinterpret_cast<const uint8_t*>(p)[e]);
 }
 
 __device__ __forceinline__ float wave_max(float v) {
@@ -390,8 +394,8 @@ __global__ __launch_bounds__(256) void k_seg_gather16(MeshDev m, ProbIn in, PixD
             } else {
               const uint32_t q =
                   *reinterpret_cast<const uint32_t*>(reinterpret_cast<const uint8_t*>(in.p) + off + 4 * gl);
-              v[u] = make_float4(e4m3_dec(q & 0xffu) * sc, e4m3_dec((q >> 8) & 0xffu) * sc,
-                                 e4m3_dec((q >> 16) & 0xffu) * sc, e4m3_dec(q >> 24) * sc);
+              v[u] = make_float4(fp8_e4m3_byte<0>(q) * sc, fp8_e4m3_byte<1>(q) * sc, fp8_e4m3_byte<2>(q) * sc,
+                                 fp8_e4m3_byte<3>(q) * sc);
             }
           }
         }

@@ -101,3 +101,32 @@ def test_16bit_accumulator_stagnation(work, acc_dt):
         assert res[name][1] > 0.5        # still a usable labelling
     # per-batch binary32 sums lose less than per-pixel 16-bit rounding
     assert res["sorted"][0].mean() <= res["atomic"][0].mean()
+
+
+def test_every_e4m3_code_decodes_like_the_oracle(work):
+    """All 256 E4M3 codes (negative values, subnormals, 448, both NaNs) as
+    inputs of one frame: the fused sums equal the oracle's (NaN where a NaN
+    code reached the texel), in both scatter modes."""
+    w, om, l_o, P64, lab64 = work
+    sc = w.scene
+    F, c, H, W = 2, 13, w.H, w.W
+    codes = (np.arange(F * c * H * W, dtype=np.int64) * 7919 % 256).astype(np.uint8).reshape(F, c, H, W)
+    scale = np.ones((F, H, W), np.float32)
+    A_o, _ = oracle.fuse(om.n_texels, c, l_o[:F], codes, None, scale=scale)
+    # sum of magnitudes (sign bit cleared) and observation counts bound the
+    # binary32 summation error: (n + 1) * 2^-24 * sum |p|
+    S_abs, _ = oracle.fuse(om.n_texels, c, l_o[:F], codes & np.uint8(0x7f), None, scale=scale)
+    n_obs = np.bincount(l_o[:F][l_o[:F] >= 0], minlength=om.n_texels).astype(np.float64)
+    bound = (n_obs[:, None] + 1) * 2.0 ** -24 * np.abs(S_abs)
+    for mode in (sf.SCATTER_ATOMIC, sf.SCATTER_SORTED):
+        gm = gpu_mesh((sc.vertices, sc.faces), 1, oracle.SPLIT, c)
+        q = torch.from_numpy(codes).cuda()
+        if mode == sf.SCATTER_SORTED:
+            q = q.to(memory_format=torch.channels_last)
+        gm.fuse_frames(to_dev(w.cams[:F], torch.float32), q, scale=torch.from_numpy(scale).cuda(), scatter_mode=mode)
+        torch.cuda.synchronize()
+        A = gm.accum.cpu().numpy().astype(np.float64)
+        nan_o = np.isnan(A_o)
+        assert np.array_equal(np.isnan(A), nan_o)
+        fin = ~nan_o
+        assert np.all(np.abs(A[fin] - A_o[fin]) <= bound[fin])
