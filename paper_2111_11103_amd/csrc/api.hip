@@ -151,7 +151,7 @@ lf_status check_mesh(lf_mesh m) {
 }
 
 struct FrameLayout {
-  int64_t vis, vis_n, tcnt, toff, over, tlist, l, cnt, geo, wpix, seg, rank, sums, total;
+  int64_t vis, vis_n, tcnt, tlist, l, cnt, geo, wpix, seg, rank, sums, total;
   // what the gather reads, twice: batch k uses set k % 2
   int64_t start[2], rows[2], nrows[2], ent_off[2], ent_w[2], ent_s[2], stage[2];
   int64_t list_cap, ntiles;
@@ -172,8 +172,6 @@ FrameLayout frame_layout(const MeshDev& m, int H, int W, int B, int weighting, i
   L.vis = o; o += align256(B * std::max<int64_t>(m.n_clusters, 1) * 4);
   L.vis_n = o; o += align256(B * 4);
   L.tcnt = o; o += align256(B * L.ntiles * 4);
-  L.toff = o; o += align256(B * (L.ntiles + 1) * 4);
-  L.over = o; o += align256(B * 4);
   L.tlist = o; o += align256(B * L.list_cap * 4);
   L.l = o; o += align256(B * HW * 4);
   L.cnt = o; if (weighting == LF_W_IMAGE || weighting == LF_W_LEARNED) o += align256(B * m.n_texels * 4);
@@ -209,8 +207,6 @@ RasterWs raster_ws(const FrameLayout& L, char* ws) {
   r.vis = reinterpret_cast<int32_t*>(ws + L.vis);
   r.vis_n = reinterpret_cast<int32_t*>(ws + L.vis_n);
   r.tcnt = reinterpret_cast<int32_t*>(ws + L.tcnt);
-  r.toff = reinterpret_cast<int32_t*>(ws + L.toff);
-  r.over = reinterpret_cast<int32_t*>(ws + L.over);
   r.tlist = reinterpret_cast<int32_t*>(ws + L.tlist);
   r.list_cap = L.list_cap;
   return r;

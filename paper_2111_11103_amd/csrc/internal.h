@@ -38,10 +38,8 @@ constexpr int kTileSize = 32;         // default raster tile edge (pixels)
 struct RasterWs {
   int32_t* vis;              // [B][n_clusters] visible cluster ids
   int32_t* vis_n;            // [B]
-  int32_t* tcnt;             // [B][ntiles] (zero between uses)
-  int32_t* toff;             // [B][ntiles + 1]
-  int32_t* tlist;            // [B][list_cap] triangle ids per tile
-  int32_t* over;             // [B] list overflow flags
+  int32_t* tcnt;             // [B][ntiles] tile list lengths (zero between uses)
+  int32_t* tlist;            // [B][list_cap]: ntiles lists of list_cap / ntiles triangle ids
   int64_t list_cap;
 };
 

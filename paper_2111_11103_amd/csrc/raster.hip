@@ -6,12 +6,11 @@
 //   k_cull_clusters  frame x cluster (64 consecutive triangles): conservative
 //                    frustum test of the cluster box, compact list of the
 //                    clusters that may be visible;
-//   k_bin (count)    one wave per visible cluster: set up every triangle
-//                    (transform, clip, 8-bit sub-pixel snap), count it into
-//                    every tile (16x16 or 32x32 pixels, a tuning knob) its
-//                    pixel-centre box overlaps;
-//   k_tile_scan      per frame exclusive scan of the tile counts;
-//   k_bin (fill)     same walk, writes triangle ids into the tile lists;
+//   k_bin            one wave per visible cluster: set up every triangle
+//                    (transform, clip, 8-bit sub-pixel snap) and append it
+//                    to the fixed-capacity list of every tile (16x16 or
+//                    32x32 pixels, a tuning knob) its pixel-centre box
+//                    overlaps;
 //   k_tile_raster    one workgroup per (frame, tile): a 64-bit depth|id key
 //                    per pixel in LDS, every listed triangle rasterized with
 //                    int64 edge functions and the top-left rule (small ones by
@@ -175,12 +174,16 @@ __global__ __launch_bounds__(256) void k_cull_clusters(MeshDev m, const float* _
   if (keep) vis[(int64_t)fb * m.n_clusters + slot] = (int32_t)cl;
 }
 
-// ---- 2./4. binning into tiles (count, then fill) ---------------------------------
-template <bool FILL, int TS>
+// ---- 2. binning into tiles (one pass into fixed-capacity tile lists) -----------------
+// Every tile of a frame owns `cap` list slots.  A triangle takes a slot in
+// every tile its pixel-centre box overlaps (lanes on the same tile share one
+// atomic); the tile's counter keeps counting past `cap`, which tells the
+// raster to fall back to walking the frame's visible clusters for that tile.
+template <int TS>
 __global__ __launch_bounds__(256) void k_bin(MeshDev m, const float* __restrict__ cams, int H, int W,
                                              const int32_t* __restrict__ vis, const int32_t* __restrict__ vis_n,
-                                             int32_t* __restrict__ tcnt, const int32_t* __restrict__ toff,
-                                             int32_t* __restrict__ tlist, int64_t list_cap) {
+                                             int32_t* __restrict__ tcnt, int32_t* __restrict__ tlist, int64_t list_cap,
+                                             int cap) {
   const int fb = blockIdx.y;
   const Cam cam = load_cam(cams + 16 * (int64_t)fb);
   const int ntx = (W + TS - 1) / TS, nty = (H + TS - 1) / TS;
@@ -188,6 +191,7 @@ __global__ __launch_bounds__(256) void k_bin(MeshDev m, const float* __restrict_
   const int lane = threadIdx.x & 63;
   const int nvis = vis_n[fb];
   int32_t* cnt = tcnt + (int64_t)fb * ntiles;
+  int32_t* lst = tlist + (int64_t)fb * list_cap;
   for (int w = blockIdx.x * 4 + (threadIdx.x >> 6); w < nvis; w += gridDim.x * 4) {
     const int64_t cl = vis[(int64_t)fb * m.n_clusters + w];
     const int64_t t = cl * kClusterTris + lane;
@@ -204,56 +208,20 @@ __global__ __launch_bounds__(256) void k_bin(MeshDev m, const float* __restrict_
       const unsigned long long act = __ballot(more);
       if (act == 0) break;
       const int leader_tile = __shfl(tile, __ffsll(act) - 1);
-      const unsigned long long grp = __ballot(more && tile == leader_tile);
+      const bool mine = more && tile == leader_tile;
+      const unsigned long long grp = __ballot(mine);
       const int leader = __ffsll(grp) - 1;
       const int rank = __popcll(grp & ((1ull << lane) - 1ull));
-      if (!FILL) {
-        if (lane == leader) atomicAdd(cnt + leader_tile, __popcll(grp));
-      } else {
-        int base = 0;
-        if (lane == leader) base = atomicSub(cnt + leader_tile, __popcll(grp)) - __popcll(grp);
-        base = __shfl(base, leader);
-        if (more && tile == leader_tile) {
-          const int64_t pos = (int64_t)toff[(int64_t)fb * (ntiles + 1) + leader_tile] + base + rank;
-          if (pos < list_cap) tlist[(int64_t)fb * list_cap + pos] = (int32_t)t;
-        }
-      }
-      if (more && tile == leader_tile) {
+      int base = 0;
+      if (lane == leader) base = atomicAdd(cnt + leader_tile, __popcll(grp));
+      base = __shfl(base, leader);
+      if (mine) {
+        const int pos = base + rank;
+        if (pos < cap) lst[(int64_t)leader_tile * cap + pos] = (int32_t)t;
         if (++tx > tx1) { tx = tx0; ++ty; }
         more = ty <= ty1;
       }
     }
-  }
-}
-
-// ---- 3. per-frame exclusive scan of tile counts ------------------------------------
-__global__ __launch_bounds__(1024) void k_tile_scan(const int32_t* __restrict__ tcnt, int ntiles,
-                                                    int32_t* __restrict__ toff, int64_t list_cap,
-                                                    int32_t* __restrict__ over) {
-  __shared__ int part[1024];
-  const int fb = blockIdx.x;
-  const int32_t* c = tcnt + (int64_t)fb * ntiles;
-  int32_t* o = toff + (int64_t)fb * (ntiles + 1);
-  int64_t carry = 0;
-  for (int base = 0; base < ntiles; base += 1024) {
-    const int i = base + threadIdx.x;
-    const int v = i < ntiles ? c[i] : 0;
-    part[threadIdx.x] = v;
-    __syncthreads();
-    for (int d = 1; d < 1024; d <<= 1) {
-      const int a = threadIdx.x >= d ? part[threadIdx.x - d] : 0;
-      __syncthreads();
-      part[threadIdx.x] += a;
-      __syncthreads();
-    }
-    const int64_t here = carry + part[threadIdx.x] - v;
-    if (i < ntiles) o[i] = (int32_t)std::min<int64_t>(here, list_cap);
-    carry += part[1023];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    o[ntiles] = (int32_t)std::min<int64_t>(carry, list_cap);
-    over[fb] = carry > list_cap ? 1 : 0;
   }
 }
 
@@ -360,8 +328,8 @@ __device__ __forceinline__ void raster_entries(const TileCtx& c, const Setup& s,
 template <int TS>
 __global__ __launch_bounds__(256) void k_tile_raster(MeshDev m, const float* __restrict__ cams, int H, int W,
                                                      const int32_t* __restrict__ vis, const int32_t* __restrict__ vis_n,
-                                                     const int32_t* __restrict__ toff, const int32_t* __restrict__ tlist,
-                                                     int64_t list_cap, const int32_t* __restrict__ over, RasterOut out) {
+                                                     int32_t* __restrict__ tcnt, const int32_t* __restrict__ tlist,
+                                                     int64_t list_cap, int cap, RasterOut out) {
   __shared__ unsigned long long key[TS * TS];
   __shared__ float rxs[TS], rys[TS];
   const int fb = blockIdx.y;
@@ -371,16 +339,20 @@ __global__ __launch_bounds__(256) void k_tile_raster(MeshDev m, const float* __r
   const int tile = blockIdx.x;
   const int tx0 = (tile % ntx) * TS, ty0 = (tile / ntx) * TS;
   const int tx1 = min(tx0 + TS, W) - 1, ty1 = min(ty0 + TS, H) - 1;
+  // entries of this tile's list; the counter is left at zero for the next use
+  int32_t* tc = tcnt + (int64_t)fb * ntiles + tile;
+  const int n_ent = *tc;
   for (int i = threadIdx.x; i < TS * TS; i += 256) key[i] = ~0ull;
   if (threadIdx.x < TS) rxs[threadIdx.x] = ray_x(cam, tx0 + threadIdx.x);
   else if (threadIdx.x < 2 * TS) rys[threadIdx.x - TS] = ray_y(cam, ty0 + threadIdx.x - TS);
   __syncthreads();
+  if (threadIdx.x == 0) *tc = 0;
   const TileCtx c{key, rxs, rys, tx0, ty0, TS, m.small_px};
   const int64_t HW = (int64_t)H * W;
 
-  if (!over[fb]) {
-    const int e0 = toff[(int64_t)fb * (ntiles + 1) + tile], e1 = toff[(int64_t)fb * (ntiles + 1) + tile + 1];
-    const int32_t* lst = tlist + (int64_t)fb * list_cap;
+  if (n_ent <= cap) {
+    const int e0 = 0, e1 = n_ent;
+    const int32_t* lst = tlist + (int64_t)fb * list_cap + (int64_t)tile * cap;
     for (int base = e0; base < e1; base += 256) {   // same trip count for the whole block
       const int e = base + threadIdx.x;
       const bool have = e < e1;
@@ -395,7 +367,7 @@ __global__ __launch_bounds__(256) void k_tile_raster(MeshDev m, const float* __r
       raster_entries(c, s, tri, have, max(s.x0, tx0), min(s.x1, tx1), max(s.y0, ty0), min(s.y1, ty1));
     }
   } else {
-    // the tile lists overflowed their capacity: walk every triangle of every
+    // the tile's list overflowed its capacity: walk every triangle of every
     // visible cluster instead (slow, same result)
     const int nvis = vis_n[fb];
     for (int w0 = 0; w0 < nvis; w0 += 4) {
@@ -503,13 +475,11 @@ hipError_t render_batch_ts(const MeshDev& m, const float* cams, int nb, int H, i
     k_cull_clusters<<<dim3((unsigned)((m.n_clusters + 255) / 256), (unsigned)nb), 256, 0, s>>>(m, cams, H, W, ws.vis,
                                                                                                ws.vis_n);
   const unsigned gb = (unsigned)std::min<int64_t>((m.n_clusters + 3) / 4 + 1, 256);
-  k_bin<false, TS><<<dim3(gb, (unsigned)nb), 256, 0, s>>>(m, cams, H, W, ws.vis, ws.vis_n, ws.tcnt, ws.toff, ws.tlist,
-                                                      ws.list_cap);
-  k_tile_scan<<<dim3((unsigned)nb), 1024, 0, s>>>(ws.tcnt, ntiles, ws.toff, ws.list_cap, ws.over);
-  k_bin<true, TS><<<dim3(gb, (unsigned)nb), 256, 0, s>>>(m, cams, H, W, ws.vis, ws.vis_n, ws.tcnt, ws.toff, ws.tlist,
-                                                     ws.list_cap);
-  k_tile_raster<TS><<<dim3((unsigned)ntiles, (unsigned)nb), 256, 0, s>>>(m, cams, H, W, ws.vis, ws.vis_n, ws.toff,
-                                                                         ws.tlist, ws.list_cap, ws.over, out);
+  const int cap = (int)std::min<int64_t>(ws.list_cap / ntiles, INT32_MAX);
+  k_bin<TS><<<dim3(gb, (unsigned)nb), 256, 0, s>>>(m, cams, H, W, ws.vis, ws.vis_n, ws.tcnt, ws.tlist, ws.list_cap,
+                                                   cap);
+  k_tile_raster<TS><<<dim3((unsigned)ntiles, (unsigned)nb), 256, 0, s>>>(m, cams, H, W, ws.vis, ws.vis_n, ws.tcnt,
+                                                                         ws.tlist, ws.list_cap, cap, out);
   return hipGetLastError();
 }
 

@@ -310,3 +310,41 @@ def test_sorted_pipeline_many_small_batches(cfg1):
         P_o, lab_o = oracle.finalize(A_o, W_o)
         compare_normalized(tex.cpu().numpy(), P_o)
         compare_labels(lab.cpu().numpy(), P_o, lab_o)
+
+
+def test_dense_tile_overflows_to_cluster_walk():
+    """3,000 small overlapping triangles packed into one 32x32 tile of a
+    640x480 frame: that tile's list exceeds its capacity and the raster walks
+    the frame's visible clusters instead; ids and depths stay bit-exact."""
+    say("[case] dense single-tile scene (list capacity overflow)")
+    rng = np.random.default_rng(11)
+    T = 3000
+    fx, cx, cy = 512.0, 320.0, 240.0
+    cam = np.array([fx, fx, cx, cy, 1, 0, 0, 0, 1, 0, 0, 0, 1, 0, 0, 0], np.float32)
+    pc = rng.uniform(98.0, 126.0, (T, 2))
+    z = rng.uniform(2.0, 3.0, T)
+    V = []
+    for i in range(T):
+        size = rng.uniform(0.5, 4.0)
+        for k in range(3):
+            ang = rng.uniform(0, 2 * np.pi)
+            px, py = pc[i] + size * np.array([np.cos(ang), np.sin(ang)])
+            zz = z[i] + rng.uniform(-0.01, 0.01)
+            V.append([(px - cx) * zz / fx, (py - cy) * zz / fx, zz])
+    # a few large triangles across many tiles, behind and in front
+    for zz in (1.5, 4.0):
+        for (a, b, c) in (((-1, -1), (1, -1), (-1, 1)), ((1, -1), (1, 1), (-1, 1))):
+            for p in (a, b, c):
+                V.append([p[0] * zz, p[1] * zz * 0.75, zz])
+    V = np.asarray(V, np.float32)
+    F_ = np.arange(V.shape[0], dtype=np.int32).reshape(-1, 3)
+    gm = gpu_mesh((V, F_), 2, oracle.SPLIT, 4)
+    om = oracle_mesh(V, F_, 2, oracle.SPLIT)
+    cams = cam[None]
+    _, l_o = compare_raster(gm, om, cams, 480, 640)
+    probs = torch.softmax(torch.randn((1, 4, 480, 640), generator=torch.Generator().manual_seed(3)), 1)
+    gm.fuse_frames(to_dev(cams, torch.float32), probs.to(memory_format=torch.channels_last).cuda(),
+                   scatter_mode=sf.SCATTER_SORTED)
+    torch.cuda.synchronize()
+    A_o, _ = oracle.fuse(om.n_texels, 4, l_o, probs.numpy())
+    compare_fused(gm.accum.cpu().numpy(), A_o)
