@@ -403,6 +403,39 @@ def main():
             forms[name] = {"value": 2 * npx / tt, "ms_per_step": 1000 * tt / 2,
                            "stage_ms_per_step": {STAGES[k]: pr.ms[k] / 2 for k in range(8) if pr.launches[k]}}
         mesh.bind_mlp(None)
+        # the paper's texture resolution: a_t from the worst-case frame, s_t =
+        # max(1, ceil(0.2 sqrt(a_t))), SQUARE texels (Section 3.1)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        area = mesh.triangle_max_pixels(cams, H, W, batch=32)
+        s_face = sf.texel_resolution(area, 0.2)
+        ev1.record()
+        ev1.synchronize()
+        area_ms = ev0.elapsed_time(ev1)
+        mesh_g = sf.Mesh(torch.as_tensor(sc.vertices, device=dev), torch.as_tensor(sc.faces, device=dev),
+                         n_classes=c, scheme=sf.SQUARE, s_face=s_face, keep_weights=False)
+        mesh_g.set_tuning(**mesh.get_tuning())
+        tex_g = torch.empty((mesh_g.n_texels, c), dtype=torch.float32, device=dev)
+        lab_g = torch.empty(mesh_g.n_texels, dtype=torch.uint8, device=dev)
+        ws_g = mesh_g.frame_ws(H, W, args.batch, 1, args.scatter, probs=probs)
+
+        def gamma_step():
+            mesh_g.reset()
+            mesh_g.fuse_frames(cams, probs, valid=valid, weighting=1, l_out=l_out, batch=args.batch,
+                               scatter_mode=args.scatter, ws=ws_g)
+            sf._check(L.lf_finalize(mesh_g._h, sf._ptr(tex_g), sf.F32, sf._ptr(lab_g), sf._stream()))
+            mesh_g.render_labels(lab_g, l=l_out, valid=valid, out=labels_img)
+        gamma_step()
+        torch.cuda.synchronize()
+        tg = time.perf_counter()
+        for _ in range(2):
+            gamma_step()
+        torch.cuda.synchronize()
+        tg = (time.perf_counter() - tg) / 2
+        forms["square_gamma0.2_w_image"] = {"value": npx / tg, "ms_per_step": 1000 * tg,
+                                            "texels": mesh_g.n_texels, "area_pass_ms": area_ms,
+                                            "max_s": int(s_face.max())}
+        del mesh_g, tex_g, lab_g, ws_g
         # FP8 E4M3 input with a per-pixel scale (quantised in chunks, channels-last)
         q = torch.empty((F, c, H, W), dtype=torch.uint8, device=dev).to(memory_format=torch.channels_last)
         qs = torch.empty((F, H, W), dtype=torch.float32, device=dev)

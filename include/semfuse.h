@@ -299,6 +299,27 @@ lf_status lf_extract_features(lf_mesh mesh, const float* d_cams, int32_t F, int3
                               float* d_phi, float* d_target, int32_t* d_pix, int64_t cap,
                               uint64_t* d_count, void* d_ws, int64_t ws_bytes, hipStream_t stream);
 
+/* ---- Texel resolution from the worst-case frame (Section 3.1) -------------
+ * a_t = the largest number of pixel centres triangle t covers (as the
+ * z-buffer's winner) in any frame; s_t = max(1, ceil(gamma * sqrt(a_t))).
+ * A mesh loaded with d_s_face = s_t (and the paper's SQUARE scheme) has the
+ * paper's texture resolution for that gamma.  Pixels count whether or not
+ * they are valid. */
+
+/* Workspace bytes of lf_triangle_max_pixels for frames of H x W, `batch` at a time. */
+lf_status lf_area_ws_bytes(lf_mesh mesh, int32_t H, int32_t W, int32_t batch, int64_t* bytes);
+
+/* Raise d_area [T] (int32, caller-owned; zero it to start) to every frame's
+ * pixel count of each triangle, over F frames (cameras as in
+ * lf_fuse_frames).  Several calls accumulate the maximum. */
+lf_status lf_triangle_max_pixels(lf_mesh mesh, const float* d_cams, int32_t F, int32_t H, int32_t W,
+                                 int32_t* d_area, void* d_ws, int64_t ws_bytes, hipStream_t stream);
+
+/* d_s_face [n_faces] = max(1, ceil(gamma * sqrt(d_area))) in binary32
+ * (correctly rounded square root), capped at 4096. */
+lf_status lf_texel_resolution(const int32_t* d_area, int64_t n_faces, float gamma, int32_t* d_s_face,
+                              hipStream_t stream);
+
 /* Per-stage kernel timing with HIP events recorded on the launch stream
  * around every kernel of a stage (instrumentation for roofline reports).
  * Stages: 0 ray tables + raster, 1 resolve, 2 scatter, 3 counts, 4 finalize,

@@ -213,3 +213,23 @@ def render(l, label, valid=None):
     v = None if valid is None else _c(valid, np.uint8)
     lib().or_render(l.size, _ptr(l), _ptr(v), _ptr(_c(label, np.uint8)), _ptr(out))
     return out
+
+
+def triangle_max_pixels(tri_frames, n_faces):
+    """a_t of Section 3.1: the most pixels triangle t wins in any one frame
+    (tri_frames: per-frame triangle ids [F,H,W] from the oracle raster; -1 =
+    none).  Every covered pixel counts, valid or not."""
+    area = np.zeros(n_faces, np.int64)
+    for f in range(tri_frames.shape[0]):
+        t = tri_frames[f][tri_frames[f] >= 0]
+        area = np.maximum(area, np.bincount(t, minlength=n_faces))
+    return area.astype(np.int32)
+
+
+def texel_resolution(area, gamma):
+    """s_t = max(1, ceil(gamma * sqrt(a_t))) of Section 3.1, evaluated in
+    binary32 (the paper fixes no precision; the decision is taken in the
+    kernel's), capped at 4096."""
+    a = np.asarray(area, np.float32)
+    v = np.ceil(np.float32(gamma) * np.sqrt(a))
+    return np.clip(np.maximum(v, 1), 1, 4096).astype(np.int32)

@@ -584,6 +584,61 @@ lf_status lf_fuse_frames(lf_mesh mesh, const float* d_cams, int32_t F, int32_t H
   return fuse_impl(a, d_ws, stream);
 }
 
+lf_status lf_area_ws_bytes(lf_mesh mesh, int32_t H, int32_t W, int32_t batch, int64_t* bytes) {
+  g_err[0] = 0;
+  lf_status st = check_mesh(mesh);
+  if (st != LF_OK) return st;
+  if ((st = check_frames(1, H, W)) != LF_OK) return st;
+  if (batch < 1 || batch > 65535) return fail(LF_EINVAL, "batch must be in [1, 65535]");
+  if (bytes)
+    *bytes = frame_layout(mesh->d, H, W, batch, LF_W_PIXEL, LF_SCATTER_ATOMIC).total +
+             align256((int64_t)batch * std::max<int64_t>(mesh->d.T, 1) * 4);
+  return LF_OK;
+}
+
+lf_status lf_triangle_max_pixels(lf_mesh mesh, const float* d_cams, int32_t F, int32_t H, int32_t W, int32_t* d_area,
+                                 void* d_ws, int64_t ws_bytes, hipStream_t stream) {
+  g_err[0] = 0;
+  lf_status st = check_mesh(mesh);
+  if (st != LF_OK) return st;
+  if ((st = check_frames(F, H, W)) != LF_OK) return st;
+  if (F == 0 || mesh->d.T == 0) return LF_OK;
+  if (!d_cams || !d_area || !d_ws) return fail(LF_EINVAL, "NULL argument");
+  if (reinterpret_cast<uintptr_t>(d_ws) & 255) return fail(LF_EINVAL, "workspace must be 256-byte aligned");
+  const MeshDev& d = mesh->d;
+  auto total = [&](int b) {
+    return frame_layout(d, H, W, b, LF_W_PIXEL, LF_SCATTER_ATOMIC).total + align256((int64_t)b * d.T * 4);
+  };
+  int B = 1;
+  while (B < F && B < 64 && total(B * 2) <= ws_bytes) B *= 2;
+  if (B > F) B = F;
+  if (ws_bytes < total(B)) return fail(LF_ESIZE, "workspace %lld < %lld bytes", (long long)ws_bytes, (long long)total(B));
+  const FrameLayout L = frame_layout(d, H, W, B, LF_W_PIXEL, LF_SCATTER_ATOMIC);
+  char* ws = reinterpret_cast<char*>(d_ws);
+  int32_t* tri = reinterpret_cast<int32_t*>(ws + L.l);
+  int32_t* tricnt = reinterpret_cast<int32_t*>(ws + L.total);
+  LF_TRY(launch_zero(ws + L.tcnt, B * L.ntiles * 4, stream), "clear tile counts");
+  LF_TRY(launch_zero(tricnt, (int64_t)B * d.T * 4, stream), "clear triangle counts");
+  for (int f0 = 0; f0 < F; f0 += B) {
+    const int nb = (F - f0) < B ? (F - f0) : B;
+    RasterOut out{nullptr, tri, nullptr, nullptr, nullptr, 0, nullptr, nullptr, nullptr, tricnt};
+    if ((st = render_batch(mesh, d_cams, f0, nb, H, W, L, ws, out, stream)) != LF_OK) return st;
+    LF_TRY(launch_area_max(tri, nb, H, W, tricnt, d.T, d_area, stream), "area max");
+  }
+  return LF_OK;
+}
+
+lf_status lf_texel_resolution(const int32_t* d_area, int64_t n_faces, float gamma, int32_t* d_s_face,
+                              hipStream_t stream) {
+  g_err[0] = 0;
+  if (n_faces < 0) return fail(LF_EINVAL, "negative face count");
+  if (!(gamma >= 0.0f) || gamma > 1e6f) return fail(LF_EINVAL, "gamma must be in [0, 1e6]");
+  if (n_faces == 0) return LF_OK;
+  if (!d_area || !d_s_face) return fail(LF_EINVAL, "NULL argument");
+  LF_TRY(launch_texel_resolution(d_area, n_faces, gamma, d_s_face, stream), "texel resolution");
+  return LF_OK;
+}
+
 lf_status lf_fuse_ws_bytes(lf_mesh mesh, int32_t H, int32_t W, int32_t batch, int32_t weighting,
                            int32_t scatter_mode, int32_t prob_dtype, const int64_t* h_strides, int64_t* bytes) {
   g_err[0] = 0;

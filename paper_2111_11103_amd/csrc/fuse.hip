@@ -196,6 +196,56 @@ __global__ __launch_bounds__(256) void k_clear_counts(const int32_t* __restrict_
   if (li >= 0) cnt[(int64_t)fb * cnt_stride + li] = 0;
 }
 
+// ---- texel resolution (Section 3.1): a_t = most pixels triangle t covers in
+// any frame; s_t = max(1, ceil(gamma * sqrt(a_t))) ----------------------------------
+// Per pixel of each frame: raise area[t] to the frame's count of t (the same
+// value from every pixel of t), then a second kernel clears the counts.
+__global__ __launch_bounds__(256) void k_area_max(const int32_t* __restrict__ tri, int H, int W,
+                                                  const int32_t* __restrict__ tricnt, int64_t T,
+                                                  int32_t* __restrict__ area) {
+  const int fb = blockIdx.y;
+  const int64_t HW = (int64_t)H * W;
+  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (p >= HW) return;
+  const int32_t t = tri[(int64_t)fb * HW + p];
+  if (t >= 0) atomicMax(area + t, tricnt[(int64_t)fb * T + t]);
+}
+
+__global__ __launch_bounds__(256) void k_area_clear(const int32_t* __restrict__ tri, int H, int W,
+                                                    int32_t* __restrict__ tricnt, int64_t T) {
+  const int fb = blockIdx.y;
+  const int64_t HW = (int64_t)H * W;
+  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (p >= HW) return;
+  const int32_t t = tri[(int64_t)fb * HW + p];
+  if (t >= 0) tricnt[(int64_t)fb * T + t] = 0;
+}
+
+hipError_t launch_area_max(const int32_t* tri, int nf, int H, int W, int32_t* tricnt, int64_t T, int32_t* area,
+                           hipStream_t s) {
+  if (nf <= 0) return hipSuccess;
+  const int64_t HW = (int64_t)H * W;
+  const dim3 g((unsigned)((HW + 255) / 256), (unsigned)nf);
+  k_area_max<<<g, 256, 0, s>>>(tri, H, W, tricnt, T, area);
+  k_area_clear<<<g, 256, 0, s>>>(tri, H, W, tricnt, T);
+  return hipGetLastError();
+}
+
+// binary32 throughout (gamma, correctly rounded sqrt, product, ceil)
+__global__ __launch_bounds__(256) void k_texel_resolution(const int32_t* __restrict__ area, int64_t T, float gamma,
+                                                          int32_t* __restrict__ s_face) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= T) return;
+  const float v = ceilf(gamma * sqrtf((float)area[t]));
+  s_face[t] = v > 1.0f ? (int32_t)fminf(v, 4096.0f) : 1;
+}
+
+hipError_t launch_texel_resolution(const int32_t* area, int64_t T, float gamma, int32_t* s_face, hipStream_t s) {
+  if (T <= 0) return hipSuccess;
+  k_texel_resolution<<<dim3((unsigned)((T + 255) / 256)), 256, 0, s>>>(area, T, gamma, s_face);
+  return hipGetLastError();
+}
+
 hipError_t launch_clear_counts(const int32_t* l, const uint8_t* /*valid*/, int nf, int H, int W, int32_t* cnt,
                                int64_t cnt_stride, hipStream_t s) {
   if (nf <= 0) return hipSuccess;

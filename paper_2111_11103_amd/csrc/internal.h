@@ -55,6 +55,7 @@ struct RasterOut {
   int32_t* rank;             // [B][H][W] rank of the pixel within its row's segment
   float4* geo;               // [B][H][W] learned-weight geometry: cos of the viewing angle,
                              // z / (1 + z), centroid closeness, 0 (zeros where no triangle)
+  int32_t* tricnt;           // [B][T] pixels covered per triangle (texel-resolution pre-pass)
 };
 
 struct ProbIn {
@@ -101,6 +102,11 @@ hipError_t launch_seg_gather(const MeshDev& m, const ProbIn& in, int f_first, in
                              const float* ent_s, hipStream_t s);
 hipError_t launch_render(const int32_t* l, const uint8_t* valid, const uint8_t* labels, int64_t npx,
                          uint8_t* out, hipStream_t s);
+
+// texel resolution from the worst-case frame (fuse.hip)
+hipError_t launch_area_max(const int32_t* tri, int nf, int H, int W, int32_t* tricnt, int64_t T, int32_t* area,
+                           hipStream_t s);
+hipError_t launch_texel_resolution(const int32_t* area, int64_t T, float gamma, int32_t* s_face, hipStream_t s);
 
 // learned per-observation weight (mlp.hip)
 int mlp_nparam();

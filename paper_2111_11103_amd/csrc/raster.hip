@@ -445,6 +445,11 @@ __global__ __launch_bounds__(256) void k_tile_raster(MeshDev m, const float* __r
     for (int r = 0; r < PPT; ++r)
       if (use[r]) atomicAdd(out.cnt + (int64_t)fb * out.cnt_stride + l[r], 1);
   }
+  if (out.tricnt) {
+#pragma unroll
+    for (int r = 0; r < PPT; ++r)
+      if (tri[r] >= 0) atomicAdd(out.tricnt + (int64_t)fb * m.T + tri[r], 1);
+  }
   if (out.seg) {
     int rk[PPT];
 #pragma unroll

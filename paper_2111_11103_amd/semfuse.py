@@ -90,6 +90,9 @@ def lib():
             L.lf_extract_features.argtypes = [_p, _p, _i32, _i32, _i32, _p, _i32, _p, _p, _p, _p, _p, _p, _p, _i64,
                                               _p, _p, _i64, _p]
             L.lf_fuse_ws_bytes.argtypes = [_p, _i32, _i32, _i32, _i32, _i32, _i32, _p, C.POINTER(_i64)]
+            L.lf_area_ws_bytes.argtypes = [_p, _i32, _i32, _i32, C.POINTER(_i64)]
+            L.lf_triangle_max_pixels.argtypes = [_p, _p, _i32, _i32, _i32, _p, _p, _i64, _p]
+            L.lf_texel_resolution.argtypes = [_p, _i64, C.c_float, _p, _p]
             L.lf_set_tuning.argtypes = [_p, C.POINTER(_Tuning)]
             L.lf_get_tuning.argtypes = [_p, C.POINTER(_Tuning)]
             L.lf_batch_ws_bytes.argtypes = [C.POINTER(_SceneJob), _i32, C.POINTER(_i64)]
@@ -103,7 +106,7 @@ def lib():
                          "lf_mlp_sizes", "lf_mlp_pack", "lf_mlp_bind", "lf_mlp_forward", "lf_mlp_grad",
                          "lf_adam_step", "lf_extract_features", "lf_set_tuning", "lf_get_tuning",
                          "lf_batch_ws_bytes", "lf_fuse_batch", "lf_graph_capture_batch", "lf_graph_launch",
-                         "lf_fuse_ws_bytes"):
+                         "lf_fuse_ws_bytes", "lf_area_ws_bytes", "lf_triangle_max_pixels", "lf_texel_resolution"):
                 getattr(L, name).restype = _i32
             _lib = L
     return _lib
@@ -292,6 +295,23 @@ class Mesh:
         _check(lib().lf_rasterize(self._h, _ptr(cams), F, H, W, _ptr(out["tri"]), _ptr(out["l"]), _ptr(out["z"]),
                                   _ptr(ws), ws.numel(), _stream()))
         return out
+
+    # -- texel resolution from the worst-case frame ---------------------------------------
+    def triangle_max_pixels(self, cams, H, W, area=None, batch=16):
+        """lf_triangle_max_pixels -> int32 [T]: most pixels each triangle covers in any frame
+        (accumulates into ``area`` when given)."""
+        _need_cuda(cams, "cams", torch.float32)
+        cams = cams.contiguous()
+        if area is None:
+            area = torch.zeros(self.n_faces, dtype=torch.int32, device=self.device)
+        _need_cuda(area, "area", torch.int32)
+        b = max(1, min(int(batch), cams.shape[0]))
+        n = _i64()
+        _check(lib().lf_area_ws_bytes(self._h, H, W, b, C.byref(n)))
+        ws = torch.empty(n.value, dtype=torch.uint8, device=self.device)
+        _check(lib().lf_triangle_max_pixels(self._h, _ptr(cams), cams.shape[0], H, W, _ptr(area), _ptr(ws), ws.numel(),
+                                            _stream()))
+        return area
 
     # -- tuning and jobs ----------------------------------------------------------------
     def set_tuning(self, tile=32, gather_unroll=8, small_px=48, gather_waves=32):
@@ -499,3 +519,12 @@ class Graph:
         if h is not None and h.value and _lib is not None:
             _lib.lf_graph_free(h)
             self._h = None
+
+
+def texel_resolution(area: torch.Tensor, gamma: float) -> torch.Tensor:
+    """lf_texel_resolution: per-face s = max(1, ceil(gamma * sqrt(area))) (int32 [T])."""
+    _need_cuda(area, "area", torch.int32)
+    area = area.contiguous()
+    s = torch.empty_like(area)
+    _check(lib().lf_texel_resolution(_ptr(area), area.numel(), float(gamma), _ptr(s), _stream()))
+    return s

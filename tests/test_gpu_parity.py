@@ -348,3 +348,32 @@ def test_dense_tile_overflows_to_cluster_walk():
     torch.cuda.synchronize()
     A_o, _ = oracle.fuse(om.n_texels, 4, l_o, probs.numpy())
     compare_fused(gm.accum.cpu().numpy(), A_o)
+
+
+@pytest.mark.parametrize("gamma", [0.2, 1.0])
+def test_texel_resolution_from_worst_frame(cfg1, gamma):
+    """Section 3.1: a_t (most pixels a triangle wins in any frame) bit-exact,
+    s_t = max(1, ceil(gamma sqrt(a_t))) exact, then the paper's SQUARE
+    texels at that per-face resolution fused with w^(I)."""
+    w = cfg1
+    sc = w.scene
+    gm = gpu_mesh((sc.vertices, sc.faces), 1, oracle.SPLIT, 13)
+    om = oracle_mesh(sc.vertices, sc.faces, 1, oracle.SPLIT)
+    cams = to_dev(w.cams, torch.float32)
+    area = gm.triangle_max_pixels(cams, w.H, w.W, batch=6)
+    tri_o, _ = om.raster_frames(w.cams, w.H, w.W)
+    area_o = oracle.triangle_max_pixels(tri_o, sc.n_faces)
+    assert np.array_equal(area.cpu().numpy(), area_o)
+    s_g = sf.texel_resolution(area, gamma)
+    s_o = oracle.texel_resolution(area_o, gamma)
+    assert np.array_equal(s_g.cpu().numpy(), s_o)
+    say(f"  gamma {gamma}: max a_t {area_o.max()}, s_t in [{s_o.min()}, {s_o.max()}], "
+        f"{int((s_o * (s_o + 1) // 2).sum())} texels")
+    gm2 = gpu_mesh((sc.vertices, sc.faces), 1, oracle.SQUARE, 13, s_face=s_o)
+    om2 = oracle_mesh(sc.vertices, sc.faces, 1, oracle.SQUARE, s_face=s_o)
+    _, l_o = compare_raster(gm2, om2, w.cams, w.H, w.W)
+    gm2.fuse_frames(cams, w.probs.to(memory_format=torch.channels_last).cuda(), valid=w.valid.cuda(),
+                    weighting=sf.W_IMAGE)
+    torch.cuda.synchronize()
+    A_o, W_o = oracle.fuse(om2.n_texels, 13, l_o, w.probs.numpy(), w.valid.numpy(), weighting=sf.W_IMAGE)
+    compare_fused(gm2.accum.cpu().numpy(), A_o)

@@ -133,3 +133,22 @@ def test_out_of_triangle_points_are_clamped():
             # u < 0 clamps to the column a = 0; u + v > 1 to the diagonal cell
             assert oracle.texel_id(s, scheme, -0.5, 0.0) == oracle.texel_id(s, scheme, 0.0, 0.0)
             assert oracle.texel_id(s, scheme, 0.99, 0.99) == oracle.texel_id(s, scheme, 0.99, 0.0)
+
+
+def test_texel_resolution_closed_forms():
+    """s = max(1, ceil(gamma sqrt(a))) (Section 3.1): gamma = 0 never
+    subdivides, empty triangles keep one texel, perfect squares are exact."""
+    a = np.array([0, 1, 4, 16, 17, 100, 101, 10**6], np.int32)
+    assert np.array_equal(oracle.texel_resolution(a, 0.0), np.ones(8, np.int32))
+    assert np.array_equal(oracle.texel_resolution(a, 1.0), [1, 1, 2, 4, 5, 10, 11, 1000])
+    assert np.array_equal(oracle.texel_resolution(a, 0.5), [1, 1, 1, 2, 3, 5, 6, 500])
+    assert oracle.texel_resolution(np.array([10**9], np.int32), 1000.0)[0] == 4096
+
+
+def test_triangle_max_pixels_by_hand():
+    tri = np.full((3, 4, 5), -1, np.int32)
+    tri[0, :2, :2] = 0          # 4 pixels of triangle 0 in frame 0
+    tri[1, :, :] = 1            # 20 pixels of triangle 1 in frame 1
+    tri[2, 0, 0] = 0            # 1 pixel of 0, 3 of 2 in frame 2
+    tri[2, 1, :3] = 2
+    assert list(oracle.triangle_max_pixels(tri, 4)) == [4, 20, 3, 0]
