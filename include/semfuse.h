@@ -52,7 +52,7 @@ typedef enum {
 } lf_status;
 
 typedef enum { LF_TEX_SQUARE = 0, LF_TEX_SPLIT = 1 } lf_texel_scheme;
-typedef enum { LF_W_PIXEL = 0, LF_W_IMAGE = 1, LF_W_LEARNED = 2 } lf_weighting;
+typedef enum { LF_W_PIXEL = 0, LF_W_IMAGE = 1, LF_W_LEARNED = 2, LF_W_MIX = 3 } lf_weighting;
 typedef enum { LF_AGG_SUM = 0, LF_AGG_MUL = 1, LF_AGG_MAXSUM = 2 } lf_aggregator;
 typedef enum { LF_F32 = 0, LF_BF16 = 1, LF_F16 = 2, LF_FP8_E4M3 = 3 } lf_dtype;
 typedef enum {
@@ -108,6 +108,9 @@ lf_status lf_load_mesh(const lf_mesh_opts* opts, const float* d_vertices, int64_
                        void* d_mesh_ws, int64_t mesh_ws_bytes, void* d_accum, float* d_wsum,
                        int64_t n_texels, hipStream_t stream, lf_mesh* out);
 
+/* alpha of LF_W_MIX for this mesh (0 = w^(P), 1 = w^(I)); LF_EINVAL outside [0, 1]. */
+lf_status lf_set_weight_mix(lf_mesh mesh, float alpha);
+
 /* Clear the accumulator (and weight sums): start a new fusion. */
 lf_status lf_reset(lf_mesh mesh, hipStream_t stream);
 
@@ -129,8 +132,11 @@ lf_status lf_fuse_ws_bytes(lf_mesh mesh, int32_t H, int32_t W, int32_t batch, in
  *  d_probs  probability input, element strides[4] = (frame, class, y, x);
  *  prob_dtype LF_F32 or LF_FP8_E4M3 (then d_scale [F][H][W] float32);
  *  d_valid  [F][H][W] uint8 (0 = pixel without depth, skipped) or NULL;
- *  weighting LF_W_PIXEL (w = 1), LF_W_IMAGE (w = 1/|K_i ∩ K_x|) or
- *           LF_W_LEARNED (w = the bound MLP's output, see lf_mlp_bind);
+ *  weighting LF_W_PIXEL (w = 1), LF_W_IMAGE (w = 1/|K_i ∩ K_x|),
+ *           LF_W_LEARNED (w = the bound MLP's output, see lf_mlp_bind) or
+ *           LF_W_MIX (w = (1 - alpha) + alpha/|K_i ∩ K_x|, the weights
+ *           between w^(P) and w^(I) of the evaluation, Fig. 4a; alpha from
+ *           lf_set_weight_mix, default 1/2);
  *  d_l_out  [F][H][W] int32 texel rows (-1 = no triangle) or NULL;
  *  d_ws     workspace of lf_frame_ws_bytes(H, W, batch) bytes, 256-aligned;
  *  scatter_mode  LF_SCATTER_AUTO / ATOMIC / SORTED / STAGED (same result up

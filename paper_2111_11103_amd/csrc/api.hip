@@ -174,7 +174,7 @@ FrameLayout frame_layout(const MeshDev& m, int H, int W, int B, int weighting, i
   L.tcnt = o; o += align256(B * L.ntiles * 4);
   L.tlist = o; o += align256(B * L.list_cap * 4);
   L.l = o; o += align256(B * HW * 4);
-  L.cnt = o; if (weighting == LF_W_IMAGE || weighting == LF_W_LEARNED) o += align256(B * m.n_texels * 4);
+  L.cnt = o; if (weighting != LF_W_PIXEL) o += align256(B * m.n_texels * 4);
   L.geo = o; if (weighting == LF_W_LEARNED) o += align256(B * HW * 16);
   L.wpix = o; if (weighting == LF_W_LEARNED) o += align256(B * HW * 4);
   L.seg = o; if (L.sorted) o += align256(m.n_texels * 4);
@@ -302,6 +302,7 @@ lf_status lf_load_mesh(const lf_mesh_opts* opts, const float* d_vertices, int64_
   d.gather_unroll = 8;
   d.small_px = 48;
   d.gather_waves = 32;
+  d.mix = 0.5f;
 
   LF_TRY(launch_zero(d.err, 4, stream), "clear flag");
   if (per_face)
@@ -402,7 +403,7 @@ lf_status check_fuse(const FuseArgs& a, const void* ws, int64_t ws_bytes) {
   if (!a.cams || !a.probs || !a.strides || !ws) return fail(LF_EINVAL, "NULL argument");
   if (a.dtype != LF_F32 && a.dtype != LF_FP8_E4M3) return fail(LF_EINVAL, "probabilities must be F32 or FP8_E4M3");
   if (a.dtype == LF_FP8_E4M3 && !a.scale) return fail(LF_EINVAL, "FP8 input needs the per-pixel scale");
-  if (a.weighting < LF_W_PIXEL || a.weighting > LF_W_LEARNED) return fail(LF_EINVAL, "unknown weighting %d", a.weighting);
+  if (a.weighting < LF_W_PIXEL || a.weighting > LF_W_MIX) return fail(LF_EINVAL, "unknown weighting %d", a.weighting);
   if (a.weighting == LF_W_LEARNED && !a.mesh->mlp)
     return fail(LF_ESTATE, "learned weighting needs weights bound by lf_mlp_bind");
   if (a.scatter_mode < LF_SCATTER_AUTO || a.scatter_mode > LF_SCATTER_STAGED) return fail(LF_EINVAL, "bad scatter mode");
@@ -481,10 +482,10 @@ lf_status fuse_impl(const FuseArgs& a, void* d_ws, hipStream_t stream) {
                "segment scan");
         if (staged)
           LF_TRY(launch_seg_stage(in, fi, nb, H, W, d.c, lb, rank, start, eo, ew, stg, a.weighting, cnt, d.n_texels,
-                                  wpix, stream), "segment stage");
+                                  wpix, d.mix, stream), "segment stage");
         else
           LF_TRY(launch_seg_fill(in, fi, nb, H, W, lb, rank, start, eo, ew, es, a.weighting, cnt, d.n_texels, wpix,
-                                 stream), "segment fill");
+                                 d.mix, stream), "segment fill");
       }
       LF_TRY(hipEventRecord(mesh->sorted_ev[k], stream), "record sorted");
       LF_TRY(hipStreamWaitEvent(mesh->side, mesh->sorted_ev[k], 0), "wait for sort");
@@ -499,7 +500,8 @@ lf_status fuse_impl(const FuseArgs& a, void* d_ws, hipStream_t stream) {
       ++nbatch;
     } else {
       StageTimer tm(mesh, 2, stream);
-      LF_TRY(launch_scatter_atomic(d, in, fi, nb, H, W, lb, a.weighting, cnt, d.n_texels, wpix, stream), "scatter");
+      LF_TRY(launch_scatter_atomic(d, in, fi, nb, H, W, lb, a.weighting, cnt, d.n_texels, wpix, d.mix, stream),
+             "scatter");
     }
     if (cnt) {
       StageTimer tm(mesh, 3, stream);
@@ -845,6 +847,15 @@ lf_status lf_set_tuning(lf_mesh mesh, const lf_tuning* t) {
   mesh->d.gather_waves = t->gather_waves;
   mesh->d.tile = t->tile;
   mesh->d.gather_unroll = t->gather_unroll;
+  return LF_OK;
+}
+
+lf_status lf_set_weight_mix(lf_mesh mesh, float alpha) {
+  g_err[0] = 0;
+  lf_status st = check_mesh(mesh);
+  if (st != LF_OK) return st;
+  if (!(alpha >= 0.0f && alpha <= 1.0f)) return fail(LF_EINVAL, "alpha must be in [0, 1]");
+  mesh->d.mix = alpha;
   return LF_OK;
 }
 

@@ -40,7 +40,7 @@ template <int TW, int TH, int K, int CC, int DT, int AGG, int AT>
 __global__ __launch_bounds__(TW * TH) void k_scatter_hash(MeshDev m, ProbIn in, int f_first, int nf, int H, int W,
                                                            const int32_t* __restrict__ lbuf, int weighting,
                                                            const int32_t* __restrict__ cnt, int64_t cnt_stride,
-                                                           const float* __restrict__ wpix) {
+                                                           const float* __restrict__ wpix, float mix) {
   constexpr int NT = TW * TH;
   constexpr int HS = 2048;            // hash slots (power of two)
   constexpr int RC = 1024;            // LDS rows
@@ -85,6 +85,7 @@ __global__ __launch_bounds__(TW * TH) void k_scatter_hash(MeshDev m, ProbIn in, 
         float w = 1.0f;
         if (weighting == 1) w = 1.0f / (float)cnt[(int64_t)fb * cnt_stride + l];
         else if (weighting == 2) w = wpix[pi];
+        else if (weighting == 3) w = (1.0f - mix) + mix / (float)cnt[(int64_t)fb * cnt_stride + l];
         lk[k] = l;
         wk[k] = w;
         if (DT == 3) sck[k] = in.scale[gi];
@@ -164,13 +165,13 @@ __global__ __launch_bounds__(TW * TH) void k_scatter_hash(MeshDev m, ProbIn in, 
 
 hipError_t launch_scatter_atomic(const MeshDev& m, const ProbIn& in, int f_first, int nf, int H, int W,
                                  const int32_t* l, int weighting, const int32_t* cnt, int64_t cnt_stride,
-                                 const float* wpix, hipStream_t s) {
+                                 const float* wpix, float mix, hipStream_t s) {
   if (nf <= 0) return hipSuccess;
   constexpr int TW = 16, TH = 16, K = 4, CC = 8;
   dim3 grid((unsigned)(((W + TW - 1) / TW) * ((H + TH - 1) / TH)), (unsigned)((nf + K - 1) / K));
 #define LF_SCATTER(DT, AGG, AT)                                                                     \
   k_scatter_hash<TW, TH, K, CC, DT, AGG, AT><<<grid, TW * TH, 0, s>>>(m, in, f_first, nf, H, W, l, weighting, cnt, \
-                                                                       cnt_stride, wpix)
+                                                                       cnt_stride, wpix, mix)
 #define LF_SCATTER2(DT)                                                   \
   do {                                                                    \
     if (m.aggregator == 1) LF_SCATTER(DT, 1, 0);                          \

@@ -25,6 +25,7 @@ struct MeshDev {
   int32_t gather_unroll;     // observations in flight per row in the sorted gather: 4 or 8
   int32_t small_px;          // pixel boxes up to this area are rasterized by one lane
   int32_t gather_waves;      // resident waves per CU the sorted gather's grid is sized for
+  float mix;                 // alpha of the mixed weight (1 - alpha) w^(P) + alpha w^(I)
 };
 
 __device__ __forceinline__ int64_t row_offset(const MeshDev& m, int64_t t) {
@@ -85,7 +86,7 @@ hipError_t launch_render_batch(const MeshDev& m, const float* cams, int nb, int 
                                const RasterOut& out, hipStream_t s);
 hipError_t launch_scatter_atomic(const MeshDev& m, const ProbIn& in, int f_first, int nf, int H, int W,
                                  const int32_t* l, int weighting, const int32_t* cnt, int64_t cnt_stride,
-                                 const float* wpix, hipStream_t s);
+                                 const float* wpix, float mix, hipStream_t s);
 hipError_t launch_clear_counts(const int32_t* l, const uint8_t* valid, int nf, int H, int W, int32_t* cnt,
                                int64_t cnt_stride, hipStream_t s);
 hipError_t launch_finalize(const MeshDev& m, void* tex_out, int tex_dtype, uint8_t* labels, hipStream_t s);
@@ -93,10 +94,11 @@ hipError_t launch_seg_scan(const int32_t* seg, int64_t n, int32_t* sums, int32_t
                            int32_t* nrows, hipStream_t s);
 hipError_t launch_seg_fill(const ProbIn& in, int f_first, int nf, int H, int W, const int32_t* l, const int32_t* rank,
                            const int32_t* start, uint32_t* ent_pix, float* ent_w, float* ent_s, int weighting,
-                           const int32_t* cnt, int64_t cnt_stride, const float* wpix, hipStream_t s);
+                           const int32_t* cnt, int64_t cnt_stride, const float* wpix, float mix, hipStream_t s);
 hipError_t launch_seg_stage(const ProbIn& in, int f_first, int nf, int H, int W, int c, const int32_t* l,
                             const int32_t* rank, const int32_t* start, uint32_t* ent_pix, float* ent_w, float* staging,
-                            int weighting, const int32_t* cnt, int64_t cnt_stride, const float* wpix, hipStream_t s);
+                            int weighting, const int32_t* cnt, int64_t cnt_stride, const float* wpix, float mix,
+                            hipStream_t s);
 hipError_t launch_seg_gather(const MeshDev& m, const ProbIn& in, int f_first, int H, int W, const int32_t* start,
                              const int32_t* rows, const int32_t* nrows, const uint32_t* ent_pix, const float* ent_w,
                              const float* ent_s, hipStream_t s);

@@ -119,7 +119,7 @@ __global__ __launch_bounds__(256) void k_seg_fill(ProbIn in, int f_first, int H,
                                                   uint32_t* __restrict__ ent_pix, float* __restrict__ ent_w,
                                                   float* __restrict__ ent_s, int weighting,
                                                   const int32_t* __restrict__ cnt, int64_t cnt_stride,
-                                                  const float* __restrict__ wpix) {
+                                                  const float* __restrict__ wpix, float mix) {
   constexpr int P = 4;
   const int fb = blockIdx.y;
   const int64_t HW = (int64_t)H * W;
@@ -145,6 +145,7 @@ __global__ __launch_bounds__(256) void k_seg_fill(ProbIn in, int f_first, int H,
       float w = 1.0f;
       if (weighting == 1) w = 1.0f / (float)cnt[(int64_t)fb * cnt_stride + l[k]];
       else if (weighting == 2) w = wpix[(int64_t)fb * HW + p[k]];
+      else if (weighting == 3) w = (1.0f - mix) + mix / (float)cnt[(int64_t)fb * cnt_stride + l[k]];
       ent_w[pos] = w;
     }
     if (ent_s) ent_s[pos] = in.scale[(int64_t)(f_first + fb) * HW + p[k]];
@@ -166,7 +167,7 @@ __global__ __launch_bounds__(256) void k_seg_stage(ProbIn in, int f_first, int H
                                                    const int32_t* __restrict__ start, uint32_t* __restrict__ ent_pix,
                                                    float* __restrict__ ent_w, float* __restrict__ staging,
                                                    int weighting, const int32_t* __restrict__ cnt, int64_t cnt_stride,
-                                                   const float* __restrict__ wpix) {
+                                                   const float* __restrict__ wpix, float mix) {
   extern __shared__ float stage_lds[];
   int* spos = reinterpret_cast<int*>(stage_lds);            // [256]
   float* sv = stage_lds + 256;                              // [c][kStageRow]
@@ -187,6 +188,7 @@ __global__ __launch_bounds__(256) void k_seg_stage(ProbIn in, int f_first, int H
       float w = 1.0f;
       if (weighting == 1) w = 1.0f / (float)cnt[(int64_t)fb * cnt_stride + l];
       else if (weighting == 2) w = wpix[(int64_t)fb * HW + p];
+      else if (weighting == 3) w = (1.0f - mix) + mix / (float)cnt[(int64_t)fb * cnt_stride + l];
       ent_w[pos] = w;
     }
   }
@@ -505,25 +507,26 @@ hipError_t launch_seg_scan(const int32_t* seg, int64_t n, int32_t* sums, int32_t
 
 hipError_t launch_seg_stage(const ProbIn& in, int f_first, int nf, int H, int W, int c, const int32_t* l,
                             const int32_t* rank, const int32_t* start, uint32_t* ent_pix, float* ent_w, float* staging,
-                            int weighting, const int32_t* cnt, int64_t cnt_stride, const float* wpix, hipStream_t s) {
+                            int weighting, const int32_t* cnt, int64_t cnt_stride, const float* wpix, float mix,
+                            hipStream_t s) {
   if (nf <= 0) return hipSuccess;
   if (c > kStageMaxC || (c & 3) || in.dtype != 0) return hipErrorInvalidValue;
   const int64_t HW = (int64_t)H * W;
   const size_t lds = (size_t)(256 + c * kStageRow) * 4;
   k_seg_stage<<<dim3((unsigned)((HW + 255) / 256), (unsigned)nf), 256, lds, s>>>(in, f_first, H, W, c, l, rank, start,
                                                                                  ent_pix, ent_w, staging, weighting,
-                                                                                 cnt, cnt_stride, wpix);
+                                                                                 cnt, cnt_stride, wpix, mix);
   return hipGetLastError();
 }
 
 hipError_t launch_seg_fill(const ProbIn& in, int f_first, int nf, int H, int W, const int32_t* l, const int32_t* rank,
                            const int32_t* start, uint32_t* ent_pix, float* ent_w, float* ent_s, int weighting,
-                           const int32_t* cnt, int64_t cnt_stride, const float* wpix, hipStream_t s) {
+                           const int32_t* cnt, int64_t cnt_stride, const float* wpix, float mix, hipStream_t s) {
   if (nf <= 0) return hipSuccess;
   const int64_t HW = (int64_t)H * W;
   k_seg_fill<<<dim3((unsigned)((HW + 1023) / 1024), (unsigned)nf), 256, 0, s>>>(in, f_first, H, W, l, rank, start, ent_pix,
                                                                               ent_w, ent_s, weighting, cnt, cnt_stride,
-                                                                              wpix);
+                                                                              wpix, mix);
   return hipGetLastError();
 }
 

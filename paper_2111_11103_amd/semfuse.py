@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(HERE, "libsemfuse.so")
 # enums of semfuse.h
 LF_OK, LF_EINVAL, LF_ESIZE, LF_EHIP, LF_ESTATE = 0, -1, -2, -3, -4
 SQUARE, SPLIT = 0, 1
-W_PIXEL, W_IMAGE, W_LEARNED = 0, 1, 2
+W_PIXEL, W_IMAGE, W_LEARNED, W_MIX = 0, 1, 2, 3
 AGG_SUM, AGG_MUL, AGG_MAXSUM = 0, 1, 2
 F32, BF16, F16, FP8_E4M3 = 0, 1, 2, 3
 SCATTER_AUTO, SCATTER_ATOMIC, SCATTER_SORTED, SCATTER_STAGED = 0, 1, 2, 3
@@ -91,6 +91,7 @@ def lib():
                                               _p, _p, _i64, _p]
             L.lf_fuse_ws_bytes.argtypes = [_p, _i32, _i32, _i32, _i32, _i32, _i32, _p, C.POINTER(_i64)]
             L.lf_area_ws_bytes.argtypes = [_p, _i32, _i32, _i32, C.POINTER(_i64)]
+            L.lf_set_weight_mix.argtypes = [_p, C.c_float]
             L.lf_triangle_max_pixels.argtypes = [_p, _p, _i32, _i32, _i32, _p, _p, _i64, _p]
             L.lf_texel_resolution.argtypes = [_p, _i64, C.c_float, _p, _p]
             L.lf_set_tuning.argtypes = [_p, C.POINTER(_Tuning)]
@@ -106,7 +107,8 @@ def lib():
                          "lf_mlp_sizes", "lf_mlp_pack", "lf_mlp_bind", "lf_mlp_forward", "lf_mlp_grad",
                          "lf_adam_step", "lf_extract_features", "lf_set_tuning", "lf_get_tuning",
                          "lf_batch_ws_bytes", "lf_fuse_batch", "lf_graph_capture_batch", "lf_graph_launch",
-                         "lf_fuse_ws_bytes", "lf_area_ws_bytes", "lf_triangle_max_pixels", "lf_texel_resolution"):
+                         "lf_fuse_ws_bytes", "lf_area_ws_bytes", "lf_triangle_max_pixels", "lf_texel_resolution",
+                         "lf_set_weight_mix"):
                 getattr(L, name).restype = _i32
             _lib = L
     return _lib
@@ -295,6 +297,10 @@ class Mesh:
         _check(lib().lf_rasterize(self._h, _ptr(cams), F, H, W, _ptr(out["tri"]), _ptr(out["l"]), _ptr(out["z"]),
                                   _ptr(ws), ws.numel(), _stream()))
         return out
+
+    def set_weight_mix(self, alpha: float):
+        """lf_set_weight_mix: alpha of weighting=W_MIX ((1 - alpha) w^(P) + alpha w^(I))."""
+        _check(lib().lf_set_weight_mix(self._h, float(alpha)))
 
     # -- texel resolution from the worst-case frame ---------------------------------------
     def triangle_max_pixels(self, cams, H, W, area=None, batch=16):

@@ -377,3 +377,63 @@ def test_texel_resolution_from_worst_frame(cfg1, gamma):
     torch.cuda.synchronize()
     A_o, W_o = oracle.fuse(om2.n_texels, 13, l_o, w.probs.numpy(), w.valid.numpy(), weighting=sf.W_IMAGE)
     compare_fused(gm2.accum.cpu().numpy(), A_o)
+
+
+@pytest.mark.parametrize("scatter", [sf.SCATTER_ATOMIC, sf.SCATTER_SORTED])
+def test_mixed_weight_and_frame_subsampling(cfg1, scatter):
+    """Weights between w^(P) and w^(I) (Fig. 4a): w = (1 - a) + a / n, which by
+    linearity of the sum fuses to (1 - a) A^(P) + a A^(I) of the oracle; and
+    frames taken at uniform intervals (Fig. 4b) straight from a strided view
+    of the inputs."""
+    w = cfg1
+    sc = w.scene
+    om = oracle_mesh(sc.vertices, sc.faces, 1, oracle.SPLIT)
+    _, l_o = om.raster_frames(w.cams, w.H, w.W)
+    probs = w.probs.to(memory_format=torch.channels_last).cuda() if scatter == sf.SCATTER_SORTED else w.probs.cuda()
+    A_p, W_p = oracle.fuse(om.n_texels, 13, l_o, w.probs.numpy(), w.valid.numpy(), weighting=sf.W_PIXEL)
+    A_i, W_i = oracle.fuse(om.n_texels, 13, l_o, w.probs.numpy(), w.valid.numpy(), weighting=sf.W_IMAGE)
+    seen = (l_o >= 0) & (w.valid.numpy() != 0)
+    n_obs = np.bincount(l_o[seen], minlength=om.n_texels).astype(np.float64)
+    for alpha in (0.0, 0.25, 1.0):
+        gm = gpu_mesh((sc.vertices, sc.faces), 1, oracle.SPLIT, 13)
+        gm.set_weight_mix(alpha)
+        gm.fuse_frames(to_dev(w.cams, torch.float32), probs, valid=w.valid.cuda(), weighting=sf.W_MIX,
+                       scatter_mode=scatter, batch=7)
+        torch.cuda.synchronize()
+        compare_fused(gm.accum.cpu().numpy(), (1 - alpha) * A_p + alpha * A_i)
+        # weight sums: one binary32 add per observation (the atomic path), so
+        # within (n + 1) 2^-24 of the total
+        W_ref = (1 - alpha) * W_p + alpha * W_i
+        assert np.all(np.abs(gm.wsum.cpu().numpy() - W_ref) <= (n_obs + 1) * 2.0 ** -24 * W_ref)
+    with pytest.raises(sf.SemfuseError):
+        gm.set_weight_mix(1.5)
+    # every third frame, from a strided view (no copy of the probabilities)
+    gm = gpu_mesh((sc.vertices, sc.faces), 1, oracle.SPLIT, 13)
+    gm.fuse_frames(to_dev(w.cams[::3], torch.float32), probs[::3], valid=w.valid[::3].cuda(), weighting=sf.W_IMAGE,
+                   scatter_mode=scatter)
+    torch.cuda.synchronize()
+    A_s, _ = oracle.fuse(om.n_texels, 13, l_o[::3], w.probs.numpy()[::3], w.valid.numpy()[::3], weighting=sf.W_IMAGE)
+    compare_fused(gm.accum.cpu().numpy(), A_s)
+
+
+def test_paper_final_configuration(cfg1):
+    """The paper's chosen setup (Section 4.2): f_mul, w^(I), gamma = 0.2 on
+    the SQUARE texels; accumulator, normalised texture and labels against
+    the oracle."""
+    w = cfg1
+    sc = w.scene
+    gm0 = gpu_mesh((sc.vertices, sc.faces), 1, oracle.SPLIT, 13)
+    cams = to_dev(w.cams, torch.float32)
+    s_face = sf.texel_resolution(gm0.triangle_max_pixels(cams, w.H, w.W), 0.2).cpu().numpy()
+    gm = gpu_mesh((sc.vertices, sc.faces), 1, oracle.SQUARE, 13, aggregator=sf.AGG_MUL, s_face=s_face)
+    om = oracle_mesh(sc.vertices, sc.faces, 1, oracle.SQUARE, s_face=s_face)
+    _, l_o = om.raster_frames(w.cams, w.H, w.W)
+    gm.fuse_frames(cams, w.probs.to(memory_format=torch.channels_last).cuda(), valid=w.valid.cuda(),
+                   weighting=sf.W_IMAGE)
+    tex, lab = gm.finalize()
+    torch.cuda.synchronize()
+    A_o, W_o = oracle.fuse(om.n_texels, 13, l_o, w.probs.numpy(), w.valid.numpy(), weighting=sf.W_IMAGE,
+                           aggregator=sf.AGG_MUL)
+    compare_fused(gm.accum.cpu().numpy(), A_o, aggregator=sf.AGG_MUL)
+    P_o, lab_o = oracle.finalize(A_o, W_o, aggregator=sf.AGG_MUL)
+    compare_labels(lab.cpu().numpy(), P_o, lab_o)
