@@ -351,13 +351,7 @@ __global__ __launch_bounds__(256) void k_seg_gather16(MeshDev m, ProbIn in, PixD
                                                       const uint32_t* __restrict__ ent,
                                                       const float* __restrict__ ent_w, const float* __restrict__ ent_s) {
   const int gl = threadIdx.x & 15;                       // lane in group = class chunk
-  // Workgroups go to the 8 XCDs round-robin (block b to XCD b % 8); give
-  // each XCD a contiguous range of logical blocks, so neighbouring texel rows
-  // -- whose pixels share cache lines -- are gathered under the same L2.
-  // The grid is a multiple of 8 blocks, which makes this a permutation.
-  const unsigned nb8 = gridDim.x >> 3;
-  const int64_t lblock = (int64_t)(blockIdx.x & 7u) * nb8 + (blockIdx.x >> 3);
-  const int64_t g0 = (lblock * 256 + threadIdx.x) >> 4;
+  const int64_t g0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 4;
   const int64_t ng = ((int64_t)gridDim.x * 256) >> 4;
   const int c = m.c;
   const int nv = c >> 2;
@@ -461,7 +455,7 @@ hipError_t launch_seg_gather(const MeshDev& m, const ProbIn& in, int f_first, in
     // enough resident groups to cover the machine; each walks the row list
     // grid: gather_waves resident waves (4 row groups each) on each of the 256 CUs
     const int64_t groups = std::min<int64_t>(m.n_texels, (int64_t)256 * m.gather_waves * 4);
-    dim3 g((unsigned)((((groups * 16 + 255) / 256) + 7) & ~int64_t(7)));
+    dim3 g((unsigned)((groups * 16 + 255) / 256));
 #define LF_R(DT, AGG, AT)                                                                                    \
   do {                                                                                                       \
     if (m.gather_unroll == 4)                                                                                \
