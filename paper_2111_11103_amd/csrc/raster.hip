@@ -29,10 +29,13 @@ namespace lf {
 namespace {
 
 
-// Snapped screen polygon of one triangle in one frame.
+// Snapped screen triangle of one triangle in one frame.  Only scalars, so
+// that it lives in registers: a triangle that crosses a clip plane and
+// becomes a polygon of more than three vertices is marked by n and its
+// polygon recomputed (same arithmetic, same bits) where it is drawn.
 struct Setup {
-  int n;                       // polygon vertex count (0 = nothing to draw)
-  int PX[8], PY[8];            // snapped vertices, 1/256 px
+  int n;                       // 0 = nothing to draw, 3 = triangle, 4..8 = clipped polygon
+  int ax, ay, bx, by, cx, cy;  // the triangle (n == 3), 1/256 px
   RayK rk;                     // ray-cast constants of the original triangle
   int x0, x1, y0, y1;          // pixel-centre box, clamped to the image
 };
@@ -47,10 +50,23 @@ __device__ __forceinline__ void load_tri(const MeshDev& m, const Cam& cam, int64
   C = to_cam(cam, q2[0], q2[1], q2[2]);
 }
 
+// Snapped polygon of the camera-space triangle (A, B, C) clipped by the five
+// planes; returns its vertex count (0..8).  Out of line: only triangles
+// that cross a plane take this path.
+__device__ __noinline__ int clipped_polygon(const Cam& cam, float z_near, V3 A, V3 B, V3 C, int (&PX)[8],
+                                               int (&PY)[8]) {
+  V3 P[8];
+  P[0] = A; P[1] = B; P[2] = C;
+  const int n = clip_poly(P, 3, cam, z_near);
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+    if (i < n) snap(cam, P[i], &PX[i], &PY[i]);
+  return n;
+}
+
 __device__ __forceinline__ void setup_triangle(const MeshDev& m, const Cam& cam, int64_t t, int H, int W, Setup& s) {
   s.n = 0;
-#pragma unroll
-  for (int i = 0; i < 8; ++i) { s.PX[i] = 0; s.PY[i] = 0; }
+  s.ax = s.ay = s.bx = s.by = s.cx = s.cy = 0;
   s.x0 = 0; s.x1 = -1; s.y0 = 0; s.y1 = -1;
   V3 A, B, C;
   load_tri(m, cam, t, A, B, C);
@@ -61,27 +77,29 @@ __device__ __forceinline__ void setup_triangle(const MeshDev& m, const Cam& cam,
                     clip_dist(p, C, cam, m.z_near) < 0.0f);
   if (gone) return;
   s.rk = ray_consts(A, B, C);
+  int xmin, xmax, ymin, ymax;
   if (inside_all(A, cam, m.z_near) && inside_all(B, cam, m.z_near) && inside_all(C, cam, m.z_near)) {
-    snap(cam, A, &s.PX[0], &s.PY[0]);
-    snap(cam, B, &s.PX[1], &s.PY[1]);
-    snap(cam, C, &s.PX[2], &s.PY[2]);
+    snap(cam, A, &s.ax, &s.ay);
+    snap(cam, B, &s.bx, &s.by);
+    snap(cam, C, &s.cx, &s.cy);
     s.n = 3;
+    xmin = min(min(s.ax, s.bx), s.cx); xmax = max(max(s.ax, s.bx), s.cx);
+    ymin = min(min(s.ay, s.by), s.cy); ymax = max(max(s.ay, s.by), s.cy);
   } else {
-    V3 P[8];
-    P[0] = A; P[1] = B; P[2] = C;
-    s.n = clip_poly(P, 3, cam, m.z_near);
-#pragma unroll
-    for (int i = 0; i < 8; ++i)
-      if (i < s.n) snap(cam, P[i], &s.PX[i], &s.PY[i]);
-  }
-  if (s.n < 3) { s.n = 0; return; }
-  int xmin = s.PX[0], xmax = s.PX[0], ymin = s.PY[0], ymax = s.PY[0];
-#pragma unroll
-  for (int i = 1; i < 8; ++i)
-    if (i < s.n) {
-      xmin = min(xmin, s.PX[i]); xmax = max(xmax, s.PX[i]);
-      ymin = min(ymin, s.PY[i]); ymax = max(ymax, s.PY[i]);
+    int PX[8], PY[8];
+    const int n = clipped_polygon(cam, m.z_near, A, B, C, PX, PY);
+    if (n < 3) return;
+    s.n = n;
+    if (n == 3) {
+      s.ax = PX[0]; s.ay = PY[0]; s.bx = PX[1]; s.by = PY[1]; s.cx = PX[2]; s.cy = PY[2];
     }
+    xmin = xmax = PX[0];
+    ymin = ymax = PY[0];
+    for (int i = 1; i < n; ++i) {
+      xmin = min(xmin, PX[i]); xmax = max(xmax, PX[i]);
+      ymin = min(ymin, PY[i]); ymax = max(ymax, PY[i]);
+    }
+  }
   // pixel x is a candidate iff its centre 256x + 128 lies in [xmin, xmax]
   s.x0 = max((xmin + 127) >> 8, 0);
   s.x1 = min((xmax - 128) >> 8, W - 1);
@@ -116,14 +134,6 @@ __device__ __forceinline__ long long efn(int xi, int yi, int xj, int yj, int px,
 __device__ __forceinline__ bool covers(const Edge3& e, int px, int py) {
   return efn(e.x0, e.y0, e.x1, e.y1, px, py) >= e.b01 && efn(e.x1, e.y1, e.x2, e.y2, px, py) >= e.b12 &&
          efn(e.x2, e.y2, e.x0, e.y0, px, py) >= e.b20;
-}
-
-// v[i] for a runtime i without dynamic register indexing.
-__device__ __forceinline__ int pick8(const int (&v)[8], int i) {
-  int r = v[0];
-#pragma unroll
-  for (int k = 1; k < 8; ++k) r = (i == k) ? v[k] : r;
-  return r;
 }
 
 // Conservative cluster-vs-frustum test: outside if all 8 box corners lie
@@ -278,15 +288,29 @@ __device__ __forceinline__ void raster_thread(const TileCtx& c, const RayK& rk, 
 
 
 // Rasterize the triangle this lane holds (`s`, restricted to the pixel box
-// x0..x1 x y0..y1 of the tile); large boxes are done by the whole wave.
-__device__ __forceinline__ void raster_entries(const TileCtx& c, const Setup& s, uint32_t tri, bool have, int x0,
-                                               int x1, int y0, int y1) {
+// x0..x1 x y0..y1 of the tile); large boxes are done by the whole wave, one
+// triangle at a time, 8x8 pixels per step.  A clipped polygon is drawn as the
+// fan (v0, vi, vi+1).
+__device__ __forceinline__ void raster_entries(const TileCtx& c, const MeshDev& m, const Cam& cam, const Setup& s,
+                                               uint32_t tri, bool have, int x0, int x1, int y0, int y1) {
   const int lane = threadIdx.x & 63;
   const bool any = have && s.n >= 3 && x0 <= x1 && y0 <= y1;
   const bool small = any && (x1 - x0 + 1) * (y1 - y0 + 1) <= c.small_px;
   if (small) {
+    int PX[8], PY[8];
+    if (s.n > 3) {
+      V3 A, B, C;
+      load_tri(m, cam, tri, A, B, C);
+      clipped_polygon(cam, m.z_near, A, B, C, PX, PY);
+    }
     for (int i = 1; i + 1 < s.n; ++i) {
-      const Edge3 e = orient(s.PX[0], s.PY[0], pick8(s.PX, i), pick8(s.PY, i), pick8(s.PX, i + 1), pick8(s.PY, i + 1));
+      int ax, ay, bx, by, cx, cy;
+      if (s.n == 3) {
+        ax = s.ax; ay = s.ay; bx = s.bx; by = s.by; cx = s.cx; cy = s.cy;
+      } else {
+        ax = PX[0]; ay = PY[0]; bx = PX[i]; by = PY[i]; cx = PX[i + 1]; cy = PY[i + 1];
+      }
+      const Edge3 e = orient(ax, ay, bx, by, cx, cy);
       if (e.ok) raster_thread(c, s.rk, tri, e, x0, x1, y0, y1);
     }
   }
@@ -295,29 +319,36 @@ __device__ __forceinline__ void raster_entries(const TileCtx& c, const Setup& s,
     const int src = __ffsll(big) - 1;
     big &= big - 1;
     const int bn = __shfl(s.n, src);
-    int bx[8], by[8];
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      bx[i] = __shfl(s.PX[i], src);
-      by[i] = __shfl(s.PY[i], src);
-    }
     RayK bk;
     bk.n = V3{__shfl(s.rk.n.x, src), __shfl(s.rk.n.y, src), __shfl(s.rk.n.z, src)};
     bk.d = __shfl(s.rk.d, src);
     const int bx0 = __shfl(x0, src), bx1 = __shfl(x1, src), by0 = __shfl(y0, src), by1 = __shfl(y1, src);
     const uint32_t btri = (uint32_t)__shfl((int)tri, src);
+    const int sax = __shfl(s.ax, src), say = __shfl(s.ay, src), sbx = __shfl(s.bx, src), sby = __shfl(s.by, src),
+              scx = __shfl(s.cx, src), scy = __shfl(s.cy, src);
+    int PX[8], PY[8];
+    if (bn > 3) {
+      // every lane clips the same (broadcast) triangle
+      V3 A, B, C;
+      load_tri(m, cam, btri, A, B, C);
+      clipped_polygon(cam, m.z_near, A, B, C, PX, PY);
+    }
     const int ox = lane & 7, oy = lane >> 3;
-    for (int yb = by0; yb <= by1; yb += 8) {
-      for (int xb = bx0; xb <= bx1; xb += 8) {
-        const int x = xb + ox, y = yb + oy;
-        if (x > bx1 || y > by1) continue;
-        const int pcx = 256 * x + 128, pcy = 256 * y + 128;
-        bool cov = false;
-        for (int i = 1; i + 1 < bn; ++i) {
-          const Edge3 e = orient(bx[0], by[0], pick8(bx, i), pick8(by, i), pick8(bx, i + 1), pick8(by, i + 1));
-          cov = cov || (e.ok && covers(e, pcx, pcy));
+    for (int i = 1; i + 1 < bn; ++i) {
+      int ax, ay, bx, by, cx, cy;
+      if (bn == 3) {
+        ax = sax; ay = say; bx = sbx; by = sby; cx = scx; cy = scy;
+      } else {
+        ax = PX[0]; ay = PY[0]; bx = PX[i]; by = PY[i]; cx = PX[i + 1]; cy = PY[i + 1];
+      }
+      const Edge3 e = orient(ax, ay, bx, by, cx, cy);
+      if (!e.ok) continue;
+      for (int yb = by0; yb <= by1; yb += 8) {
+        for (int xb = bx0; xb <= bx1; xb += 8) {
+          const int x = xb + ox, y = yb + oy;
+          if (x > bx1 || y > by1) continue;
+          if (covers(e, 256 * x + 128, 256 * y + 128)) emit_lds(c, bk, x, y, btri);
         }
-        if (cov) emit_lds(c, bk, x, y, btri);
       }
     }
   }
@@ -364,7 +395,7 @@ __global__ __launch_bounds__(256) void k_tile_raster(MeshDev m, const float* __r
         tri = (uint32_t)lst[e];
         setup_triangle(m, cam, tri, H, W, s);
       }
-      raster_entries(c, s, tri, have, max(s.x0, tx0), min(s.x1, tx1), max(s.y0, ty0), min(s.y1, ty1));
+      raster_entries(c, m, cam, s, tri, have, max(s.x0, tx0), min(s.x1, tx1), max(s.y0, ty0), min(s.y1, ty1));
     }
   } else {
     // the tile's list overflowed its capacity: walk every triangle of every
@@ -379,7 +410,7 @@ __global__ __launch_bounds__(256) void k_tile_raster(MeshDev m, const float* __r
       s.x0 = 0; s.x1 = -1; s.y0 = 0; s.y1 = -1;
       const bool have = t < m.T;
       if (have) setup_triangle(m, cam, t, H, W, s);
-      raster_entries(c, s, (uint32_t)t, have, max(s.x0, tx0), min(s.x1, tx1), max(s.y0, ty0), min(s.y1, ty1));
+      raster_entries(c, m, cam, s, (uint32_t)t, have, max(s.x0, tx0), min(s.x1, tx1), max(s.y0, ty0), min(s.y1, ty1));
     }
   }
   __syncthreads();
