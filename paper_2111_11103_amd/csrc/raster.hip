@@ -471,23 +471,41 @@ __global__ __launch_bounds__(256) void k_tile_raster(MeshDev m, const float* __r
       }
     }
   }
-  if (out.cnt) {
-#pragma unroll
-    for (int r = 0; r < PPT; ++r)
-      if (use[r]) atomicAdd(out.cnt + (int64_t)fb * out.cnt_stride + l[r], 1);
-  }
   if (out.tricnt) {
 #pragma unroll
     for (int r = 0; r < PPT; ++r)
       if (tri[r] >= 0) atomicAdd(out.tricnt + (int64_t)fb * m.T + tri[r], 1);
   }
-  if (out.seg) {
-    int rk[PPT];
+  if (out.seg || out.cnt) {
+    // A wave holds whole tile rows (TS consecutive lanes per row).  Pixels
+    // next to each other in a row that see the same texel row form a run; the
+    // run's first lane adds the run length to the row's counters with one
+    // atomic, and the run's pixels take consecutive ranks from its base.
+    const int lane = threadIdx.x & 63;
+    const unsigned long long below = (2ull << lane) - 1ull;   // lanes 0..lane (lane 63: all)
+    constexpr unsigned long long kRowStart = TS == 16 ? 0x0001000100010001ull : 0x0000000100000001ull;
+    int rk[PPT], head[PPT];
 #pragma unroll
-    for (int r = 0; r < PPT; ++r) rk[r] = use[r] ? atomicAdd(out.seg + l[r], 1) : 0;
+    for (int r = 0; r < PPT; ++r) {
+      const int key = use[r] ? l[r] : -1;
+      const int prev = __shfl_up(key, 1);
+      const unsigned long long heads = __ballot(key != prev) | kRowStart;
+      const unsigned long long after = heads & ~below;
+      const int next = after ? __ffsll(after) - 1 : 64;
+      head[r] = 63 - __clzll(heads & below);
+      const bool lead = use[r] && head[r] == lane;
+      int base = 0;
+      if (lead && out.cnt) atomicAdd(out.cnt + (int64_t)fb * out.cnt_stride + l[r], next - lane);
+      if (lead && out.seg) base = atomicAdd(out.seg + l[r], next - lane);
+      rk[r] = base;
+    }
+    if (out.seg) {
 #pragma unroll
-    for (int r = 0; r < PPT; ++r)
-      if (use[r]) out.rank[pix[r]] = rk[r];
+      for (int r = 0; r < PPT; ++r) {
+        const int base = __shfl(rk[r], head[r]);
+        if (use[r]) out.rank[pix[r]] = base + (lane - head[r]);
+      }
+    }
   }
 #pragma unroll
   for (int r = 0; r < PPT; ++r) {
