@@ -52,9 +52,11 @@ __device__ __forceinline__ void load_tri(const MeshDev& m, const Cam& cam, int64
 
 // Snapped polygon of the camera-space triangle (A, B, C) clipped by the five
 // planes; returns its vertex count (0..8).  Out of line: only triangles
-// that cross a plane take this path.
-__device__ __noinline__ int clipped_polygon(const Cam& cam, float z_near, V3 A, V3 B, V3 C, int (&PX)[8],
-                                               int (&PY)[8]) {
+// that cross a plane take this path.  It reads the camera record itself, so
+// that callers need not keep their copy in (per-lane scratch) memory.
+__device__ __noinline__ int clipped_polygon(const float* __restrict__ cam_rec, float z_near, V3 A, V3 B, V3 C,
+                                            int (&PX)[8], int (&PY)[8]) {
+  const Cam cam = load_cam(cam_rec);
   V3 P[8];
   P[0] = A; P[1] = B; P[2] = C;
   const int n = clip_poly(P, 3, cam, z_near);
@@ -64,7 +66,8 @@ __device__ __noinline__ int clipped_polygon(const Cam& cam, float z_near, V3 A, 
   return n;
 }
 
-__device__ __forceinline__ void setup_triangle(const MeshDev& m, const Cam& cam, int64_t t, int H, int W, Setup& s) {
+__device__ __forceinline__ void setup_triangle(const MeshDev& m, const Cam& cam, const float* cam_rec, int64_t t, int H,
+                                               int W, Setup& s) {
   s.n = 0;
   s.ax = s.ay = s.bx = s.by = s.cx = s.cy = 0;
   s.x0 = 0; s.x1 = -1; s.y0 = 0; s.y1 = -1;
@@ -87,7 +90,7 @@ __device__ __forceinline__ void setup_triangle(const MeshDev& m, const Cam& cam,
     ymin = min(min(s.ay, s.by), s.cy); ymax = max(max(s.ay, s.by), s.cy);
   } else {
     int PX[8], PY[8];
-    const int n = clipped_polygon(cam, m.z_near, A, B, C, PX, PY);
+    const int n = clipped_polygon(cam_rec, m.z_near, A, B, C, PX, PY);
     if (n < 3) return;
     s.n = n;
     if (n == 3) {
@@ -208,7 +211,7 @@ __global__ __launch_bounds__(256) void k_bin(MeshDev m, const float* __restrict_
     Setup s;
     s.n = 0;
     s.x0 = 0; s.x1 = -1; s.y0 = 0; s.y1 = -1;
-    if (t < m.T) setup_triangle(m, cam, t, H, W, s);
+    if (t < m.T) setup_triangle(m, cam, cams + 16 * (int64_t)fb, t, H, W, s);
     // walk this lane's tile range; lanes currently on the same tile share one atomic
     const int tx0 = s.x0 / TS, tx1 = s.x1 / TS, ty0 = s.y0 / TS, ty1 = s.y1 / TS;
     int tx = tx0, ty = ty0;
@@ -245,6 +248,7 @@ struct TileCtx {
   int tx0, ty0;              // tile origin (pixels)
   int ts;                    // tile edge
   int small_px;              // boxes up to this area: one lane per triangle
+  const float* cam_rec;      // the frame's camera record (global memory)
 };
 
 __device__ __forceinline__ void emit_lds(const TileCtx& c, const RayK& rk, int x, int y, uint32_t tri) {
@@ -301,7 +305,7 @@ __device__ __forceinline__ void raster_entries(const TileCtx& c, const MeshDev& 
     if (s.n > 3) {
       V3 A, B, C;
       load_tri(m, cam, tri, A, B, C);
-      clipped_polygon(cam, m.z_near, A, B, C, PX, PY);
+      clipped_polygon(c.cam_rec, m.z_near, A, B, C, PX, PY);
     }
     for (int i = 1; i + 1 < s.n; ++i) {
       int ax, ay, bx, by, cx, cy;
@@ -331,7 +335,7 @@ __device__ __forceinline__ void raster_entries(const TileCtx& c, const MeshDev& 
       // every lane clips the same (broadcast) triangle
       V3 A, B, C;
       load_tri(m, cam, btri, A, B, C);
-      clipped_polygon(cam, m.z_near, A, B, C, PX, PY);
+      clipped_polygon(c.cam_rec, m.z_near, A, B, C, PX, PY);
     }
     const int ox = lane & 7, oy = lane >> 3;
     for (int i = 1; i + 1 < bn; ++i) {
@@ -378,7 +382,7 @@ __global__ __launch_bounds__(256) void k_tile_raster(MeshDev m, const float* __r
   else if (threadIdx.x < 2 * TS) rys[threadIdx.x - TS] = ray_y(cam, ty0 + threadIdx.x - TS);
   __syncthreads();
   if (threadIdx.x == 0) *tc = 0;
-  const TileCtx c{key, rxs, rys, tx0, ty0, TS, m.small_px};
+  const TileCtx c{key, rxs, rys, tx0, ty0, TS, m.small_px, cams + 16 * (int64_t)fb};
   const int64_t HW = (int64_t)H * W;
 
   if (n_ent <= cap) {
@@ -393,7 +397,7 @@ __global__ __launch_bounds__(256) void k_tile_raster(MeshDev m, const float* __r
       uint32_t tri = 0;
       if (have) {
         tri = (uint32_t)lst[e];
-        setup_triangle(m, cam, tri, H, W, s);
+        setup_triangle(m, cam, c.cam_rec, tri, H, W, s);
       }
       raster_entries(c, m, cam, s, tri, have, max(s.x0, tx0), min(s.x1, tx1), max(s.y0, ty0), min(s.y1, ty1));
     }
@@ -409,7 +413,7 @@ __global__ __launch_bounds__(256) void k_tile_raster(MeshDev m, const float* __r
       s.n = 0;
       s.x0 = 0; s.x1 = -1; s.y0 = 0; s.y1 = -1;
       const bool have = t < m.T;
-      if (have) setup_triangle(m, cam, t, H, W, s);
+      if (have) setup_triangle(m, cam, c.cam_rec, t, H, W, s);
       raster_entries(c, m, cam, s, (uint32_t)t, have, max(s.x0, tx0), min(s.x1, tx1), max(s.y0, ty0), min(s.y1, ty1));
     }
   }
