@@ -240,7 +240,7 @@ def main():
     ap.add_argument("--tile", type=int, default=32, help="raster tile edge (with an explicit --batch)")
     ap.add_argument("--unroll", type=int, default=8, help="sorted-gather unroll (with an explicit --batch)")
     ap.add_argument("--small", type=int, default=48, help="single-lane triangle box area (with an explicit --batch)")
-    ap.add_argument("--gwaves", type=int, default=32, help="gather grid waves per CU (with an explicit --batch)")
+    ap.add_argument("--gwaves", type=int, default=8, help="gather grid waves per CU (with an explicit --batch)")
     ap.add_argument("--weighting", type=int, default=0, help="0 w^(P), 1 w^(I)")
     ap.add_argument("--layout", default="nhwc", choices=["nchw", "nhwc"])
     ap.add_argument("--cpu-frames", type=int, default=200)

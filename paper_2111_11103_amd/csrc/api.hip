@@ -301,7 +301,7 @@ lf_status lf_load_mesh(const lf_mesh_opts* opts, const float* d_vertices, int64_
   d.tile = kTileSize;
   d.gather_unroll = 8;
   d.small_px = 48;
-  d.gather_waves = 32;
+  d.gather_waves = 8;
   d.mix = 0.5f;
 
   LF_TRY(launch_zero(d.err, 4, stream), "clear flag");

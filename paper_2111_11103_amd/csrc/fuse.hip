@@ -328,6 +328,20 @@ __global__ __launch_bounds__(256) void k_finalize(MeshDev m, void* __restrict__ 
   }
   if (!out) return;
   __syncthreads();
+  if (OUT == 0 && (c & 3) == 0 && (reinterpret_cast<uintptr_t>(out) & 15) == 0) {
+    float4* dst = reinterpret_cast<float4*>(reinterpret_cast<float*>(out) + x0 * c);
+    const int c4 = c >> 2;
+    int r = threadIdx.x / c4, j = 4 * (threadIdx.x - r * c4);
+    const int dr = 256 / c4, dj = 4 * (256 - dr * c4);
+    for (int i = threadIdx.x; i < nr * c4; i += 256) {
+      const float* q = rows + r * cp + j;
+      dst[i] = make_float4(q[0], q[1], q[2], q[3]);
+      r += dr;
+      j += dj;
+      if (j >= c) { j -= c; ++r; }
+    }
+    return;
+  }
   int r = threadIdx.x / c, j = threadIdx.x - (threadIdx.x / c) * c;
   const int dr = 256 / c, dj = 256 - dr * c;
   for (int i = threadIdx.x; i < nr * c; i += 256) {
@@ -361,45 +375,34 @@ hipError_t launch_finalize(const MeshDev& m, void* tex_out, int tex_dtype, uint8
   return hipGetLastError();
 }
 
-// ---- render-back: 8 pixels per thread (two 16-byte loads of rows) ----------
+// ---- render-back: a texel label per pixel (255 where unseen or invalid) ------
 __global__ __launch_bounds__(256) void k_render(const int32_t* __restrict__ l, const uint8_t* __restrict__ valid,
                                                 const uint8_t* __restrict__ labels, int64_t npx,
                                                 uint8_t* __restrict__ out) {
-  const int64_t i = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 8;
-  if (i >= npx) return;
-  if (i + 8 <= npx && (reinterpret_cast<uintptr_t>(l + i) & 15) == 0 && (reinterpret_cast<uintptr_t>(out + i) & 7) == 0) {
-    const int4 a = *reinterpret_cast<const int4*>(l + i);
-    const int4 b = *reinterpret_cast<const int4*>(l + i + 4);
-    const int li[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
-    uint64_t vv = ~0ull;
-    if (valid) {
-      vv = 0;
-      if ((reinterpret_cast<uintptr_t>(valid + i) & 7) == 0) {
-        const uint64_t raw = *reinterpret_cast<const uint64_t*>(valid + i);
+  // 8 pixels per thread at a stride of 256: every load, label gather and
+  // store instruction of a wave covers 64 neighbouring pixels, which see
+  // neighbouring texels, so a gather touches few cache lines.
+  constexpr int P = 8;
+  const int64_t base = (int64_t)blockIdx.x * (256 * P) + threadIdx.x;
+  int32_t li[P];
+  bool ok[P];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) vv |= (uint64_t)(((raw >> (8 * k)) & 0xffu) ? 0xffu : 0u) << (8 * k);
-      } else {
-#pragma unroll
-        for (int k = 0; k < 8; ++k) vv |= (uint64_t)(valid[i + k] ? 0xffu : 0u) << (8 * k);
-      }
-    }
-    uint64_t o = 0;
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const bool ok = li[k] >= 0 && ((vv >> (8 * k)) & 0xffu);
-      const uint64_t lab = ok ? labels[li[k]] : 255u;
-      o |= lab << (8 * k);
-    }
-    *reinterpret_cast<uint64_t*>(out + i) = o;
-    return;
+  for (int k = 0; k < P; ++k) {
+    const int64_t p = base + (int64_t)k * 256;
+    ok[k] = p < npx;
+    li[k] = ok[k] ? l[p] : -1;
   }
-  for (int k = 0; k < 8; ++k) {
-    const int64_t p = i + k;
-    if (p < npx) {
-      const int32_t li = l[p];
-      out[p] = (li >= 0 && (!valid || valid[p])) ? labels[li] : (uint8_t)255;
-    }
+  if (valid) {
+#pragma unroll
+    for (int k = 0; k < P; ++k)
+      if (ok[k] && !valid[base + (int64_t)k * 256]) li[k] = -1;
   }
+  uint8_t lab[P];
+#pragma unroll
+  for (int k = 0; k < P; ++k) lab[k] = li[k] >= 0 ? labels[li[k]] : (uint8_t)255;
+#pragma unroll
+  for (int k = 0; k < P; ++k)
+    if (ok[k]) out[base + (int64_t)k * 256] = lab[k];
 }
 
 hipError_t launch_render(const int32_t* l, const uint8_t* valid, const uint8_t* labels, int64_t npx, uint8_t* out,

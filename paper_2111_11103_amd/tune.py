@@ -137,7 +137,7 @@ def autotune(mesh: sf.Mesh, cams: torch.Tensor, probs: torch.Tensor, *, scale=No
     modes = scatter_modes(probs)
     batches = [b for b in BATCHES if b <= max(nf, BATCHES[0])]
     best = {"batch": min(32, batches[-1]), "scatter_mode": modes[0], "tile": 32, "small_px": 48,
-            "gather_unroll": 8, "gather_waves": 32}
+            "gather_unroll": 8, "gather_waves": 8}
     best_ms = trial(best)
     sweeps = [("batch", batches), ("scatter_mode", modes), ("tile", TILES), ("small_px", SMALL),
               ("gather_unroll", UNROLLS), ("gather_waves", GATHER_WAVES)]
