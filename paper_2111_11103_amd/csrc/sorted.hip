@@ -113,7 +113,11 @@ __global__ __launch_bounds__(256) void k_seg_scan(const int32_t* __restrict__ cn
 
 // ---- fill ------------------------------------------------------------------------
 // 4 pixels per thread; every phase is issued for all 4 before the next so
-// the dependent loads (row, then its segment start) overlap.
+// the dependent loads (row, then its segment start) overlap.  Workgroups are
+// dealt to the 8 XCDs in turn and the grid's width is a multiple of 8, so
+// block x runs on XCD x % 8; it takes pixel chunk (x % 8) * (width / 8) +
+// x / 8, which gives every XCD one band of image rows in every frame: the
+// texel rows seen in a band, and the entry lines they own, stay under one L2.
 __global__ __launch_bounds__(256) void k_seg_fill(ProbIn in, int f_first, int H, int W, const int32_t* __restrict__ lbuf,
                                                   const int32_t* __restrict__ rank, const int32_t* __restrict__ start,
                                                   uint32_t* __restrict__ ent_pix, float* __restrict__ ent_w,
@@ -126,9 +130,10 @@ __global__ __launch_bounds__(256) void k_seg_fill(ProbIn in, int f_first, int H,
   int l[P], st[P];
   int64_t p[P];
   bool ok[P];
+  const int64_t chunk = (int64_t)(blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
 #pragma unroll
   for (int k = 0; k < P; ++k) {
-    p[k] = ((int64_t)blockIdx.x * P + k) * 256 + threadIdx.x;
+    p[k] = (chunk * P + k) * 256 + threadIdx.x;
     ok[k] = p[k] < HW;
     l[k] = ok[k] ? lbuf[(int64_t)fb * HW + p[k]] : -1;
     if (l[k] >= 0 && in.valid && !in.valid[(int64_t)(f_first + fb) * HW + p[k]]) l[k] = -1;
@@ -524,9 +529,9 @@ hipError_t launch_seg_fill(const ProbIn& in, int f_first, int nf, int H, int W, 
                            const int32_t* cnt, int64_t cnt_stride, const float* wpix, float mix, hipStream_t s) {
   if (nf <= 0) return hipSuccess;
   const int64_t HW = (int64_t)H * W;
-  k_seg_fill<<<dim3((unsigned)((HW + 1023) / 1024), (unsigned)nf), 256, 0, s>>>(in, f_first, H, W, l, rank, start, ent_pix,
-                                                                              ent_w, ent_s, weighting, cnt, cnt_stride,
-                                                                              wpix, mix);
+  const unsigned gx = (unsigned)(((HW + 1023) / 1024 + 7) / 8 * 8);   // chunks, rounded up to a multiple of 8
+  k_seg_fill<<<dim3(gx, (unsigned)nf), 256, 0, s>>>(in, f_first, H, W, l, rank, start, ent_pix, ent_w, ent_s, weighting,
+                                                    cnt, cnt_stride, wpix, mix);
   return hipGetLastError();
 }
 
