@@ -49,18 +49,25 @@ def kernel_source_digest():
     return h.hexdigest()[:16]
 
 
+GATHER_KNOBS = ("batch", "scatter_mode", "gather_unroll", "gather_waves")   # what the gather's launch depends on
+
+
 def measured_traffic(launch):
     """HBM bytes per fused pixel of the gather from the committed counter
-    summary, or None when the kernel's sources or the launch configuration
-    differ from those measured."""
+    summary (one record per measured launch configuration), or None when the
+    kernel's sources differ from those measured or no record has this
+    launch's gather configuration."""
     try:
         with open(TRAFFIC_FILE) as fh:
             t = json.loads(fh.readline())       # first line: the figures; the rest: how they were taken
     except (OSError, ValueError):
         return None
-    if t.get("source_digest") != kernel_source_digest() or any(t.get(k) != v for k, v in launch.items()):
+    if t.get("source_digest") != kernel_source_digest():
         return None
-    return t.get("bytes_per_px")
+    for rec in t.get("records", []):
+        if all(rec.get(k) == launch.get(k) for k in GATHER_KNOBS):
+            return rec.get("bytes_per_px")
+    return None
 
 
 def cpu_baseline(work, n_frames: int):
