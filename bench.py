@@ -250,6 +250,8 @@ def main():
     ap.add_argument("--gwaves", type=int, default=8, help="gather grid waves per CU (with an explicit --batch)")
     ap.add_argument("--weighting", type=int, default=0, help="0 w^(P), 1 w^(I)")
     ap.add_argument("--layout", default="nhwc", choices=["nchw", "nhwc"])
+    ap.add_argument("--input", default="f32", choices=["f32", "fp8"],
+                    help="headline input: FP32 probabilities, or OCP E4M3 codes with a per-pixel FP32 scale")
     ap.add_argument("--cpu-frames", type=int, default=200)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the NCHW / FP8 / w^(I) / learned throughput legs")
@@ -297,10 +299,23 @@ def main():
     lab = torch.empty(mesh.n_texels, dtype=torch.uint8, device=dev)
     valid = work.valid
     L = sf.lib()
+    head_probs, head_scale = probs, None
+    if args.input == "fp8":
+        # quantised in chunks, in the layout of the FP32 input
+        head_probs = torch.empty((F, c, H, W), dtype=torch.uint8, device=dev)
+        if args.layout == "nhwc":
+            head_probs = head_probs.to(memory_format=torch.channels_last)
+        head_scale = torch.empty((F, H, W), dtype=torch.float32, device=dev)
+        for f0 in range(0, F, 50):
+            qq, ss = S.quantize_fp8(probs[f0:f0 + 50])
+            head_probs[f0:f0 + 50] = qq
+            head_scale[f0:f0 + 50] = ss
+        del qq, ss
     tuning = None
     if args.batch <= 0:
         from paper_2111_11103_amd import tune
-        tuning = tune.autotune(mesh, cams, probs, valid=valid, weighting=args.weighting, probe_frames=64, log=log)
+        tuning = tune.autotune(mesh, cams, head_probs, scale=head_scale, valid=valid, weighting=args.weighting,
+                               probe_frames=64, log=log)
         args.batch, args.scatter = int(tuning["batch"]), int(tuning["scatter_mode"])
     else:
         mesh.set_tuning(args.tile, args.unroll, args.small, args.gwaves)
@@ -334,7 +349,7 @@ def main():
         log(f"[bench] {tag}: {steps} steps, {1000 * t_total / steps:.3f} ms/step")
         return t_total, prof
 
-    step, ws = make_step(probs, args.weighting)
+    step, ws = make_step(head_probs, args.weighting, scale=head_scale)
     t_total, prof = timed(step, args.steps, args.warmup, "headline")
     ms_step = 1000.0 * t_total / args.steps
     npx = F * H * W
@@ -345,8 +360,8 @@ def main():
     # roofline of the dominant kernel (the gather, stage 2): algorithmic bytes
     # = every pixel's c class values + its valid byte, per launch (one launch
     # per batch of frames); duration = mean of the HIP-event-timed launches
-    in_bytes = {torch.float32: 4, torch.uint8: 1}[probs.dtype]
-    per_px = c * in_bytes + 1
+    in_bytes = {torch.float32: 4, torch.uint8: 1}[head_probs.dtype]
+    per_px = c * in_bytes + 1 + (4 if head_scale is not None else 0)     # classes, validity byte, FP8 scale
     launches = prof.launches[2]
     scat_ms = prof.ms[2] / launches
     px_per_launch = npx * args.steps / launches
@@ -378,7 +393,9 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"room mesh {sc.n_faces} triangles, SPLIT s=3 ({mesh.n_texels} texels), "
-                               f"{F} frames {W}x{H}, c={c}, FP32 {args.layout.upper()} probabilities, "
+                               f"{F} frames {W}x{H}, c={c}, "
+                               + ("FP32 " if args.input == "f32" else "FP8 E4M3 (per-pixel FP32 scale) ")
+                               + f"{args.layout.upper()} probabilities, "
                                f"weighting {'w^(I)' if args.weighting else 'w^(P)'}",
                    "frames": F, "H": H, "W": W, "classes": c, "triangles": sc.n_faces, "texels": mesh.n_texels,
                    "batch": args.batch, "scatter_mode": args.scatter, "frame_ws_bytes": ws.numel(),

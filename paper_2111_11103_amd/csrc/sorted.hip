@@ -387,23 +387,34 @@ __global__ __launch_bounds__(256) void k_seg_gather16(MeshDev m, ProbIn in, PixD
       for (int h = 0; h < cnt; h += U) {
         float4 v[U];
         float w[U];
+        uint32_t q[U];                             // E4M3: raw codes, decoded once every load is issued
+        float sc[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const int src = h + u;
           const uint32_t e = __shfl(my_e, src, 16);
           w[u] = __shfl(my_w, src, 16);            // 0 past the segment end
-          const float sc = __shfl(my_s, src, 16);
+          sc[u] = DT == 3 ? __shfl(my_s, src, 16) : 1.0f;
           const int64_t off = dec(in, e);
           v[u] = make_float4(1.f, 1.f, 1.f, 1.f);
+          q[u] = 0u;
           if (act && src < cnt) {
-            if constexpr (DT == 0) {
+            if constexpr (DT == 0)
               v[u] = *reinterpret_cast<const float4*>(reinterpret_cast<const float*>(in.p) + off + 4 * gl);
-            } else {
-              const uint32_t q =
-                  *reinterpret_cast<const uint32_t*>(reinterpret_cast<const uint8_t*>(in.p) + off + 4 * gl);
-              v[u] = make_float4(fp8_e4m3_byte<0>(q) * sc, fp8_e4m3_byte<1>(q) * sc, fp8_e4m3_byte<2>(q) * sc,
-                                 fp8_e4m3_byte<3>(q) * sc);
-            }
+            else
+              q[u] = *reinterpret_cast<const uint32_t*>(reinterpret_cast<const uint8_t*>(in.p) + off + 4 * gl);
+          }
+        }
+        if constexpr (DT == 3) {
+          // per-component selects (a select of whole vectors would be turned
+          // into a load through a selected address, i.e. scratch memory)
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const bool okq = act && h + u < cnt;
+            v[u].x = okq ? fp8_e4m3_byte<0>(q[u]) * sc[u] : 1.0f;
+            v[u].y = okq ? fp8_e4m3_byte<1>(q[u]) * sc[u] : 1.0f;
+            v[u].z = okq ? fp8_e4m3_byte<2>(q[u]) * sc[u] : 1.0f;
+            v[u].w = okq ? fp8_e4m3_byte<3>(q[u]) * sc[u] : 1.0f;
           }
         }
 #pragma unroll
