@@ -248,7 +248,8 @@ def main():
     ap.add_argument("--unroll", type=int, default=8, help="sorted-gather unroll (with an explicit --batch)")
     ap.add_argument("--small", type=int, default=48, help="single-lane triangle box area (with an explicit --batch)")
     ap.add_argument("--gwaves", type=int, default=8, help="gather grid waves per CU (with an explicit --batch)")
-    ap.add_argument("--weighting", type=int, default=0, help="0 w^(P), 1 w^(I)")
+    ap.add_argument("--weighting", type=int, default=0,
+                    help="0 w^(P), 1 w^(I), 2 learned (a seeded, untrained network), 3 mixed w^(P)/w^(I)")
     ap.add_argument("--layout", default="nhwc", choices=["nchw", "nhwc"])
     ap.add_argument("--input", default="f32", choices=["f32", "fp8"],
                     help="headline input: FP32 probabilities, or OCP E4M3 codes with a per-pixel FP32 scale")
@@ -311,6 +312,8 @@ def main():
             head_probs[f0:f0 + 50] = qq
             head_scale[f0:f0 + 50] = ss
         del qq, ss
+    if args.weighting == sf.W_LEARNED:
+        mesh.bind_mlp(sf.WeightMLP("cuda", seed=0))
     tuning = None
     if args.batch <= 0:
         from paper_2111_11103_amd import tune
@@ -396,7 +399,7 @@ def main():
                                f"{F} frames {W}x{H}, c={c}, "
                                + ("FP32 " if args.input == "f32" else "FP8 E4M3 (per-pixel FP32 scale) ")
                                + f"{args.layout.upper()} probabilities, "
-                               f"weighting {'w^(I)' if args.weighting else 'w^(P)'}",
+                               f"weighting {['w^(P)', 'w^(I)', 'learned', 'mixed'][args.weighting]}",
                    "frames": F, "H": H, "W": W, "classes": c, "triangles": sc.n_faces, "texels": mesh.n_texels,
                    "batch": args.batch, "scatter_mode": args.scatter, "frame_ws_bytes": ws.numel(),
                    "tuning": mesh.get_tuning(), "autotuned": tuning is not None},

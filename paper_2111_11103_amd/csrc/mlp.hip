@@ -192,8 +192,12 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const void* __restrict__ pa
 // Probability features of pixel (frame f, y, x): normalised entropy, top-1,
 // top-1 minus top-2.  Also returns the first maximal class.
 // Running entropy / top-2 / first-argmax update with class j's probability.
+// The entropy is accumulated in bits with the hardware base-2 logarithm
+// (normalised by log2 c below, the same value as nats / ln c); terms of
+// probabilities below the smallest normal binary32 (each under 1e-36) are
+// left out.
 __device__ __forceinline__ void prob_step(float p, int j, float& h, float& p1, float& p2, int& best) {
-  if (p > 0.0f) h -= p * logf(p);
+  if (p >= 1.17549435e-38f) h -= p * __log2f(p);
   if (p > p1) { p2 = p1; p1 = p; best = j; }
   else if (p > p2) p2 = p;
 }
@@ -251,7 +255,7 @@ __device__ __forceinline__ void prob_features(const ProbIn& in, int64_t base, fl
     }
   }
   if (c < 2) p2 = 0.0f;
-  ent = c > 1 ? h / logf((float)c) : 0.0f;
+  ent = c > 1 ? h / log2f((float)c) : 0.0f;
 }
 
 // phi of one observation from the renderer's per-pixel geometry (cos of the
