@@ -413,6 +413,25 @@ def main():
         "stage_ms_per_step": stage_ms,
     }
 
+    # the same gather launches without the concurrent raster (gathers on the
+    # caller's stream, one batch after another) on a grid for the whole device
+    saved = mesh.get_tuning()
+    mesh.set_overlap(False)
+    mesh.set_tuning(saved["tile"], saved["gather_unroll"], saved["small_px"], 32)
+    st_iso = make_step(head_probs, args.weighting, scale=head_scale)[0]
+    tt_iso, pr_iso = timed(st_iso, 2, 1, "gather alone")
+    mesh.set_overlap(True)
+    mesh.set_tuning(**saved)
+    iso_ms = pr_iso.ms[2] / pr_iso.launches[2]
+    iso_px = npx * 2 / pr_iso.launches[2]
+    iso_gbs = iso_px * per_px / (iso_ms * 1e-3) / 1e9
+    result["roofline_isolated"] = {"kernel": "k_seg_gather16", "bound": "hbm", "achieved": iso_gbs,
+                                   "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": iso_gbs / HBM_PEAK_GBS,
+                                   "kernel_ms": iso_ms, "gather_waves": 32,
+                                   "step_value_without_overlap": 2 * npx / tt_iso}
+    log(f"[bench] gather alone: {iso_ms:.3f} ms/launch, {iso_gbs:.0f} GB/s algorithmic "
+        f"({iso_gbs / HBM_PEAK_GBS:.1%}); whole step without overlap {2 * npx / tt_iso / 1e9:.2f} G px/s")
+
     if not args.no_forms:
         forms = {}
         legs = [("nchw", lambda: make_step(probs_nchw, 0, scatter=0)[0], None)]

@@ -191,6 +191,14 @@ typedef struct {
 lf_status lf_set_tuning(lf_mesh mesh, const lf_tuning* tuning);
 lf_status lf_get_tuning(lf_mesh mesh, lf_tuning* tuning);
 
+/* Whether the texel-sorted scatter overlaps batches (default 1): each
+ * batch's gather runs on the mesh's second stream while the caller's stream
+ * renders and sorts the next batch.  0 runs the gathers on the caller's
+ * stream, one batch after another, so that a gather has the whole device
+ * (used to time the gather kernel alone).  Results do not depend on it.
+ * Errors: LF_ESTATE for an invalid mesh handle. */
+lf_status lf_set_overlap(lf_mesh mesh, int32_t enabled);
+
 /* ---- Many scenes in one call, and as one captured graph ---------------------
  * One job = one complete fusion of a scene (Sections 3.2 and 3.3): clear its
  * accumulator, fuse its F frames (as lf_fuse_frames), normalise every texel

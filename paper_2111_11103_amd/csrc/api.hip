@@ -52,6 +52,7 @@ struct lf_mesh_s {
   hipStream_t side = nullptr;
   hipEvent_t sorted_ev[2] = {nullptr, nullptr};    // batch's entries are ready (caller's stream)
   hipEvent_t gathered_ev[2] = {nullptr, nullptr};  // batch's gather is done (side stream)
+  bool overlap = true;                              // false: gathers run on the caller's stream
   ~lf_mesh_s() {
     for (int i = 0; i < 2; ++i) {
       if (sorted_ev[i]) (void)hipEventDestroy(sorted_ev[i]);
@@ -448,7 +449,8 @@ lf_status fuse_impl(const FuseArgs& a, void* d_ws, hipStream_t stream) {
   if (cnt) LF_TRY(launch_zero(cnt, (int64_t)B * d.n_texels * 4, stream), "clear counts");
   int32_t* rank = sorted ? reinterpret_cast<int32_t*>(ws + L.rank) : nullptr;
   lf_status status;
-  int nbatch = 0;      // sorted batches issued: batch k's gather runs on mesh->side
+  int nbatch = 0;      // sorted batches issued: batch k's gather runs on `side`
+  hipStream_t side = mesh->overlap ? mesh->side : stream;
   for (int f0 = 0; f0 < a.F;) {
     int nb = (a.F - f0) < B ? (a.F - f0) : B;
     const int fi = a.pool > 0 ? f0 % a.pool : f0;     // input frame of the batch's first frame
@@ -488,15 +490,15 @@ lf_status fuse_impl(const FuseArgs& a, void* d_ws, hipStream_t stream) {
                                  d.mix, stream), "segment fill");
       }
       LF_TRY(hipEventRecord(mesh->sorted_ev[k], stream), "record sorted");
-      LF_TRY(hipStreamWaitEvent(mesh->side, mesh->sorted_ev[k], 0), "wait for sort");
+      LF_TRY(hipStreamWaitEvent(side, mesh->sorted_ev[k], 0), "wait for sort");
       {
-        StageTimer tm(mesh, 2, mesh->side);
+        StageTimer tm(mesh, 2, side);
         // staged observations: contiguous class vectors at element offset slot * c
         const ProbIn gin = staged ? ProbIn{stg, nullptr, nullptr, 0, 1, 0, 0, LF_F32} : in;
-        LF_TRY(launch_seg_gather(d, gin, staged ? 0 : fi, H, W, start, rows, nrows, eo, ew, es, mesh->side),
+        LF_TRY(launch_seg_gather(d, gin, staged ? 0 : fi, H, W, start, rows, nrows, eo, ew, es, side),
                "segment gather");
       }
-      LF_TRY(hipEventRecord(mesh->gathered_ev[k], mesh->side), "record gathered");
+      LF_TRY(hipEventRecord(mesh->gathered_ev[k], side), "record gathered");
       ++nbatch;
     } else {
       StageTimer tm(mesh, 2, stream);
@@ -847,6 +849,14 @@ lf_status lf_set_tuning(lf_mesh mesh, const lf_tuning* t) {
   mesh->d.gather_waves = t->gather_waves;
   mesh->d.tile = t->tile;
   mesh->d.gather_unroll = t->gather_unroll;
+  return LF_OK;
+}
+
+lf_status lf_set_overlap(lf_mesh mesh, int32_t enabled) {
+  g_err[0] = 0;
+  lf_status st = check_mesh(mesh);
+  if (st != LF_OK) return st;
+  mesh->overlap = enabled != 0;
   return LF_OK;
 }
 

@@ -96,6 +96,7 @@ def lib():
             L.lf_texel_resolution.argtypes = [_p, _i64, C.c_float, _p, _p]
             L.lf_set_tuning.argtypes = [_p, C.POINTER(_Tuning)]
             L.lf_get_tuning.argtypes = [_p, C.POINTER(_Tuning)]
+            L.lf_set_overlap.argtypes = [_p, _i32]
             L.lf_batch_ws_bytes.argtypes = [C.POINTER(_SceneJob), _i32, C.POINTER(_i64)]
             L.lf_fuse_batch.argtypes = [C.POINTER(_SceneJob), _i32, _p, _i64, _p]
             L.lf_graph_capture_batch.argtypes = [C.POINTER(_SceneJob), _i32, _p, _i64, _p, C.POINTER(_p)]
@@ -108,7 +109,7 @@ def lib():
                          "lf_adam_step", "lf_extract_features", "lf_set_tuning", "lf_get_tuning",
                          "lf_batch_ws_bytes", "lf_fuse_batch", "lf_graph_capture_batch", "lf_graph_launch",
                          "lf_fuse_ws_bytes", "lf_area_ws_bytes", "lf_triangle_max_pixels", "lf_texel_resolution",
-                         "lf_set_weight_mix"):
+                         "lf_set_weight_mix", "lf_set_overlap"):
                 getattr(L, name).restype = _i32
             _lib = L
     return _lib
@@ -324,6 +325,11 @@ class Mesh:
         """lf_set_tuning (results do not depend on it)."""
         _check(lib().lf_set_tuning(self._h, C.byref(_Tuning(tile, gather_unroll, small_px, gather_waves))))
         self._fws.clear()
+
+    def set_overlap(self, enabled=True):
+        """lf_set_overlap: gathers on the mesh's second stream (True) or on the
+        caller's stream (False); results do not depend on it."""
+        _check(lib().lf_set_overlap(self._h, 1 if enabled else 0))
 
     def get_tuning(self):
         t = _Tuning()

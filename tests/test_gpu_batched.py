@@ -94,6 +94,11 @@ def test_tunings_do_not_change_results(scenes):
         _check(jobs, scenes[:1], f"tile {tile} unroll {unroll}")
         r = meshes[0].rasterize(to_dev(d["cams"], torch.float32), d["H"], d["W"])
         assert np.array_equal(r["l"].cpu().numpy(), d["l_o"])
+    # gathers on the caller's stream (no overlap between batches)
+    jobs, meshes2 = _jobs(scenes[:1])
+    meshes2[0].set_overlap(False)
+    sf.fuse_batch(jobs)
+    _check(jobs, scenes[:1], "no overlap")
     # FP8 channels-last input (scene 2) through the gather's 4-deep unroll and the smallest grid
     for unroll, gw in ((4, 1), (4, 8), (8, 32)):
         t = {"tile": 16, "gather_unroll": unroll, "small_px": 24, "gather_waves": gw}
