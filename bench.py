@@ -31,6 +31,7 @@ METRIC = "fused pixels/sec (c=40, 640×480) + % HBM roofline; learned/BF16 vs pl
 HBM_PEAK_GBS = 8000.0
 STAGES = ["raster", "resolve", "scatter", "counts", "finalize", "render", "reset", "mlp"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_seg_gather16_room500k_640x480_c40.txt")
+ISO_GATHER_WAVES = 512      # gather grid when it has the device alone: 8x more groups than fit, rows balance
 
 
 def log(*a):
@@ -417,7 +418,7 @@ def main():
     # caller's stream, one batch after another) on a grid for the whole device
     saved = mesh.get_tuning()
     mesh.set_overlap(False)
-    mesh.set_tuning(saved["tile"], saved["gather_unroll"], saved["small_px"], 32)
+    mesh.set_tuning(saved["tile"], saved["gather_unroll"], saved["small_px"], ISO_GATHER_WAVES)
     st_iso = make_step(head_probs, args.weighting, scale=head_scale)[0]
     tt_iso, pr_iso = timed(st_iso, 2, 1, "gather alone")
     mesh.set_overlap(True)
@@ -427,7 +428,7 @@ def main():
     iso_gbs = iso_px * per_px / (iso_ms * 1e-3) / 1e9
     result["roofline_isolated"] = {"kernel": "k_seg_gather16", "bound": "hbm", "achieved": iso_gbs,
                                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": iso_gbs / HBM_PEAK_GBS,
-                                   "kernel_ms": iso_ms, "gather_waves": 32,
+                                   "kernel_ms": iso_ms, "gather_waves": ISO_GATHER_WAVES,
                                    "step_value_without_overlap": 2 * npx / tt_iso}
     log(f"[bench] gather alone: {iso_ms:.3f} ms/launch, {iso_gbs:.0f} GB/s algorithmic "
         f"({iso_gbs / HBM_PEAK_GBS:.1%}); whole step without overlap {2 * npx / tt_iso / 1e9:.2f} G px/s")

@@ -178,9 +178,10 @@ lf_status lf_rasterize(lf_mesh mesh, const float* d_cams, int32_t F, int32_t H, 
  * default 8) and the largest pixel-box area a triangle may have to be
  * rasterized by a single lane rather than a whole wave (1..1024; default
  * 48), and the resident waves per compute unit the gather's grid is sized
- * for (1..32; default 8: fewer leave room for the next batch's raster,
- * which runs concurrently on a second stream).  Frame batch size and scatter
- * mode are per-call arguments.
+ * for (1..1024; default 8: fewer leave room for the next batch's raster,
+ * which runs concurrently on a second stream; more than fit at once, e.g.
+ * 512, balance rows of uneven length when the gather has the device alone).
+ * Frame batch size and scatter mode are per-call arguments.
  * lf_frame_ws_bytes depends on the tile: query it after lf_set_tuning. */
 typedef struct {
     int32_t tile;

@@ -843,8 +843,8 @@ lf_status lf_set_tuning(lf_mesh mesh, const lf_tuning* t) {
   if (t->gather_unroll != 4 && t->gather_unroll != 8)
     return fail(LF_EINVAL, "gather_unroll must be 4 or 8, got %d", t->gather_unroll);
   if (t->small_px < 1 || t->small_px > 1024) return fail(LF_EINVAL, "small_px must be in [1, 1024], got %d", t->small_px);
-  if (t->gather_waves < 1 || t->gather_waves > 32)
-    return fail(LF_EINVAL, "gather_waves must be in [1, 32], got %d", t->gather_waves);
+  if (t->gather_waves < 1 || t->gather_waves > 1024)
+    return fail(LF_EINVAL, "gather_waves must be in [1, 1024], got %d", t->gather_waves);
   mesh->d.small_px = t->small_px;
   mesh->d.gather_waves = t->gather_waves;
   mesh->d.tile = t->tile;

@@ -86,7 +86,7 @@ def test_fuse_batch_matches_oracle(scenes):
 
 def test_tunings_do_not_change_results(scenes):
     d = scenes[0]
-    for tile, unroll, small, gw in ((16, 4, 12, 8), (16, 8, 1, 1), (32, 4, 96, 32)):
+    for tile, unroll, small, gw in ((16, 4, 12, 8), (16, 8, 1, 1), (32, 4, 96, 32), (32, 8, 48, 512)):
         t = {"tile": tile, "gather_unroll": unroll, "small_px": small, "gather_waves": gw}
         jobs, meshes = _jobs(scenes[:1], tunings=[t])
         assert meshes[0].get_tuning() == t
@@ -109,6 +109,8 @@ def test_tunings_do_not_change_results(scenes):
         meshes[0].set_tuning(24, 8)
     with pytest.raises(sf.SemfuseError):
         meshes[0].set_tuning(32, 8, 0)
+    with pytest.raises(sf.SemfuseError):
+        meshes[0].set_tuning(32, 8, 48, 1025)
 
 
 def test_graph_replays_match_oracle(scenes):
