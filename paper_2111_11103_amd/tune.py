@@ -10,7 +10,8 @@ atomic always), raster tile edge (16, 32), the largest triangle box
 rasterized by one lane (12, 24, 48, 96 pixels), the sorted gather's unroll
 (4, 8) and the resident waves per CU its grid is sized for (8, 16, 32).  The
 search is coordinate descent from the library defaults: each knob in turn is
-swept with the others held, and the fastest value kept.  The choice is
+swept with the others held, and a value replaces the current one only when
+it is more than 1% faster (smaller differences are timing noise).  The choice is
 cached in a JSON file keyed by that tuple.  Results never depend on the
 choice; only speed does.  Timing uses events on the stream the library
 launches on; the mesh's accumulator is cleared afterwards.
@@ -32,6 +33,7 @@ TILES = (16, 32)
 SMALL = (12, 24, 48, 96)
 UNROLLS = (4, 8)
 GATHER_WAVES = (8, 16, 32)
+MIN_GAIN = 0.01     # a candidate replaces the incumbent only when faster by more than this (timing noise)
 _lock = threading.Lock()
 
 
@@ -147,7 +149,7 @@ def autotune(mesh: sf.Mesh, cams: torch.Tensor, probs: torch.Tensor, *, scale=No
         for v in values:
             cand = dict(best, **{knob: v})
             ms = trial(cand)
-            if ms < best_ms:
+            if ms < best_ms * (1.0 - MIN_GAIN):
                 best, best_ms = cand, ms
     mesh.reset()
     mesh._fws.clear()
