@@ -418,7 +418,7 @@ def frame_inputs(scene, cams, H, W, margin, sigma, blob_frac, invalid_frac, seed
 def config1(device="cpu", seed=0, n_frames=20, H=120, W=160, structured=False):
     """Plain FP32 parity workload: 2,100-triangle room, c = 13, 20 frames at
     160x120.  ``structured`` makes the probability noise depend on the view
-    (see make_probs); the learned weighting trains and is judged on both."""
+    (see make_probs); the learned weighting trains and is evaluated on both."""
     sc = room_scene(seed=seed, room=(6.0, 5.0, 3.0), n_boxes=6, n_classes=13, room_grid=13, box_grid=1)
     cams = circle_cameras(sc, n_frames, W, H)
     probs, valid, gt = frame_inputs(sc, cams, H, W, margin=4.0, sigma=1.5, blob_frac=0.10,
