@@ -101,8 +101,9 @@ lf_status lf_mesh_sizes(const lf_mesh_opts* opts, int64_t n_vertices, int64_t n_
  *  d_wsum     [n_texels] float32 total weight per texel, kept (may be NULL
  *             unless aggregator == MUL).
  * Waits on `stream` for index validation: LF_EINVAL if a face index is out of
- * range or an s is < 1.  The caller keeps vertices, workspace and accumulator
- * alive until lf_free_mesh. */
+ * range or an s is < 1.  The triangles' vertex positions are copied into the
+ * mesh workspace here: later changes to d_vertices are not seen.  The caller
+ * keeps vertices, workspace and accumulator alive until lf_free_mesh. */
 lf_status lf_load_mesh(const lf_mesh_opts* opts, const float* d_vertices, int64_t n_vertices,
                        const int32_t* d_faces, int64_t n_faces, const int32_t* d_s_face,
                        void* d_mesh_ws, int64_t mesh_ws_bytes, void* d_accum, float* d_wsum,

@@ -116,13 +116,14 @@ int64_t per_tri(int32_t s, int32_t scheme) {
 }
 
 struct MeshLayout {
-  int64_t faces_uv, s_face, off, cl_box, err, scan, total;
+  int64_t faces_uv, tri_v, s_face, off, cl_box, err, scan, total;
 };
 
 MeshLayout mesh_layout(int64_t T, bool per_face) {
   MeshLayout L{};
   int64_t o = 0;
   L.faces_uv = o; o += align256(T * 3 * 4);
+  L.tri_v = o; o += align256(T * 48);
   L.s_face = o; if (per_face) o += align256(T * 4);
   L.off = o; if (per_face) o += align256((T + 1) * 8);
   const int64_t ncl = (T + kClusterTris - 1) / kClusterTris;
@@ -282,6 +283,7 @@ lf_status lf_load_mesh(const lf_mesh_opts* opts, const float* d_vertices, int64_
   MeshDev d{};
   d.verts = d_vertices;
   d.faces_uv = reinterpret_cast<int32_t*>(ws + L.faces_uv);
+  d.tri_v = reinterpret_cast<float4*>(ws + L.tri_v);
   d.s_face = per_face ? reinterpret_cast<int32_t*>(ws + L.s_face) : nullptr;
   d.off = per_face ? reinterpret_cast<int64_t*>(ws + L.off) : nullptr;
   d.cl_box = reinterpret_cast<float*>(ws + L.cl_box);

@@ -11,6 +11,7 @@ constexpr int kClusterTris = 64;      // triangles per culling cluster (one wave
 struct MeshDev {
   const float* verts;        // [V][3]
   int32_t* faces_uv;         // [T][3] vertex indices in uv order (A, B, C)
+  float4* tri_v;             // [T][3] positions of A, B, C in uv order: (A.xyz B.x) (B.yz C.xy) (C.z 0 0 0)
   int32_t* s_face;           // [T] or nullptr (uniform s)
   int64_t* off;              // [T+1] row offsets or nullptr (uniform: t * n_per)
   float* cl_box;             // [n_clusters][8]: lo.xyz, hi.xyz, magnitude bound, pad

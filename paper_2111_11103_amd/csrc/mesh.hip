@@ -7,7 +7,8 @@ namespace lf {
 
 // uv origin = the vertex whose interior angle is closest to 90 degrees:
 // smallest (a.b)^2 / ((a.a)(b.b)) over the three corners (binary32, first
-// minimum wins).  faces_uv = (origin, next, next-next) in input order.
+// minimum wins).  faces_uv = (origin, next, next-next) in input order, and
+// tri_v the three positions in that order.
 __global__ __launch_bounds__(256) void k_mesh_prep(MeshDev m, const int32_t* __restrict__ faces) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= m.T) return;
@@ -24,6 +25,7 @@ __global__ __launch_bounds__(256) void k_mesh_prep(MeshDev m, const int32_t* __r
     m.faces_uv[3 * t + 0] = 0;
     m.faces_uv[3 * t + 1] = 0;
     m.faces_uv[3 * t + 2] = 0;
+    for (int k = 0; k < 3; ++k) m.tri_v[3 * t + k] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     return;
   }
   V3 P[3];
@@ -46,6 +48,11 @@ __global__ __launch_bounds__(256) void k_mesh_prep(MeshDev m, const int32_t* __r
   m.faces_uv[3 * t + 0] = idx[o];
   m.faces_uv[3 * t + 1] = idx[(o + 1) % 3];
   m.faces_uv[3 * t + 2] = idx[(o + 2) % 3];
+  // triangle-major copy of the positions: one 48-byte read per triangle
+  const V3 A = P[o], B = P[(o + 1) % 3], C = P[(o + 2) % 3];
+  m.tri_v[3 * t + 0] = make_float4(A.x, A.y, A.z, B.x);
+  m.tri_v[3 * t + 1] = make_float4(B.y, B.z, C.x, C.y);
+  m.tri_v[3 * t + 2] = make_float4(C.z, 0.0f, 0.0f, 0.0f);
 }
 
 hipError_t launch_mesh_prep(const MeshDev& m, const int32_t* faces, hipStream_t s) {

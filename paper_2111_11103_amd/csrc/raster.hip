@@ -40,14 +40,13 @@ struct Setup {
   int x0, x1, y0, y1;          // pixel-centre box, clamped to the image
 };
 
+// Camera-space corners of triangle t (uv order) from the triangle-major copy
+// of the positions: one dependent read instead of indices, then vertices.
 __device__ __forceinline__ void load_tri(const MeshDev& m, const Cam& cam, int64_t t, V3& A, V3& B, V3& C) {
-  const int i0 = m.faces_uv[3 * t], i1 = m.faces_uv[3 * t + 1], i2 = m.faces_uv[3 * t + 2];
-  const float* q0 = m.verts + 3 * (int64_t)i0;
-  const float* q1 = m.verts + 3 * (int64_t)i1;
-  const float* q2 = m.verts + 3 * (int64_t)i2;
-  A = to_cam(cam, q0[0], q0[1], q0[2]);
-  B = to_cam(cam, q1[0], q1[1], q1[2]);
-  C = to_cam(cam, q2[0], q2[1], q2[2]);
+  const float4 p = m.tri_v[3 * t], q = m.tri_v[3 * t + 1], r = m.tri_v[3 * t + 2];
+  A = to_cam(cam, p.x, p.y, p.z);
+  B = to_cam(cam, p.w, q.x, q.y);
+  C = to_cam(cam, q.z, q.w, r.x);
 }
 
 // Snapped polygon of the camera-space triangle (A, B, C) clipped by the five
@@ -426,7 +425,7 @@ __global__ __launch_bounds__(256) void k_tile_raster(MeshDev m, const float* __r
   float z[PPT];
   int64_t pix[PPT];
   bool in[PPT], use[PPT];
-  int fi[PPT][3];
+  float4 tv[PPT][3];
   float4 geo[PPT];
 #pragma unroll
   for (int r = 0; r < PPT; ++r) {
@@ -443,9 +442,9 @@ __global__ __launch_bounds__(256) void k_tile_raster(MeshDev m, const float* __r
 #pragma unroll
   for (int r = 0; r < PPT; ++r) {
     if (tri[r] >= 0) {
-      fi[r][0] = m.faces_uv[3 * (int64_t)tri[r]];
-      fi[r][1] = m.faces_uv[3 * (int64_t)tri[r] + 1];
-      fi[r][2] = m.faces_uv[3 * (int64_t)tri[r] + 2];
+      tv[r][0] = m.tri_v[3 * (int64_t)tri[r]];
+      tv[r][1] = m.tri_v[3 * (int64_t)tri[r] + 1];
+      tv[r][2] = m.tri_v[3 * (int64_t)tri[r] + 2];
     }
     use[r] = tri[r] >= 0 && (!out.valid || out.valid[pix[r]]);
   }
@@ -453,11 +452,8 @@ __global__ __launch_bounds__(256) void k_tile_raster(MeshDev m, const float* __r
   for (int r = 0; r < PPT; ++r) {
     if (tri[r] >= 0) {
       const int i = threadIdx.x + 256 * r;
-      const float* q0 = m.verts + 3 * (int64_t)fi[r][0];
-      const float* q1 = m.verts + 3 * (int64_t)fi[r][1];
-      const float* q2 = m.verts + 3 * (int64_t)fi[r][2];
-      const RayK rk = ray_consts(to_cam(cam, q0[0], q0[1], q0[2]), to_cam(cam, q1[0], q1[1], q1[2]),
-                                 to_cam(cam, q2[0], q2[1], q2[2]));
+      const float4 p = tv[r][0], q = tv[r][1], t3 = tv[r][2];
+      const RayK rk = ray_consts(to_cam(cam, p.x, p.y, p.z), to_cam(cam, p.w, q.x, q.y), to_cam(cam, q.z, q.w, t3.x));
       const float rx = rxs[i % TS], ry = rys[i / TS];
       const float den = rdot(rx, ry, rk.n);
       z[r] = rk.d / den;
