@@ -188,14 +188,24 @@ __global__ __launch_bounds__(256) void k_cull_clusters(MeshDev m, const float* _
 
 // ---- 2. binning into tiles (one pass into fixed-capacity tile lists) -----------------
 // Every tile of a frame owns `cap` list slots.  A triangle takes a slot in
-// every tile its pixel-centre box overlaps (lanes on the same tile share one
-// atomic); the tile's counter keeps counting past `cap`, which tells the
-// raster to fall back to walking the frame's visible clusters for that tile.
+// every tile its pixel-centre box overlaps; the tile's counter keeps counting
+// past `cap`, which tells the raster to fall back to walking the frame's
+// visible clusters for that tile.
+//
+// With the frame's tile counts fitting in LDS (dynamic LDS of 2 * ntiles
+// ints), a block bins its four clusters together: it counts its triangles
+// per tile with LDS atomics, reserves each touched tile's slots with one
+// global atomic (all issued at once, none waited for inside a loop), then
+// places every triangle at the tile's base plus an LDS rank.  Otherwise the
+// lanes of a wave that are on the same tile share one global atomic.
+constexpr int kBinLdsTiles = 4096;
+
 template <int TS>
 __global__ __launch_bounds__(256) void k_bin(MeshDev m, const float* __restrict__ cams, int H, int W,
                                              const int32_t* __restrict__ vis, const int32_t* __restrict__ vis_n,
                                              int32_t* __restrict__ tcnt, int32_t* __restrict__ tlist, int64_t list_cap,
                                              int cap) {
+  extern __shared__ int tile_lds[];       // [ntiles] counts, then bases; [ntiles] ranks
   const int fb = blockIdx.y;
   const Cam cam = load_cam(cams + 16 * (int64_t)fb);
   const int ntx = (W + TS - 1) / TS, nty = (H + TS - 1) / TS;
@@ -204,6 +214,46 @@ __global__ __launch_bounds__(256) void k_bin(MeshDev m, const float* __restrict_
   const int nvis = vis_n[fb];
   int32_t* cnt = tcnt + (int64_t)fb * ntiles;
   int32_t* lst = tlist + (int64_t)fb * list_cap;
+  if (ntiles <= kBinLdsTiles) {
+    int* tb = tile_lds;
+    int* tr = tile_lds + ntiles;
+    for (int w0 = blockIdx.x * 4; w0 < nvis; w0 += gridDim.x * 4) {   // same trip count for the whole block
+      const int w = w0 + (threadIdx.x >> 6);
+      int64_t t = m.T;
+      Setup s;
+      s.n = 0;
+      s.x0 = 0; s.x1 = -1; s.y0 = 0; s.y1 = -1;
+      if (w < nvis) {
+        t = vis[(int64_t)fb * m.n_clusters + w] * (int64_t)kClusterTris + lane;
+        if (t < m.T) setup_triangle(m, cam, cams + 16 * (int64_t)fb, t, H, W, s);
+      }
+      const bool draw = t < m.T && s.n != 0;
+      const int tx0 = s.x0 / TS, tx1 = s.x1 / TS, ty0 = s.y0 / TS, ty1 = s.y1 / TS;
+      for (int i = threadIdx.x; i < ntiles; i += 256) {
+        tb[i] = 0;
+        tr[i] = 0;
+      }
+      __syncthreads();
+      if (draw)
+        for (int ty = ty0; ty <= ty1; ++ty)
+          for (int tx = tx0; tx <= tx1; ++tx) atomicAdd(&tb[ty * ntx + tx], 1);
+      __syncthreads();
+      for (int i = threadIdx.x; i < ntiles; i += 256) {
+        const int n = tb[i];
+        if (n) tb[i] = atomicAdd(cnt + i, n);
+      }
+      __syncthreads();
+      if (draw)
+        for (int ty = ty0; ty <= ty1; ++ty)
+          for (int tx = tx0; tx <= tx1; ++tx) {
+            const int tile = ty * ntx + tx;
+            const int pos = tb[tile] + atomicAdd(&tr[tile], 1);
+            if (pos < cap) lst[(int64_t)tile * cap + pos] = (int32_t)t;
+          }
+      __syncthreads();                    // the next round clears the arrays
+    }
+    return;
+  }
   for (int w = blockIdx.x * 4 + (threadIdx.x >> 6); w < nvis; w += gridDim.x * 4) {
     const int64_t cl = vis[(int64_t)fb * m.n_clusters + w];
     const int64_t t = cl * kClusterTris + lane;
@@ -530,8 +580,9 @@ hipError_t render_batch_ts(const MeshDev& m, const float* cams, int nb, int H, i
                                                                                                ws.vis_n);
   const unsigned gb = (unsigned)std::min<int64_t>((m.n_clusters + 3) / 4 + 1, 256);
   const int cap = (int)std::min<int64_t>(ws.list_cap / ntiles, INT32_MAX);
-  k_bin<TS><<<dim3(gb, (unsigned)nb), 256, 0, s>>>(m, cams, H, W, ws.vis, ws.vis_n, ws.tcnt, ws.tlist, ws.list_cap,
-                                                   cap);
+  const size_t bin_lds = ntiles <= kBinLdsTiles ? (size_t)ntiles * 2 * sizeof(int) : 0;
+  k_bin<TS><<<dim3(gb, (unsigned)nb), 256, bin_lds, s>>>(m, cams, H, W, ws.vis, ws.vis_n, ws.tcnt, ws.tlist,
+                                                         ws.list_cap, cap);
   k_tile_raster<TS><<<dim3((unsigned)ntiles, (unsigned)nb), 256, 0, s>>>(m, cams, H, W, ws.vis, ws.vis_n, ws.tcnt,
                                                                          ws.tlist, ws.list_cap, cap, out);
   return hipGetLastError();
