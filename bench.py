@@ -259,6 +259,8 @@ def main():
     ap.add_argument("--no-forms", action="store_true", help="skip the NCHW / FP8 / w^(I) / learned throughput legs")
     ap.add_argument("--no-accuracy", action="store_true", help="skip the label-accuracy report")
     ap.add_argument("--no-batched", action="store_true", help="skip the 16-scene batched graph leg")
+    ap.add_argument("--no-isolated", action="store_true",
+                    help="skip timing the gather alone (roofline_isolated); for profiling the headline launches")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration) and exit")
     args = ap.parse_args()
@@ -416,22 +418,28 @@ def main():
 
     # the same gather launches without the concurrent raster (gathers on the
     # caller's stream, one batch after another) on a grid for the whole device
-    saved = mesh.get_tuning()
-    mesh.set_overlap(False)
-    mesh.set_tuning(saved["tile"], saved["gather_unroll"], saved["small_px"], ISO_GATHER_WAVES)
-    st_iso = make_step(head_probs, args.weighting, scale=head_scale)[0]
-    tt_iso, pr_iso = timed(st_iso, 2, 1, "gather alone")
-    mesh.set_overlap(True)
-    mesh.set_tuning(**saved)
-    iso_ms = pr_iso.ms[2] / pr_iso.launches[2]
-    iso_px = npx * 2 / pr_iso.launches[2]
-    iso_gbs = iso_px * per_px / (iso_ms * 1e-3) / 1e9
-    result["roofline_isolated"] = {"kernel": "k_seg_gather16", "bound": "hbm", "achieved": iso_gbs,
-                                   "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": iso_gbs / HBM_PEAK_GBS,
-                                   "kernel_ms": iso_ms, "gather_waves": ISO_GATHER_WAVES,
-                                   "step_value_without_overlap": 2 * npx / tt_iso}
-    log(f"[bench] gather alone: {iso_ms:.3f} ms/launch, {iso_gbs:.0f} GB/s algorithmic "
-        f"({iso_gbs / HBM_PEAK_GBS:.1%}); whole step without overlap {2 * npx / tt_iso / 1e9:.2f} G px/s")
+    def isolated_leg(result):
+        saved = mesh.get_tuning()
+        mesh.set_overlap(False)
+        mesh.set_tuning(saved["tile"], saved["gather_unroll"], saved["small_px"], ISO_GATHER_WAVES)
+        st_iso = make_step(head_probs, args.weighting, scale=head_scale)[0]
+        tt_iso, pr_iso = timed(st_iso, 2, 1, "gather alone")
+        mesh.set_overlap(True)
+        mesh.set_tuning(**saved)
+        iso_ms = pr_iso.ms[2] / pr_iso.launches[2]
+        iso_px = npx * 2 / pr_iso.launches[2]
+        iso_gbs = iso_px * per_px / (iso_ms * 1e-3) / 1e9
+        result["roofline_isolated"] = {"kernel": "k_seg_gather16", "bound": "hbm", "achieved": iso_gbs,
+                                       "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": iso_gbs / HBM_PEAK_GBS,
+                                       "kernel_ms": iso_ms, "gather_waves": ISO_GATHER_WAVES,
+                                       "step_value_without_overlap": 2 * npx / tt_iso}
+        log(f"[bench] gather alone: {iso_ms:.3f} ms/launch, {iso_gbs:.0f} GB/s algorithmic "
+            f"({iso_gbs / HBM_PEAK_GBS:.1%}); whole step without overlap {2 * npx / tt_iso / 1e9:.2f} G px/s")
+
+    if args.no_isolated:
+        result["roofline_isolated"] = None
+    else:
+        isolated_leg(result)
 
     if not args.no_forms:
         forms = {}
