@@ -10,13 +10,18 @@
 //                    (transform, clip, 8-bit sub-pixel snap) and append it
 //                    to the fixed-capacity list of every tile (16x16 or
 //                    32x32 pixels, a tuning knob) its pixel-centre box
-//                    overlaps;
+//                    overlaps (slots reserved per block through LDS tile
+//                    counters);
 //   k_tile_raster    one workgroup per (frame, tile): a 64-bit depth|id key
 //                    per pixel in LDS, every listed triangle rasterized with
-//                    int64 edge functions and the top-left rule (small ones by
-//                    one thread, large ones by the whole wave), ds_min_u64 on
-//                    the key; then every pixel resolves its winner into
-//                    (triangle, texel row, depth) and writes them out.
+//                    exact integer edge functions and the top-left rule (small
+//                    ones by one thread, large ones by the whole wave),
+//                    ds_min_u64 on the key; then every pixel resolves its
+//                    winner into (triangle, texel row, depth) and writes them
+//                    out, with one texel-row count atomic per run of
+//                    same-row pixels.
+// Triangles are read from a triangle-major copy of their positions built at
+// load (one dependent read per triangle).
 // The key order (depth bits, then triangle id) makes the result independent
 // of the order fragments arrive in.
 #include <algorithm>
