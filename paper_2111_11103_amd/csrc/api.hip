@@ -453,10 +453,37 @@ lf_status fuse_impl(const FuseArgs& a, void* d_ws, hipStream_t stream) {
   lf_status status;
   int nbatch = 0;      // sorted batches issued: batch k's gather runs on `side`
   hipStream_t side = mesh->overlap ? mesh->side : stream;
+  // batches: frames [f0, f0 + nb) read input frames [fi, fi + nb)
+  struct Batch {
+    int f0, nb, fi;
+  };
+  std::vector<Batch> batches;
   for (int f0 = 0; f0 < a.F;) {
     int nb = (a.F - f0) < B ? (a.F - f0) : B;
     const int fi = a.pool > 0 ? f0 % a.pool : f0;     // input frame of the batch's first frame
-    if (a.pool > 0 && nb > a.pool - fi) nb = a.pool - fi;
+    if (a.pool > 0 && nb > a.pool - fi) nb = a.pool - fi;   // batches never straddle the end of the pool
+    batches.push_back(Batch{f0, nb, fi});
+    f0 += nb;
+  }
+  // Planar inputs: the side stream transposes each batch into pixel-major
+  // rows (staging set j % 2), batch j + 1 while batch j is sorted on the
+  // caller's stream; the fill and the gather then read the rows like
+  // channels-last input.  Stream order on the side stream protects a set
+  // from being rewritten before its gather has read it.
+  auto stage_batch = [&](size_t j) -> lf_status {
+    StageTimer tm(mesh, 3, side);
+    LF_TRY(launch_planar_rows(in, batches[j].fi, batches[j].nb, H, W, d.c,
+                              reinterpret_cast<float*>(ws + L.stage[j & 1]), side), "planar rows");
+    return LF_OK;
+  };
+  if (staged && !batches.empty()) {
+    // the input may come from work on the caller's stream
+    LF_TRY(hipEventRecord(mesh->sorted_ev[1], stream), "record call start");
+    LF_TRY(hipStreamWaitEvent(side, mesh->sorted_ev[1], 0), "wait for call start");
+    if ((status = stage_batch(0)) != LF_OK) return status;
+  }
+  for (size_t j = 0; j < batches.size(); ++j) {
+    const int f0 = batches[j].f0, nb = batches[j].nb, fi = batches[j].fi;
     const float* cams_in = a.cams + 16 * (int64_t)(f0 - fi);  // camera of input index fi + k is f0 + k
     int32_t* lb = a.l_out ? a.l_out + (int64_t)f0 * HW : reinterpret_cast<int32_t*>(ws + L.l);
     const uint8_t* vb = a.valid ? a.valid + (int64_t)fi * HW : nullptr;
@@ -484,19 +511,22 @@ lf_status fuse_impl(const FuseArgs& a, void* d_ws, hipStream_t stream) {
         LF_TRY(launch_zero(nrows, 4, stream), "clear row count");
         LF_TRY(launch_seg_scan(seg, d.n_texels, reinterpret_cast<int32_t*>(ws + L.sums), start, rows, nrows, stream),
                "segment scan");
+        // staged rows of the batch: frame stride H*W*c, row stride W*c, pixel stride c
+        const ProbIn sin{stg, nullptr, a.valid ? a.valid + (int64_t)fi * HW : nullptr, HW * d.c, 1,
+                         (int64_t)W * d.c, d.c, LF_F32};
         if (staged)
-          LF_TRY(launch_seg_stage(in, fi, nb, H, W, d.c, lb, rank, start, eo, ew, stg, a.weighting, cnt, d.n_texels,
-                                  wpix, d.mix, stream), "segment stage");
+          LF_TRY(launch_seg_fill(sin, 0, nb, H, W, lb, rank, start, eo, ew, nullptr, a.weighting, cnt, d.n_texels,
+                                 wpix, d.mix, stream), "segment fill");
         else
           LF_TRY(launch_seg_fill(in, fi, nb, H, W, lb, rank, start, eo, ew, es, a.weighting, cnt, d.n_texels, wpix,
                                  d.mix, stream), "segment fill");
       }
       LF_TRY(hipEventRecord(mesh->sorted_ev[k], stream), "record sorted");
+      if (staged && j + 1 < batches.size() && (status = stage_batch(j + 1)) != LF_OK) return status;
       LF_TRY(hipStreamWaitEvent(side, mesh->sorted_ev[k], 0), "wait for sort");
       {
         StageTimer tm(mesh, 2, side);
-        // staged observations: contiguous class vectors at element offset slot * c
-        const ProbIn gin = staged ? ProbIn{stg, nullptr, nullptr, 0, 1, 0, 0, LF_F32} : in;
+        const ProbIn gin = staged ? ProbIn{stg, nullptr, nullptr, HW * d.c, 1, (int64_t)W * d.c, d.c, LF_F32} : in;
         LF_TRY(launch_seg_gather(d, gin, staged ? 0 : fi, H, W, start, rows, nrows, eo, ew, es, side),
                "segment gather");
       }
@@ -511,7 +541,6 @@ lf_status fuse_impl(const FuseArgs& a, void* d_ws, hipStream_t stream) {
       StageTimer tm(mesh, 3, stream);
       LF_TRY(launch_clear_counts(lb, vb, nb, H, W, cnt, d.n_texels, stream), "clear counts");
     }
-    f0 += nb;
   }
   // the call is complete on the caller's stream once the last gather is
   if (nbatch > 0) LF_TRY(hipStreamWaitEvent(stream, mesh->gathered_ev[(nbatch - 1) & 1], 0), "join gathers");

@@ -96,10 +96,10 @@ hipError_t launch_seg_scan(const int32_t* seg, int64_t n, int32_t* sums, int32_t
 hipError_t launch_seg_fill(const ProbIn& in, int f_first, int nf, int H, int W, const int32_t* l, const int32_t* rank,
                            const int32_t* start, uint32_t* ent_pix, float* ent_w, float* ent_s, int weighting,
                            const int32_t* cnt, int64_t cnt_stride, const float* wpix, float mix, hipStream_t s);
-hipError_t launch_seg_stage(const ProbIn& in, int f_first, int nf, int H, int W, int c, const int32_t* l,
-                            const int32_t* rank, const int32_t* start, uint32_t* ent_pix, float* ent_w, float* staging,
-                            int weighting, const int32_t* cnt, int64_t cnt_stride, const float* wpix, float mix,
-                            hipStream_t s);
+// Frames [f_first, f_first + nf) of planar FP32 input as pixel-major rows of
+// c floats: staging[(f - f_first) * H * W + p][j] (c % 4 == 0, c <= 60).
+hipError_t launch_planar_rows(const ProbIn& in, int f_first, int nf, int H, int W, int c, float* staging,
+                              hipStream_t s);
 hipError_t launch_seg_gather(const MeshDev& m, const ProbIn& in, int f_first, int H, int W, const int32_t* start,
                              const int32_t* rows, const int32_t* nrows, const uint32_t* ent_pix, const float* ent_w,
                              const float* ent_s, hipStream_t s);

@@ -157,51 +157,41 @@ __global__ __launch_bounds__(256) void k_seg_fill(ProbIn in, int f_first, int H,
   }
 }
 
-// ---- staged fill (planar inputs) ----------------------------------------------------------
-// For inputs whose classes are far apart in memory (NCHW), the fill also
-// moves every observation's class vector to its slot of a staging array, so
-// the gather then reads each texel's observations as one contiguous run.
-// A block takes 256 consecutive pixels of one frame: each class plane is read
-// coalesced into LDS (padded rows, no bank conflicts), then the rows are
-// written out as float4 runs (c % 4 == 0, c <= 60, FP32; LDS sized by c).
+// ---- planar inputs: transpose to rows ----------------------------------------------------
+// For inputs whose classes are far apart in memory (NCHW), frames are first
+// transposed into a staging array of contiguous class vectors (pixel-major,
+// c floats per pixel), which the fill and gather then treat like
+// channels-last input.  A block takes 256 consecutive pixels of one frame:
+// each class plane is read coalesced into LDS (padded rows, no bank
+// conflicts), then the block's 256 x c floats are written out as contiguous
+// float4 runs (c % 4 == 0, c <= 60, FP32; LDS sized by c).
 constexpr int kStageMaxC = 60;
 constexpr int kStageRow = 257;     // padded LDS row of one class (256 pixels)
 
-__global__ __launch_bounds__(256) void k_seg_stage(ProbIn in, int f_first, int H, int W, int c,
-                                                   const int32_t* __restrict__ lbuf, const int32_t* __restrict__ rank,
-                                                   const int32_t* __restrict__ start, uint32_t* __restrict__ ent_pix,
-                                                   float* __restrict__ ent_w, float* __restrict__ staging,
-                                                   int weighting, const int32_t* __restrict__ cnt, int64_t cnt_stride,
-                                                   const float* __restrict__ wpix, float mix) {
-  extern __shared__ float stage_lds[];
-  int* spos = reinterpret_cast<int*>(stage_lds);            // [256]
-  float* sv = stage_lds + 256;                              // [c][kStageRow]
+__global__ __launch_bounds__(256) void k_planar_rows(ProbIn in, int f_first, int H, int W, int c,
+                                                     float* __restrict__ staging) {
+  extern __shared__ float sv[];                             // [c][kStageRow]
   const int fb = blockIdx.y;
   const int64_t HW = (int64_t)H * W;
   const int t = threadIdx.x;
-  const int64_t p = (int64_t)blockIdx.x * 256 + t;
-  int l = -1;
-  if (p < HW) {
-    l = lbuf[(int64_t)fb * HW + p];
-    if (l >= 0 && in.valid && !in.valid[(int64_t)(f_first + fb) * HW + p]) l = -1;
-  }
-  int pos = -1;
-  if (l >= 0) {
-    pos = start[l] + rank[(int64_t)fb * HW + p];
-    ent_pix[pos] = (uint32_t)pos * (uint32_t)c;
-    if (ent_w) {
-      float w = 1.0f;
-      if (weighting == 1) w = 1.0f / (float)cnt[(int64_t)fb * cnt_stride + l];
-      else if (weighting == 2) w = wpix[(int64_t)fb * HW + p];
-      else if (weighting == 3) w = (1.0f - mix) + mix / (float)cnt[(int64_t)fb * cnt_stride + l];
-      ent_w[pos] = w;
+  const int64_t p0 = (int64_t)blockIdx.x * 256;
+  const int64_t p = p0 + t;
+  const float* base = reinterpret_cast<const float*>(in.p) + (int64_t)(f_first + fb) * in.sf;
+  if (in.sx == 1 && in.sy == W && (HW & 3) == 0 && (in.sc & 3) == 0 && (in.sf & 3) == 0 &&
+      (reinterpret_cast<uintptr_t>(in.p) & 15) == 0) {
+    // dense planes: float4 loads of 4 consecutive pixels, every load of the block independent
+    const int n4 = (int)min<int64_t>(64, (HW - p0) >> 2);
+    for (int i = t; i < c * 64; i += 256) {
+      const int j = i >> 6, k = i & 63;
+      if (k < n4) {
+        const float4 v = *reinterpret_cast<const float4*>(base + (int64_t)j * in.sc + p0 + 4 * k);
+        float* d = sv + j * kStageRow + 4 * k;
+        d[0] = v.x; d[1] = v.y; d[2] = v.z; d[3] = v.w;
+      }
     }
-  }
-  spos[t] = pos;
-  if (p < HW) {
+  } else if (p < HW) {
     const int y = (int)(p / W), x = (int)(p - (int64_t)y * W);
-    const float* src = reinterpret_cast<const float*>(in.p) + (int64_t)(f_first + fb) * in.sf + (int64_t)y * in.sy +
-                       (int64_t)x * in.sx;
+    const float* src = base + (int64_t)y * in.sy + (int64_t)x * in.sx;
     float* dst = sv + t;
 #pragma unroll 4
     for (int j = 0; j < c; ++j) {
@@ -212,15 +202,13 @@ __global__ __launch_bounds__(256) void k_seg_stage(ProbIn in, int f_first, int H
   __syncthreads();
   // output element i (in float4 units) of the block is (row, q) = (i / nq, i % nq): walk it incrementally
   const int nq = c >> 2;
+  const int n = (int)min<int64_t>(256, HW - p0);
   const int drow = 256 / nq, dq = 256 - drow * nq;
   int row = t / nq, q = t - (t / nq) * nq;
-  for (int i = t; i < 256 * nq; i += 256) {
-    const int ps = spos[row];
-    if (ps >= 0) {
-      const float* col = sv + 4 * q * kStageRow + row;
-      const float4 v = make_float4(col[0], col[kStageRow], col[2 * kStageRow], col[3 * kStageRow]);
-      *reinterpret_cast<float4*>(staging + (int64_t)ps * c + 4 * q) = v;
-    }
+  float4* out = reinterpret_cast<float4*>(staging + ((int64_t)fb * HW + p0) * c);
+  for (int i = t; i < n * nq; i += 256) {
+    const float* col = sv + 4 * q * kStageRow + row;
+    out[i] = make_float4(col[0], col[kStageRow], col[2 * kStageRow], col[3 * kStageRow]);
     row += drow;
     q += dq;
     if (q >= nq) { q -= nq; ++row; }
@@ -521,17 +509,13 @@ hipError_t launch_seg_scan(const int32_t* seg, int64_t n, int32_t* sums, int32_t
   return hipGetLastError();
 }
 
-hipError_t launch_seg_stage(const ProbIn& in, int f_first, int nf, int H, int W, int c, const int32_t* l,
-                            const int32_t* rank, const int32_t* start, uint32_t* ent_pix, float* ent_w, float* staging,
-                            int weighting, const int32_t* cnt, int64_t cnt_stride, const float* wpix, float mix,
-                            hipStream_t s) {
+hipError_t launch_planar_rows(const ProbIn& in, int f_first, int nf, int H, int W, int c, float* staging,
+                              hipStream_t s) {
   if (nf <= 0) return hipSuccess;
   if (c > kStageMaxC || (c & 3) || in.dtype != 0) return hipErrorInvalidValue;
   const int64_t HW = (int64_t)H * W;
-  const size_t lds = (size_t)(256 + c * kStageRow) * 4;
-  k_seg_stage<<<dim3((unsigned)((HW + 255) / 256), (unsigned)nf), 256, lds, s>>>(in, f_first, H, W, c, l, rank, start,
-                                                                                 ent_pix, ent_w, staging, weighting,
-                                                                                 cnt, cnt_stride, wpix, mix);
+  const size_t lds = (size_t)c * kStageRow * 4;
+  k_planar_rows<<<dim3((unsigned)((HW + 255) / 256), (unsigned)nf), 256, lds, s>>>(in, f_first, H, W, c, staging);
   return hipGetLastError();
 }
 
