@@ -59,8 +59,8 @@ typedef enum {
     LF_SCATTER_AUTO = 0,     /* SORTED when a pixel's classes are contiguous, else STAGED when allowed, else ATOMIC */
     LF_SCATTER_ATOMIC = 1,   /* LDS-hash pre-reduction, then FP32 atomics (any strides, any dtype) */
     LF_SCATTER_SORTED = 2,   /* texel-sorted gather reading each pixel's classes in place */
-    LF_SCATTER_STAGED = 3    /* texel-sorted gather of class vectors first copied to their sorted slots
-                                (planar inputs; FP32, c % 4 == 0, c <= 60) */
+    LF_SCATTER_STAGED = 3    /* frames first transposed to pixel-major rows in the frame workspace, then
+                                the texel-sorted gather (planar inputs; FP32, c % 4 == 0, c <= 60) */
 } lf_scatter_mode;
 
 typedef struct lf_mesh_s* lf_mesh;
