@@ -228,11 +228,26 @@ __device__ __forceinline__ float wave_max(float v) {
   return v;
 }
 
+// Compensated (Kahan) addition of x to the running sum s, its rounding error
+// carried in c (the sum is s - c): the error of a row's sum then stays within
+// about 2 * 2^-24 of the sum of magnitudes however many observations the row
+// has, where a plain running sum drifts with their number (a texel seen by
+// tens of thousands of pixels in a batch).  Finite terms only.
+__device__ __forceinline__ void kahan_add(float& s, float& c, float x) {
+  const float y = x - c;
+  const float t = s + y;
+  c = (t - s) - y;
+  s = t;
+}
+
+// SUM and MAXSUM rows are summed with compensation; MUL rows (sums of logs,
+// which may be -inf) with plain additions.
 template <int NCH, int DT, int AGG>
-__device__ __forceinline__ void accumulate(float (&acc)[NCH], const float (&v)[NCH], float w, int lane, int c) {
+__device__ __forceinline__ void accumulate(float (&acc)[NCH], float (&cmp)[NCH], const float (&v)[NCH], float w,
+                                           int lane, int c) {
   if constexpr (AGG == 0) {
 #pragma unroll
-    for (int ch = 0; ch < NCH; ++ch) acc[ch] += w * v[ch];
+    for (int ch = 0; ch < NCH; ++ch) kahan_add(acc[ch], cmp[ch], w * v[ch]);
   } else if constexpr (AGG == 1) {
 #pragma unroll
     for (int ch = 0; ch < NCH; ++ch) acc[ch] += w * logf(v[ch]);
@@ -242,7 +257,7 @@ __device__ __forceinline__ void accumulate(float (&acc)[NCH], const float (&v)[N
     for (int ch = 0; ch < NCH; ++ch) mx = fmaxf(mx, (lane + 64 * ch < c) ? v[ch] : -__builtin_inff());
     mx = wave_max(mx);
 #pragma unroll
-    for (int ch = 0; ch < NCH; ++ch) acc[ch] += w * ((v[ch] == mx) ? v[ch] : 0.0f);
+    for (int ch = 0; ch < NCH; ++ch) kahan_add(acc[ch], cmp[ch], w * ((v[ch] == mx) ? v[ch] : 0.0f));
   }
 }
 
@@ -283,9 +298,9 @@ __global__ __launch_bounds__(256) void k_seg_gather(MeshDev m, ProbIn in, PixDec
       const int j = lane + 64 * ch;
       old[ch] = j < c ? acc_load<AT>(m.accum, x * c + j) : 0.0f;
     }
-    float acc[NCH];
+    float acc[NCH], cmp[NCH];
 #pragma unroll
-    for (int ch = 0; ch < NCH; ++ch) acc[ch] = 0.0f;
+    for (int ch = 0; ch < NCH; ++ch) acc[ch] = cmp[ch] = 0.0f;
     float wsum = 0.0f;
     for (int b = seg_s; b < seg_e; b += 64) {
       const int k = b + lane;
@@ -315,7 +330,7 @@ __global__ __launch_bounds__(256) void k_seg_gather(MeshDev m, ProbIn in, PixDec
 #pragma unroll
         for (int u = 0; u < kGatherUnroll; ++u) {
           if (i0 + u < cnt) {
-            accumulate<NCH, DT, AGG>(acc, v[u], w[u], lane, c);
+            accumulate<NCH, DT, AGG>(acc, cmp, v[u], w[u], lane, c);
             wsum += w[u];
           }
         }
@@ -324,7 +339,7 @@ __global__ __launch_bounds__(256) void k_seg_gather(MeshDev m, ProbIn in, PixDec
 #pragma unroll
     for (int ch = 0; ch < NCH; ++ch) {
       const int j = lane + 64 * ch;
-      if (j < c) acc_store<AT>(m.accum, x * c + j, old[ch] + acc[ch]);
+      if (j < c) acc_store<AT>(m.accum, x * c + j, old[ch] + (acc[ch] - cmp[ch]));
     }
     if (m.wsum && lane == 0) m.wsum[x] += wsum;
   }
@@ -354,6 +369,7 @@ __global__ __launch_bounds__(256) void k_seg_gather16(MeshDev m, ProbIn in, PixD
     const int64_t x = rows[g];
     const int s0 = start[x], s1 = start[x + 1];
     float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+    float4 cmp = make_float4(0.f, 0.f, 0.f, 0.f);   // compensation of the SUM / MAXSUM sums
     float4 old = make_float4(0.f, 0.f, 0.f, 0.f);
     if (act) {
       if constexpr (AT == 0) {
@@ -366,6 +382,9 @@ __global__ __launch_bounds__(256) void k_seg_gather16(MeshDev m, ProbIn in, PixD
     }
     float wsum = 0.0f;
     for (int k0 = s0; k0 < s1; k0 += 16) {
+      // up to 16 observations summed plainly, the chunk sums then added to the
+      // row with compensation (SUM / MAXSUM) or plainly (MUL: sums of logs)
+      float4 part = make_float4(0.f, 0.f, 0.f, 0.f);
       const int kk = k0 + gl;
       const bool okl = kk < s1;
       const uint32_t my_e = okl ? ent[kk] : 0u;
@@ -417,16 +436,28 @@ __global__ __launch_bounds__(256) void k_seg_gather16(MeshDev m, ProbIn in, PixD
             t = make_float4(t.x == mx ? t.x : 0.f, t.y == mx ? t.y : 0.f, t.z == mx ? t.z : 0.f,
                             t.w == mx ? t.w : 0.f);
           }
-          acc.x += w[u] * t.x;
-          acc.y += w[u] * t.y;
-          acc.z += w[u] * t.z;
-          acc.w += w[u] * t.w;
+          part.x += w[u] * t.x;
+          part.y += w[u] * t.y;
+          part.z += w[u] * t.z;
+          part.w += w[u] * t.w;
           wsum += w[u];
         }
       }
+      if constexpr (AGG == 1) {
+        acc.x += part.x;
+        acc.y += part.y;
+        acc.z += part.z;
+        acc.w += part.w;
+      } else {
+        kahan_add(acc.x, cmp.x, part.x);
+        kahan_add(acc.y, cmp.y, part.y);
+        kahan_add(acc.z, cmp.z, part.z);
+        kahan_add(acc.w, cmp.w, part.w);
+      }
     }
     if (act) {
-      const float4 nv4 = make_float4(old.x + acc.x, old.y + acc.y, old.z + acc.z, old.w + acc.w);
+      const float4 nv4 = make_float4(old.x + (acc.x - cmp.x), old.y + (acc.y - cmp.y), old.z + (acc.z - cmp.z),
+                                     old.w + (acc.w - cmp.w));
       if constexpr (AT == 0) {
         *reinterpret_cast<float4*>(reinterpret_cast<float*>(m.accum) + x * c + 4 * gl) = nv4;
       } else {
