@@ -77,6 +77,24 @@ def scatter_modes(probs: torch.Tensor):
     return modes
 
 
+def coordinate_descent(trial, start, sweeps, min_gain=MIN_GAIN):
+    """Sweep each (knob, values) in turn with the other knobs held; a value
+    replaces the current one only when its time is more than `min_gain`
+    (relative) below the best so far.  The gather's knobs are skipped while
+    the atomic scatter is chosen.  Returns (best configuration, its time)."""
+    best = dict(start)
+    best_ms = trial(best)
+    for knob, values in sweeps:
+        if knob in ("gather_unroll", "gather_waves") and best.get("scatter_mode") == sf.SCATTER_ATOMIC:
+            continue                            # these only affect the sorted gather
+        for v in values:
+            cand = dict(best, **{knob: v})
+            ms = trial(cand)
+            if ms < best_ms * (1.0 - min_gain):
+                best, best_ms = cand, ms
+    return best, best_ms
+
+
 def _ws_bytes(mesh, H, W, batch, weighting, mode, probs):
     n = C.c_int64()
     dt = sf.F32 if probs.dtype == torch.float32 else sf.FP8_E4M3
@@ -138,19 +156,11 @@ def autotune(mesh: sf.Mesh, cams: torch.Tensor, probs: torch.Tensor, *, scale=No
 
     modes = scatter_modes(probs)
     batches = [b for b in BATCHES if b <= max(nf, BATCHES[0])]
-    best = {"batch": min(32, batches[-1]), "scatter_mode": modes[0], "tile": 32, "small_px": 48,
-            "gather_unroll": 8, "gather_waves": 8}
-    best_ms = trial(best)
+    start = {"batch": min(32, batches[-1]), "scatter_mode": modes[0], "tile": 32, "small_px": 48,
+             "gather_unroll": 8, "gather_waves": 8}
     sweeps = [("batch", batches), ("scatter_mode", modes), ("tile", TILES), ("small_px", SMALL),
               ("gather_unroll", UNROLLS), ("gather_waves", GATHER_WAVES)]
-    for knob, values in sweeps:
-        if knob in ("gather_unroll", "gather_waves") and best["scatter_mode"] == sf.SCATTER_ATOMIC:
-            continue                            # these only affect the sorted gather
-        for v in values:
-            cand = dict(best, **{knob: v})
-            ms = trial(cand)
-            if ms < best_ms * (1.0 - MIN_GAIN):
-                best, best_ms = cand, ms
+    best, best_ms = coordinate_descent(trial, start, sweeps)
     mesh.reset()
     mesh._fws.clear()
     if not math.isfinite(best_ms):

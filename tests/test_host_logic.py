@@ -1,0 +1,75 @@
+"""Host-side logic that needs no GPU: the autotuner's coordinate descent and
+the bench's lookup of committed counter records."""
+import json
+
+import pytest
+
+import bench
+from paper_2111_11103_amd import semfuse as sf
+from paper_2111_11103_amd import tune
+
+SWEEPS = [("batch", (8, 16, 32, 64)), ("scatter_mode", (sf.SCATTER_SORTED, sf.SCATTER_ATOMIC)),
+          ("tile", (16, 32)), ("gather_unroll", (4, 8)), ("gather_waves", (8, 16, 32))]
+START = {"batch": 32, "scatter_mode": sf.SCATTER_SORTED, "tile": 32, "gather_unroll": 8, "gather_waves": 8}
+
+
+def _cost(table):
+    """Separable cost: sum of per-knob costs (a value missing from a knob's table costs 0)."""
+    calls = []
+
+    def trial(cfg):
+        calls.append(dict(cfg))
+        return 1.0 + sum(table.get(k, {}).get(v, 0.0) for k, v in cfg.items())
+    return trial, calls
+
+
+def test_descent_finds_separable_minimum():
+    trial, calls = _cost({"batch": {8: 0.5, 16: 0.3, 32: 0.2, 64: 0.0},
+                          "tile": {16: 0.0, 32: 0.1},
+                          "gather_waves": {8: 0.05, 16: 0.0, 32: 0.2}})
+    best, ms = tune.coordinate_descent(trial, START, SWEEPS, min_gain=0.01)
+    assert best == {"batch": 64, "scatter_mode": sf.SCATTER_SORTED, "tile": 16, "gather_unroll": 8,
+                    "gather_waves": 16}
+    assert ms == pytest.approx(1.0)
+    assert calls[0] == START                       # the start is timed first
+    assert len(calls) == 1 + sum(len(v) for _, v in SWEEPS)
+
+
+def test_descent_keeps_incumbent_within_noise():
+    # unroll 4 is 0.5% faster than the default 8: below the 1% threshold, kept at 8
+    trial, _ = _cost({"gather_unroll": {4: 0.0, 8: 0.005}})
+    best, _ = tune.coordinate_descent(trial, START, SWEEPS, min_gain=0.01)
+    assert best["gather_unroll"] == 8
+    best, _ = tune.coordinate_descent(trial, START, SWEEPS, min_gain=0.0)
+    assert best["gather_unroll"] == 4
+
+
+def test_descent_skips_gather_knobs_for_atomic_scatter():
+    trial, calls = _cost({"scatter_mode": {sf.SCATTER_SORTED: 0.5, sf.SCATTER_ATOMIC: 0.0}})
+    best, _ = tune.coordinate_descent(trial, START, SWEEPS, min_gain=0.01)
+    assert best["scatter_mode"] == sf.SCATTER_ATOMIC
+    # after the switch no unroll or wave candidate is timed
+    swept = [c for c in calls[1 + 4 + 2 + 2:]]
+    assert swept == []
+
+
+def _traffic_file(tmp_path, digest, records):
+    path = tmp_path / "traffic.txt"
+    path.write_text(json.dumps({"kernel": "k_seg_gather16", "source_digest": digest, "records": records}) +
+                    "\n\nnotes\n")
+    return str(path)
+
+
+def test_traffic_record_lookup(tmp_path, monkeypatch):
+    recs = [{"batch": 64, "scatter_mode": 2, "gather_unroll": 8, "gather_waves": 8, "bytes_per_px": 217.4},
+            {"batch": 32, "scatter_mode": 2, "gather_unroll": 8, "gather_waves": 8, "bytes_per_px": 216.7}]
+    digest = bench.kernel_source_digest()
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", _traffic_file(tmp_path, digest, recs))
+    launch = {"batch": 64, "scatter_mode": 2, "gather_unroll": 8, "gather_waves": 8, "tile": 16, "small_px": 12}
+    assert bench.measured_traffic(launch) == 217.4          # tile and box size do not change the gather
+    assert bench.measured_traffic(dict(launch, batch=32)) == 216.7
+    assert bench.measured_traffic(dict(launch, gather_waves=16)) is None   # no record for this launch
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", _traffic_file(tmp_path, "0" * 16, recs))
+    assert bench.measured_traffic(launch) is None           # kernel sources changed since the counters
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "missing.txt"))
+    assert bench.measured_traffic(launch) is None
