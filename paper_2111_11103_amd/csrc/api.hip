@@ -438,7 +438,6 @@ lf_status fuse_impl(const FuseArgs& a, void* d_ws, hipStream_t stream) {
   const int64_t* st = a.strides;
   ProbIn in{a.probs, a.scale, a.valid, st[0], st[1], st[2], st[3], a.dtype};
   const bool learned = a.weighting == LF_W_LEARNED;
-  int32_t* cnt = a.weighting != LF_W_PIXEL ? reinterpret_cast<int32_t*>(ws + L.cnt) : nullptr;
   float4* geo = learned ? reinterpret_cast<float4*>(ws + L.geo) : nullptr;
   float* wpix = learned ? reinterpret_cast<float*>(ws + L.wpix) : nullptr;
   // the sorted path stores batch-relative element offsets in 32 bits
@@ -446,6 +445,15 @@ lf_status fuse_impl(const FuseArgs& a, void* d_ws, hipStream_t stream) {
   const bool sorted = staged || (mode == LF_SCATTER_SORTED &&
                                  ((int64_t)(B - 1) * st[0] + (int64_t)(H - 1) * st[2] + (int64_t)(W - 1) * st[3] +
                                   (int64_t)d.c * st[1]) < ((int64_t)1 << 32));
+  // staged rows of a batch: frame stride H*W*c, row stride W*c, pixel stride c
+  auto staged_in = [&](const void* rows_p, const uint8_t* valid) {
+    return ProbIn{rows_p, nullptr, valid, HW * d.c, 1, (int64_t)W * d.c, d.c, LF_F32};
+  };
+  // w^(I) and the mixed weight on the grouped gather: it counts each row's
+  // observations per frame itself, so no per-frame count array is kept
+  const bool frame_counts = sorted && (a.weighting == LF_W_IMAGE || a.weighting == LF_W_MIX) &&
+                            seg_frame_counts_ok(d, staged ? staged_in(ws + L.stage[0], nullptr) : in, B, H, W);
+  int32_t* cnt = (a.weighting != LF_W_PIXEL && !frame_counts) ? reinterpret_cast<int32_t*>(ws + L.cnt) : nullptr;
   int32_t* seg = sorted ? reinterpret_cast<int32_t*>(ws + L.seg) : nullptr;
   LF_TRY(launch_zero(ws + L.tcnt, B * L.ntiles * 4, stream), "clear tile counts");
   if (cnt) LF_TRY(launch_zero(cnt, (int64_t)B * d.n_texels * 4, stream), "clear counts");
@@ -501,7 +509,7 @@ lf_status fuse_impl(const FuseArgs& a, void* d_ws, hipStream_t stream) {
       int32_t* rows = reinterpret_cast<int32_t*>(ws + L.rows[k]);
       int32_t* nrows = reinterpret_cast<int32_t*>(ws + L.nrows[k]);
       uint32_t* eo = reinterpret_cast<uint32_t*>(ws + L.ent_off[k]);
-      float* ew = a.weighting != LF_W_PIXEL ? reinterpret_cast<float*>(ws + L.ent_w[k]) : nullptr;
+      float* ew = (a.weighting != LF_W_PIXEL && !frame_counts) ? reinterpret_cast<float*>(ws + L.ent_w[k]) : nullptr;
       float* es = a.dtype == LF_FP8_E4M3 ? reinterpret_cast<float*>(ws + L.ent_s[k]) : nullptr;
       float* stg = staged ? reinterpret_cast<float*>(ws + L.stage[k]) : nullptr;
       // set k was last read by the gather two batches ago
@@ -511,9 +519,7 @@ lf_status fuse_impl(const FuseArgs& a, void* d_ws, hipStream_t stream) {
         LF_TRY(launch_zero(nrows, 4, stream), "clear row count");
         LF_TRY(launch_seg_scan(seg, d.n_texels, reinterpret_cast<int32_t*>(ws + L.sums), start, rows, nrows, stream),
                "segment scan");
-        // staged rows of the batch: frame stride H*W*c, row stride W*c, pixel stride c
-        const ProbIn sin{stg, nullptr, a.valid ? a.valid + (int64_t)fi * HW : nullptr, HW * d.c, 1,
-                         (int64_t)W * d.c, d.c, LF_F32};
+        const ProbIn sin = staged_in(stg, a.valid ? a.valid + (int64_t)fi * HW : nullptr);
         if (staged)
           LF_TRY(launch_seg_fill(sin, 0, nb, H, W, lb, rank, start, eo, ew, nullptr, a.weighting, cnt, d.n_texels,
                                  wpix, d.mix, stream), "segment fill");
@@ -526,8 +532,9 @@ lf_status fuse_impl(const FuseArgs& a, void* d_ws, hipStream_t stream) {
       LF_TRY(hipStreamWaitEvent(side, mesh->sorted_ev[k], 0), "wait for sort");
       {
         StageTimer tm(mesh, 2, side);
-        const ProbIn gin = staged ? ProbIn{stg, nullptr, nullptr, HW * d.c, 1, (int64_t)W * d.c, d.c, LF_F32} : in;
-        LF_TRY(launch_seg_gather(d, gin, staged ? 0 : fi, H, W, start, rows, nrows, eo, ew, es, side),
+        const ProbIn gin = staged ? staged_in(stg, nullptr) : in;
+        LF_TRY(launch_seg_gather(d, gin, staged ? 0 : fi, H, W, start, rows, nrows, eo, ew, es, nb,
+                                 frame_counts ? a.weighting : 0, d.mix, side),
                "segment gather");
       }
       LF_TRY(hipEventRecord(mesh->gathered_ev[k], side), "record gathered");

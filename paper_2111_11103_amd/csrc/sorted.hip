@@ -351,13 +351,23 @@ __global__ __launch_bounds__(256) void k_seg_gather(MeshDev m, ProbIn in, PixDec
 // instruction fetches four contiguous class vectors.  The group loads 16
 // observation offsets at once (one per lane, shuffled out) and keeps U (4 or
 // 8) observations in flight.  Groups walk the compact list of touched rows.
+//
+// Per-frame weights (frame_w = 1: w^(I) = 1 / n, 3: (1 - mix) + mix / n, with
+// n the number of pixels of the observation's frame that see the texel,
+// Section 3.3.1): a row's observations of one frame are exactly that frame's
+// pixels on the texel, so n is counted per row in an LDS histogram over the
+// batch's frames (one per group, nf counters) before the row is summed; an
+// observation's frame is its stored element offset divided by the frame
+// stride sfd.  Nothing per frame and texel is kept in device memory.
 template <int DT, int AGG, int AT, int U>
 __global__ __launch_bounds__(256) void k_seg_gather16(MeshDev m, ProbIn in, PixDecode dec,
                                                       const int32_t* __restrict__ start,
                                                       const int32_t* __restrict__ rows,
                                                       const int32_t* __restrict__ nrows,
                                                       const uint32_t* __restrict__ ent,
-                                                      const float* __restrict__ ent_w, const float* __restrict__ ent_s) {
+                                                      const float* __restrict__ ent_w, const float* __restrict__ ent_s,
+                                                      uint32_t sfd, int nf, int frame_w, float mix) {
+  extern __shared__ int fcnt[];                          // [16 groups][nf] when frame_w != 0
   const int gl = threadIdx.x & 15;                       // lane in group = class chunk
   const int64_t g0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 4;
   const int64_t ng = ((int64_t)gridDim.x * 256) >> 4;
@@ -365,9 +375,18 @@ __global__ __launch_bounds__(256) void k_seg_gather16(MeshDev m, ProbIn in, PixD
   const int nv = c >> 2;
   const bool act = gl < nv;
   const int nr = *nrows;
+  int* my_cnt = fcnt + (threadIdx.x >> 4) * nf;
+  if (frame_w) {
+    for (int i = threadIdx.x; i < 16 * nf; i += 256) fcnt[i] = 0;
+    __syncthreads();
+  }
   for (int64_t g = g0; g < nr; g += ng) {
     const int64_t x = rows[g];
     const int s0 = start[x], s1 = start[x + 1];
+    if (frame_w) {
+      for (int k = s0 + gl; k < s1; k += 16) atomicAdd(&my_cnt[ent[k] / sfd], 1);
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");   // the row's counts before they are read
+    }
     float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
     float4 cmp = make_float4(0.f, 0.f, 0.f, 0.f);   // compensation of the SUM / MAXSUM sums
     float4 old = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -388,7 +407,13 @@ __global__ __launch_bounds__(256) void k_seg_gather16(MeshDev m, ProbIn in, PixD
       const int kk = k0 + gl;
       const bool okl = kk < s1;
       const uint32_t my_e = okl ? ent[kk] : 0u;
-      const float my_w = okl ? (ent_w ? ent_w[kk] : 1.0f) : 0.0f;
+      float my_w;
+      if (frame_w) {
+        const float n = okl ? (float)my_cnt[my_e / sfd] : 1.0f;
+        my_w = okl ? (frame_w == 1 ? 1.0f / n : (1.0f - mix) + mix / n) : 0.0f;
+      } else {
+        my_w = okl ? (ent_w ? ent_w[kk] : 1.0f) : 0.0f;
+      }
       const float my_s = (DT == 3 && okl) ? ent_s[kk] : 1.0f;
       const int cnt = min(16, s1 - k0);
       for (int h = 0; h < cnt; h += U) {
@@ -469,24 +494,42 @@ __global__ __launch_bounds__(256) void k_seg_gather16(MeshDev m, ProbIn in, PixD
       }
     }
     if (m.wsum && gl == 0) m.wsum[x] += wsum;
+    if (frame_w) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");   // every read of the row's counts first
+      for (int i = gl; i < nf; i += 16) my_cnt[i] = 0;
+    }
   }
+}
+
+constexpr int kCountFrames = 256;   // frames per batch the gather's frame counters cover (16 KB of LDS)
+
+// 4-class chunks of contiguous classes: 16-byte (FP32) / 4-byte (E4M3) aligned
+static bool grouped_ok(const MeshDev& m, const ProbIn& in) {
+  const int64_t esz = in.dtype == 0 ? 4 : 1;
+  const int64_t chunk = 4 * esz;
+  return in.sc == 1 && m.c <= 64 && (m.c % 4) == 0 && (reinterpret_cast<uintptr_t>(in.p) % chunk) == 0 &&
+         ((in.sf * esz) % chunk) == 0 && ((in.sy * esz) % chunk) == 0 && ((in.sx * esz) % chunk) == 0 &&
+         (reinterpret_cast<uintptr_t>(m.accum) % 16) == 0;
+}
+
+// The frame of a stored offset fb * sf + y * sy + x * sx is offset / sf when
+// every pixel's offset within a frame is below the frame stride.
+bool seg_frame_counts_ok(const MeshDev& m, const ProbIn& in, int nf, int H, int W) {
+  if (!grouped_ok(m, in) || nf < 1 || nf > kCountFrames) return false;
+  return nf == 1 || (in.sf > (int64_t)(H - 1) * in.sy + (int64_t)(W - 1) * in.sx && in.sf < ((int64_t)1 << 32));
 }
 
 hipError_t launch_seg_gather(const MeshDev& m, const ProbIn& in, int f_first, int H, int W, const int32_t* start,
                              const int32_t* rows, const int32_t* nrows, const uint32_t* ent, const float* ent_w,
-                             const float* ent_s, hipStream_t s) {
+                             const float* ent_s, int nf, int frame_w, float mix, hipStream_t s) {
   if (m.n_texels == 0) return hipSuccess;
-  (void)H;
-  (void)W;
+  if (frame_w && ((frame_w != 1 && frame_w != 3) || !seg_frame_counts_ok(m, in, nf, H, W)))
+    return hipErrorInvalidValue;
   const PixDecode dec{(int64_t)f_first * in.sf};
-  // 4-class chunks of contiguous classes: 16-byte (FP32) / 4-byte (E4M3) aligned
-  const int64_t esz = in.dtype == 0 ? 4 : 1;
-  const int64_t chunk = 4 * esz;
-  const bool grouped = in.sc == 1 && m.c <= 64 && (m.c % 4) == 0 &&
-                       (reinterpret_cast<uintptr_t>(in.p) % chunk) == 0 && ((in.sf * esz) % chunk) == 0 &&
-                       ((in.sy * esz) % chunk) == 0 && ((in.sx * esz) % chunk) == 0 &&
-                       (reinterpret_cast<uintptr_t>(m.accum) % 16) == 0;
+  const bool grouped = grouped_ok(m, in);
   if (grouped) {
+    const uint32_t sfd = nf > 1 ? (uint32_t)in.sf : 0xffffffffu;   // every stored offset is below 2^32 - 1
+    const size_t lds = frame_w ? (size_t)16 * nf * 4 : 0;
     // enough resident groups to cover the machine; each walks the row list
     // grid: gather_waves resident waves (4 row groups each) on each of the 256 CUs
     const int64_t groups = std::min<int64_t>(m.n_texels, (int64_t)256 * m.gather_waves * 4);
@@ -494,9 +537,11 @@ hipError_t launch_seg_gather(const MeshDev& m, const ProbIn& in, int f_first, in
 #define LF_R(DT, AGG, AT)                                                                                    \
   do {                                                                                                       \
     if (m.gather_unroll == 4)                                                                                \
-      k_seg_gather16<DT, AGG, AT, 4><<<g, 256, 0, s>>>(m, in, dec, start, rows, nrows, ent, ent_w, ent_s);   \
+      k_seg_gather16<DT, AGG, AT, 4><<<g, 256, lds, s>>>(m, in, dec, start, rows, nrows, ent, ent_w, ent_s,  \
+                                                         sfd, nf, frame_w, mix);                            \
     else                                                                                                     \
-      k_seg_gather16<DT, AGG, AT, 8><<<g, 256, 0, s>>>(m, in, dec, start, rows, nrows, ent, ent_w, ent_s);   \
+      k_seg_gather16<DT, AGG, AT, 8><<<g, 256, lds, s>>>(m, in, dec, start, rows, nrows, ent, ent_w, ent_s,  \
+                                                         sfd, nf, frame_w, mix);                            \
   } while (0)
 #define LF_R2(DT)                                                                                            \
   do {                                                                                                       \
