@@ -87,9 +87,18 @@ struct WaveLds {
   float* logit;    // [64]
 };
 
+// Orders the LDS exchanges between the lanes of one wave: the LDS performs a
+// wave's operations in issue order, so only the compiler has to keep them in
+// program order (fences and a wave-level scheduling barrier).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Evaluate the network for the 64 observations of a wave (lane = observation).
-// Must be reached by every thread of the block (it synchronises the block
-// around the LDS exchanges between lanes).
+// Every lane of the wave must reach it; L is the wave's own LDS, so waves do
+// not wait for each other.
 __device__ float mlp_wave(const float (&phi)[NI], const MlpW& W, const WaveLds& L) {
   const int lane = threadIdx.x & 63;
   const int col = lane & 15, grp = lane >> 4;
@@ -106,7 +115,7 @@ __device__ float mlp_wave(const float (&phi)[NI], const MlpW& W, const WaveLds& 
     }
     bw1[n] = t;
   }
-  __syncthreads();
+  wave_lds_sync();
   // layer 1: h1[sample][unit] for 4 sample tiles x 4 unit tiles
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
@@ -127,7 +136,7 @@ __device__ float mlp_wave(const float (&phi)[NI], const MlpW& W, const WaveLds& 
       }
     }
   }
-  __syncthreads();
+  wave_lds_sync();
   // layer 2 + output layer
   float part[4][4];
 #pragma unroll
@@ -167,7 +176,7 @@ __device__ float mlp_wave(const float (&phi)[NI], const MlpW& W, const WaveLds& 
       for (int o = 8; o > 0; o >>= 1) v += __shfl_xor(v, o, 16);
       if (col == 0) L.logit[t * 16 + 4 * grp + r] = v + W.b3[0];
     }
-  __syncthreads();
+  wave_lds_sync();
   const float z = L.logit[lane];
   return 1.0f / (1.0f + expf(-z));
 }
@@ -280,9 +289,10 @@ __device__ __forceinline__ void observation_features(const ProbIn& in, int64_t b
 }
 
 // Fused inference during fusion: weight of every valid covered pixel of the
-// batch (0 elsewhere).
+// batch (0 elsewhere).  The LDS of a block admits four waves per SIMD; the
+// register budget is held to that occupancy (no AGPR overflow, no spills).
 template <int DT>
-__global__ __launch_bounds__(256) void k_mlp_weights(const void* __restrict__ packed, ProbIn in, int f_first, int H,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_mlp_weights(const void* __restrict__ packed, ProbIn in, int f_first, int H,
                                                      int W, const float* __restrict__ cams,
                                                      const int32_t* __restrict__ lbuf, const float4* __restrict__ geo,
                                                      const int32_t* __restrict__ cnt, int64_t cnt_stride, int c,
