@@ -454,6 +454,8 @@ lf_status fuse_impl(const FuseArgs& a, void* d_ws, hipStream_t stream) {
   const bool frame_counts = sorted && (a.weighting == LF_W_IMAGE || a.weighting == LF_W_MIX) &&
                             seg_frame_counts_ok(d, staged ? staged_in(ws + L.stage[0], nullptr) : in, B, H, W);
   int32_t* cnt = (a.weighting != LF_W_PIXEL && !frame_counts) ? reinterpret_cast<int32_t*>(ws + L.cnt) : nullptr;
+  // E4M3 with pixels dense in the input: the gather reads the scales itself
+  const bool scale_direct = sorted && !staged && seg_scale_direct_ok(d, in, B, H, W);
   int32_t* seg = sorted ? reinterpret_cast<int32_t*>(ws + L.seg) : nullptr;
   LF_TRY(launch_zero(ws + L.tcnt, B * L.ntiles * 4, stream), "clear tile counts");
   if (cnt) LF_TRY(launch_zero(cnt, (int64_t)B * d.n_texels * 4, stream), "clear counts");
@@ -510,7 +512,7 @@ lf_status fuse_impl(const FuseArgs& a, void* d_ws, hipStream_t stream) {
       int32_t* nrows = reinterpret_cast<int32_t*>(ws + L.nrows[k]);
       uint32_t* eo = reinterpret_cast<uint32_t*>(ws + L.ent_off[k]);
       float* ew = (a.weighting != LF_W_PIXEL && !frame_counts) ? reinterpret_cast<float*>(ws + L.ent_w[k]) : nullptr;
-      float* es = a.dtype == LF_FP8_E4M3 ? reinterpret_cast<float*>(ws + L.ent_s[k]) : nullptr;
+      float* es = (a.dtype == LF_FP8_E4M3 && !scale_direct) ? reinterpret_cast<float*>(ws + L.ent_s[k]) : nullptr;
       float* stg = staged ? reinterpret_cast<float*>(ws + L.stage[k]) : nullptr;
       // set k was last read by the gather two batches ago
       if (nbatch >= 2) LF_TRY(hipStreamWaitEvent(stream, mesh->gathered_ev[k], 0), "wait for gather");

@@ -111,6 +111,10 @@ hipError_t launch_seg_gather(const MeshDev& m, const ProbIn& in, int f_first, in
 // each observation's frame from its stored element offset and count frames
 // itself.
 bool seg_frame_counts_ok(const MeshDev& m, const ProbIn& in, int nf, int H, int W);
+// Whether the gather of E4M3 input `in` can read each observation's scale
+// from the input's scale array itself (then the fill stores no scales and
+// ent_s is passed as nullptr).
+bool seg_scale_direct_ok(const MeshDev& m, const ProbIn& in, int nf, int H, int W);
 hipError_t launch_render(const int32_t* l, const uint8_t* valid, const uint8_t* labels, int64_t npx,
                          uint8_t* out, hipStream_t s);
 

@@ -4,7 +4,8 @@ itself (LDS counters) instead of reading per-frame counts written by the
 raster: parity with the oracle for ragged batches, one-frame batches, FP8
 input, planar input through the staged path, rows of several hundred thousand
 observations, and a frame-innermost layout whose frames cannot be recovered
-from the stored offsets (that one takes the per-frame count array)."""
+from the stored offsets (that one takes the per-frame count array).  Also the
+E4M3 scales the same gather reads from the input's scale array."""
 import numpy as np
 import pytest
 import torch
@@ -139,3 +140,27 @@ def test_image_weight_on_very_long_rows():
         _check_wsum(gm, W_o, l_o, valid.numpy())
     # every frame adds weight 1 to each texel it sees: W = number of frames
     assert np.allclose(W_o, 3.0)
+
+
+@pytest.mark.parametrize("layout", ["nhwc", "frame_innermost"])
+def test_fp8_scales_read_by_gather(case, layout):
+    """E4M3 input on the grouped gather: with pixels dense in the input
+    (channels-last) the gather reads each observation's scale from the
+    [F][H][W] scale array itself; the frame-innermost layout keeps the
+    per-entry scales written by the fill.  Both equal the oracle."""
+    w, probs, om, l_o = case
+    say(f"  FP8 w^(P), {layout}")
+    sc = w.scene
+    valid = w.valid.numpy()
+    q, scale = S.quantize_fp8(probs)
+    A8, _ = oracle.fuse(om.n_texels, C, l_o, q.numpy(), valid, scale=scale.numpy())
+    if layout == "nhwc":
+        x = q.to(memory_format=torch.channels_last).cuda()
+    else:
+        x = q.permute(2, 3, 0, 1).contiguous().permute(2, 3, 0, 1).cuda()
+    for batch in (7, 1):
+        gm = gpu_mesh((sc.vertices, sc.faces), 1, oracle.SPLIT, C)
+        gm.fuse_frames(to_dev(w.cams, torch.float32), x, scale=scale.cuda(), valid=w.valid.cuda(), batch=batch,
+                       scatter_mode=sf.SCATTER_SORTED)
+        torch.cuda.synchronize()
+        compare_fused(gm.accum.cpu().numpy(), A8)
