@@ -178,7 +178,8 @@ FrameLayout frame_layout(const MeshDev& m, int H, int W, int B, int weighting, i
   L.l = o; o += align256(B * HW * 4);
   L.cnt = o; if (weighting != LF_W_PIXEL) o += align256(B * m.n_texels * 4);
   L.geo = o; if (weighting == LF_W_LEARNED) o += align256(B * HW * 16);
-  L.wpix = o; if (weighting == LF_W_LEARNED) o += align256(B * HW * 4);
+  // learned weights: two sets on the sorted path, whose gather reads them in place
+  L.wpix = o; if (weighting == LF_W_LEARNED) o += align256((L.sorted ? 2 : 1) * B * HW * 4);
   L.seg = o; if (L.sorted) o += align256(m.n_texels * 4);
   L.rank = o; if (L.sorted) o += align256(B * HW * 4);
   L.sums = o; if (L.sorted) o += align256((m.n_texels / 8192 + 2) * 4);
@@ -439,7 +440,7 @@ lf_status fuse_impl(const FuseArgs& a, void* d_ws, hipStream_t stream) {
   ProbIn in{a.probs, a.scale, a.valid, st[0], st[1], st[2], st[3], a.dtype};
   const bool learned = a.weighting == LF_W_LEARNED;
   float4* geo = learned ? reinterpret_cast<float4*>(ws + L.geo) : nullptr;
-  float* wpix = learned ? reinterpret_cast<float*>(ws + L.wpix) : nullptr;
+  float* wpix_sets = learned ? reinterpret_cast<float*>(ws + L.wpix) : nullptr;   // [1 or 2][B][H][W]
   // the sorted path stores batch-relative element offsets in 32 bits
   const bool staged = mode == LF_SCATTER_STAGED && (int64_t)B * HW * d.c < ((int64_t)1 << 32);
   const bool sorted = staged || (mode == LF_SCATTER_SORTED &&
@@ -454,8 +455,10 @@ lf_status fuse_impl(const FuseArgs& a, void* d_ws, hipStream_t stream) {
   const bool frame_counts = sorted && (a.weighting == LF_W_IMAGE || a.weighting == LF_W_MIX) &&
                             seg_frame_counts_ok(d, staged ? staged_in(ws + L.stage[0], nullptr) : in, B, H, W);
   int32_t* cnt = (a.weighting != LF_W_PIXEL && !frame_counts) ? reinterpret_cast<int32_t*>(ws + L.cnt) : nullptr;
-  // E4M3 with pixels dense in the input: the gather reads the scales itself
-  const bool scale_direct = sorted && !staged && seg_scale_direct_ok(d, in, B, H, W);
+  // pixels dense in the gather's input: it reads E4M3 scales and the learned
+  // weight by pixel index itself, and the fill copies neither
+  const bool pix_direct =
+      sorted && seg_pixels_dense_ok(d, staged ? staged_in(ws + L.stage[0], nullptr) : in, B, H, W);
   int32_t* seg = sorted ? reinterpret_cast<int32_t*>(ws + L.seg) : nullptr;
   LF_TRY(launch_zero(ws + L.tcnt, B * L.ntiles * 4, stream), "clear tile counts");
   if (cnt) LF_TRY(launch_zero(cnt, (int64_t)B * d.n_texels * 4, stream), "clear counts");
@@ -500,19 +503,23 @@ lf_status fuse_impl(const FuseArgs& a, void* d_ws, hipStream_t stream) {
     if (seg) LF_TRY(launch_zero(seg, d.n_texels * 4, stream), "clear segments");
     RasterOut out{lb, nullptr, nullptr, vb, cnt, d.n_texels, seg, rank, geo};
     if ((status = render_batch(mesh, a.cams, f0, nb, H, W, L, ws, out, stream)) != LF_OK) return status;
+    const int k = nbatch & 1;   // sorted path: buffer set of this batch
+    float* wpix = learned ? wpix_sets + (sorted ? (int64_t)k * B * HW : 0) : nullptr;
     if (learned) {
+      // weight set k may still be read by the gather two batches back
+      if (sorted && nbatch >= 2) LF_TRY(hipStreamWaitEvent(stream, mesh->gathered_ev[k], 0), "wait for gather");
       StageTimer tm(mesh, 7, stream);
       LF_TRY(launch_mlp_weights(mesh->mlp, in, fi, nb, H, W, cams_in, lb, geo, cnt, d.n_texels, d.c, wpix, stream),
              "learned weights");
     }
     if (sorted) {
-      const int k = nbatch & 1;
       int32_t* start = reinterpret_cast<int32_t*>(ws + L.start[k]);
       int32_t* rows = reinterpret_cast<int32_t*>(ws + L.rows[k]);
       int32_t* nrows = reinterpret_cast<int32_t*>(ws + L.nrows[k]);
       uint32_t* eo = reinterpret_cast<uint32_t*>(ws + L.ent_off[k]);
-      float* ew = (a.weighting != LF_W_PIXEL && !frame_counts) ? reinterpret_cast<float*>(ws + L.ent_w[k]) : nullptr;
-      float* es = (a.dtype == LF_FP8_E4M3 && !scale_direct) ? reinterpret_cast<float*>(ws + L.ent_s[k]) : nullptr;
+      float* ew = (a.weighting != LF_W_PIXEL && !frame_counts && !(learned && pix_direct))
+                      ? reinterpret_cast<float*>(ws + L.ent_w[k]) : nullptr;
+      float* es = (a.dtype == LF_FP8_E4M3 && !pix_direct) ? reinterpret_cast<float*>(ws + L.ent_s[k]) : nullptr;
       float* stg = staged ? reinterpret_cast<float*>(ws + L.stage[k]) : nullptr;
       // set k was last read by the gather two batches ago
       if (nbatch >= 2) LF_TRY(hipStreamWaitEvent(stream, mesh->gathered_ev[k], 0), "wait for gather");
@@ -536,7 +543,8 @@ lf_status fuse_impl(const FuseArgs& a, void* d_ws, hipStream_t stream) {
         StageTimer tm(mesh, 2, side);
         const ProbIn gin = staged ? staged_in(stg, nullptr) : in;
         LF_TRY(launch_seg_gather(d, gin, staged ? 0 : fi, H, W, start, rows, nrows, eo, ew, es, nb,
-                                 frame_counts ? a.weighting : 0, d.mix, side),
+                                 frame_counts ? a.weighting : 0, d.mix, (learned && pix_direct) ? wpix : nullptr,
+                                 side),
                "segment gather");
       }
       LF_TRY(hipEventRecord(mesh->gathered_ev[k], side), "record gathered");

@@ -100,21 +100,24 @@ hipError_t launch_seg_fill(const ProbIn& in, int f_first, int nf, int H, int W, 
 // c floats: staging[(f - f_first) * H * W + p][j] (c % 4 == 0, c <= 60).
 hipError_t launch_planar_rows(const ProbIn& in, int f_first, int nf, int H, int W, int c, float* staging,
                               hipStream_t s);
-// Weights of the batch's observations: from ent_w (or 1) when frame_w is 0;
-// with frame_w = LF_W_IMAGE or LF_W_MIX the gather counts every row's
-// observations per frame of the nf-frame batch itself (only where
-// seg_frame_counts_ok holds).
+// Weights of the batch's observations: from ent_w (or 1) when frame_w is 0
+// and wpix is null; with frame_w = LF_W_IMAGE or LF_W_MIX the gather counts
+// every row's observations per frame of the nf-frame batch itself (only where
+// seg_frame_counts_ok holds); with wpix ([nf][H][W] per-pixel weights) it
+// reads them by pixel index, as it reads E4M3 scales when ent_s is null (only
+// where seg_pixels_dense_ok holds).
 hipError_t launch_seg_gather(const MeshDev& m, const ProbIn& in, int f_first, int H, int W, const int32_t* start,
                              const int32_t* rows, const int32_t* nrows, const uint32_t* ent_pix, const float* ent_w,
-                             const float* ent_s, int nf, int frame_w, float mix, hipStream_t s);
+                             const float* ent_s, int nf, int frame_w, float mix, const float* wpix,
+                             hipStream_t s);
 // Whether the gather of input `in` (batches of at most nf frames) can recover
 // each observation's frame from its stored element offset and count frames
 // itself.
 bool seg_frame_counts_ok(const MeshDev& m, const ProbIn& in, int nf, int H, int W);
-// Whether the gather of E4M3 input `in` can read each observation's scale
-// from the input's scale array itself (then the fill stores no scales and
-// ent_s is passed as nullptr).
-bool seg_scale_direct_ok(const MeshDev& m, const ProbIn& in, int nf, int H, int W);
+// Whether the gather of input `in` can recover each observation's pixel
+// index from its stored offset, to read E4M3 scales and per-pixel weights by
+// it (then the fill stores neither).
+bool seg_pixels_dense_ok(const MeshDev& m, const ProbIn& in, int nf, int H, int W);
 hipError_t launch_render(const int32_t* l, const uint8_t* valid, const uint8_t* labels, int64_t npx,
                          uint8_t* out, hipStream_t s);
 

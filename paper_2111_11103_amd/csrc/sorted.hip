@@ -360,9 +360,11 @@ __global__ __launch_bounds__(256) void k_seg_gather(MeshDev m, ProbIn in, PixDec
 // observation's frame is its stored element offset divided by the frame
 // stride sfd.  Nothing per frame and texel is kept in device memory.
 //
-// E4M3 scales: from ent_s (one per entry, written by the fill), or, when
-// spix != 0 (pixels dense in the input: offset = pixel index * spix), read
-// from the input's own [F][H][W] scale array at sbase + offset / spix.
+// Pixels dense in the input (spix != 0: a stored offset is spix times the
+// batch-relative pixel index): E4M3 scales are read from the input's own
+// [F][H][W] scale array at sbase + index, and per-pixel weights (wpix, the
+// learned weight, [B][H][W]) at the index, instead of from ent_s / ent_w
+// copies written by the fill.
 template <int DT, int AGG, int AT, int U>
 __global__ __launch_bounds__(256) void k_seg_gather16(MeshDev m, ProbIn in, PixDecode dec,
                                                       const int32_t* __restrict__ start,
@@ -371,7 +373,7 @@ __global__ __launch_bounds__(256) void k_seg_gather16(MeshDev m, ProbIn in, PixD
                                                       const uint32_t* __restrict__ ent,
                                                       const float* __restrict__ ent_w, const float* __restrict__ ent_s,
                                                       uint32_t sfd, int nf, int frame_w, float mix, uint32_t spix,
-                                                      int64_t sbase) {
+                                                      int64_t sbase, const float* __restrict__ wpix) {
   extern __shared__ int fcnt[];                          // [16 groups][nf] when frame_w != 0
   const int gl = threadIdx.x & 15;                       // lane in group = class chunk
   const int64_t g0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 4;
@@ -412,16 +414,19 @@ __global__ __launch_bounds__(256) void k_seg_gather16(MeshDev m, ProbIn in, PixD
       const int kk = k0 + gl;
       const bool okl = kk < s1;
       const uint32_t my_e = okl ? ent[kk] : 0u;
+      const uint32_t my_p = spix ? my_e / spix : 0u;   // batch-relative pixel index
       float my_w;
       if (frame_w) {
         const float n = okl ? (float)my_cnt[my_e / sfd] : 1.0f;
         my_w = okl ? (frame_w == 1 ? 1.0f / n : (1.0f - mix) + mix / n) : 0.0f;
+      } else if (wpix) {
+        my_w = okl ? wpix[my_p] : 0.0f;
       } else {
         my_w = okl ? (ent_w ? ent_w[kk] : 1.0f) : 0.0f;
       }
       float my_s = 1.0f;
       if constexpr (DT == 3) {
-        if (okl) my_s = spix ? in.scale[sbase + my_e / spix] : ent_s[kk];
+        if (okl) my_s = spix ? in.scale[sbase + my_p] : ent_s[kk];
       }
       const int cnt = min(16, s1 - k0);
       for (int h = 0; h < cnt; h += U) {
@@ -529,21 +534,23 @@ bool seg_frame_counts_ok(const MeshDev& m, const ProbIn& in, int nf, int H, int 
 
 // A stored offset fb * sf + y * sy + x * sx is sx times the batch-relative
 // pixel index (fb * H + y) * W + x when sy = W * sx and sf = H * W * sx.
-bool seg_scale_direct_ok(const MeshDev& m, const ProbIn& in, int nf, int H, int W) {
-  if (in.dtype != 3 || !in.scale || !grouped_ok(m, in) || in.sx < 1 || in.sx >= ((int64_t)1 << 32)) return false;
+bool seg_pixels_dense_ok(const MeshDev& m, const ProbIn& in, int nf, int H, int W) {
+  if (!grouped_ok(m, in) || in.sx < 1 || in.sx >= ((int64_t)1 << 32)) return false;
   return in.sy == (int64_t)W * in.sx && (nf == 1 || in.sf == (int64_t)H * W * in.sx);
 }
 
 hipError_t launch_seg_gather(const MeshDev& m, const ProbIn& in, int f_first, int H, int W, const int32_t* start,
                              const int32_t* rows, const int32_t* nrows, const uint32_t* ent, const float* ent_w,
-                             const float* ent_s, int nf, int frame_w, float mix, hipStream_t s) {
+                             const float* ent_s, int nf, int frame_w, float mix, const float* wpix,
+                             hipStream_t s) {
   if (m.n_texels == 0) return hipSuccess;
   if (frame_w && ((frame_w != 1 && frame_w != 3) || !seg_frame_counts_ok(m, in, nf, H, W)))
     return hipErrorInvalidValue;
-  // E4M3 without per-entry scales: read them from the input's scale array
-  const bool scale_direct = in.dtype == 3 && !ent_s;
-  if (scale_direct && !seg_scale_direct_ok(m, in, nf, H, W)) return hipErrorInvalidValue;
-  const uint32_t spix = scale_direct ? (uint32_t)in.sx : 0u;
+  // E4M3 without per-entry scales, or per-pixel weights: read by pixel index
+  const bool direct = (in.dtype == 3 && !ent_s) || wpix;
+  if (direct && ((in.dtype == 3 && !in.scale) || (frame_w && wpix) || !seg_pixels_dense_ok(m, in, nf, H, W)))
+    return hipErrorInvalidValue;
+  const uint32_t spix = direct ? (uint32_t)in.sx : 0u;
   const int64_t sbase = (int64_t)f_first * H * W;
   const PixDecode dec{(int64_t)f_first * in.sf};
   const bool grouped = grouped_ok(m, in);
@@ -558,10 +565,10 @@ hipError_t launch_seg_gather(const MeshDev& m, const ProbIn& in, int f_first, in
   do {                                                                                                       \
     if (m.gather_unroll == 4)                                                                                \
       k_seg_gather16<DT, AGG, AT, 4><<<g, 256, lds, s>>>(m, in, dec, start, rows, nrows, ent, ent_w, ent_s,  \
-                                                         sfd, nf, frame_w, mix, spix, sbase);               \
+                                                         sfd, nf, frame_w, mix, spix, sbase, wpix);         \
     else                                                                                                     \
       k_seg_gather16<DT, AGG, AT, 8><<<g, 256, lds, s>>>(m, in, dec, start, rows, nrows, ent, ent_w, ent_s,  \
-                                                         sfd, nf, frame_w, mix, spix, sbase);               \
+                                                         sfd, nf, frame_w, mix, spix, sbase, wpix);         \
   } while (0)
 #define LF_R2(DT)                                                                                            \
   do {                                                                                                       \

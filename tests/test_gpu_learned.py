@@ -214,6 +214,44 @@ def test_learned_fusion_matches_oracle(scene, mode):
     assert float((lab_g[seen] == lab_o[seen]).mean()) >= 0.99
 
 
+@pytest.mark.parametrize("layout", ["nhwc", "staged"])
+def test_learned_fusion_on_grouped_gather(scene, layout):
+    """c = 16 (classes in 4-class chunks): the texel-sorted gather reads each
+    observation's inferred weight from the per-pixel weight array by pixel
+    index (channels-last input, and planar input staged as rows), over two
+    alternating weight sets; batches of 2 and 4 frames (3 and 2 batches).
+    Same bound as the fusion test above."""
+    w, om, l_o, _, lab = scene
+    sc = w.scene
+    c = 16
+    g = torch.Generator().manual_seed(77)
+    probs = torch.softmax(2.0 * torch.randn((len(w.cams), c, w.H, w.W), generator=g), 1)
+    p = _params(7)
+    phi_o, _, pix_o = _oracle_features(w, om, lab, probs=probs.numpy())
+    wts = omlp.forward(p, phi_o).astype(np.float32)
+    wpix = np.zeros(l_o.shape, np.float32).reshape(-1)
+    wpix[pix_o] = wts
+    A_o, W_o = oracle.fuse(om.n_texels, c, l_o, probs.numpy(), w.valid.numpy(), weighting=oracle.W_GIVEN,
+                           wpix=wpix.reshape(l_o.shape))
+    A_plain, _ = oracle.fuse(om.n_texels, c, l_o, probs.numpy(), w.valid.numpy())
+    x = probs.to(memory_format=torch.channels_last).cuda() if layout == "nhwc" else probs.cuda()
+    mode = sf.SCATTER_SORTED if layout == "nhwc" else sf.SCATTER_STAGED
+    mlp = sf.WeightMLP("cuda", torch.from_numpy(p))
+    for batch in (2, 4):
+        say(f"  learned weight, {layout}, batch {batch}")
+        gm = gpu_mesh((sc.vertices, sc.faces), 1, oracle.SPLIT, c)
+        gm.bind_mlp(mlp)
+        gm.fuse_frames(to_dev(w.cams, torch.float32), x, valid=w.valid.cuda(), weighting=sf.W_LEARNED,
+                       scatter_mode=mode, batch=batch)
+        A = gm.accum.cpu().numpy().astype(np.float64)
+        delta = 5e-3
+        err = np.abs(A - A_o)
+        assert np.all(err <= 1e-5 * np.abs(A_o) + delta * A_plain + 1e-30)
+        rel_row = (err / np.maximum(np.abs(A_o), 1e-30)).max(1)
+        seen = W_o > 0
+        assert float((rel_row[seen] <= 1e-5).mean()) >= 0.5
+
+
 def test_training_and_heldout_gain():
     """Train on 50 seeded scenes (seeds 100-149, view-dependent noise) with the
     project's kernels, then fuse 10 held-out scenes (seeds 200-209) with the
