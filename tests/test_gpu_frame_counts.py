@@ -164,3 +164,37 @@ def test_fp8_scales_read_by_gather(case, layout):
                        scatter_mode=sf.SCATTER_SORTED)
         torch.cuda.synchronize()
         compare_fused(gm.accum.cpu().numpy(), A8)
+
+
+def test_large_batches_and_pooled_fp8(case):
+    """The 20 frames repeated 15 times (300 frames): by linearity the fused
+    sums are 15 times those of the 20 distinct frames (w^(I) weights repeat
+    with their frames).  Batches of 300 frames exceed the gather's 256 frame
+    counters, so w^(I) takes the per-frame count array; batches of 64 count
+    in the gather.  The same 300 frames as a scene job over an input pool of
+    the 20 FP8 frames (frame f reads input f % 20): the gather reads each
+    scale at the pooled input frame."""
+    w, probs, om, l_o = case
+    sc = w.scene
+    valid = w.valid.numpy()
+    rep = 15
+    cams = to_dev(np.concatenate([w.cams] * rep), torch.float32)
+    A_o, W_o = oracle.fuse(om.n_texels, C, l_o, probs.numpy(), valid, weighting=sf.W_IMAGE)
+    x = probs.cuda().repeat(rep, 1, 1, 1).contiguous(memory_format=torch.channels_last)
+    v = w.valid.cuda().repeat(rep, 1, 1)
+    for batch in (300, 64):
+        say(f"  w^(I), 300 frames, batch {batch}")
+        gm = gpu_mesh((sc.vertices, sc.faces), 1, oracle.SPLIT, C)
+        gm.fuse_frames(cams, x, valid=v, weighting=sf.W_IMAGE, batch=batch, scatter_mode=sf.SCATTER_SORTED)
+        torch.cuda.synchronize()
+        compare_fused(gm.accum.cpu().numpy(), rep * A_o)
+    del x, v
+    say("  FP8 w^(P), 300 frames from a pool of 20, batch 64")
+    q, scale = S.quantize_fp8(probs)
+    A8, _ = oracle.fuse(om.n_texels, C, l_o, q.numpy(), valid, scale=scale.numpy())
+    gm = gpu_mesh((sc.vertices, sc.faces), 1, oracle.SPLIT, C)
+    job = gm.job(cams, q.to(memory_format=torch.channels_last).cuda(), scale=scale.cuda(), valid=w.valid.cuda(),
+                 pool=len(w.cams), batch=64, scatter_mode=sf.SCATTER_SORTED)
+    sf.fuse_batch([job])
+    torch.cuda.synchronize()
+    compare_fused(gm.accum.cpu().numpy(), rep * A8)
