@@ -2,16 +2,19 @@
 // point atomics: every batch of frames is counting-sorted by texel row, then
 // one wave owns each touched row and adds all of the batch's observations of
 // it in registers before a single read-modify-write of the row.
-//   k_seg_scan*   exclusive scan of the per-row observation counts (counted
-//                 while resolving the frames) -> segment starts;
-//   k_seg_fill    every valid covered pixel claims a slot in its row's
-//                 segment (atomic down-count, which also returns the counts
-//                 to zero) and stores the element offset of its class-0 value
-//                 and, when needed, its weight and FP8 scale;
-//   k_seg_gather  one wave per 64 consecutive rows, lanes = classes: for each
-//                 non-empty row, stream its observations (a contiguous 4c-byte
-//                 read per observation when classes are innermost), sum
-//                 w * f(p) in registers, then update the row once.
+//   k_seg_scan*   exclusive scan of the per-row observation counts (counted,
+//                 with every pixel's rank in its row, while resolving the
+//                 frames) -> segment starts and the list of touched rows;
+//   k_seg_fill    every valid covered pixel writes, at its row's start plus
+//                 its rank, the element offset of its class-0 value and,
+//                 where the gather cannot find them itself, its weight and
+//                 FP8 scale;
+//   k_planar_rows planar (NCHW) frames transposed to pixel-major rows first;
+//   k_seg_gather16  16 lanes per touched row (4 classes each, c <= 64,
+//                 contiguous classes): stream the row's observations, sum
+//                 w * f(p) in registers, then update the row once;
+//   k_seg_gather  one wave per 64 consecutive rows, lanes = classes (any c,
+//                 any strides).
 // Rows touched by many frames of a batch are read and written once per
 // batch instead of once per pixel.
 #include <algorithm>
@@ -64,51 +67,70 @@ __global__ __launch_bounds__(1024) void k_seg_scan_sums(int32_t* __restrict__ su
 }
 
 // Also appends every row with observations to a compact list (one global
-// atomic per block) so the gather visits only touched rows.
+// atomic per block) so the gather visits only touched rows.  A thread scans
+// 32 consecutive rows; the block's counts and starts pass through LDS
+// (padded rows of 33 words: conflict-free both ways) so that the global
+// reads and writes are coalesced.
+constexpr int kSegPer = kSegChunk / 256;   // rows per thread
+constexpr int kSegPad = kSegPer + 1;
+
 __global__ __launch_bounds__(256) void k_seg_scan(const int32_t* __restrict__ cnt, int64_t n,
                                                   const int32_t* __restrict__ sums, int32_t* __restrict__ start,
                                                   int32_t* __restrict__ rows, int32_t* __restrict__ nrows) {
+  __shared__ int sv[256 * kSegPad];
   __shared__ int part[256];
   __shared__ int zpart[256];
   __shared__ int zbase;
-  constexpr int per = kSegChunk / 256;
-  const int64_t base = (int64_t)blockIdx.x * kSegChunk + (int64_t)threadIdx.x * per;
-  int loc[per];
+  const int t = threadIdx.x;
+  const int64_t base = (int64_t)blockIdx.x * kSegChunk;
+  // element e of the chunk sits at (e / 32) * 33 + e % 32
+#pragma unroll 8
+  for (int i = 0; i < kSegPer; ++i) {
+    const int e = i * 256 + t;
+    const int64_t r = base + e;
+    sv[(e >> 5) * kSegPad + (e & 31)] = r < n ? cnt[r] : 0;
+  }
+  __syncthreads();
+  int* my = sv + t * kSegPad;   // this thread's rows base + 32 t ...
   int acc = 0;
   int nz = 0;
-#pragma unroll
-  for (int i = 0; i < per; ++i) {
-    const int64_t r = base + i;
-    const int v = r < n ? cnt[r] : 0;
-    loc[i] = acc;
+#pragma unroll 8
+  for (int i = 0; i < kSegPer; ++i) {
+    const int v = my[i];
     acc += v;
     nz += v > 0;
   }
-  part[threadIdx.x] = acc;
-  zpart[threadIdx.x] = nz;
+  part[t] = acc;
+  zpart[t] = nz;
   __syncthreads();
   for (int d = 1; d < 256; d <<= 1) {
-    const int a = threadIdx.x >= d ? part[threadIdx.x - d] : 0;
-    const int b = threadIdx.x >= d ? zpart[threadIdx.x - d] : 0;
+    const int a = t >= d ? part[t - d] : 0;
+    const int b = t >= d ? zpart[t - d] : 0;
     __syncthreads();
-    part[threadIdx.x] += a;
-    zpart[threadIdx.x] += b;
+    part[t] += a;
+    zpart[t] += b;
     __syncthreads();
   }
-  if (threadIdx.x == 255) zbase = atomicAdd(nrows, zpart[255]);
+  if (t == 255) zbase = atomicAdd(nrows, zpart[255]);
   __syncthreads();
-  const int pre = sums[blockIdx.x] + part[threadIdx.x] - acc;
-  int zpos = zbase + zpart[threadIdx.x] - nz;
-#pragma unroll
-  for (int i = 0; i < per; ++i) {
-    const int64_t r = base + i;
-    if (r < n) {
-      start[r] = pre + loc[i];
-      const int v = (i + 1 < per ? loc[i + 1] : acc) - loc[i];
-      if (v > 0) rows[zpos++] = (int32_t)r;
-    }
+  int run = sums[blockIdx.x] + part[t] - acc;
+  int zpos = zbase + zpart[t] - nz;
+  const int64_t r0 = base + (int64_t)t * kSegPer;
+#pragma unroll 8
+  for (int i = 0; i < kSegPer; ++i) {
+    const int v = my[i];
+    my[i] = run;                                   // exclusive start of the row
+    run += v;
+    if (v > 0) rows[zpos++] = (int32_t)(r0 + i);   // v > 0 only for rows below n
   }
-  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) start[n] = sums[gridDim.x];
+  __syncthreads();
+#pragma unroll 8
+  for (int i = 0; i < kSegPer; ++i) {
+    const int e = i * 256 + t;
+    const int64_t r = base + e;
+    if (r < n) start[r] = sv[(e >> 5) * kSegPad + (e & 31)];
+  }
+  if (blockIdx.x == gridDim.x - 1 && t == 0) start[n] = sums[gridDim.x];
 }
 
 // ---- fill ------------------------------------------------------------------------
