@@ -195,6 +195,34 @@ def test_nhwc_and_fp8_inputs(cfg1):
     compare_fused(gm8.accum.cpu().numpy(), A8)
 
 
+@pytest.mark.parametrize("shape,valid_mode", [((3, 16, 32), "none"), ((3, 16, 32), "aligned"),
+                                              ((3, 16, 32), "offset"), ((3, 17, 33), "aligned")])
+def test_render_back_paths(cfg1, shape, valid_mode):
+    """Label render-back over stored rows against the oracle, for pixel
+    counts that are and are not multiples of 4 and a validity array at an odd
+    address; random rows include -1 (no texel) and labels include 255."""
+    say(f"[case] render-back {shape} valid={valid_mode}")
+    sc = cfg1.scene
+    gm = gpu_mesh((sc.vertices, sc.faces), 1, oracle.SPLIT, 13)
+    n = gm.n_texels
+    rng = np.random.default_rng(21)
+    l = rng.integers(-1, n, size=shape).astype(np.int32)
+    lab = rng.integers(0, 256, size=n).astype(np.uint8)
+    valid, valid_dev = None, None
+    if valid_mode != "none":
+        valid = (rng.random(shape) > 0.3).astype(np.uint8)
+        if valid_mode == "offset":
+            buf = torch.zeros(valid.size + 1, dtype=torch.uint8, device="cuda")
+            buf[1:] = torch.from_numpy(valid.ravel()).cuda()
+            valid_dev = buf[1:].view(shape)
+            assert valid_dev.data_ptr() % 4 == 1
+        else:
+            valid_dev = to_dev(valid)
+    out = gm.render_labels(to_dev(lab), l=to_dev(l), valid=valid_dev)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), oracle.render(l, lab, valid))
+
+
 def test_errors_are_reported():
     say("[case] error statuses")
     V = torch.zeros((3, 3), device="cuda")
