@@ -355,8 +355,10 @@ __global__ __launch_bounds__(256) void k_finalize(MeshDev m, void* __restrict__ 
 hipError_t launch_finalize(const MeshDev& m, void* tex_out, int tex_dtype, uint8_t* labels, hipStream_t s) {
   if (m.n_texels == 0) return hipSuccess;
   const int cp = m.c | 1;
-  // rows per block: up to 256, within 64 KB of LDS
-  const int R = std::max(1, std::min(256, 16384 / cp));
+  // rows per block: up to 128, within 32 KB of LDS (21 KB at c = 40: seven
+  // blocks per compute unit keep more row loads in flight than three blocks
+  // of 256 rows)
+  const int R = std::max(1, std::min(128, 8192 / cp));
   const size_t lds = (size_t)R * cp * sizeof(float);
   dim3 g((unsigned)((m.n_texels + R - 1) / R));
 #define LF_FIN(O, A, T) k_finalize<O, A, T><<<g, 256, lds, s>>>(m, tex_out, labels, R)
