@@ -63,6 +63,8 @@ def _declare(L):
     L.or_coverage_count.argtypes = [_p, _i64, _p, _p, _f32, _i32, _i32, _p]
     L.or_snapped_fan.restype = _i32
     L.or_snapped_fan.argtypes = [_p, _p, _p, _f32, _p]
+    L.or_clip_triangle.restype = _i32
+    L.or_clip_triangle.argtypes = [_p, _f32, _p, _p, _p, _p]
     L.or_e4m3_decode.restype = _f64
     L.or_e4m3_decode.argtypes = [C.c_uint8]
     L.or_fuse.restype = _i32
@@ -162,6 +164,15 @@ class Mesh:
         out = np.zeros(36, np.int32)
         n = lib().or_snapped_fan(_ptr(self.vertices), _ptr(self.faces_uv[t]), _ptr(cam), float(z_near), _ptr(out))
         return out[: 6 * n].reshape(n, 3, 2)
+
+
+def clip_triangle(cam16, A, B, C, z_near=0.05):
+    """Camera-space polygon [n, 3] (binary32) of the world triangle (A, B, C),
+    corners in the order given, after the near and guard-plane clip."""
+    out = np.zeros((8, 3), np.float32)
+    n = lib().or_clip_triangle(_ptr(_c(cam16, np.float32)), float(z_near), _ptr(_c(A, np.float32)),
+                               _ptr(_c(B, np.float32)), _ptr(_c(C, np.float32)), _ptr(out))
+    return out[:n].copy()
 
 
 def e4m3_decode(q: int) -> float:

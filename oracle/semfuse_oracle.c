@@ -425,6 +425,23 @@ OR_API int32_t or_snapped_fan(const float* verts, const int32_t* fuv3, const flo
     return k;
 }
 
+/* Camera-space polygon of one triangle after the five-plane clip, before
+ * projection (for checks of the clipping rules): the world-space corners A,
+ * B, C are taken in the order given; out receives up to 8 vertices of 3
+ * floats; returns their count (0..8). */
+OR_API int32_t or_clip_triangle(const float* cam16, float z_near, const float* A, const float* B, const float* C,
+                                float* out) {
+    cam_t cam;
+    memcpy(&cam, cam16, sizeof(cam));
+    float poly[8][3];
+    to_camera(&cam, A, poly[0]);
+    to_camera(&cam, B, poly[1]);
+    to_camera(&cam, C, poly[2]);
+    int n = clip_polygon(poly, 3, &cam, z_near);
+    memcpy(out, poly, sizeof(float) * 3 * (size_t)n);
+    return n;
+}
+
 /* ---------------------------------------------------------------- fusion */
 
 /* OCP 8-bit floating point, E4M3FN: 1 sign, 4 exponent (bias 7), 3 mantissa
