@@ -276,8 +276,12 @@ lf_status lf_load_mesh(const lf_mesh_opts* opts, const float* d_vertices, int64_
   if (!per_face && (opts->s_uniform < 1 || opts->s_uniform > 4096)) return fail(LF_EINVAL, "s_uniform must be in [1, 4096]");
   const MeshLayout L = mesh_layout(n_faces, per_face);
   if (mesh_ws_bytes < L.total) return fail(LF_ESIZE, "mesh workspace %lld < %lld bytes", (long long)mesh_ws_bytes, (long long)L.total);
+  // texel rows are int32 everywhere on the device (l = id_t + id_x)
+  if (n_texels < 0 || n_texels >= ((int64_t)1 << 31))
+    return fail(LF_EINVAL, "texel count %lld outside [0, 2^31 - 1]", (long long)n_texels);
   if (!per_face) {
     const int64_t want = n_faces * per_tri(opts->s_uniform, opts->scheme);
+    if (want >= ((int64_t)1 << 31)) return fail(LF_EINVAL, "texel count %lld exceeds 2^31 - 1", (long long)want);
     if (want != n_texels) return fail(LF_ESIZE, "n_texels %lld != %lld", (long long)n_texels, (long long)want);
   }
   char* ws = reinterpret_cast<char*>(d_mesh_ws);
@@ -323,6 +327,7 @@ lf_status lf_load_mesh(const lf_mesh_opts* opts, const float* d_vertices, int64_
   if (per_face) LF_TRY(hipMemcpyAsync(&htot, d.off + n_faces, 8, hipMemcpyDeviceToHost, stream), "read total");
   LF_TRY(hipStreamSynchronize(stream), "sync");
   if (herr) return fail(LF_EINVAL, "face index out of range [0, %lld) or s < 1", (long long)n_vertices);
+  if (htot >= ((int64_t)1 << 31)) return fail(LF_EINVAL, "texel count %lld exceeds 2^31 - 1", (long long)htot);
   if (htot != n_texels) return fail(LF_ESIZE, "n_texels %lld != %lld", (long long)n_texels, (long long)htot);
   lf_mesh h = new (std::nothrow) lf_mesh_s;
   if (!h) return fail(LF_EINVAL, "out of host memory");

@@ -376,7 +376,7 @@ __global__ __launch_bounds__(256) void k_seg_gather(MeshDev m, ProbIn in, PixDec
 //
 // Per-frame weights (frame_w = 1: w^(I) = 1 / n, 3: (1 - mix) + mix / n, with
 // n the number of pixels of the observation's frame that see the texel,
-// Section 3.3.1): a row's observations of one frame are exactly that frame's
+// Section 3.2.2): a row's observations of one frame are exactly that frame's
 // pixels on the texel, so n is counted per row in an LDS histogram over the
 // batch's frames (one per group, nf counters) before the row is summed; an
 // observation's frame is its stored element offset divided by the frame

@@ -321,7 +321,7 @@ class Mesh:
         return area
 
     # -- tuning and jobs ----------------------------------------------------------------
-    def set_tuning(self, tile=32, gather_unroll=8, small_px=48, gather_waves=32):
+    def set_tuning(self, tile=32, gather_unroll=8, small_px=48, gather_waves=8):
         """lf_set_tuning (results do not depend on it)."""
         _check(lib().lf_set_tuning(self._h, C.byref(_Tuning(tile, gather_unroll, small_px, gather_waves))))
         self._fws.clear()

@@ -51,3 +51,22 @@ def test_size_query_on_host(lib):
     with pytest.raises(sf.SemfuseError):
         sf.mesh_sizes(10, 2 ** 30, s=64, n_classes=4)    # more than 2^31 texels
     assert "gfx950" in sf.version()
+
+
+def test_load_mesh_rejects_texel_counts_beyond_int32(lib):
+    """Texel rows are int32 on the device: lf_load_mesh refuses a texel count
+    of 2^31 or more (given, or implied by a uniform s) before it touches any
+    buffer (the device pointers here are never dereferenced)."""
+    from paper_2111_11103_amd import semfuse as sf
+    fake = C.c_void_p(1 << 20)                   # 256-byte aligned, never used
+    h = C.c_void_p()
+    opts = sf._MeshOpts(sf.SPLIT, 64, 4, sf.AGG_SUM, sf.F32, 0.05)
+    n_faces = 2 ** 20                            # 2^20 triangles x 64^2 texels = 2^32 rows
+    st = lib.lf_load_mesh(C.byref(opts), fake, 3, fake, n_faces, None, fake, 1 << 40, fake, None,
+                          n_faces * 64 * 64, None, C.byref(h))
+    assert st == sf.LF_EINVAL and b"2^31" in lib.lf_last_error()
+    opts = sf._MeshOpts(sf.SPLIT, 1, 4, sf.AGG_SUM, sf.F32, 0.05)
+    st = lib.lf_load_mesh(C.byref(opts), fake, 3, fake, 2 ** 31 - 1, None, fake, 1 << 40, fake, None,
+                          2 ** 31, None, C.byref(h))
+    assert st == sf.LF_EINVAL and b"2^31" in lib.lf_last_error()
+    assert not h.value

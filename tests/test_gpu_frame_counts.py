@@ -1,4 +1,4 @@
-"""w^(I) and the mixed weight (Section 3.3.1) on the grouped texel-sorted
+"""w^(I) and the mixed weight (Section 3.2.2) on the grouped texel-sorted
 gather, which counts each texel row's observations per frame of the batch
 itself (LDS counters) instead of reading per-frame counts written by the
 raster: parity with the oracle for ragged batches, one-frame batches, FP8
