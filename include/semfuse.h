@@ -98,8 +98,10 @@ lf_status lf_mesh_sizes(const lf_mesh_opts* opts, int64_t n_vertices, int64_t n_
  *  indices; d_s_face [T] int32 or NULL (then opts->s_uniform);
  *  d_mesh_ws  >= mesh_ws_bytes, 256-byte aligned, kept by the handle;
  *  d_accum    [n_texels][c] accumulator (FP32 unless opts->accum_dtype), kept;
+ *             or NULL for a texture fused window by window only (the mesh
+ *             then starts with an empty window: see lf_set_window);
  *  d_wsum     [n_texels] float32 total weight per texel, kept (may be NULL
- *             unless aggregator == MUL).
+ *             unless aggregator == MUL and d_accum is given).
  * Waits on `stream` for index validation: LF_EINVAL if a face index is out of
  * range or an s is < 1.  The triangles' vertex positions are copied into the
  * mesh workspace here: later changes to d_vertices are not seen.  The caller
@@ -111,6 +113,26 @@ lf_status lf_load_mesh(const lf_mesh_opts* opts, const float* d_vertices, int64_
 
 /* alpha of LF_W_MIX for this mesh (0 = w^(P), 1 = w^(I)); LF_EINVAL outside [0, 1]. */
 lf_status lf_set_weight_mix(lf_mesh mesh, float alpha);
+
+/* Texel-row window: out-of-core aggregation for textures larger than a device
+ * budget (Section 3.3.2 runs the aggregator on the GPU or, for larger meshes
+ * and texel resolutions, on the CPU; here the texture is fused on the GPU a
+ * window of rows at a time and the caller moves each window's result where
+ * it keeps the texture, e.g. host memory).  After this call the mesh
+ * accumulates only texel rows row_lo .. row_lo + n_rows - 1, row r at row
+ * r - row_lo of d_accum [n_rows][c] (and d_wsum [n_rows], required for MUL);
+ * pixels on other rows are skipped by lf_fuse_frames and lf_fuse_batch;
+ * lf_reset clears the window; lf_finalize writes the
+ * window's rows (texture [n_rows][c], labels [n_rows], window-relative).
+ * The renderer and lf_render_labels keep using whole-texture rows (label
+ * images read labels [n_texels]).  Per-row workspace (lf_frame_ws_bytes)
+ * shrinks with the window.  The learned weighting and lf_extract_features
+ * need the whole texture (LF_ESTATE with a window).  d_accum = NULL with
+ * row_lo = 0, n_rows = n_texels, d_wsum = NULL restores the load-time
+ * buffers.  The buffers stay the caller's; nothing is cleared here.
+ * Errors: LF_EINVAL for a window outside [0, n_texels) or a misaligned
+ * buffer. */
+lf_status lf_set_window(lf_mesh mesh, int64_t row_lo, int64_t n_rows, void* d_accum, float* d_wsum);
 
 /* Clear the accumulator (and weight sums): start a new fusion. */
 lf_status lf_reset(lf_mesh mesh, hipStream_t stream);
@@ -314,6 +336,18 @@ lf_status lf_extract_features(lf_mesh mesh, const float* d_cams, int32_t F, int3
                               const float* d_scale, const uint8_t* d_valid, const uint8_t* d_labels,
                               float* d_phi, float* d_target, int32_t* d_pix, int64_t cap,
                               uint64_t* d_count, void* d_ws, int64_t ws_bytes, hipStream_t stream);
+
+/* Agreement of label images with the frames' own labels, the statistic by
+ * which plain fusion judges the learned weight on held-out frames (the
+ * training target's notion of label error, Section 3.2.1: a pixel's label is
+ * the argmax of its distribution, first maximal class on ties):
+ * d_counts[0] += pixels of d_images [F][H][W] with a label (not 255) that are
+ * valid; d_counts[1] += those whose label equals the argmax of the pixel's
+ * own input distribution (probabilities as in lf_fuse_frames).  d_counts is
+ * two uint64 on the device, accumulated into (zero them to start). */
+lf_status lf_label_agreement(const void* d_probs, int32_t prob_dtype, const int64_t* h_strides, const float* d_scale,
+                             const uint8_t* d_valid, int32_t n_classes, int32_t F, int32_t H, int32_t W,
+                             const uint8_t* d_images, uint64_t* d_counts, hipStream_t stream);
 
 /* ---- Texel resolution from the worst-case frame (Section 3.1) -------------
  * a_t = the largest number of pixel centres triangle t covers (as the

@@ -47,6 +47,8 @@ struct lf_mesh_s {
   lf_mesh_opts opts;
   Profiler prof;
   const void* mlp = nullptr;   // bound packed weights of the learned weighting
+  void* accum_full = nullptr;  // the load-time accumulator and weight sums (all rows)
+  float* wsum_full = nullptr;
   // Second stream of the sorted path: the gather of batch k runs on it while
   // the caller's stream renders and sorts batch k + 1 (events order them).
   hipStream_t side = nullptr;
@@ -68,7 +70,8 @@ struct StageTimer {
   Profiler* p;
   int st;
   hipStream_t s;
-  StageTimer(lf_mesh_s* m, int stage, hipStream_t stream) : p(m && m->prof.on ? &m->prof : nullptr), st(stage), s(stream) {
+  StageTimer(lf_mesh_s* m, int stage, hipStream_t stream)
+      : p(m && m->prof.on ? &m->prof : nullptr), st(stage), s(stream) {
     if (p) {
       hipEvent_t e = p->take();
       if (e && hipEventRecord(e, s) == hipSuccess) p->marks[st].push_back(e);
@@ -176,19 +179,19 @@ FrameLayout frame_layout(const MeshDev& m, int H, int W, int B, int weighting, i
   L.tcnt = o; o += align256(B * L.ntiles * 4);
   L.tlist = o; o += align256(B * L.list_cap * 4);
   L.l = o; o += align256(B * HW * 4);
-  L.cnt = o; if (weighting != LF_W_PIXEL) o += align256(B * m.n_texels * 4);
+  L.cnt = o; if (weighting != LF_W_PIXEL) o += align256(B * m.n_rows * 4);
   L.geo = o; if (weighting == LF_W_LEARNED) o += align256(B * HW * 16);
   // learned weights: two sets on the sorted path, whose gather reads them in place
   L.wpix = o; if (weighting == LF_W_LEARNED) o += align256((L.sorted ? 2 : 1) * B * HW * 4);
-  L.seg = o; if (L.sorted) o += align256(m.n_texels * 4);
+  L.seg = o; if (L.sorted) o += align256(m.n_rows * 4);
   L.rank = o; if (L.sorted) o += align256(B * HW * 4);
-  L.sums = o; if (L.sorted) o += align256((m.n_texels / 8192 + 2) * 4);
+  L.sums = o; if (L.sorted) o += align256((m.n_rows / 8192 + 2) * 4);
   // AUTO may pick the staged form for planar inputs: size for it too
   const bool staged = scatter_mode == LF_SCATTER_STAGED ||
                       (scatter_mode == LF_SCATTER_AUTO && m.c % 4 == 0 && m.c <= 60);
   for (int k = 0; k < 2; ++k) {
-    L.start[k] = o; if (L.sorted) o += align256((m.n_texels + 1) * 4);
-    L.rows[k] = o; if (L.sorted) o += align256(m.n_texels * 4);
+    L.start[k] = o; if (L.sorted) o += align256((m.n_rows + 1) * 4);
+    L.rows[k] = o; if (L.sorted) o += align256(m.n_rows * 4);
     L.nrows[k] = o; if (L.sorted) o += 256;
     L.ent_off[k] = o; if (L.sorted) o += align256(B * HW * 4);
     L.ent_w[k] = o; if (L.sorted && weighting != LF_W_PIXEL) o += align256(B * HW * 4);
@@ -268,10 +271,11 @@ lf_status lf_load_mesh(const lf_mesh_opts* opts, const float* d_vertices, int64_
   lf_status st = check_opts(opts);
   if (st != LF_OK) return st;
   if (n_vertices < 1 || n_faces < 0 || n_faces >= (int64_t)1 << 31) return fail(LF_EINVAL, "bad vertex/face count");
-  if (!d_vertices || (!d_faces && n_faces > 0) || !d_mesh_ws || (!d_accum && n_texels > 0))
-    return fail(LF_EINVAL, "NULL device buffer");
+  if (!d_vertices || (!d_faces && n_faces > 0) || !d_mesh_ws) return fail(LF_EINVAL, "NULL device buffer");
+  if (!d_accum && d_wsum) return fail(LF_EINVAL, "weight sums without an accumulator");
   if (reinterpret_cast<uintptr_t>(d_mesh_ws) & 255) return fail(LF_EINVAL, "mesh workspace must be 256-byte aligned");
-  if (opts->aggregator == LF_AGG_MUL && !d_wsum) return fail(LF_EINVAL, "MUL aggregation needs the weight-sum buffer");
+  if (opts->aggregator == LF_AGG_MUL && d_accum && !d_wsum)
+    return fail(LF_EINVAL, "MUL aggregation needs the weight-sum buffer");
   const bool per_face = d_s_face != nullptr;
   if (!per_face && (opts->s_uniform < 1 || opts->s_uniform > 4096)) return fail(LF_EINVAL, "s_uniform must be in [1, 4096]");
   const MeshLayout L = mesh_layout(n_faces, per_face);
@@ -298,6 +302,8 @@ lf_status lf_load_mesh(const lf_mesh_opts* opts, const float* d_vertices, int64_
   d.V = n_vertices;
   d.T = n_faces;
   d.n_texels = n_texels;
+  d.win_lo = 0;
+  d.n_rows = d_accum ? n_texels : 0;   // no accumulator: an empty window until lf_set_window
   d.n_clusters = (n_faces + kClusterTris - 1) / kClusterTris;
   d.s_uniform = per_face ? 0 : opts->s_uniform;
   d.split = opts->scheme == LF_TEX_SPLIT;
@@ -318,8 +324,9 @@ lf_status lf_load_mesh(const lf_mesh_opts* opts, const float* d_vertices, int64_
   LF_TRY(launch_mesh_prep(d, d_faces, stream), "mesh prep");
   if (per_face) LF_TRY(launch_offsets(d, reinterpret_cast<int32_t*>(ws + L.scan), stream), "offsets");
   LF_TRY(launch_cluster_boxes(d, stream), "cluster boxes");
-  LF_TRY(launch_zero(d_accum, n_texels * opts->n_classes * (opts->accum_dtype == LF_F32 ? 4 : 2), stream),
-         "clear accumulator");
+  if (d_accum)
+    LF_TRY(launch_zero(d_accum, n_texels * opts->n_classes * (opts->accum_dtype == LF_F32 ? 4 : 2), stream),
+           "clear accumulator");
   if (d_wsum) LF_TRY(launch_zero(d_wsum, n_texels * 4, stream), "clear weights");
   int32_t herr = 0;
   int64_t htot = n_texels;
@@ -343,6 +350,8 @@ lf_status lf_load_mesh(const lf_mesh_opts* opts, const float* d_vertices, int64_
   h->magic = kMagic;
   h->d = d;
   h->opts = *opts;
+  h->accum_full = d_accum;
+  h->wsum_full = d_wsum;
   *out = h;
   return LF_OK;
 }
@@ -352,9 +361,9 @@ lf_status lf_reset(lf_mesh mesh, hipStream_t stream) {
   lf_status st = check_mesh(mesh);
   if (st != LF_OK) return st;
   StageTimer tm(mesh, 6, stream);
-  LF_TRY(launch_zero(mesh->d.accum, mesh->d.n_texels * mesh->d.c * (mesh->d.accum_dtype == LF_F32 ? 4 : 2), stream),
+  LF_TRY(launch_zero(mesh->d.accum, mesh->d.n_rows * mesh->d.c * (mesh->d.accum_dtype == LF_F32 ? 4 : 2), stream),
          "clear accumulator");
-  if (mesh->d.wsum) LF_TRY(launch_zero(mesh->d.wsum, mesh->d.n_texels * 4, stream), "clear weights");
+  if (mesh->d.wsum) LF_TRY(launch_zero(mesh->d.wsum, mesh->d.n_rows * 4, stream), "clear weights");
   return LF_OK;
 }
 
@@ -415,6 +424,8 @@ lf_status check_fuse(const FuseArgs& a, const void* ws, int64_t ws_bytes) {
   if (a.weighting < LF_W_PIXEL || a.weighting > LF_W_MIX) return fail(LF_EINVAL, "unknown weighting %d", a.weighting);
   if (a.weighting == LF_W_LEARNED && !a.mesh->mlp)
     return fail(LF_ESTATE, "learned weighting needs weights bound by lf_mlp_bind");
+  if (a.weighting == LF_W_LEARNED && a.mesh->d.n_rows != a.mesh->d.n_texels)
+    return fail(LF_ESTATE, "learned weighting needs the whole texture (no texel-row window)");
   if (a.scatter_mode < LF_SCATTER_AUTO || a.scatter_mode > LF_SCATTER_STAGED) return fail(LF_EINVAL, "bad scatter mode");
   if (a.scatter_mode == LF_SCATTER_STAGED && !stage_ok(a.mesh->d, a.dtype))
     return fail(LF_EINVAL, "the staged scatter needs FP32 input, c %% 4 == 0 and c <= 60");
@@ -466,7 +477,7 @@ lf_status fuse_impl(const FuseArgs& a, void* d_ws, hipStream_t stream) {
       sorted && seg_pixels_dense_ok(d, staged ? staged_in(ws + L.stage[0], nullptr) : in, B, H, W);
   int32_t* seg = sorted ? reinterpret_cast<int32_t*>(ws + L.seg) : nullptr;
   LF_TRY(launch_zero(ws + L.tcnt, B * L.ntiles * 4, stream), "clear tile counts");
-  if (cnt) LF_TRY(launch_zero(cnt, (int64_t)B * d.n_texels * 4, stream), "clear counts");
+  if (cnt) LF_TRY(launch_zero(cnt, (int64_t)B * d.n_rows * 4, stream), "clear counts");
   int32_t* rank = sorted ? reinterpret_cast<int32_t*>(ws + L.rank) : nullptr;
   lf_status status;
   int nbatch = 0;      // sorted batches issued: batch k's gather runs on `side`
@@ -475,38 +486,38 @@ lf_status fuse_impl(const FuseArgs& a, void* d_ws, hipStream_t stream) {
   struct Batch {
     int f0, nb, fi;
   };
-  std::vector<Batch> batches;
-  for (int f0 = 0; f0 < a.F;) {
+  auto batch_at = [&](int f0) {
     int nb = (a.F - f0) < B ? (a.F - f0) : B;
     const int fi = a.pool > 0 ? f0 % a.pool : f0;     // input frame of the batch's first frame
     if (a.pool > 0 && nb > a.pool - fi) nb = a.pool - fi;   // batches never straddle the end of the pool
-    batches.push_back(Batch{f0, nb, fi});
-    f0 += nb;
-  }
+    return Batch{f0, nb, fi};
+  };
   // Planar inputs: the side stream transposes each batch into pixel-major
   // rows (staging set j % 2), batch j + 1 while batch j is sorted on the
   // caller's stream; the fill and the gather then read the rows like
   // channels-last input.  Stream order on the side stream protects a set
   // from being rewritten before its gather has read it.
-  auto stage_batch = [&](size_t j) -> lf_status {
+  auto stage_batch = [&](const Batch& b, int j) -> lf_status {
     StageTimer tm(mesh, 3, side);
-    LF_TRY(launch_planar_rows(in, batches[j].fi, batches[j].nb, H, W, d.c,
-                              reinterpret_cast<float*>(ws + L.stage[j & 1]), side), "planar rows");
+    LF_TRY(launch_planar_rows(in, b.fi, b.nb, H, W, d.c, reinterpret_cast<float*>(ws + L.stage[j & 1]), side),
+           "planar rows");
     return LF_OK;
   };
-  if (staged && !batches.empty()) {
+  if (staged) {
     // the input may come from work on the caller's stream
     LF_TRY(hipEventRecord(mesh->sorted_ev[1], stream), "record call start");
     LF_TRY(hipStreamWaitEvent(side, mesh->sorted_ev[1], 0), "wait for call start");
-    if ((status = stage_batch(0)) != LF_OK) return status;
+    if ((status = stage_batch(batch_at(0), 0)) != LF_OK) return status;
   }
-  for (size_t j = 0; j < batches.size(); ++j) {
-    const int f0 = batches[j].f0, nb = batches[j].nb, fi = batches[j].fi;
+  int j = 0;
+  for (Batch cur = batch_at(0); cur.f0 < a.F; cur = batch_at(cur.f0 + cur.nb), ++j) {
+    const int f0 = cur.f0, nb = cur.nb, fi = cur.fi;
+    const bool more = f0 + nb < a.F;
     const float* cams_in = a.cams + 16 * (int64_t)(f0 - fi);  // camera of input index fi + k is f0 + k
     int32_t* lb = a.l_out ? a.l_out + (int64_t)f0 * HW : reinterpret_cast<int32_t*>(ws + L.l);
     const uint8_t* vb = a.valid ? a.valid + (int64_t)fi * HW : nullptr;
-    if (seg) LF_TRY(launch_zero(seg, d.n_texels * 4, stream), "clear segments");
-    RasterOut out{lb, nullptr, nullptr, vb, cnt, d.n_texels, seg, rank, geo};
+    if (seg) LF_TRY(launch_zero(seg, d.n_rows * 4, stream), "clear segments");
+    RasterOut out{lb, nullptr, nullptr, vb, cnt, d.n_rows, seg, rank, geo};
     if ((status = render_batch(mesh, a.cams, f0, nb, H, W, L, ws, out, stream)) != LF_OK) return status;
     const int k = nbatch & 1;   // sorted path: buffer set of this batch
     float* wpix = learned ? wpix_sets + (sorted ? (int64_t)k * B * HW : 0) : nullptr;
@@ -514,7 +525,7 @@ lf_status fuse_impl(const FuseArgs& a, void* d_ws, hipStream_t stream) {
       // weight set k may still be read by the gather two batches back
       if (sorted && nbatch >= 2) LF_TRY(hipStreamWaitEvent(stream, mesh->gathered_ev[k], 0), "wait for gather");
       StageTimer tm(mesh, 7, stream);
-      LF_TRY(launch_mlp_weights(mesh->mlp, in, fi, nb, H, W, cams_in, lb, geo, cnt, d.n_texels, d.c, wpix, stream),
+      LF_TRY(launch_mlp_weights(mesh->mlp, in, fi, nb, H, W, cams_in, lb, geo, cnt, d.n_rows, d.c, wpix, stream),
              "learned weights");
     }
     if (sorted) {
@@ -531,18 +542,18 @@ lf_status fuse_impl(const FuseArgs& a, void* d_ws, hipStream_t stream) {
       {
         StageTimer tm(mesh, 3, stream);
         LF_TRY(launch_zero(nrows, 4, stream), "clear row count");
-        LF_TRY(launch_seg_scan(seg, d.n_texels, reinterpret_cast<int32_t*>(ws + L.sums), start, rows, nrows, stream),
+        LF_TRY(launch_seg_scan(seg, d.n_rows, reinterpret_cast<int32_t*>(ws + L.sums), start, rows, nrows, stream),
                "segment scan");
         const ProbIn sin = staged_in(stg, a.valid ? a.valid + (int64_t)fi * HW : nullptr);
         if (staged)
-          LF_TRY(launch_seg_fill(sin, 0, nb, H, W, lb, rank, start, eo, ew, nullptr, a.weighting, cnt, d.n_texels,
-                                 wpix, d.mix, stream), "segment fill");
+          LF_TRY(launch_seg_fill(sin, 0, nb, H, W, lb, rank, start, eo, ew, nullptr, a.weighting, cnt, d.n_rows,
+                                 wpix, d.mix, d.win_lo, d.n_rows, stream), "segment fill");
         else
-          LF_TRY(launch_seg_fill(in, fi, nb, H, W, lb, rank, start, eo, ew, es, a.weighting, cnt, d.n_texels, wpix,
-                                 d.mix, stream), "segment fill");
+          LF_TRY(launch_seg_fill(in, fi, nb, H, W, lb, rank, start, eo, ew, es, a.weighting, cnt, d.n_rows, wpix,
+                                 d.mix, d.win_lo, d.n_rows, stream), "segment fill");
       }
       LF_TRY(hipEventRecord(mesh->sorted_ev[k], stream), "record sorted");
-      if (staged && j + 1 < batches.size() && (status = stage_batch(j + 1)) != LF_OK) return status;
+      if (staged && more && (status = stage_batch(batch_at(f0 + nb), j + 1)) != LF_OK) return status;
       LF_TRY(hipStreamWaitEvent(side, mesh->sorted_ev[k], 0), "wait for sort");
       {
         StageTimer tm(mesh, 2, side);
@@ -556,12 +567,12 @@ lf_status fuse_impl(const FuseArgs& a, void* d_ws, hipStream_t stream) {
       ++nbatch;
     } else {
       StageTimer tm(mesh, 2, stream);
-      LF_TRY(launch_scatter_atomic(d, in, fi, nb, H, W, lb, a.weighting, cnt, d.n_texels, wpix, d.mix, stream),
+      LF_TRY(launch_scatter_atomic(d, in, fi, nb, H, W, lb, a.weighting, cnt, d.n_rows, wpix, d.mix, stream),
              "scatter");
     }
     if (cnt) {
       StageTimer tm(mesh, 3, stream);
-      LF_TRY(launch_clear_counts(lb, vb, nb, H, W, cnt, d.n_texels, stream), "clear counts");
+      LF_TRY(launch_clear_counts(lb, vb, nb, H, W, cnt, d.n_rows, d.win_lo, stream), "clear counts");
     }
   }
   // the call is complete on the caller's stream once the last gather is
@@ -595,9 +606,9 @@ lf_status run_jobs(const lf_scene_job* jobs, int32_t n, void* d_ws, hipStream_t 
     lf_mesh m = j.mesh;
     {
       StageTimer tm(m, 6, stream);
-      LF_TRY(launch_zero(m->d.accum, m->d.n_texels * m->d.c * (m->d.accum_dtype == LF_F32 ? 4 : 2), stream),
+      LF_TRY(launch_zero(m->d.accum, m->d.n_rows * m->d.c * (m->d.accum_dtype == LF_F32 ? 4 : 2), stream),
              "clear accumulator");
-      if (m->d.wsum) LF_TRY(launch_zero(m->d.wsum, m->d.n_texels * 4, stream), "clear weights");
+      if (m->d.wsum) LF_TRY(launch_zero(m->d.wsum, m->d.n_rows * 4, stream), "clear weights");
     }
     lf_status st = fuse_impl(job_args(j), d_ws, stream);
     if (st != LF_OK) return st;
@@ -913,6 +924,32 @@ lf_status lf_set_overlap(lf_mesh mesh, int32_t enabled) {
   return LF_OK;
 }
 
+lf_status lf_set_window(lf_mesh mesh, int64_t row_lo, int64_t n_rows, void* d_accum, float* d_wsum) {
+  g_err[0] = 0;
+  lf_status st = check_mesh(mesh);
+  if (st != LF_OK) return st;
+  MeshDev& d = mesh->d;
+  if (row_lo < 0 || n_rows < 0 || row_lo + n_rows > d.n_texels)
+    return fail(LF_EINVAL, "window [%lld, %lld) outside [0, %lld)", (long long)row_lo, (long long)(row_lo + n_rows),
+                (long long)d.n_texels);
+  if (!d_accum) {
+    if (row_lo != 0 || n_rows != d.n_texels || d_wsum)
+      return fail(LF_EINVAL, "a window other than the whole texture needs its own accumulator");
+    if (!mesh->accum_full && n_rows > 0)
+      return fail(LF_ESTATE, "the mesh was loaded without a whole-texture accumulator");
+    d.accum = mesh->accum_full;
+    d.wsum = mesh->wsum_full;
+  } else {
+    if (d.aggregator == LF_AGG_MUL && !d_wsum) return fail(LF_EINVAL, "MUL aggregation needs the weight-sum buffer");
+    if (reinterpret_cast<uintptr_t>(d_accum) & 15) return fail(LF_EINVAL, "window accumulator must be 16-byte aligned");
+    d.accum = d_accum;
+    d.wsum = d_wsum;
+  }
+  d.win_lo = row_lo;
+  d.n_rows = n_rows;
+  return LF_OK;
+}
+
 lf_status lf_set_weight_mix(lf_mesh mesh, float alpha) {
   g_err[0] = 0;
   lf_status st = check_mesh(mesh);
@@ -1008,6 +1045,8 @@ lf_status lf_extract_features(lf_mesh mesh, const float* d_cams, int32_t F, int3
   if (st != LF_OK) return st;
   if ((st = check_frames(F, H, W)) != LF_OK) return st;
   if (!d_count) return fail(LF_EINVAL, "NULL count");
+  if (mesh->d.n_rows != mesh->d.n_texels)
+    return fail(LF_ESTATE, "feature extraction needs the whole texture (no texel-row window)");
   LF_TRY(launch_zero(d_count, 8, stream), "clear count");
   if (F == 0) return LF_OK;
   if (!d_cams || !d_probs || !h_strides || !d_ws || !d_phi) return fail(LF_EINVAL, "NULL argument");
@@ -1039,8 +1078,28 @@ lf_status lf_extract_features(lf_mesh mesh, const float* d_cams, int32_t F, int3
     StageTimer tm(mesh, 7, stream);
     LF_TRY(launch_extract(in, f0, nb, H, W, d_cams, lb, geo, cnt, d.n_texels, d.c, d_labels, d_phi, d_target, d_pix,
                           cap, reinterpret_cast<unsigned long long*>(d_count), stream), "extract");
-    LF_TRY(launch_clear_counts(lb, vb, nb, H, W, cnt, d.n_texels, stream), "clear counts");
+    LF_TRY(launch_clear_counts(lb, vb, nb, H, W, cnt, d.n_texels, 0, stream), "clear counts");
   }
+  return LF_OK;
+}
+
+lf_status lf_label_agreement(const void* d_probs, int32_t prob_dtype, const int64_t* h_strides, const float* d_scale,
+                             const uint8_t* d_valid, int32_t n_classes, int32_t F, int32_t H, int32_t W,
+                             const uint8_t* d_images, uint64_t* d_counts, hipStream_t stream) {
+  g_err[0] = 0;
+  lf_status st = check_frames(F, H, W);
+  if (st != LF_OK) return st;
+  if (!d_counts) return fail(LF_EINVAL, "NULL counts");
+  if (n_classes < 1 || n_classes > 255) return fail(LF_EINVAL, "n_classes must be in [1, 255]");
+  if (F == 0) return LF_OK;
+  if (!d_probs || !h_strides || !d_images) return fail(LF_EINVAL, "NULL argument");
+  if (prob_dtype != LF_F32 && prob_dtype != LF_FP8_E4M3) return fail(LF_EINVAL, "probabilities must be F32 or FP8_E4M3");
+  if (prob_dtype == LF_FP8_E4M3 && !d_scale) return fail(LF_EINVAL, "FP8 input needs the per-pixel scale");
+  for (int i = 0; i < 4; ++i)
+    if (h_strides[i] < 0) return fail(LF_EINVAL, "negative stride");
+  ProbIn in{d_probs, d_scale, d_valid, h_strides[0], h_strides[1], h_strides[2], h_strides[3], prob_dtype};
+  LF_TRY(launch_agreement(in, n_classes, F, H, W, d_images, reinterpret_cast<unsigned long long*>(d_counts), stream),
+         "agreement");
   return LF_OK;
 }
 

@@ -79,7 +79,9 @@ __global__ __launch_bounds__(TW * TH) void k_scatter_hash(MeshDev m, ProbIn in, 
     if (fb < nf && inimg) {
       const int64_t pi = (int64_t)fb * HW + (int64_t)y * W + x;
       const int64_t gi = (int64_t)(f_first + fb) * HW + (int64_t)y * W + x;
-      int l = lbuf[pi];
+      // window-relative row (-1: no triangle, invalid, or outside the window)
+      const int64_t lw = (int64_t)lbuf[pi] - m.win_lo;
+      int l = (lbuf[pi] >= 0 && lw >= 0 && lw < m.n_rows) ? (int)lw : -1;
       if (l >= 0 && in.valid && !in.valid[gi]) l = -1;
       if (l >= 0) {
         float w = 1.0f;
@@ -188,13 +190,14 @@ hipError_t launch_scatter_atomic(const MeshDev& m, const ProbIn& in, int f_first
 
 // ---- w^(I) counts are per frame: clear the entries a batch touched ---------
 __global__ __launch_bounds__(256) void k_clear_counts(const int32_t* __restrict__ l, int H, int W,
-                                                      int32_t* __restrict__ cnt, int64_t cnt_stride) {
+                                                      int32_t* __restrict__ cnt, int64_t cnt_stride, int64_t win_lo) {
   const int fb = blockIdx.y;
   const int64_t HW = (int64_t)H * W;
   const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (p >= HW) return;
   const int32_t li = l[(int64_t)fb * HW + p];
-  if (li >= 0) cnt[(int64_t)fb * cnt_stride + li] = 0;
+  const int64_t lw = (int64_t)li - win_lo;
+  if (li >= 0 && lw >= 0 && lw < cnt_stride) cnt[(int64_t)fb * cnt_stride + lw] = 0;
 }
 
 // ---- texel resolution (Section 3.1): a_t = most pixels triangle t covers in
@@ -248,10 +251,10 @@ hipError_t launch_texel_resolution(const int32_t* area, int64_t T, float gamma, 
 }
 
 hipError_t launch_clear_counts(const int32_t* l, const uint8_t* /*valid*/, int nf, int H, int W, int32_t* cnt,
-                               int64_t cnt_stride, hipStream_t s) {
+                               int64_t cnt_stride, int64_t win_lo, hipStream_t s) {
   if (nf <= 0) return hipSuccess;
   const int64_t HW = (int64_t)H * W;
-  k_clear_counts<<<dim3((unsigned)((HW + 255) / 256), (unsigned)nf), 256, 0, s>>>(l, H, W, cnt, cnt_stride);
+  k_clear_counts<<<dim3((unsigned)((HW + 255) / 256), (unsigned)nf), 256, 0, s>>>(l, H, W, cnt, cnt_stride, win_lo);
   return hipGetLastError();
 }
 
@@ -275,7 +278,7 @@ __global__ __launch_bounds__(256) void k_finalize(MeshDev m, void* __restrict__ 
   const int c = m.c;
   const int cp = c | 1;
   const int64_t x0 = (int64_t)blockIdx.x * R;
-  const int nr = (int)min<int64_t>(R, m.n_texels - x0);
+  const int nr = (int)min<int64_t>(R, m.n_rows - x0);
   const int64_t a0 = x0 * c;
   // element i of the block's rows sits at row i / c: walk (row, class) pairs
   // incrementally instead of dividing per element
@@ -353,14 +356,14 @@ __global__ __launch_bounds__(256) void k_finalize(MeshDev m, void* __restrict__ 
 }
 
 hipError_t launch_finalize(const MeshDev& m, void* tex_out, int tex_dtype, uint8_t* labels, hipStream_t s) {
-  if (m.n_texels == 0) return hipSuccess;
+  if (m.n_rows == 0) return hipSuccess;
   const int cp = m.c | 1;
   // rows per block: up to 128, within 32 KB of LDS (21 KB at c = 40: seven
   // blocks per compute unit keep more row loads in flight than three blocks
   // of 256 rows)
   const int R = std::max(1, std::min(128, 8192 / cp));
   const size_t lds = (size_t)R * cp * sizeof(float);
-  dim3 g((unsigned)((m.n_texels + R - 1) / R));
+  dim3 g((unsigned)((m.n_rows + R - 1) / R));
 #define LF_FIN(O, A, T) k_finalize<O, A, T><<<g, 256, lds, s>>>(m, tex_out, labels, R)
 #define LF_FIN2(O)                                              \
   do {                                                          \
@@ -405,6 +408,64 @@ __global__ __launch_bounds__(256) void k_render(const int32_t* __restrict__ l, c
 #pragma unroll
   for (int k = 0; k < P; ++k)
     if (ok[k]) out[base + (int64_t)k * 256] = lab[k];
+}
+
+// ---- agreement of label images with the frames' own argmax ------------------
+// counts[0] += pixels with a label (not 255) and valid; counts[1] += those
+// whose label equals the argmax of the pixel's own distribution (first
+// maximal class).  One block per 256 pixels of a frame; one atomic pair per
+// block.
+template <int DT>
+__global__ __launch_bounds__(256) void k_agreement(ProbIn in, int c, int H, int W, const uint8_t* __restrict__ img,
+                                                   unsigned long long* __restrict__ counts) {
+  __shared__ unsigned int part[2][4];
+  const int f = blockIdx.y;
+  const int64_t HW = (int64_t)H * W;
+  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  unsigned int n = 0, agree = 0;
+  if (p < HW) {
+    const uint8_t lab = img[(int64_t)f * HW + p];
+    const bool ok = lab != 255 && (!in.valid || in.valid[(int64_t)f * HW + p]);
+    if (ok) {
+      const int y = (int)(p / W), x = (int)(p - (int64_t)y * W);
+      const int64_t base = (int64_t)f * in.sf + (int64_t)y * in.sy + (int64_t)x * in.sx;
+      const float sc = DT == 3 ? in.scale[(int64_t)f * HW + p] : 1.0f;
+      float best = -__builtin_inff();
+      int arg = 0;
+      for (int j = 0; j < c; ++j) {
+        float v;
+        if constexpr (DT == 0) v = reinterpret_cast<const float*>(in.p)[base + (int64_t)j * in.sc];
+        else v = fp8_e4m3(reinterpret_cast<const uint8_t*>(in.p)[base + (int64_t)j * in.sc]) * sc;
+        if (v > best) { best = v; arg = j; }
+      }
+      n = 1;
+      agree = arg == lab;
+    }
+  }
+  // wave sums, then one atomic pair per block
+  const unsigned long long bn = __ballot(n != 0), ba = __ballot(agree != 0);
+  const int wv = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    part[0][wv] = (unsigned)__popcll(bn);
+    part[1][wv] = (unsigned)__popcll(ba);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned tn = part[0][0] + part[0][1] + part[0][2] + part[0][3];
+    const unsigned ta = part[1][0] + part[1][1] + part[1][2] + part[1][3];
+    if (tn) atomicAdd(counts, (unsigned long long)tn);
+    if (ta) atomicAdd(counts + 1, (unsigned long long)ta);
+  }
+}
+
+hipError_t launch_agreement(const ProbIn& in, int c, int F, int H, int W, const uint8_t* img,
+                            unsigned long long* counts, hipStream_t s) {
+  if (F <= 0) return hipSuccess;
+  const int64_t HW = (int64_t)H * W;
+  const dim3 g((unsigned)((HW + 255) / 256), (unsigned)F);
+  if (in.dtype == 0) k_agreement<0><<<g, 256, 0, s>>>(in, c, H, W, img, counts);
+  else k_agreement<3><<<g, 256, 0, s>>>(in, c, H, W, img, counts);
+  return hipGetLastError();
 }
 
 hipError_t launch_render(const int32_t* l, const uint8_t* valid, const uint8_t* labels, int64_t npx, uint8_t* out,

@@ -16,9 +16,10 @@ struct MeshDev {
   int64_t* off;              // [T+1] row offsets or nullptr (uniform: t * n_per)
   float* cl_box;             // [n_clusters][8]: lo.xyz, hi.xyz, magnitude bound, pad
   int32_t* err;              // [1] validation flag
-  void* accum;               // [n_texels][c]
-  float* wsum;               // [n_texels] or nullptr
+  void* accum;               // [n_rows][c]: texel rows win_lo .. win_lo + n_rows - 1
+  float* wsum;               // [n_rows] or nullptr
   int64_t V, T, n_texels, n_clusters;
+  int64_t win_lo, n_rows;    // the accumulator's texel-row window (0, n_texels unless set)
   int32_t s_uniform, split, c, aggregator, accum_dtype;
   int32_t n_per;             // texels per triangle when uniform
   float z_near;
@@ -88,14 +89,19 @@ hipError_t launch_render_batch(const MeshDev& m, const float* cams, int nb, int 
 hipError_t launch_scatter_atomic(const MeshDev& m, const ProbIn& in, int f_first, int nf, int H, int W,
                                  const int32_t* l, int weighting, const int32_t* cnt, int64_t cnt_stride,
                                  const float* wpix, float mix, hipStream_t s);
+// Per-frame counts are indexed by window-relative rows l - win_lo (rows
+// outside [win_lo, win_lo + cnt_stride) are skipped).
 hipError_t launch_clear_counts(const int32_t* l, const uint8_t* valid, int nf, int H, int W, int32_t* cnt,
-                               int64_t cnt_stride, hipStream_t s);
+                               int64_t cnt_stride, int64_t win_lo, hipStream_t s);
 hipError_t launch_finalize(const MeshDev& m, void* tex_out, int tex_dtype, uint8_t* labels, hipStream_t s);
 hipError_t launch_seg_scan(const int32_t* seg, int64_t n, int32_t* sums, int32_t* start, int32_t* rows,
                            int32_t* nrows, hipStream_t s);
+// Pixels whose row lies outside [win_lo, win_lo + n_rows) are skipped; start
+// and cnt are indexed by window-relative rows.
 hipError_t launch_seg_fill(const ProbIn& in, int f_first, int nf, int H, int W, const int32_t* l, const int32_t* rank,
                            const int32_t* start, uint32_t* ent_pix, float* ent_w, float* ent_s, int weighting,
-                           const int32_t* cnt, int64_t cnt_stride, const float* wpix, float mix, hipStream_t s);
+                           const int32_t* cnt, int64_t cnt_stride, const float* wpix, float mix, int64_t win_lo,
+                           int64_t n_rows, hipStream_t s);
 // Frames [f_first, f_first + nf) of planar FP32 input as pixel-major rows of
 // c floats: staging[(f - f_first) * H * W + p][j] (c % 4 == 0, c <= 60).
 hipError_t launch_planar_rows(const ProbIn& in, int f_first, int nf, int H, int W, int c, float* staging,
@@ -118,6 +124,10 @@ bool seg_frame_counts_ok(const MeshDev& m, const ProbIn& in, int nf, int H, int 
 // index from its stored offset, to read E4M3 scales and per-pixel weights by
 // it (then the fill stores neither).
 bool seg_pixels_dense_ok(const MeshDev& m, const ProbIn& in, int nf, int H, int W);
+// counts[0] += labelled valid pixels of the label images img [F][H][W],
+// counts[1] += those whose label is the argmax of the pixel's own input.
+hipError_t launch_agreement(const ProbIn& in, int c, int F, int H, int W, const uint8_t* img,
+                            unsigned long long* counts, hipStream_t s);
 hipError_t launch_render(const int32_t* l, const uint8_t* valid, const uint8_t* labels, int64_t npx,
                          uint8_t* out, hipStream_t s);
 

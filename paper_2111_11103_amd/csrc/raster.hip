@@ -539,26 +539,31 @@ __global__ __launch_bounds__(256) void k_tile_raster(MeshDev m, const float* __r
     const int lane = threadIdx.x & 63;
     const unsigned long long below = (2ull << lane) - 1ull;   // lanes 0..lane (lane 63: all)
     constexpr unsigned long long kRowStart = TS == 16 ? 0x0001000100010001ull : 0x0000000100000001ull;
+    // only rows inside the accumulator's window are counted (row l is
+    // counted at l - win_lo)
     int rk[PPT], head[PPT];
+    bool win[PPT];
 #pragma unroll
     for (int r = 0; r < PPT; ++r) {
-      const int key = use[r] ? l[r] : -1;
+      const int64_t lw = (int64_t)l[r] - m.win_lo;
+      win[r] = use[r] && lw >= 0 && lw < m.n_rows;
+      const int key = win[r] ? l[r] : -1;
       const int prev = __shfl_up(key, 1);
       const unsigned long long heads = __ballot(key != prev) | kRowStart;
       const unsigned long long after = heads & ~below;
       const int next = after ? __ffsll(after) - 1 : 64;
       head[r] = 63 - __clzll(heads & below);
-      const bool lead = use[r] && head[r] == lane;
+      const bool lead = win[r] && head[r] == lane;
       int base = 0;
-      if (lead && out.cnt) atomicAdd(out.cnt + (int64_t)fb * out.cnt_stride + l[r], next - lane);
-      if (lead && out.seg) base = atomicAdd(out.seg + l[r], next - lane);
+      if (lead && out.cnt) atomicAdd(out.cnt + (int64_t)fb * out.cnt_stride + lw, next - lane);
+      if (lead && out.seg) base = atomicAdd(out.seg + lw, next - lane);
       rk[r] = base;
     }
     if (out.seg) {
 #pragma unroll
       for (int r = 0; r < PPT; ++r) {
         const int base = __shfl(rk[r], head[r]);
-        if (use[r]) out.rank[pix[r]] = base + (lane - head[r]);
+        if (win[r]) out.rank[pix[r]] = base + (lane - head[r]);
       }
     }
   }

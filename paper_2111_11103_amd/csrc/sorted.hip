@@ -145,7 +145,8 @@ __global__ __launch_bounds__(256) void k_seg_fill(ProbIn in, int f_first, int H,
                                                   uint32_t* __restrict__ ent_pix, float* __restrict__ ent_w,
                                                   float* __restrict__ ent_s, int weighting,
                                                   const int32_t* __restrict__ cnt, int64_t cnt_stride,
-                                                  const float* __restrict__ wpix, float mix) {
+                                                  const float* __restrict__ wpix, float mix, int64_t win_lo,
+                                                  int64_t n_rows) {
   constexpr int P = 4;
   const int fb = blockIdx.y;
   const int64_t HW = (int64_t)H * W;
@@ -157,7 +158,9 @@ __global__ __launch_bounds__(256) void k_seg_fill(ProbIn in, int f_first, int H,
   for (int k = 0; k < P; ++k) {
     p[k] = (chunk * P + k) * 256 + threadIdx.x;
     ok[k] = p[k] < HW;
-    l[k] = ok[k] ? lbuf[(int64_t)fb * HW + p[k]] : -1;
+    // window-relative row (-1: no triangle, invalid, or outside the window)
+    const int64_t lw = ok[k] ? (int64_t)lbuf[(int64_t)fb * HW + p[k]] - win_lo : -1;
+    l[k] = (lw >= 0 && lw < n_rows) ? (int)lw : -1;
     if (l[k] >= 0 && in.valid && !in.valid[(int64_t)(f_first + fb) * HW + p[k]]) l[k] = -1;
   }
 #pragma unroll
@@ -299,11 +302,11 @@ __global__ __launch_bounds__(256) void k_seg_gather(MeshDev m, ProbIn in, PixDec
                                                     const float* __restrict__ ent_w, const float* __restrict__ ent_s) {
   const int lane = threadIdx.x & 63;
   const int64_t x0 = (((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6) * 64;
-  if (x0 >= m.n_texels) return;
+  if (x0 >= m.n_rows) return;
   const int c = m.c;
   const int64_t xl = x0 + lane;
   int s = 0, e = 0;
-  if (xl < m.n_texels) {
+  if (xl < m.n_rows) {
     s = start[xl];
     e = start[xl + 1];
   }
@@ -565,7 +568,7 @@ hipError_t launch_seg_gather(const MeshDev& m, const ProbIn& in, int f_first, in
                              const int32_t* rows, const int32_t* nrows, const uint32_t* ent, const float* ent_w,
                              const float* ent_s, int nf, int frame_w, float mix, const float* wpix,
                              hipStream_t s) {
-  if (m.n_texels == 0) return hipSuccess;
+  if (m.n_rows == 0) return hipSuccess;
   if (frame_w && ((frame_w != 1 && frame_w != 3) || !seg_frame_counts_ok(m, in, nf, H, W)))
     return hipErrorInvalidValue;
   // E4M3 without per-entry scales, or per-pixel weights: read by pixel index
@@ -581,7 +584,7 @@ hipError_t launch_seg_gather(const MeshDev& m, const ProbIn& in, int f_first, in
     const size_t lds = frame_w ? (size_t)16 * nf * 4 : 0;
     // enough resident groups to cover the machine; each walks the row list
     // grid: gather_waves resident waves (4 row groups each) on each of the 256 CUs
-    const int64_t groups = std::min<int64_t>(m.n_texels, (int64_t)256 * m.gather_waves * 4);
+    const int64_t groups = std::min<int64_t>(m.n_rows, (int64_t)256 * m.gather_waves * 4);
     dim3 g((unsigned)((groups * 16 + 255) / 256));
 #define LF_R(DT, AGG, AT)                                                                                    \
   do {                                                                                                       \
@@ -605,7 +608,7 @@ hipError_t launch_seg_gather(const MeshDev& m, const ProbIn& in, int f_first, in
 #undef LF_R
     return hipGetLastError();
   }
-  const int64_t waves = (m.n_texels + 63) / 64;
+  const int64_t waves = (m.n_rows + 63) / 64;
   dim3 g((unsigned)((waves + 3) / 4));
 #define LF_G(NCH, DT, AGG, AT) k_seg_gather<NCH, DT, AGG, AT><<<g, 256, 0, s>>>(m, in, dec, start, ent, ent_w, ent_s)
 #define LF_G2(NCH, DT)                                                                                       \
@@ -646,12 +649,13 @@ hipError_t launch_planar_rows(const ProbIn& in, int f_first, int nf, int H, int 
 
 hipError_t launch_seg_fill(const ProbIn& in, int f_first, int nf, int H, int W, const int32_t* l, const int32_t* rank,
                            const int32_t* start, uint32_t* ent_pix, float* ent_w, float* ent_s, int weighting,
-                           const int32_t* cnt, int64_t cnt_stride, const float* wpix, float mix, hipStream_t s) {
+                           const int32_t* cnt, int64_t cnt_stride, const float* wpix, float mix, int64_t win_lo,
+                           int64_t n_rows, hipStream_t s) {
   if (nf <= 0) return hipSuccess;
   const int64_t HW = (int64_t)H * W;
   const unsigned gx = (unsigned)(((HW + 1023) / 1024 + 7) / 8 * 8);   // chunks, rounded up to a multiple of 8
   k_seg_fill<<<dim3(gx, (unsigned)nf), 256, 0, s>>>(in, f_first, H, W, l, rank, start, ent_pix, ent_w, ent_s, weighting,
-                                                    cnt, cnt_stride, wpix, mix);
+                                                    cnt, cnt_stride, wpix, mix, win_lo, n_rows);
   return hipGetLastError();
 }
 

@@ -107,3 +107,49 @@ def evaluate(w, mlp: sf.WeightMLP | None, device="cuda"):
         if "input" not in res:
             res["input"] = float((probs.argmax(1)[seen] == gt[seen]).float().mean())
     return res
+
+
+@torch.no_grad()
+def judge(mesh, cams, probs, mlp, *, valid=None, scale=None, holdout_every=5, batch=16,
+          scatter_mode=sf.SCATTER_AUTO, margin=0.0):
+    """Plain uniform fusion as judge and fallback of the learned weight.
+
+    Every ``holdout_every``-th frame is held out.  The other frames are fused
+    twice -- with w^(P) = 1 and with the learned weight -- and each fused
+    texture's labels are rendered into the held-out frames and compared with
+    those frames' own argmax labels (lf_label_agreement): the label error the
+    learned weight is trained to reduce, measured on frames neither fusion
+    saw.  The learned weight is kept only when its agreement beats plain
+    fusion's by more than ``margin``; otherwise the fallback is w = 1.  The
+    mesh's accumulator is left clear.  Returns a dict with ``choice``
+    (sf.W_LEARNED or sf.W_PIXEL) and both agreements."""
+    F = cams.shape[0]
+    if F < 2 or holdout_every < 2:
+        raise ValueError("the judge needs at least two frames and holdout_every >= 2")
+    dev = probs.device
+    ho = (torch.arange(F, device=dev) % holdout_every) == holdout_every - 1
+    fi, hi = (~ho).nonzero().squeeze(1), ho.nonzero().squeeze(1)
+    cams_f, cams_h = cams[fi].contiguous(), cams[hi].contiguous()
+    probs_f, probs_h = probs[fi], probs[hi]
+    valid_f = valid_h = scale_f = scale_h = None
+    if valid is not None:
+        valid_f, valid_h = valid[fi].contiguous(), valid[hi].contiguous()
+    if scale is not None:
+        scale_f, scale_h = scale[fi].contiguous(), scale[hi].contiguous()
+    H, W = probs.shape[2], probs.shape[3]
+    l_h = mesh.rasterize(cams_h, H, W, want=("l",))["l"]
+    agree = {}
+    for name, wt in (("plain", sf.W_PIXEL), ("learned", sf.W_LEARNED)):
+        if wt == sf.W_LEARNED:
+            mesh.bind_mlp(mlp)
+        mesh.reset()
+        mesh.fuse_frames(cams_f, probs_f, scale=scale_f, valid=valid_f, weighting=wt, batch=batch,
+                         scatter_mode=scatter_mode)
+        _, lab = mesh.finalize(want_tex=False)
+        img = mesh.render_labels(lab, l=l_h, valid=valid_h)
+        n, a = (int(v) for v in sf.label_agreement(probs_h, img, scale=scale_h, valid=valid_h).cpu())
+        agree[name] = a / max(n, 1)
+    mesh.reset()
+    choice = sf.W_LEARNED if agree["learned"] > agree["plain"] + margin else sf.W_PIXEL
+    return {"choice": choice, "agreement_plain": agree["plain"], "agreement_learned": agree["learned"],
+            "heldout_frames": int(hi.numel()), "fused_frames": int(fi.numel())}

@@ -74,6 +74,8 @@ def lib():
             L.lf_frame_ws_bytes.argtypes = [_p, _i32, _i32, _i32, _i32, _i32, C.POINTER(_i64)]
             L.lf_fuse_frames.argtypes = [_p, _p, _i32, _i32, _i32, _p, _i32, _p, _p, _p, _i32, _p, _p, _i64, _i32,
                                          _i32, _p]
+            L.lf_set_window.argtypes = [_p, _i64, _i64, _p, _p]
+            L.lf_label_agreement.argtypes = [_p, _i32, _p, _p, _p, _i32, _i32, _i32, _i32, _p, _p, _p]
             L.lf_finalize.argtypes = [_p, _p, _i32, _p, _p]
             L.lf_render_labels.argtypes = [_p, _p, _i32, _i32, _i32, _p, _p, _p, _p, _p, _i64, _p]
             L.lf_rasterize.argtypes = [_p, _p, _i32, _i32, _i32, _p, _p, _p, _p, _i64, _p]
@@ -109,7 +111,8 @@ def lib():
                          "lf_adam_step", "lf_extract_features", "lf_set_tuning", "lf_get_tuning",
                          "lf_batch_ws_bytes", "lf_fuse_batch", "lf_graph_capture_batch", "lf_graph_launch",
                          "lf_fuse_ws_bytes", "lf_area_ws_bytes", "lf_triangle_max_pixels", "lf_texel_resolution",
-                         "lf_set_weight_mix", "lf_set_overlap"):
+                         "lf_set_weight_mix", "lf_set_overlap", "lf_set_window",
+                         "lf_label_agreement"):
                 getattr(L, name).restype = _i32
             _lib = L
     return _lib
@@ -174,7 +177,8 @@ class Mesh:
 
     def __init__(self, vertices: torch.Tensor, faces: torch.Tensor, *, n_classes: int, s: int = 1,
                  scheme: int = SPLIT, aggregator: int = AGG_SUM, s_face: torch.Tensor | None = None,
-                 z_near: float = 0.05, keep_weights: bool = True, accum_dtype=torch.float32):
+                 z_near: float = 0.05, keep_weights: bool = True, accum_dtype=torch.float32,
+                 whole_texture: bool = True):
         _need_cuda(vertices, "vertices", torch.float32)
         _need_cuda(faces, "faces", torch.int32)
         vertices = vertices.contiguous()
@@ -188,9 +192,15 @@ class Mesh:
         self.vertices = vertices
         self.n_faces = int(faces.shape[0])
         self.ws = torch.empty(max(ws_bytes, 256), dtype=torch.uint8, device=self.device)
-        self.accum = torch.empty((self.n_texels, self.c), dtype=accum_dtype, device=self.device)
+        # whole_texture=False: no accumulator of all rows (the texture is fused
+        # window by window, see set_window / fuse_windowed)
+        self.accum = torch.empty((self.n_texels, self.c), dtype=accum_dtype, device=self.device) \
+            if whole_texture else None
         self.wsum = torch.empty(self.n_texels, dtype=torch.float32, device=self.device) \
-            if (keep_weights or aggregator == AGG_MUL) else None
+            if (whole_texture and (keep_weights or aggregator == AGG_MUL)) else None
+        self.accum_dtype = accum_dtype
+        self.aggregator = aggregator
+        self.win = (0, self.n_texels if whole_texture else 0)
         sf = None
         if s_face is not None:
             sf = s_face.to(device=self.device, dtype=torch.int32).contiguous()
@@ -257,9 +267,11 @@ class Mesh:
                                     weighting, _ptr(l_out), _ptr(ws), ws.numel(), b, scatter_mode, _stream()))
 
     def finalize(self, tex_dtype=torch.float32, want_tex=True):
-        """lf_finalize -> (texture [n_texels, c] or None, labels [n_texels] uint8)."""
-        tex = torch.empty((self.n_texels, self.c), dtype=tex_dtype, device=self.device) if want_tex else None
-        lab = torch.empty(self.n_texels, dtype=torch.uint8, device=self.device)
+        """lf_finalize -> (texture [rows, c] or None, labels [rows] uint8) of the
+        current texel-row window (all n_texels rows unless a window is set)."""
+        n = self.win[1]
+        tex = torch.empty((n, self.c), dtype=tex_dtype, device=self.device) if want_tex else None
+        lab = torch.empty(n, dtype=torch.uint8, device=self.device)
         _check(lib().lf_finalize(self._h, _ptr(tex), _TEX_DT[tex_dtype], _ptr(lab), _stream()))
         return tex, lab
 
@@ -298,6 +310,53 @@ class Mesh:
         _check(lib().lf_rasterize(self._h, _ptr(cams), F, H, W, _ptr(out["tri"]), _ptr(out["l"]), _ptr(out["z"]),
                                   _ptr(ws), ws.numel(), _stream()))
         return out
+
+    def set_window(self, row_lo=0, n_rows=None, accum=None, wsum=None):
+        """lf_set_window: accumulate only texel rows [row_lo, row_lo + n_rows)
+        into ``accum`` [n_rows, c] (and ``wsum`` [n_rows]); no arguments restore
+        the whole-texture accumulator given at load."""
+        n_rows = self.n_texels if n_rows is None else int(n_rows)
+        _need_cuda(accum, "accum", self.accum_dtype)
+        _need_cuda(wsum, "wsum", torch.float32)
+        if accum is not None and (not accum.is_contiguous() or tuple(accum.shape) != (n_rows, self.c)):
+            raise ValueError("accum must be a contiguous [n_rows, c] tensor")
+        _check(lib().lf_set_window(self._h, int(row_lo), n_rows, _ptr(accum), _ptr(wsum)))
+        self.win = (int(row_lo), n_rows)
+        self._win_bufs = (accum, wsum)
+        self._fws.clear()
+
+    def fuse_windowed(self, cams, probs, *, window_rows, scale=None, valid=None, weighting=W_PIXEL, batch=16,
+                      scatter_mode=SCATTER_AUTO, tex_dtype=torch.float32, labels=None, tex_out=None):
+        """Out-of-core fusion: the texture is fused ``window_rows`` texel rows
+        at a time (every window renders all frames again and aggregates only
+        its rows into a device buffer of window_rows x c), normalised, and its
+        rows copied out.  Returns (texture [n_texels, c] in ``tex_out`` -- by
+        default pinned host memory -- and labels [n_texels] uint8 on the
+        device, for render_labels).  The whole-texture state is restored
+        afterwards."""
+        window_rows = max(1, min(int(window_rows), self.n_texels))
+        if labels is None:
+            labels = torch.empty(self.n_texels, dtype=torch.uint8, device=self.device)
+        if tex_out is None:
+            tex_out = torch.empty((self.n_texels, self.c), dtype=tex_dtype, pin_memory=True)
+        acc = torch.empty((window_rows, self.c), dtype=self.accum_dtype, device=self.device)
+        ws = torch.empty(window_rows, dtype=torch.float32, device=self.device) if self.aggregator == AGG_MUL else None
+        saved = self.win
+        for lo in range(0, self.n_texels, window_rows):
+            n = min(window_rows, self.n_texels - lo)
+            self.set_window(lo, n, acc[:n], None if ws is None else ws[:n])
+            self.reset()
+            self.fuse_frames(cams, probs, scale=scale, valid=valid, weighting=weighting, batch=batch,
+                             scatter_mode=scatter_mode)
+            t, lab = self.finalize(tex_dtype)
+            labels[lo:lo + n].copy_(lab)
+            tex_out[lo:lo + n].copy_(t, non_blocking=tex_out.is_pinned())
+        torch.cuda.current_stream().synchronize()
+        if saved[1] == self.n_texels and self.accum is not None:
+            self.set_window()
+        else:
+            self.set_window(0, 0, acc[:0], None if ws is None else ws[:0])
+        return tex_out, labels
 
     def set_weight_mix(self, alpha: float):
         """lf_set_weight_mix: alpha of weighting=W_MIX ((1 - alpha) w^(P) + alpha w^(I))."""
@@ -531,6 +590,23 @@ class Graph:
         if h is not None and h.value and _lib is not None:
             _lib.lf_graph_free(h)
             self._h = None
+
+
+def label_agreement(probs, images, *, scale=None, valid=None, counts=None):
+    """lf_label_agreement -> int64 [2] device tensor: (labelled valid pixels,
+    those whose label is the pixel's own argmax), accumulated into ``counts``."""
+    F, c, H, W = probs.shape
+    dt, strides, scale = _probs_arg(probs, scale)
+    _need_cuda(images, "images", torch.uint8)
+    _need_cuda(valid, "valid", torch.uint8)
+    images = images.contiguous()
+    if valid is not None:
+        valid = valid.contiguous()
+    if counts is None:
+        counts = torch.zeros(2, dtype=torch.int64, device=probs.device)
+    _check(lib().lf_label_agreement(_ptr(probs), dt, strides, _ptr(scale), _ptr(valid), c, F, H, W, _ptr(images),
+                                    _ptr(counts), _stream()))
+    return counts
 
 
 def texel_resolution(area: torch.Tensor, gamma: float) -> torch.Tensor:

@@ -30,7 +30,10 @@ def _fuse_both(gm, om, w, cams, probs_np, valid_np, weighting, aggregator=sf.AGG
                    batch=batch, scatter_mode=scatter, scale=scale)
     torch.cuda.synchronize()
     l_g = l_out.cpu().numpy()
-    return l_g
+    # the oracle is fed its own rows; the GPU's must equal them bit for bit
+    _, l_o = om.raster_frames(cams, H, W)
+    assert np.array_equal(l_g, l_o), f"{int((l_g != l_o).sum())} texel rows differ from the oracle"
+    return l_o
 
 
 def test_config1_raster_bit_exact(cfg1):
@@ -177,7 +180,8 @@ def test_nhwc_and_fp8_inputs(cfg1):
     l_out = torch.empty((10, cfg1.H, cfg1.W), dtype=torch.int32, device="cuda")
     gm.fuse_frames(to_dev(cams, torch.float32), nhwc, l_out=l_out)
     torch.cuda.synchronize()
-    l_g = l_out.cpu().numpy()
+    _, l_g = om.raster_frames(cams, cfg1.H, cfg1.W)
+    assert np.array_equal(l_out.cpu().numpy(), l_g)
     A_o, _ = oracle.fuse(om.n_texels, 13, l_g, probs.numpy())
     compare_fused(gm.accum.cpu().numpy(), A_o)
     q, scale = S.quantize_fp8(probs)
@@ -186,6 +190,7 @@ def test_nhwc_and_fp8_inputs(cfg1):
         gm8 = gpu_mesh((sc.vertices, sc.faces), 1, oracle.SPLIT, 13)
         gm8.fuse_frames(to_dev(cams, torch.float32), q.cuda(), scale=scale.cuda(), l_out=l_out, scatter_mode=mode)
         torch.cuda.synchronize()
+        assert np.array_equal(l_out.cpu().numpy(), l_g)
         compare_fused(gm8.accum.cpu().numpy(), A8)
     # channels-last FP8 codes
     q_cl = q.to(memory_format=torch.channels_last).cuda()
