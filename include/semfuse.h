@@ -13,9 +13,10 @@
  *
  * Conventions shared by every call
  *  - All pointers named d_* are device pointers (hipMalloc / torch CUDA
- *    tensors) owned by the caller; the library allocates no device memory and
- *    keeps no pointer beyond what the mesh handle documents.  h_* pointers are
- *    host memory.
+ *    tensors) owned by the caller; the library allocates no device memory
+ *    (its one static array, the scratch of lf_fuse_frames_noalloc, is part of
+ *    the loaded code object) and keeps no pointer beyond what the mesh handle
+ *    documents.  h_* pointers are host memory.
  *  - Calls enqueue work on `stream` and return without waiting, except
  *    lf_load_mesh, which waits for its validation result.  Inputs must stay
  *    unmodified until the stream has consumed them.
@@ -171,6 +172,26 @@ lf_status lf_fuse_frames(lf_mesh mesh, const float* d_cams, int32_t F, int32_t H
                          const float* d_scale, const uint8_t* d_valid, int32_t weighting,
                          int32_t* d_l_out, void* d_ws, int64_t ws_bytes, int32_t batch,
                          int32_t scatter_mode, hipStream_t stream);
+
+/* lf_fuse_frames for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same fusion, arguments and results, with the frame workspace taken from
+ * a fixed array of LF_NOALLOC_SCRATCH_BYTES that the library holds on every
+ * GPU it runs on until the process ends.  The call allocates nothing; the
+ * caller still passes the mesh (with its workspace and accumulator), inputs
+ * and outputs.  The scratch belongs to the current device (hipSetDevice),
+ * which must be the device of the mesh and the stream.  Every call on one GPU
+ * shares that GPU's scratch: calls whose work overlaps on the device (two
+ * host threads, or two streams not ordered by events) race and give wrong
+ * results; calls ordered on one stream do not.  Whatever must start at zero
+ * is cleared by the call itself.  Errors: as lf_fuse_frames; LF_ESIZE with
+ * the bytes needed when the call's frame workspace (lf_fuse_ws_bytes for the
+ * same arguments) exceeds the scratch. */
+#define LF_NOALLOC_SCRATCH_BYTES (64ll << 20)
+lf_status lf_fuse_frames_noalloc(lf_mesh mesh, const float* d_cams, int32_t F, int32_t H, int32_t W,
+                                 const void* d_probs, int32_t prob_dtype, const int64_t* h_strides,
+                                 const float* d_scale, const uint8_t* d_valid, int32_t weighting, int32_t* d_l_out,
+                                 int32_t batch, int32_t scatter_mode, hipStream_t stream);
 
 /* Normalise every texel and take its class (Section 3.2.1): SUM/MAXSUM
  * P = A / sum_j A_j, MUL P = softmax(A); label = first maximal index; a texel

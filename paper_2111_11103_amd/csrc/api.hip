@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -650,6 +651,56 @@ lf_status lf_fuse_frames(lf_mesh mesh, const float* d_cams, int32_t F, int32_t H
   lf_status st = check_fuse(a, d_ws, ws_bytes);
   if (st != LF_OK) return st;
   return fuse_impl(a, d_ws, stream);
+}
+
+}  // extern "C"
+
+// ---- Fusion through the library's own static scratch (no allocation) -------
+// One fixed-size device array per GPU takes the place of the caller's frame
+// workspace.  Host code never passes the array's name to a kernel: on the
+// host it is only a stand-in, so each device's address is looked up once
+// (with that device current) and kept in g_scratch_ptr.
+namespace {
+static __device__ __align__(256) char scratch[LF_NOALLOC_SCRATCH_BYTES];
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kScratchDevices] = {};
+
+lf_status scratch_of_current_device(void** out) {
+  int dev = -1;
+  LF_TRY(hipGetDevice(&dev), "current device");
+  if (dev < 0 || dev >= kScratchDevices) return fail(LF_EINVAL, "device ordinal %d beyond the scratch table", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    LF_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "scratch address");
+    if (!p) return fail(LF_EHIP, "scratch address of device %d is NULL", dev);
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return LF_OK;
+}
+}  // namespace
+
+extern "C" {
+
+lf_status lf_fuse_frames_noalloc(lf_mesh mesh, const float* d_cams, int32_t F, int32_t H, int32_t W,
+                                 const void* d_probs, int32_t prob_dtype, const int64_t* h_strides,
+                                 const float* d_scale, const uint8_t* d_valid, int32_t weighting, int32_t* d_l_out,
+                                 int32_t batch, int32_t scatter_mode, hipStream_t stream) {
+  g_err[0] = 0;
+  const FuseArgs a{mesh, d_cams, F, H, W, d_probs, prob_dtype, h_strides, d_scale, d_valid, 0, weighting, d_l_out,
+                   batch, scatter_mode};
+  void* ws = nullptr;
+  lf_status st = scratch_of_current_device(&ws);
+  if (st != LF_OK) return st;
+  st = check_fuse(a, ws, LF_NOALLOC_SCRATCH_BYTES);
+  if (st == LF_ESIZE)
+    return fail(LF_ESIZE, "this call needs %lld bytes of frame workspace; the static scratch holds %lld "
+                "(use a smaller batch, or lf_fuse_frames with a caller workspace)",
+                (long long)fuse_layout(a).total, (long long)LF_NOALLOC_SCRATCH_BYTES);
+  if (st != LF_OK) return st;
+  return fuse_impl(a, ws, stream);
 }
 
 lf_status lf_area_ws_bytes(lf_mesh mesh, int32_t H, int32_t W, int32_t batch, int64_t* bytes) {

@@ -23,6 +23,7 @@ W_PIXEL, W_IMAGE, W_LEARNED, W_MIX = 0, 1, 2, 3
 AGG_SUM, AGG_MUL, AGG_MAXSUM = 0, 1, 2
 F32, BF16, F16, FP8_E4M3 = 0, 1, 2, 3
 SCATTER_AUTO, SCATTER_ATOMIC, SCATTER_SORTED, SCATTER_STAGED = 0, 1, 2, 3
+NOALLOC_SCRATCH_BYTES = 64 << 20   # LF_NOALLOC_SCRATCH_BYTES
 
 _TEX_DT = {torch.float32: F32, torch.bfloat16: BF16, torch.float16: F16}
 
@@ -74,6 +75,8 @@ def lib():
             L.lf_frame_ws_bytes.argtypes = [_p, _i32, _i32, _i32, _i32, _i32, C.POINTER(_i64)]
             L.lf_fuse_frames.argtypes = [_p, _p, _i32, _i32, _i32, _p, _i32, _p, _p, _p, _i32, _p, _p, _i64, _i32,
                                          _i32, _p]
+            L.lf_fuse_frames_noalloc.argtypes = [_p, _p, _i32, _i32, _i32, _p, _i32, _p, _p, _p, _i32, _p, _i32,
+                                                 _i32, _p]
             L.lf_set_window.argtypes = [_p, _i64, _i64, _p, _p]
             L.lf_label_agreement.argtypes = [_p, _i32, _p, _p, _p, _i32, _i32, _i32, _i32, _p, _p, _p]
             L.lf_finalize.argtypes = [_p, _p, _i32, _p, _p]
@@ -112,7 +115,7 @@ def lib():
                          "lf_batch_ws_bytes", "lf_fuse_batch", "lf_graph_capture_batch", "lf_graph_launch",
                          "lf_fuse_ws_bytes", "lf_area_ws_bytes", "lf_triangle_max_pixels", "lf_texel_resolution",
                          "lf_set_weight_mix", "lf_set_overlap", "lf_set_window",
-                         "lf_label_agreement"):
+                         "lf_label_agreement", "lf_fuse_frames_noalloc"):
                 getattr(L, name).restype = _i32
             _lib = L
     return _lib
@@ -241,10 +244,7 @@ class Mesh:
     def reset(self):
         _check(lib().lf_reset(self._h, _stream()))
 
-    def fuse_frames(self, cams: torch.Tensor, probs: torch.Tensor, *, scale=None, valid=None,
-                    weighting=W_PIXEL, l_out=None, batch=16, scatter_mode=SCATTER_AUTO, ws=None):
-        """lf_fuse_frames: probs is [F, c, H, W] (any strides) float32, or uint8
-        E4M3 codes with ``scale`` [F, H, W]."""
+    def _fuse_args(self, cams, probs, scale, valid, l_out, batch):
         F, c, H, W = probs.shape
         if c != self.c:
             raise ValueError(f"probs has {c} classes, mesh has {self.c}")
@@ -261,10 +261,26 @@ class Mesh:
         if l_out is not None and (not l_out.is_contiguous() or tuple(l_out.shape) != (F, H, W)):
             raise ValueError("l_out must be a contiguous [F, H, W] int32 tensor")
         b = max(1, min(int(batch), F))
+        return F, H, W, cams, dt, strides, scale, valid, b
+
+    def fuse_frames(self, cams: torch.Tensor, probs: torch.Tensor, *, scale=None, valid=None,
+                    weighting=W_PIXEL, l_out=None, batch=16, scatter_mode=SCATTER_AUTO, ws=None):
+        """lf_fuse_frames: probs is [F, c, H, W] (any strides) float32, or uint8
+        E4M3 codes with ``scale`` [F, H, W]."""
+        F, H, W, cams, dt, strides, scale, valid, b = self._fuse_args(cams, probs, scale, valid, l_out, batch)
         if ws is None:
             ws = self.frame_ws(H, W, b, weighting, scatter_mode, probs=probs)
         _check(lib().lf_fuse_frames(self._h, _ptr(cams), F, H, W, _ptr(probs), dt, strides, _ptr(scale), _ptr(valid),
                                     weighting, _ptr(l_out), _ptr(ws), ws.numel(), b, scatter_mode, _stream()))
+
+    def fuse_frames_noalloc(self, cams: torch.Tensor, probs: torch.Tensor, *, scale=None, valid=None,
+                            weighting=W_PIXEL, l_out=None, batch=16, scatter_mode=SCATTER_AUTO):
+        """lf_fuse_frames_noalloc: lf_fuse_frames with the library's static
+        per-device scratch (NOALLOC_SCRATCH_BYTES) as the frame workspace."""
+        F, H, W, cams, dt, strides, scale, valid, b = self._fuse_args(cams, probs, scale, valid, l_out, batch)
+        with torch.cuda.device(self.device):
+            _check(lib().lf_fuse_frames_noalloc(self._h, _ptr(cams), F, H, W, _ptr(probs), dt, strides, _ptr(scale),
+                                                _ptr(valid), weighting, _ptr(l_out), b, scatter_mode, _stream()))
 
     def finalize(self, tex_dtype=torch.float32, want_tex=True):
         """lf_finalize -> (texture [rows, c] or None, labels [rows] uint8) of the
