@@ -30,7 +30,7 @@ sys.path.insert(0, ROOT)
 METRIC = "fused pixels/sec (c=40, 640×480) + % HBM roofline; learned/BF16 vs plain at label acc"
 HBM_PEAK_GBS = 8000.0
 STAGES = ["raster", "resolve", "scatter", "counts", "finalize", "render", "reset", "mlp"]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_seg_gather16_room500k_640x480_c40.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_bucket_gather16_room500k_640x480_c40.txt")
 ISO_GATHER_WAVES = 512      # gather grid when it has the device alone: 8x more groups than fit, rows balance
 
 
@@ -71,25 +71,108 @@ def measured_traffic(launch):
     return None
 
 
-def cpu_baseline(work, n_frames: int):
-    """The CPU oracle (raster on the host's cores, binary64 fusion) on the
-    first ``n_frames`` frames of the same workload; fused pixels/s."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def oracle_fuse_timed(work, n_frames: int, threads: int):
+    """The CPU oracle (raster on `threads` host threads, binary64 fusion) on
+    the first ``n_frames`` frames of the workload: (seconds, rows, A)."""
     import oracle
     sc = work.scene
-    threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
-    threads = max(1, min(threads, 16))
     probs = work.probs[:n_frames].cpu().numpy()
     valid = work.valid[:n_frames].cpu().numpy()
-    cams = work.cams[:n_frames]
     t0 = time.perf_counter()
     om = oracle.Mesh(sc.vertices, sc.faces, s=work.s, scheme=work.scheme)
-    _, l = om.raster_frames(cams, work.H, work.W, threads=threads)
-    oracle.fuse(om.n_texels, sc.n_classes, l, probs, valid)
-    dt = time.perf_counter() - t0
-    px = n_frames * work.H * work.W
-    return {"value": px / dt, "unit": "fused pixels/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {n_frames} of {len(work.cams)} frames of the same workload (raster on {threads} "
-                      f"threads, binary64 fusion on 1 thread), {dt:.1f} s"}
+    _, l = om.raster_frames(work.cams[:n_frames], work.H, work.W, threads=threads)
+    A, _ = oracle.fuse(om.n_texels, sc.n_classes, l, probs, valid)
+    return time.perf_counter() - t0, l, A
+
+
+def cpu_baseline(work, n_frames: int, n_frames_1t: int):
+    """The CPU oracle on the first ``n_frames`` frames with the box's threads
+    (up to 16, its CPU share) and on the first ``n_frames_1t`` frames with one
+    thread; fused pixels/s.  Also returns the oracle's rows and binary64
+    texture of the larger sample, for the benchmark's own result check."""
+    threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    threads = max(1, min(threads, 16))
+    px = work.H * work.W
+    dt, l, A = oracle_fuse_timed(work, n_frames, threads)
+    dt1, _, _ = oracle_fuse_timed(work, n_frames_1t, 1)
+    res = {"value": n_frames * px / dt, "unit": "fused pixels/s", "cores": threads, "kind": "oracle",
+           "sample": f"first {n_frames} of {len(work.cams)} frames of the same workload (raster on {threads} "
+                     f"threads, binary64 fusion on 1 thread), {dt:.1f} s",
+           "one_thread": {"value": n_frames_1t * px / dt1, "cores": 1,
+                          "sample": f"first {n_frames_1t} frames, raster and fusion on 1 thread, {dt1:.1f} s"},
+           "cpu_model": cpu_model()}
+    return res, l, A
+
+
+def device_probe(dev, copy_mib=2048, n_atomics=1 << 26):
+    """Measured ceilings of the device: a plain device-to-device copy (bytes
+    read + written per second) and FP32 atomic additions per second (torch's
+    index_add_) to scattered distinct addresses, to consecutive addresses
+    (16 lanes per 64-byte line) and to 64 contended addresses."""
+    import torch
+    n = copy_mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    b.copy_(a)
+    e0.record()
+    for _ in range(5):
+        b.copy_(a)
+    e1.record()
+    e1.synchronize()
+    copy_gbs = 5 * 2 * n * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    g = torch.Generator(device=dev).manual_seed(0)
+    src = torch.ones(n_atomics, dtype=torch.float32, device=dev)
+    out = torch.zeros(n_atomics, dtype=torch.float32, device=dev)
+    cases = {"scattered_distinct": torch.randperm(n_atomics, device=dev, generator=g),
+             "consecutive_distinct": torch.arange(n_atomics, device=dev),
+             "contended_64_addresses": torch.arange(n_atomics, device=dev) % 64}
+    rates = {}
+    for name, idx in cases.items():
+        out.index_add_(0, idx, src)
+        e0.record()
+        for _ in range(3):
+            out.index_add_(0, idx, src)
+        e1.record()
+        e1.synchronize()
+        rates[name] = 3 * n_atomics / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, out, cases
+    torch.cuda.empty_cache()
+    return {"copy_gbs": copy_gbs, "copy_bytes": 2 * n * 4,
+            "fp32_atomic_add_g_per_s": rates, "atomic_ops_per_case": n_atomics}
+
+
+def result_check(mesh, cams, probs, valid, l_oracle, A_oracle, batch, scatter, tol=1e-5):
+    """The headline launch configuration run again on the oracle's sample of
+    frames into a cleared accumulator: texel rows bit-exact, every fused
+    entry within ``tol`` relative of the binary64 oracle."""
+    import numpy as np
+    import torch
+    n = l_oracle.shape[0]
+    l_g = torch.empty((n,) + tuple(l_oracle.shape[1:]), dtype=torch.int32, device=probs.device)
+    mesh.reset()
+    mesh.fuse_frames(cams[:n], probs[:n], valid=valid[:n], l_out=l_g, batch=batch, scatter_mode=scatter)
+    torch.cuda.synchronize()
+    rows_equal = bool(np.array_equal(l_g.cpu().numpy(), l_oracle))
+    A_g = mesh.accum.cpu().numpy().astype(np.float64)
+    err = np.abs(A_g - A_oracle)
+    bad = int((err > tol * np.abs(A_oracle)).sum())
+    worst = float((err / np.maximum(np.abs(A_oracle), 1e-300)).max())
+    mesh.reset()
+    return {"frames": n, "texel_rows_bit_exact": rows_equal, "entries": int(A_oracle.size),
+            "entries_beyond_tol": bad, "tol_rel": tol, "max_rel_err": worst, "ok": rows_equal and bad == 0}
 
 
 def accuracy_report(log_fn):
@@ -132,6 +215,55 @@ def accuracy_report(log_fn):
     res["workload"] = ("held-out rooms (2,100 triangles, c=13, 20 frames 160x120, view-dependent noise, seeds "
                        "200-209); learned weight trained on seeds 100-149 by the library's kernels")
     return res, mlp
+
+
+def weight_and_frame_sweeps(log_fn, seeds=range(200, 210)):
+    """The evaluation's two sweeps on synthetic held-out rooms (2,100
+    triangles, c = 13, 20 frames 160x120, view-dependent noise), with the
+    evaluation's f_mul aggregator and triangles as texels (gamma = 0, s = 1):
+    pixel accuracy for weights w = (1 - alpha) w^(P) + alpha w^(I) (Fig. 4a),
+    and for frames taken at uniform intervals with w^(I) (Fig. 4b).  Fused
+    labels are rendered into all 20 frames (pixels whose texel no fused frame
+    saw render void and count as wrong)."""
+    import numpy as np
+    import torch
+    from paper_2111_11103_amd import scenes as S
+    from paper_2111_11103_amd import semfuse as sf
+    alphas = (0.0, 0.25, 0.5, 0.75, 1.0)
+    steps = (1, 2, 3, 4, 5, 10, 20)
+    acc_a = {a: [] for a in alphas}
+    acc_f = {st: [] for st in steps}
+    for sd in seeds:
+        w = S.config1(device="cuda", seed=sd, structured=True)
+        sc = w.scene
+        cams = torch.as_tensor(w.cams, dtype=torch.float32, device="cuda")
+        seen = None
+
+        def fused_accuracy(frames, weighting, alpha=None):
+            nonlocal seen
+            mesh = sf.Mesh(torch.as_tensor(sc.vertices, device="cuda"), torch.as_tensor(sc.faces, device="cuda"),
+                           n_classes=sc.n_classes, s=1, scheme=sf.SPLIT, aggregator=sf.AGG_MUL)
+            if alpha is not None:
+                mesh.set_weight_mix(alpha)
+            mesh.fuse_frames(cams[frames], w.probs[frames], valid=w.valid[frames], weighting=weighting)
+            _, lab = mesh.finalize(want_tex=False)
+            out = mesh.render_labels(lab, cams=cams, H=w.H, W=w.W, valid=w.valid)
+            if seen is None:
+                l = mesh.rasterize(cams, w.H, w.W, want=("l",))["l"]
+                seen = (l >= 0) & (w.valid != 0)
+            return float((out[seen].long() == w.gt[seen]).float().mean())
+
+        for a in alphas:
+            acc_a[a].append(fused_accuracy(slice(None), sf.W_MIX, a))
+        for st in steps:
+            acc_f[st].append(fused_accuracy(slice(None, None, st), sf.W_IMAGE))
+    res = {"aggregator": "f_mul", "texels": "triangles (s = 1)",
+           "accuracy_vs_alpha": {f"{a:g}": float(np.mean(v)) for a, v in acc_a.items()},
+           "accuracy_vs_frame_fraction": {f"{1 / st:.3g}": float(np.mean(v)) for st, v in acc_f.items()},
+           "workload": "held-out rooms (2,100 triangles, c=13, 20 frames 160x120, view-dependent noise, seeds "
+                       "200-209); labels rendered into all 20 frames"}
+    log_fn(f"[bench] weight / frame sweeps: {res}")
+    return res
 
 
 def learned_scale_report(mlp, log_fn, n_frames=1000, pool=16):
@@ -255,6 +387,7 @@ def main():
     ap.add_argument("--input", default="f32", choices=["f32", "fp8"],
                     help="headline input: FP32 probabilities, or OCP E4M3 codes with a per-pixel FP32 scale")
     ap.add_argument("--cpu-frames", type=int, default=200)
+    ap.add_argument("--cpu-frames-1t", type=int, default=16, help="frames of the one-thread oracle timing")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the NCHW / FP8 / w^(I) / learned throughput legs")
     ap.add_argument("--no-accuracy", action="store_true", help="skip the label-accuracy report")
@@ -408,13 +541,19 @@ def main():
                    "tuning": mesh.get_tuning(), "autotuned": tuning is not None},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_seg_gather16", "kernel_ms": scat_ms, "launches": launches,
+                     "kernel": "k_bucket_gather16", "kernel_ms": scat_ms, "launches": launches,
                      "bytes_per_px": per_px, "px_per_launch": px_per_launch,
                      "row_rmw_bytes_per_launch": rmw_bytes,
                      "achieved_incl_row_rmw": (px_per_launch * per_px + rmw_bytes) / (scat_ms * 1e-3) / 1e9},
         "step_hbm_frac": b_min / (t_total / args.steps) / 1e9 / HBM_PEAK_GBS,
         "stage_ms_per_step": stage_ms,
     }
+
+    probe = device_probe(dev)
+    result["device_probe"] = probe
+    result["roofline"]["measured_copy_gbs"] = probe["copy_gbs"]
+    result["roofline"]["frac_of_measured_copy"] = achieved / probe["copy_gbs"]
+    log(f"[bench] device probe: {probe}")
 
     # the same gather launches without the concurrent raster (gathers on the
     # caller's stream, one batch after another) on a grid for the whole device
@@ -429,10 +568,11 @@ def main():
         iso_ms = pr_iso.ms[2] / pr_iso.launches[2]
         iso_px = npx * 2 / pr_iso.launches[2]
         iso_gbs = iso_px * per_px / (iso_ms * 1e-3) / 1e9
-        result["roofline_isolated"] = {"kernel": "k_seg_gather16", "bound": "hbm", "achieved": iso_gbs,
+        result["roofline_isolated"] = {"kernel": "k_bucket_gather16", "bound": "hbm", "achieved": iso_gbs,
                                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": iso_gbs / HBM_PEAK_GBS,
                                        "kernel_ms": iso_ms, "gather_waves": ISO_GATHER_WAVES,
                                        "step_value_without_overlap": 2 * npx / tt_iso}
+        result["roofline_isolated"]["frac_of_measured_copy"] = iso_gbs / probe["copy_gbs"]
         log(f"[bench] gather alone: {iso_ms:.3f} ms/launch, {iso_gbs:.0f} GB/s algorithmic "
             f"({iso_gbs / HBM_PEAK_GBS:.1%}); whole step without overlap {2 * npx / tt_iso / 1e9:.2f} G px/s")
 
@@ -508,14 +648,19 @@ def main():
         log(f"[bench] forms: " + ", ".join(f"{k} {v['value'] / 1e9:.2f} G px/s" for k, v in forms.items()))
 
     if not args.no_cpu:
-        log(f"[bench] CPU oracle on {args.cpu_frames} frames ...")
-        result["cpu_baseline"] = cpu_baseline(work, min(args.cpu_frames, F))
+        log(f"[bench] CPU oracle on {args.cpu_frames} frames (all threads) and {args.cpu_frames_1t} (one thread) ...")
+        result["cpu_baseline"], l_o, A_o = cpu_baseline(work, min(args.cpu_frames, F), min(args.cpu_frames_1t, F))
+        if head_scale is None and args.weighting == 0:
+            result["check"] = result_check(mesh, cams, head_probs, valid, l_o, A_o, args.batch, args.scatter)
+            log(f"[bench] result check against the oracle: {result['check']}")
+        del l_o, A_o
     else:
         result["cpu_baseline"] = None
 
     if not args.no_accuracy:
         result["accuracy"], mlp = accuracy_report(log)
         result["learned_at_scale"] = learned_scale_report(mlp, log)
+        result["sweeps"] = weight_and_frame_sweeps(log)
         del mlp
 
     if not args.no_batched:

@@ -158,9 +158,10 @@ lf_status check_mesh(lf_mesh m) {
 
 struct FrameLayout {
   int64_t vis, vis_n, tcnt, tlist, l, cnt, geo, wpix, seg, rank, sums, total;
-  // what the gather reads, twice: batch k uses set k % 2
-  int64_t start[2], rows[2], nrows[2], ent_off[2], ent_w[2], ent_s[2], stage[2];
-  int64_t list_cap, ntiles;
+  // what the gather reads, twice: batch k uses set k % 2 (counts: [0] spans, [1] non-empty buckets)
+  int64_t bstart[2], blist[2], counts[2], rec[2], rec_w[2], rec_s[2], spans[2], ent_off[2], ent_w[2], ent_s[2],
+      stage[2];
+  int64_t list_cap, ntiles, n_buckets;
   bool sorted;
 };
 
@@ -168,12 +169,18 @@ int64_t tiles_of(int H, int W, int ts) {
   return (int64_t)((W + ts - 1) / ts) * ((H + ts - 1) / ts);
 }
 
-FrameLayout frame_layout(const MeshDev& m, int H, int W, int B, int weighting, int scatter_mode) {
+// grouped: 1 = the grouped gather reads the bucket records (no second sort
+// through memory), 0 = the per-class gather (sorted through memory), -1 =
+// not known (room for both).
+FrameLayout frame_layout(const MeshDev& m, int H, int W, int B, int weighting, int scatter_mode, int grouped = -1) {
   FrameLayout L{};
   const int64_t HW = (int64_t)H * W;
   L.ntiles = tiles_of(H, W, m.tile);
   L.list_cap = 4 * m.T + 64 * L.ntiles + 1024;
   L.sorted = scatter_mode != LF_SCATTER_ATOMIC;
+  L.n_buckets = (m.n_rows + (1 << kBucketShift) - 1) >> kBucketShift;
+  const int64_t max_spans = std::min<int64_t>(m.n_rows, B * HW);
+  const bool spans = L.sorted && grouped != 1;
   int64_t o = 0;
   L.vis = o; o += align256(B * std::max<int64_t>(m.n_clusters, 1) * 4);
   L.vis_n = o; o += align256(B * 4);
@@ -184,19 +191,25 @@ FrameLayout frame_layout(const MeshDev& m, int H, int W, int B, int weighting, i
   L.geo = o; if (weighting == LF_W_LEARNED) o += align256(B * HW * 16);
   // learned weights: two sets on the sorted path, whose gather reads them in place
   L.wpix = o; if (weighting == LF_W_LEARNED) o += align256((L.sorted ? 2 : 1) * B * HW * 4);
-  L.seg = o; if (L.sorted) o += align256(m.n_rows * 4);
+  // first level of the sorted path, used on the caller's stream only: bucket
+  // counts and ranks (resolve), scan partial sums
+  L.seg = o; if (L.sorted) o += align256(L.n_buckets * 4);
   L.rank = o; if (L.sorted) o += align256(B * HW * 4);
-  L.sums = o; if (L.sorted) o += align256((m.n_rows / 8192 + 2) * 4);
+  L.sums = o; if (L.sorted) o += align256((L.n_buckets / 8192 + 2) * 4);
   // AUTO may pick the staged form for planar inputs: size for it too
   const bool staged = scatter_mode == LF_SCATTER_STAGED ||
                       (scatter_mode == LF_SCATTER_AUTO && m.c % 4 == 0 && m.c <= 60);
   for (int k = 0; k < 2; ++k) {
-    L.start[k] = o; if (L.sorted) o += align256((m.n_rows + 1) * 4);
-    L.rows[k] = o; if (L.sorted) o += align256(m.n_rows * 4);
-    L.nrows[k] = o; if (L.sorted) o += 256;
-    L.ent_off[k] = o; if (L.sorted) o += align256(B * HW * 4);
-    L.ent_w[k] = o; if (L.sorted && weighting != LF_W_PIXEL) o += align256(B * HW * 4);
-    L.ent_s[k] = o; if (L.sorted) o += align256(B * HW * 4);
+    L.bstart[k] = o; if (L.sorted) o += align256((L.n_buckets + 1) * 4);
+    L.blist[k] = o; if (L.sorted) o += align256(L.n_buckets * 4);
+    L.counts[k] = o; if (L.sorted) o += 256;
+    L.rec[k] = o; if (L.sorted) o += align256(B * HW * 8);
+    L.rec_w[k] = o; if (L.sorted && weighting != LF_W_PIXEL) o += align256(B * HW * 4);
+    L.rec_s[k] = o; if (L.sorted) o += align256(B * HW * 4);
+    L.spans[k] = o; if (spans) o += align256(max_spans * 16);
+    L.ent_off[k] = o; if (spans) o += align256(B * HW * 4);
+    L.ent_w[k] = o; if (spans && weighting != LF_W_PIXEL) o += align256(B * HW * 4);
+    L.ent_s[k] = o; if (spans) o += align256(B * HW * 4);
     L.stage[k] = o; if (staged) o += align256(B * HW * m.c * 4);
   }
   L.total = o;
@@ -409,9 +422,28 @@ int resolve_mode(const FuseArgs& a) {
   return stage_ok(a.mesh->d, a.dtype) ? LF_SCATTER_STAGED : LF_SCATTER_ATOMIC;
 }
 
+// Whether the sorted path of these arguments gathers with the grouped gather:
+// 1 yes, 0 no (the per-class gather), -1 not known (no input pointer given:
+// room for both).
+int fuse_grouped(const FuseArgs& a, int mode) {
+  if (mode != LF_SCATTER_SORTED && mode != LF_SCATTER_STAGED) return 0;
+  const MeshDev& d = a.mesh->d;
+  if (mode == LF_SCATTER_STAGED) {
+    // staged rows: 256-byte aligned workspace, c floats per pixel
+    const int64_t c = d.c;
+    const ProbIn st{reinterpret_cast<const void*>(uintptr_t(256)), nullptr, nullptr, (int64_t)a.H * a.W * c, 1,
+                    (int64_t)a.W * c, c, LF_F32};
+    return seg_grouped_ok(d, st) ? 1 : 0;
+  }
+  if (!a.probs) return -1;
+  const ProbIn in{a.probs, a.scale, a.valid, a.strides[0], a.strides[1], a.strides[2], a.strides[3], a.dtype};
+  return seg_grouped_ok(d, in) ? 1 : 0;
+}
+
 FrameLayout fuse_layout(const FuseArgs& a) {
   const int B = a.batch < a.F ? a.batch : a.F;
-  return frame_layout(a.mesh->d, a.H, a.W, B > 0 ? B : 1, a.weighting, resolve_mode(a));
+  const int mode = resolve_mode(a);
+  return frame_layout(a.mesh->d, a.H, a.W, B > 0 ? B : 1, a.weighting, mode, fuse_grouped(a, mode));
 }
 
 lf_status check_fuse(const FuseArgs& a, const void* ws, int64_t ws_bytes) {
@@ -476,6 +508,8 @@ lf_status fuse_impl(const FuseArgs& a, void* d_ws, hipStream_t stream) {
   // weight by pixel index itself, and the fill copies neither
   const bool pix_direct =
       sorted && seg_pixels_dense_ok(d, staged ? staged_in(ws + L.stage[0], nullptr) : in, B, H, W);
+  // the grouped gather reads the bucket records; any other layout is sorted by row through memory first
+  const bool grouped = sorted && (staged || seg_grouped_ok(d, in));
   int32_t* seg = sorted ? reinterpret_cast<int32_t*>(ws + L.seg) : nullptr;
   LF_TRY(launch_zero(ws + L.tcnt, B * L.ntiles * 4, stream), "clear tile counts");
   if (cnt) LF_TRY(launch_zero(cnt, (int64_t)B * d.n_rows * 4, stream), "clear counts");
@@ -517,7 +551,7 @@ lf_status fuse_impl(const FuseArgs& a, void* d_ws, hipStream_t stream) {
     const float* cams_in = a.cams + 16 * (int64_t)(f0 - fi);  // camera of input index fi + k is f0 + k
     int32_t* lb = a.l_out ? a.l_out + (int64_t)f0 * HW : reinterpret_cast<int32_t*>(ws + L.l);
     const uint8_t* vb = a.valid ? a.valid + (int64_t)fi * HW : nullptr;
-    if (seg) LF_TRY(launch_zero(seg, d.n_rows * 4, stream), "clear segments");
+    if (seg) LF_TRY(launch_zero(seg, L.n_buckets * 4, stream), "clear bucket counts");
     RasterOut out{lb, nullptr, nullptr, vb, cnt, d.n_rows, seg, rank, geo};
     if ((status = render_batch(mesh, a.cams, f0, nb, H, W, L, ws, out, stream)) != LF_OK) return status;
     const int k = nbatch & 1;   // sorted path: buffer set of this batch
@@ -530,39 +564,51 @@ lf_status fuse_impl(const FuseArgs& a, void* d_ws, hipStream_t stream) {
              "learned weights");
     }
     if (sorted) {
-      int32_t* start = reinterpret_cast<int32_t*>(ws + L.start[k]);
-      int32_t* rows = reinterpret_cast<int32_t*>(ws + L.rows[k]);
-      int32_t* nrows = reinterpret_cast<int32_t*>(ws + L.nrows[k]);
-      uint32_t* eo = reinterpret_cast<uint32_t*>(ws + L.ent_off[k]);
-      float* ew = (a.weighting != LF_W_PIXEL && !frame_counts && !(learned && pix_direct))
-                      ? reinterpret_cast<float*>(ws + L.ent_w[k]) : nullptr;
-      float* es = (a.dtype == LF_FP8_E4M3 && !pix_direct) ? reinterpret_cast<float*>(ws + L.ent_s[k]) : nullptr;
+      int32_t* counts = reinterpret_cast<int32_t*>(ws + L.counts[k]);   // [0] spans, [1] non-empty buckets
+      const bool need_w = a.weighting != LF_W_PIXEL && !frame_counts && !(learned && pix_direct);
+      const bool need_s = a.dtype == LF_FP8_E4M3 && !pix_direct;
+      uint2* rec = reinterpret_cast<uint2*>(ws + L.rec[k]);
+      float* rw = need_w ? reinterpret_cast<float*>(ws + L.rec_w[k]) : nullptr;
+      float* rs = need_s ? reinterpret_cast<float*>(ws + L.rec_s[k]) : nullptr;
+      int32_t* bstart = reinterpret_cast<int32_t*>(ws + L.bstart[k]);
+      int32_t* blist = reinterpret_cast<int32_t*>(ws + L.blist[k]);
       float* stg = staged ? reinterpret_cast<float*>(ws + L.stage[k]) : nullptr;
+      // the per-class gather reads rows sorted through memory
+      int4* spans = grouped ? nullptr : reinterpret_cast<int4*>(ws + L.spans[k]);
+      uint32_t* eo = grouped ? nullptr : reinterpret_cast<uint32_t*>(ws + L.ent_off[k]);
+      float* ew = (!grouped && need_w) ? reinterpret_cast<float*>(ws + L.ent_w[k]) : nullptr;
+      float* es = (!grouped && need_s) ? reinterpret_cast<float*>(ws + L.ent_s[k]) : nullptr;
       // set k was last read by the gather two batches ago
       if (nbatch >= 2) LF_TRY(hipStreamWaitEvent(stream, mesh->gathered_ev[k], 0), "wait for gather");
       {
         StageTimer tm(mesh, 3, stream);
-        LF_TRY(launch_zero(nrows, 4, stream), "clear row count");
-        LF_TRY(launch_seg_scan(seg, d.n_rows, reinterpret_cast<int32_t*>(ws + L.sums), start, rows, nrows, stream),
-               "segment scan");
+        LF_TRY(launch_zero(counts, 8, stream), "clear span and bucket counts");
+        LF_TRY(launch_seg_scan(seg, L.n_buckets, reinterpret_cast<int32_t*>(ws + L.sums), bstart, blist, counts + 1,
+                               stream),
+               "bucket scan");
         const ProbIn sin = staged_in(stg, a.valid ? a.valid + (int64_t)fi * HW : nullptr);
         if (staged)
-          LF_TRY(launch_seg_fill(sin, 0, nb, H, W, lb, rank, start, eo, ew, nullptr, a.weighting, cnt, d.n_rows,
-                                 wpix, d.mix, d.win_lo, d.n_rows, stream), "segment fill");
+          LF_TRY(launch_seg_fill(sin, 0, nb, H, W, lb, rank, bstart, rec, rw, nullptr, a.weighting, cnt, d.n_rows,
+                                 wpix, d.mix, d.win_lo, d.n_rows, stream), "bucket fill");
         else
-          LF_TRY(launch_seg_fill(in, fi, nb, H, W, lb, rank, start, eo, ew, es, a.weighting, cnt, d.n_rows, wpix,
-                                 d.mix, d.win_lo, d.n_rows, stream), "segment fill");
+          LF_TRY(launch_seg_fill(in, fi, nb, H, W, lb, rank, bstart, rec, rw, rs, a.weighting, cnt, d.n_rows, wpix,
+                                 d.mix, d.win_lo, d.n_rows, stream), "bucket fill");
+        if (!grouped)
+          LF_TRY(launch_bucket_sort(L.n_buckets, bstart, blist, counts + 1, rec, rw, rs, eo, ew, es, spans, counts,
+                                    stream), "bucket sort");
       }
       LF_TRY(hipEventRecord(mesh->sorted_ev[k], stream), "record sorted");
       if (staged && more && (status = stage_batch(batch_at(f0 + nb), j + 1)) != LF_OK) return status;
       LF_TRY(hipStreamWaitEvent(side, mesh->sorted_ev[k], 0), "wait for sort");
       {
         StageTimer tm(mesh, 2, side);
-        const ProbIn gin = staged ? staged_in(stg, nullptr) : in;
-        LF_TRY(launch_seg_gather(d, gin, staged ? 0 : fi, H, W, start, rows, nrows, eo, ew, es, nb,
-                                 frame_counts ? a.weighting : 0, d.mix, (learned && pix_direct) ? wpix : nullptr,
-                                 side),
-               "segment gather");
+        if (grouped)
+          LF_TRY(launch_bucket_gather(d, staged ? staged_in(stg, nullptr) : in, staged ? 0 : fi, H, W, L.n_buckets,
+                                      bstart, blist, counts + 1, rec, rw, rs, nb, frame_counts ? a.weighting : 0,
+                                      d.mix, (learned && pix_direct) ? wpix : nullptr, side),
+                 "bucket gather");
+        else
+          LF_TRY(launch_seg_gather(d, in, fi, spans, counts, eo, ew, es, side), "segment gather");
       }
       LF_TRY(hipEventRecord(mesh->gathered_ev[k], side), "record gathered");
       ++nbatch;

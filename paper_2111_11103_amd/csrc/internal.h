@@ -36,6 +36,9 @@ __device__ __forceinline__ int64_t row_offset(const MeshDev& m, int64_t t) {
 __device__ __forceinline__ int tri_s(const MeshDev& m, int64_t t) { return m.s_face ? m.s_face[t] : m.s_uniform; }
 
 constexpr int kTileSize = 32;         // default raster tile edge (pixels)
+constexpr int kBucketShift = 4;       // sorted scatter: texel rows per first-level bucket = 2^kBucketShift
+constexpr int kTileSlotBits = 9;      // the tile raster's table of buckets seen in the tile: 2^9 slots
+constexpr int kTileSlots = 1 << kTileSlotBits;
 
 // Raster workspace of one batch (all caller memory).
 struct RasterWs {
@@ -54,8 +57,9 @@ struct RasterOut {
   const uint8_t* valid;      // validity of the batch's pixels
   int32_t* cnt;              // per-frame texel counts [B][cnt_stride] (w^(I))
   int64_t cnt_stride;
-  int32_t* seg;              // per-row observation counts of the batch (sorted scatter)
-  int32_t* rank;             // [B][H][W] rank of the pixel within its row's segment
+  int32_t* seg;              // per-bucket observation counts of the batch (sorted scatter):
+                             // bucket = window-relative row >> kBucketShift
+  int32_t* rank;             // [B][H][W] rank of the pixel within its bucket's segment
   float4* geo;               // [B][H][W] learned-weight geometry: cos of the viewing angle,
                              // z / (1 + z), centroid closeness, 0 (zeros where no triangle)
   int32_t* tricnt;           // [B][T] pixels covered per triangle (texel-resolution pre-pass)
@@ -94,27 +98,48 @@ hipError_t launch_scatter_atomic(const MeshDev& m, const ProbIn& in, int f_first
 hipError_t launch_clear_counts(const int32_t* l, const uint8_t* valid, int nf, int H, int W, int32_t* cnt,
                                int64_t cnt_stride, int64_t win_lo, hipStream_t s);
 hipError_t launch_finalize(const MeshDev& m, void* tex_out, int tex_dtype, uint8_t* labels, hipStream_t s);
+// Exclusive scan of n counters into start[0..n] and the list of counters
+// that are non-zero (rows[0 .. *nrows)); *nrows must be zero beforehand.
 hipError_t launch_seg_scan(const int32_t* seg, int64_t n, int32_t* sums, int32_t* start, int32_t* rows,
                            int32_t* nrows, hipStream_t s);
-// Pixels whose row lies outside [win_lo, win_lo + n_rows) are skipped; start
-// and cnt are indexed by window-relative rows.
+// Pixels whose row lies outside [win_lo, win_lo + n_rows) are skipped;
+// buckets and cnt are indexed by window-relative rows.  Every other valid
+// covered pixel writes rec[bstart[bucket] + rank] = (element offset of its
+// class-0 value relative to frame f_first, row within the bucket), and its
+// weight / E4M3 scale into rec_w / rec_s where those are given.
 hipError_t launch_seg_fill(const ProbIn& in, int f_first, int nf, int H, int W, const int32_t* l, const int32_t* rank,
-                           const int32_t* start, uint32_t* ent_pix, float* ent_w, float* ent_s, int weighting,
+                           const int32_t* bstart, uint2* rec, float* rec_w, float* rec_s, int weighting,
                            const int32_t* cnt, int64_t cnt_stride, const float* wpix, float mix, int64_t win_lo,
                            int64_t n_rows, hipStream_t s);
+// Second level of the sort through memory (layouts the grouped gather does
+// not take): every non-empty bucket's records ordered by row into ent (and
+// ent_w / ent_s) within the bucket's range, with one span (window-relative
+// row, start, end, 0) per touched row appended to spans; *nspans must be
+// zero beforehand.
+hipError_t launch_bucket_sort(int64_t n_buckets, const int32_t* bstart, const int32_t* blist, const int32_t* nblist,
+                              const uint2* rec, const float* rec_w, const float* rec_s, uint32_t* ent, float* ent_w,
+                              float* ent_s, int4* spans, int32_t* nspans, hipStream_t s);
 // Frames [f_first, f_first + nf) of planar FP32 input as pixel-major rows of
 // c floats: staging[(f - f_first) * H * W + p][j] (c % 4 == 0, c <= 60).
 hipError_t launch_planar_rows(const ProbIn& in, int f_first, int nf, int H, int W, int c, float* staging,
                               hipStream_t s);
-// Weights of the batch's observations: from ent_w (or 1) when frame_w is 0
-// and wpix is null; with frame_w = LF_W_IMAGE or LF_W_MIX the gather counts
-// every row's observations per frame of the nf-frame batch itself (only where
-// seg_frame_counts_ok holds); with wpix ([nf][H][W] per-pixel weights) it
-// reads them by pixel index, as it reads E4M3 scales when ent_s is null (only
-// where seg_pixels_dense_ok holds).
-hipError_t launch_seg_gather(const MeshDev& m, const ProbIn& in, int f_first, int H, int W, const int32_t* start,
-                             const int32_t* rows, const int32_t* nrows, const uint32_t* ent_pix, const float* ent_w,
-                             const float* ent_s, int nf, int frame_w, float mix, const float* wpix,
+// Whether the input's classes are contiguous 4-class chunks the grouped
+// gather reads (c <= 64, c % 4 == 0, aligned).
+bool seg_grouped_ok(const MeshDev& m, const ProbIn& in);
+// Grouped gather from the bucket-ordered records of a batch of nf frames.
+// Weights: from rec_w (or 1) when frame_w is 0 and wpix is null; with
+// frame_w = LF_W_IMAGE or LF_W_MIX the gather counts every row's observations
+// per frame itself (only where seg_frame_counts_ok holds); with wpix
+// ([nf][H][W] per-pixel weights) it reads them by pixel index, as it reads
+// E4M3 scales when rec_s is null (only where seg_pixels_dense_ok holds).
+hipError_t launch_bucket_gather(const MeshDev& m, const ProbIn& in, int f_first, int H, int W, int64_t n_buckets,
+                                const int32_t* bstart, const int32_t* blist, const int32_t* nblist, const uint2* rec,
+                                const float* rec_w, const float* rec_s, int nf, int frame_w, float mix,
+                                const float* wpix, hipStream_t s);
+// Per-class gather over the spans of k_bucket_sort (any strides; weights and
+// E4M3 scales per entry).
+hipError_t launch_seg_gather(const MeshDev& m, const ProbIn& in, int f_first, const int4* spans,
+                             const int32_t* nspans, const uint32_t* ent, const float* ent_w, const float* ent_s,
                              hipStream_t s);
 // Whether the gather of input `in` (batches of at most nf frames) can recover
 // each observation's frame from its stored element offset and count frames

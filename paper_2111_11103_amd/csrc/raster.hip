@@ -421,6 +421,7 @@ __global__ __launch_bounds__(256) void k_tile_raster(MeshDev m, const float* __r
                                                      int64_t list_cap, int cap, RasterOut out) {
   __shared__ unsigned long long key[TS * TS];
   __shared__ float rxs[TS], rys[TS];
+  __shared__ int hkey[kTileSlots], hcnt[kTileSlots], hbase[kTileSlots];   // the tile's bucket table
   const int fb = blockIdx.y;
   const Cam cam = load_cam(cams + 16 * (int64_t)fb);
   const int ntx = (W + TS - 1) / TS, nty = (H + TS - 1) / TS;
@@ -532,37 +533,80 @@ __global__ __launch_bounds__(256) void k_tile_raster(MeshDev m, const float* __r
       if (tri[r] >= 0) atomicAdd(out.tricnt + (int64_t)fb * m.T + tri[r], 1);
   }
   if (out.seg || out.cnt) {
-    // A wave holds whole tile rows (TS consecutive lanes per row).  Pixels
-    // next to each other in a row that see the same texel row form a run; the
-    // run's first lane adds the run length to the row's counters with one
-    // atomic, and the run's pixels take consecutive ranks from its base.
+    // A wave holds whole tile rows (TS consecutive lanes per row).  Lanes next
+    // to each other with the same key form a run; the run's first lane adds
+    // the run length to the key's counter with one atomic.  Only rows inside
+    // the accumulator's window count (row l is counted at l - win_lo).
     const int lane = threadIdx.x & 63;
     const unsigned long long below = (2ull << lane) - 1ull;   // lanes 0..lane (lane 63: all)
-    constexpr unsigned long long kRowStart = TS == 16 ? 0x0001000100010001ull : 0x0000000100000001ull;
-    // only rows inside the accumulator's window are counted (row l is
-    // counted at l - win_lo)
-    int rk[PPT], head[PPT];
     bool win[PPT];
+    int lw[PPT];
 #pragma unroll
     for (int r = 0; r < PPT; ++r) {
-      const int64_t lw = (int64_t)l[r] - m.win_lo;
-      win[r] = use[r] && lw >= 0 && lw < m.n_rows;
-      const int key = win[r] ? l[r] : -1;
-      const int prev = __shfl_up(key, 1);
-      const unsigned long long heads = __ballot(key != prev) | kRowStart;
-      const unsigned long long after = heads & ~below;
-      const int next = after ? __ffsll(after) - 1 : 64;
-      head[r] = 63 - __clzll(heads & below);
-      const bool lead = win[r] && head[r] == lane;
-      int base = 0;
-      if (lead && out.cnt) atomicAdd(out.cnt + (int64_t)fb * out.cnt_stride + lw, next - lane);
-      if (lead && out.seg) base = atomicAdd(out.seg + lw, next - lane);
-      rk[r] = base;
+      const int64_t d = (int64_t)l[r] - m.win_lo;
+      win[r] = use[r] && d >= 0 && d < m.n_rows;
+      lw[r] = win[r] ? (int)d : -1;
     }
-    if (out.seg) {
+    if (out.cnt) {
+      // per-frame pixel counts of every texel row (w^(I) outside the grouped gather)
+      constexpr unsigned long long kRowStart = TS == 16 ? 0x0001000100010001ull : 0x0000000100000001ull;
 #pragma unroll
       for (int r = 0; r < PPT; ++r) {
-        const int base = __shfl(rk[r], head[r]);
+        const int key = lw[r];
+        const int prev = __shfl_up(key, 1);
+        const unsigned long long heads = __ballot(key != prev) | kRowStart;
+        const unsigned long long after = heads & ~below;
+        const int next = after ? __ffsll(after) - 1 : 64;
+        if (win[r] && 63 - __clzll(heads & below) == lane)
+          atomicAdd(out.cnt + (int64_t)fb * out.cnt_stride + key, next - lane);
+      }
+    }
+    if (out.seg) {
+      // sorted scatter, first level: pixels counted per bucket of
+      // 2^kBucketShift texel rows.  Runs of same-bucket lanes add their
+      // length to the tile's count of the bucket (an LDS table, open
+      // addressing); then one global atomic per (tile, bucket) reserves the
+      // tile's slots, and a run's pixels take consecutive ranks from its
+      // place in them, so the fill writes them contiguously.  A bucket that
+      // finds the table full is counted with a global atomic per run.
+      for (int i = threadIdx.x; i < kTileSlots; i += 256) {
+        hkey[i] = -1;
+        hcnt[i] = 0;
+      }
+      __syncthreads();
+      int slot[PPT], rb[PPT], head[PPT];
+#pragma unroll
+      for (int r = 0; r < PPT; ++r) {
+        const int key = win[r] ? lw[r] >> kBucketShift : -1;
+        const int prev = __shfl_up(key, 1);
+        const unsigned long long heads = __ballot(key != prev) | 1ull;
+        const unsigned long long after = heads & ~below;
+        const int next = after ? __ffsll(after) - 1 : 64;
+        head[r] = 63 - __clzll(heads & below);
+        slot[r] = -1;
+        rb[r] = 0;
+        if (win[r] && head[r] == lane) {
+          int h = (int)(((uint32_t)key * 2654435761u) >> (32 - kTileSlotBits));
+          for (int probe = 0; probe < kTileSlots; ++probe) {
+            const int old = atomicCAS(&hkey[h], -1, key);
+            if (old == -1 || old == key) {
+              slot[r] = h;
+              break;
+            }
+            h = (h + 1) & (kTileSlots - 1);
+          }
+          if (slot[r] >= 0) rb[r] = atomicAdd(&hcnt[slot[r]], next - lane);
+          else rb[r] = atomicAdd(out.seg + key, next - lane);   // table full: this run reserves alone
+        }
+      }
+      __syncthreads();
+      for (int i = threadIdx.x; i < kTileSlots; i += 256)
+        if (hkey[i] >= 0) hbase[i] = atomicAdd(out.seg + hkey[i], hcnt[i]);
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < PPT; ++r) {
+        const int s = __shfl(slot[r], head[r]);
+        const int base = __shfl(rb[r], head[r]) + (s >= 0 ? hbase[s] : 0);
         if (win[r]) out.rank[pix[r]] = base + (lane - head[r]);
       }
     }

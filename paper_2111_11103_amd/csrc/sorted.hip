@@ -1,20 +1,29 @@
 // Texel-sorted aggregation (Sections 3.2.1, 3.2.2, 3.3.2) without floating
 // point atomics: every batch of frames is counting-sorted by texel row, then
-// one wave owns each touched row and adds all of the batch's observations of
-// it in registers before a single read-modify-write of the row.
-//   k_seg_scan*   exclusive scan of the per-row observation counts (counted,
-//                 with every pixel's rank in its row, while resolving the
-//                 frames) -> segment starts and the list of touched rows;
-//   k_seg_fill    every valid covered pixel writes, at its row's start plus
-//                 its rank, the element offset of its class-0 value and,
-//                 where the gather cannot find them itself, its weight and
-//                 FP8 scale;
-//   k_planar_rows planar (NCHW) frames transposed to pixel-major rows first;
-//   k_seg_gather16  16 lanes per touched row (4 classes each, c <= 64,
-//                 contiguous classes): stream the row's observations, sum
-//                 w * f(p) in registers, then update the row once;
-//   k_seg_gather  one wave per 64 consecutive rows, lanes = classes (any c,
-//                 any strides).
+// a group of lanes owns each touched row and adds all of the batch's
+// observations of it in registers before a single read-modify-write of the
+// row.  The sort has two levels, so that every pass over the batch's pixels
+// reads and writes contiguous runs:
+//   (resolve)     every pixel counted in its bucket of 2^kBucketShift
+//                 consecutive texel rows, with its rank in the bucket (one
+//                 atomic per run of same-bucket pixels of a wave);
+//   k_seg_scan*   exclusive scan of the bucket counts -> bucket starts and
+//                 the list of non-empty buckets;
+//   k_seg_fill    every valid covered pixel writes, at its bucket's start
+//                 plus its rank, a record of the element offset of its
+//                 class-0 value and its row within the bucket (and, where the
+//                 gather cannot find them itself, its weight and FP8 scale);
+//   (second level) the records of every bucket ordered by row:
+//   k_bucket_gather16  contiguous classes (c <= 64, c % 4 == 0): one
+//                 workgroup per bucket sorts its records by row in LDS, then
+//                 16 lanes per row (4 classes each) stream the row's
+//                 observations, sum w * f(p) in registers and update the row
+//                 once;
+//   k_bucket_sort + k_seg_gather  any other layout: the buckets' records
+//                 sorted by row through memory (one span (row, start, end)
+//                 per touched row), then one wave per 64 touched rows,
+//                 lanes = classes (any c, any strides);
+//   k_planar_rows planar (NCHW) frames transposed to pixel-major rows first.
 // Rows touched by many frames of a batch are read and written once per
 // batch instead of once per pixel.
 #include <algorithm>
@@ -135,15 +144,18 @@ __global__ __launch_bounds__(256) void k_seg_scan(const int32_t* __restrict__ cn
 
 // ---- fill ------------------------------------------------------------------------
 // 4 pixels per thread; every phase is issued for all 4 before the next so
-// the dependent loads (row, then its segment start) overlap.  Workgroups are
-// dealt to the 8 XCDs in turn and the grid's width is a multiple of 8, so
-// block x runs on XCD x % 8; it takes pixel chunk (x % 8) * (width / 8) +
-// x / 8, which gives every XCD one band of image rows in every frame: the
-// texel rows seen in a band, and the entry lines they own, stay under one L2.
+// the dependent loads (row, then its bucket's start) overlap.  Pixels of one
+// run of the resolve have consecutive ranks, so a wave's record stores are
+// contiguous.  Workgroups are dealt to the 8 XCDs in turn and the grid's
+// width is a multiple of 8, so block x runs on XCD x % 8; it takes pixel
+// chunk (x % 8) * (width / 8) + x / 8, which gives every XCD one band of
+// image rows in every frame.
+constexpr int kBucketMask = (1 << kBucketShift) - 1;
+
 __global__ __launch_bounds__(256) void k_seg_fill(ProbIn in, int f_first, int H, int W, const int32_t* __restrict__ lbuf,
-                                                  const int32_t* __restrict__ rank, const int32_t* __restrict__ start,
-                                                  uint32_t* __restrict__ ent_pix, float* __restrict__ ent_w,
-                                                  float* __restrict__ ent_s, int weighting,
+                                                  const int32_t* __restrict__ rank, const int32_t* __restrict__ bstart,
+                                                  uint2* __restrict__ rec, float* __restrict__ rec_w,
+                                                  float* __restrict__ rec_s, int weighting,
                                                   const int32_t* __restrict__ cnt, int64_t cnt_stride,
                                                   const float* __restrict__ wpix, float mix, int64_t win_lo,
                                                   int64_t n_rows) {
@@ -164,21 +176,81 @@ __global__ __launch_bounds__(256) void k_seg_fill(ProbIn in, int f_first, int H,
     if (l[k] >= 0 && in.valid && !in.valid[(int64_t)(f_first + fb) * HW + p[k]]) l[k] = -1;
   }
 #pragma unroll
-  for (int k = 0; k < P; ++k) st[k] = l[k] >= 0 ? start[l[k]] + rank[(int64_t)fb * HW + p[k]] : 0;
+  for (int k = 0; k < P; ++k) st[k] = l[k] >= 0 ? bstart[l[k] >> kBucketShift] + rank[(int64_t)fb * HW + p[k]] : 0;
 #pragma unroll
   for (int k = 0; k < P; ++k) {
     if (l[k] < 0) continue;
     const int pos = st[k];
     const int y = (int)(p[k] / W), x = (int)(p[k] - (int64_t)y * W);
-    ent_pix[pos] = (uint32_t)((int64_t)fb * in.sf + (int64_t)y * in.sy + (int64_t)x * in.sx);
-    if (ent_w) {
+    rec[pos] = make_uint2((uint32_t)((int64_t)fb * in.sf + (int64_t)y * in.sy + (int64_t)x * in.sx),
+                          (uint32_t)(l[k] & kBucketMask));
+    if (rec_w) {
       float w = 1.0f;
       if (weighting == 1) w = 1.0f / (float)cnt[(int64_t)fb * cnt_stride + l[k]];
       else if (weighting == 2) w = wpix[(int64_t)fb * HW + p[k]];
       else if (weighting == 3) w = (1.0f - mix) + mix / (float)cnt[(int64_t)fb * cnt_stride + l[k]];
-      ent_w[pos] = w;
+      rec_w[pos] = w;
     }
-    if (ent_s) ent_s[pos] = in.scale[(int64_t)(f_first + fb) * HW + p[k]];
+    if (rec_s) rec_s[pos] = in.scale[(int64_t)(f_first + fb) * HW + p[k]];
+  }
+}
+
+// ---- second level, through memory: rows within a bucket -------------------------------
+// For the per-class gather (any strides): one workgroup per non-empty bucket
+// (walking the list): the bucket's records are counted per row in LDS, the
+// counts scanned into the rows' segment starts (within the bucket's own range
+// of the entry arrays), every touched row appends its span (row, start,
+// end), and every record is moved to its row's next free slot.  Within a
+// row, entries keep no particular order.
+constexpr int kBucketRows = 1 << kBucketShift;
+static_assert(kBucketRows <= 64, "one wave scans a bucket's row counts");
+
+__global__ __launch_bounds__(256) void k_bucket_sort(const int32_t* __restrict__ bstart,
+                                                     const int32_t* __restrict__ blist,
+                                                     const int32_t* __restrict__ nblist, const uint2* __restrict__ rec,
+                                                     const float* __restrict__ rec_w, const float* __restrict__ rec_s,
+                                                     uint32_t* __restrict__ ent, float* __restrict__ ent_w,
+                                                     float* __restrict__ ent_s, int4* __restrict__ spans,
+                                                     int32_t* __restrict__ nspans) {
+  __shared__ int hist[kBucketRows];
+  const int t = threadIdx.x;
+  const int nb = *nblist;
+  for (int g = blockIdx.x; g < nb; g += gridDim.x) {
+    const int b = blist[g];
+    const int s0 = bstart[b], s1 = bstart[b + 1];
+    if (t < kBucketRows) hist[t] = 0;
+    __syncthreads();
+    for (int i = s0 + t; i < s1; i += 256) atomicAdd(&hist[rec[i].y & kBucketMask], 1);
+    __syncthreads();
+    if (t < 64) {
+      const int cnt = t < kBucketRows ? hist[t] : 0;
+      int incl = cnt, nz = cnt > 0;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const int a = __shfl_up(incl, o), z = __shfl_up(nz, o);
+        if (t >= o) {
+          incl += a;
+          nz += z;
+        }
+      }
+      int base = 0;
+      if (t == 63) base = atomicAdd(nspans, nz);
+      base = __shfl(base, 63);
+      if (t < kBucketRows) {
+        const int st = s0 + incl - cnt;
+        hist[t] = st;                                   // the row's cursor
+        if (cnt > 0) spans[base + nz - 1] = make_int4(b * kBucketRows + t, st, st + cnt, 0);
+      }
+    }
+    __syncthreads();
+    for (int i = s0 + t; i < s1; i += 256) {
+      const uint2 q = rec[i];
+      const int d = atomicAdd(&hist[q.y & kBucketMask], 1);
+      ent[d] = q.x;
+      if (ent_w) ent_w[d] = rec_w[i];
+      if (ent_s) ent_s[d] = rec_s[i];
+    }
+    __syncthreads();                               // hist is cleared for the next bucket
   }
 }
 
@@ -295,27 +367,32 @@ struct PixDecode {
   __device__ __forceinline__ int64_t operator()(const ProbIn&, uint32_t q) const { return base + (int64_t)q; }
 };
 
-// Lanes = classes (any stride, any c): one wave per 64 consecutive rows.
+// Lanes = classes (any stride, any c): one wave per 64 consecutive spans
+// (touched rows).
 template <int NCH, int DT, int AGG, int AT>
-__global__ __launch_bounds__(256) void k_seg_gather(MeshDev m, ProbIn in, PixDecode dec, const int32_t* __restrict__ start,
+__global__ __launch_bounds__(256) void k_seg_gather(MeshDev m, ProbIn in, PixDecode dec, const int4* __restrict__ spans,
+                                                    const int32_t* __restrict__ nspans,
                                                     const uint32_t* __restrict__ ent_pix,
                                                     const float* __restrict__ ent_w, const float* __restrict__ ent_s) {
   const int lane = threadIdx.x & 63;
   const int64_t x0 = (((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6) * 64;
-  if (x0 >= m.n_rows) return;
+  const int ns = *nspans;
+  if (x0 >= ns) return;
   const int c = m.c;
   const int64_t xl = x0 + lane;
-  int s = 0, e = 0;
-  if (xl < m.n_rows) {
-    s = start[xl];
-    e = start[xl + 1];
+  int s = 0, e = 0, row = 0;
+  if (xl < ns) {
+    const int4 sp = spans[xl];
+    row = sp.x;
+    s = sp.y;
+    e = sp.z;
   }
   unsigned long long todo = __ballot(e > s);
   while (todo) {
     const int src = __ffsll(todo) - 1;
     todo &= todo - 1;
     const int seg_s = __builtin_amdgcn_readlane(s, src), seg_e = __builtin_amdgcn_readlane(e, src);
-    const int64_t x = x0 + src;
+    const int64_t x = __builtin_amdgcn_readlane(row, src);
     // the row's old value is loaded first so its latency hides behind the observations
     float old[NCH];
 #pragma unroll
@@ -375,166 +452,239 @@ __global__ __launch_bounds__(256) void k_seg_gather(MeshDev m, ProbIn in, PixDec
 // (FP32) or one 32-bit word of four codes (E4M3) per observation, so one wave
 // instruction fetches four contiguous class vectors.  The group loads 16
 // observation offsets at once (one per lane, shuffled out) and keeps U (4 or
-// 8) observations in flight.  Groups walk the compact list of touched rows.
+// 8) observations in flight.
 //
 // Per-frame weights (frame_w = 1: w^(I) = 1 / n, 3: (1 - mix) + mix / n, with
 // n the number of pixels of the observation's frame that see the texel,
 // Section 3.2.2): a row's observations of one frame are exactly that frame's
-// pixels on the texel, so n is counted per row in an LDS histogram over the
-// batch's frames (one per group, nf counters) before the row is summed; an
-// observation's frame is its stored element offset divided by the frame
-// stride sfd.  Nothing per frame and texel is kept in device memory.
+// pixels on the texel, so n is counted per row and frame in LDS from the
+// row's own observations; an observation's frame is its stored element
+// offset divided by the frame stride sfd.  Nothing per frame and texel is
+// kept in device memory.
 //
 // Pixels dense in the input (spix != 0: a stored offset is spix times the
 // batch-relative pixel index): E4M3 scales are read from the input's own
 // [F][H][W] scale array at sbase + index, and per-pixel weights (wpix, the
-// learned weight, [B][H][W]) at the index, instead of from ent_s / ent_w
+// learned weight, [B][H][W]) at the index, instead of from per-observation
 // copies written by the fill.
+struct GatherCtx {
+  int frame_w;
+  float mix;
+  uint32_t sfd;
+  uint32_t spix;
+  int64_t sbase;
+  const float* wpix;
+  const float* ew;   // per-observation weights, or nullptr
+  const float* es;   // per-observation E4M3 scales, or nullptr
+};
+
+// The observations of one row: element offsets off[0 .. n); observation k's
+// weight and scale sit at ibase + (idx ? idx[k] : k) of ew / es; fcnt = the
+// row's per-frame counts (frame weights).
+struct RowObs {
+  const uint32_t* off;
+  const uint16_t* idx;
+  int64_t ibase;
+  const int* fcnt;
+};
+
+// One group (16 lanes) adds the row's observations to texel row x: up to 16
+// observations summed plainly, the chunk sums then added to the row with
+// compensation (SUM / MAXSUM) or plainly (MUL: sums of logs), the row read
+// and written once.
 template <int DT, int AGG, int AT, int U>
-__global__ __launch_bounds__(256) void k_seg_gather16(MeshDev m, ProbIn in, PixDecode dec,
-                                                      const int32_t* __restrict__ start,
-                                                      const int32_t* __restrict__ rows,
-                                                      const int32_t* __restrict__ nrows,
-                                                      const uint32_t* __restrict__ ent,
-                                                      const float* __restrict__ ent_w, const float* __restrict__ ent_s,
-                                                      uint32_t sfd, int nf, int frame_w, float mix, uint32_t spix,
-                                                      int64_t sbase, const float* __restrict__ wpix) {
-  extern __shared__ int fcnt[];                          // [16 groups][nf] when frame_w != 0
-  const int gl = threadIdx.x & 15;                       // lane in group = class chunk
-  const int64_t g0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 4;
-  const int64_t ng = ((int64_t)gridDim.x * 256) >> 4;
+__device__ __forceinline__ void gather_row(const MeshDev& m, const ProbIn& in, const PixDecode& dec,
+                                           const GatherCtx& gc, int64_t x, int n, const RowObs& ro, int gl,
+                                           bool act) {
   const int c = m.c;
-  const int nv = c >> 2;
-  const bool act = gl < nv;
-  const int nr = *nrows;
-  int* my_cnt = fcnt + (threadIdx.x >> 4) * nf;
-  if (frame_w) {
-    for (int i = threadIdx.x; i < 16 * nf; i += 256) fcnt[i] = 0;
-    __syncthreads();
+  float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+  float4 cmp = make_float4(0.f, 0.f, 0.f, 0.f);   // compensation of the SUM / MAXSUM sums
+  float4 old = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (act) {
+    if constexpr (AT == 0) {
+      old = *reinterpret_cast<const float4*>(reinterpret_cast<const float*>(m.accum) + x * c + 4 * gl);
+    } else {
+      const int64_t i0 = x * c + 4 * gl;
+      old = make_float4(acc_load<AT>(m.accum, i0), acc_load<AT>(m.accum, i0 + 1), acc_load<AT>(m.accum, i0 + 2),
+                        acc_load<AT>(m.accum, i0 + 3));
+    }
   }
-  for (int64_t g = g0; g < nr; g += ng) {
-    const int64_t x = rows[g];
-    const int s0 = start[x], s1 = start[x + 1];
-    if (frame_w) {
-      for (int k = s0 + gl; k < s1; k += 16) atomicAdd(&my_cnt[ent[k] / sfd], 1);
-      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");   // the row's counts before they are read
+  float wsum = 0.0f;
+  for (int k0 = 0; k0 < n; k0 += 16) {
+    float4 part = make_float4(0.f, 0.f, 0.f, 0.f);
+    const int kk = k0 + gl;
+    const bool okl = kk < n;
+    const uint32_t my_e = okl ? ro.off[kk] : 0u;
+    const uint32_t my_p = gc.spix ? my_e / gc.spix : 0u;   // batch-relative pixel index
+    const int64_t ei = ro.ibase + (ro.idx ? (int64_t)ro.idx[okl ? kk : 0] : (int64_t)kk);
+    float my_w;
+    if (gc.frame_w) {
+      const float nn = okl ? (float)ro.fcnt[my_e / gc.sfd] : 1.0f;
+      my_w = okl ? (gc.frame_w == 1 ? 1.0f / nn : (1.0f - gc.mix) + gc.mix / nn) : 0.0f;
+    } else if (gc.wpix) {
+      my_w = okl ? gc.wpix[my_p] : 0.0f;
+    } else {
+      my_w = okl ? (gc.ew ? gc.ew[ei] : 1.0f) : 0.0f;
     }
-    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
-    float4 cmp = make_float4(0.f, 0.f, 0.f, 0.f);   // compensation of the SUM / MAXSUM sums
-    float4 old = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (act) {
-      if constexpr (AT == 0) {
-        old = *reinterpret_cast<const float4*>(reinterpret_cast<const float*>(m.accum) + x * c + 4 * gl);
-      } else {
-        const int64_t i0 = x * c + 4 * gl;
-        old = make_float4(acc_load<AT>(m.accum, i0), acc_load<AT>(m.accum, i0 + 1), acc_load<AT>(m.accum, i0 + 2),
-                          acc_load<AT>(m.accum, i0 + 3));
-      }
+    float my_s = 1.0f;
+    if constexpr (DT == 3) {
+      if (okl) my_s = gc.spix ? in.scale[gc.sbase + my_p] : gc.es[ei];
     }
-    float wsum = 0.0f;
-    for (int k0 = s0; k0 < s1; k0 += 16) {
-      // up to 16 observations summed plainly, the chunk sums then added to the
-      // row with compensation (SUM / MAXSUM) or plainly (MUL: sums of logs)
-      float4 part = make_float4(0.f, 0.f, 0.f, 0.f);
-      const int kk = k0 + gl;
-      const bool okl = kk < s1;
-      const uint32_t my_e = okl ? ent[kk] : 0u;
-      const uint32_t my_p = spix ? my_e / spix : 0u;   // batch-relative pixel index
-      float my_w;
-      if (frame_w) {
-        const float n = okl ? (float)my_cnt[my_e / sfd] : 1.0f;
-        my_w = okl ? (frame_w == 1 ? 1.0f / n : (1.0f - mix) + mix / n) : 0.0f;
-      } else if (wpix) {
-        my_w = okl ? wpix[my_p] : 0.0f;
-      } else {
-        my_w = okl ? (ent_w ? ent_w[kk] : 1.0f) : 0.0f;
+    const int cnt = min(16, n - k0);
+    for (int h = 0; h < cnt; h += U) {
+      float4 v[U];
+      float w[U];
+      uint32_t q[U];                             // E4M3: raw codes, decoded once every load is issued
+      float sc[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int src = h + u;
+        const uint32_t e = __shfl(my_e, src, 16);
+        w[u] = __shfl(my_w, src, 16);            // 0 past the row's end
+        sc[u] = DT == 3 ? __shfl(my_s, src, 16) : 1.0f;
+        const int64_t off = dec(in, e);
+        v[u] = make_float4(1.f, 1.f, 1.f, 1.f);
+        q[u] = 0u;
+        if (act && src < cnt) {
+          if constexpr (DT == 0)
+            v[u] = *reinterpret_cast<const float4*>(reinterpret_cast<const float*>(in.p) + off + 4 * gl);
+          else
+            q[u] = *reinterpret_cast<const uint32_t*>(reinterpret_cast<const uint8_t*>(in.p) + off + 4 * gl);
+        }
       }
-      float my_s = 1.0f;
       if constexpr (DT == 3) {
-        if (okl) my_s = spix ? in.scale[sbase + my_p] : ent_s[kk];
-      }
-      const int cnt = min(16, s1 - k0);
-      for (int h = 0; h < cnt; h += U) {
-        float4 v[U];
-        float w[U];
-        uint32_t q[U];                             // E4M3: raw codes, decoded once every load is issued
-        float sc[U];
+        // per-component selects (a select of whole vectors would be turned
+        // into a load through a selected address, i.e. scratch memory)
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-          const int src = h + u;
-          const uint32_t e = __shfl(my_e, src, 16);
-          w[u] = __shfl(my_w, src, 16);            // 0 past the segment end
-          sc[u] = DT == 3 ? __shfl(my_s, src, 16) : 1.0f;
-          const int64_t off = dec(in, e);
-          v[u] = make_float4(1.f, 1.f, 1.f, 1.f);
-          q[u] = 0u;
-          if (act && src < cnt) {
-            if constexpr (DT == 0)
-              v[u] = *reinterpret_cast<const float4*>(reinterpret_cast<const float*>(in.p) + off + 4 * gl);
-            else
-              q[u] = *reinterpret_cast<const uint32_t*>(reinterpret_cast<const uint8_t*>(in.p) + off + 4 * gl);
-          }
-        }
-        if constexpr (DT == 3) {
-          // per-component selects (a select of whole vectors would be turned
-          // into a load through a selected address, i.e. scratch memory)
-#pragma unroll
-          for (int u = 0; u < U; ++u) {
-            const bool okq = act && h + u < cnt;
-            v[u].x = okq ? fp8_e4m3_byte<0>(q[u]) * sc[u] : 1.0f;
-            v[u].y = okq ? fp8_e4m3_byte<1>(q[u]) * sc[u] : 1.0f;
-            v[u].z = okq ? fp8_e4m3_byte<2>(q[u]) * sc[u] : 1.0f;
-            v[u].w = okq ? fp8_e4m3_byte<3>(q[u]) * sc[u] : 1.0f;
-          }
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          float4 t = v[u];
-          if constexpr (AGG == 1) {
-            t = make_float4(logf(t.x), logf(t.y), logf(t.z), logf(t.w));
-          } else if constexpr (AGG == 2) {
-            float mx = act ? fmaxf(fmaxf(t.x, t.y), fmaxf(t.z, t.w)) : -__builtin_inff();
-#pragma unroll
-            for (int o = 8; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o, 16));
-            t = make_float4(t.x == mx ? t.x : 0.f, t.y == mx ? t.y : 0.f, t.z == mx ? t.z : 0.f,
-                            t.w == mx ? t.w : 0.f);
-          }
-          part.x += w[u] * t.x;
-          part.y += w[u] * t.y;
-          part.z += w[u] * t.z;
-          part.w += w[u] * t.w;
-          wsum += w[u];
+          const bool okq = act && h + u < cnt;
+          v[u].x = okq ? fp8_e4m3_byte<0>(q[u]) * sc[u] : 1.0f;
+          v[u].y = okq ? fp8_e4m3_byte<1>(q[u]) * sc[u] : 1.0f;
+          v[u].z = okq ? fp8_e4m3_byte<2>(q[u]) * sc[u] : 1.0f;
+          v[u].w = okq ? fp8_e4m3_byte<3>(q[u]) * sc[u] : 1.0f;
         }
       }
-      if constexpr (AGG == 1) {
-        acc.x += part.x;
-        acc.y += part.y;
-        acc.z += part.z;
-        acc.w += part.w;
-      } else {
-        kahan_add(acc.x, cmp.x, part.x);
-        kahan_add(acc.y, cmp.y, part.y);
-        kahan_add(acc.z, cmp.z, part.z);
-        kahan_add(acc.w, cmp.w, part.w);
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        float4 t = v[u];
+        if constexpr (AGG == 1) {
+          t = make_float4(logf(t.x), logf(t.y), logf(t.z), logf(t.w));
+        } else if constexpr (AGG == 2) {
+          float mx = act ? fmaxf(fmaxf(t.x, t.y), fmaxf(t.z, t.w)) : -__builtin_inff();
+#pragma unroll
+          for (int o = 8; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o, 16));
+          t = make_float4(t.x == mx ? t.x : 0.f, t.y == mx ? t.y : 0.f, t.z == mx ? t.z : 0.f,
+                          t.w == mx ? t.w : 0.f);
+        }
+        part.x += w[u] * t.x;
+        part.y += w[u] * t.y;
+        part.z += w[u] * t.z;
+        part.w += w[u] * t.w;
+        wsum += w[u];
       }
     }
-    if (act) {
-      const float4 nv4 = make_float4(old.x + (acc.x - cmp.x), old.y + (acc.y - cmp.y), old.z + (acc.z - cmp.z),
-                                     old.w + (acc.w - cmp.w));
-      if constexpr (AT == 0) {
-        *reinterpret_cast<float4*>(reinterpret_cast<float*>(m.accum) + x * c + 4 * gl) = nv4;
-      } else {
-        const int64_t i0 = x * c + 4 * gl;
-        acc_store<AT>(m.accum, i0, nv4.x);
-        acc_store<AT>(m.accum, i0 + 1, nv4.y);
-        acc_store<AT>(m.accum, i0 + 2, nv4.z);
-        acc_store<AT>(m.accum, i0 + 3, nv4.w);
+    if constexpr (AGG == 1) {
+      acc.x += part.x;
+      acc.y += part.y;
+      acc.z += part.z;
+      acc.w += part.w;
+    } else {
+      kahan_add(acc.x, cmp.x, part.x);
+      kahan_add(acc.y, cmp.y, part.y);
+      kahan_add(acc.z, cmp.z, part.z);
+      kahan_add(acc.w, cmp.w, part.w);
+    }
+  }
+  if (act) {
+    const float4 nv4 = make_float4(old.x + (acc.x - cmp.x), old.y + (acc.y - cmp.y), old.z + (acc.z - cmp.z),
+                                   old.w + (acc.w - cmp.w));
+    if constexpr (AT == 0) {
+      *reinterpret_cast<float4*>(reinterpret_cast<float*>(m.accum) + x * c + 4 * gl) = nv4;
+    } else {
+      const int64_t i0 = x * c + 4 * gl;
+      acc_store<AT>(m.accum, i0, nv4.x);
+      acc_store<AT>(m.accum, i0 + 1, nv4.y);
+      acc_store<AT>(m.accum, i0 + 2, nv4.z);
+      acc_store<AT>(m.accum, i0 + 3, nv4.w);
+    }
+  }
+  if (m.wsum && gl == 0) m.wsum[x] += wsum;
+}
+
+// The grouped gather straight from the bucket-ordered records: one workgroup
+// per non-empty bucket (walking the list), one group per row of the bucket
+// (kBucketRows = 16 groups).  The bucket's records are counted per row and
+// frame in LDS (frame weights), then taken kBucketChunk at a time: counted
+// per row, scanned, and moved into LDS in row order, and every group adds its
+// row's observations of the chunk (a row split over chunks is read and
+// written once per chunk, by the same workgroup, in order).
+constexpr int kBucketChunk = 2048;
+
+size_t bucket_gather_lds(int nf, int frame_w) {
+  return (size_t)kBucketChunk * 4 + (size_t)kBucketChunk * 2 + 3 * kBucketRows * 4 +
+         (frame_w ? (size_t)kBucketRows * nf * 4 : 0);
+}
+
+template <int DT, int AGG, int AT, int U>
+__global__ __launch_bounds__(256) void k_bucket_gather16(MeshDev m, ProbIn in, PixDecode dec, GatherCtx gc,
+                                                         const int32_t* __restrict__ bstart,
+                                                         const int32_t* __restrict__ blist,
+                                                         const int32_t* __restrict__ nblist,
+                                                         const uint2* __restrict__ rec, int nf) {
+  static_assert(kBucketRows == 16, "one group of 16 lanes per row of a bucket");
+  extern __shared__ int lds[];
+  uint32_t* soff = reinterpret_cast<uint32_t*>(lds);                    // [kBucketChunk] offsets, row order
+  uint16_t* sidx = reinterpret_cast<uint16_t*>(soff + kBucketChunk);    // [kBucketChunk] chunk index of each
+  int* rcnt = reinterpret_cast<int*>(sidx + kBucketChunk);              // [16] the chunk's count per row
+  int* rst = rcnt + kBucketRows;                                        // [16] start per row
+  int* rcur = rst + kBucketRows;                                        // [16] cursor per row
+  int* fc = rcur + kBucketRows;                                         // [16][nf] frame counts
+  const int t = threadIdx.x, gl = t & 15, grp = t >> 4;
+  const bool act = gl < (m.c >> 2);
+  const int nb = *nblist;
+  for (int g = blockIdx.x; g < nb; g += gridDim.x) {
+    const int b = blist[g];
+    const int s0 = bstart[b], s1 = bstart[b + 1];
+    if (gc.frame_w) {
+      for (int i = t; i < kBucketRows * nf; i += 256) fc[i] = 0;
+      __syncthreads();
+      for (int i = s0 + t; i < s1; i += 256) {
+        const uint2 q = rec[i];
+        atomicAdd(&fc[(q.y & kBucketMask) * nf + q.x / gc.sfd], 1);
       }
     }
-    if (m.wsum && gl == 0) m.wsum[x] += wsum;
-    if (frame_w) {
-      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");   // every read of the row's counts first
-      for (int i = gl; i < nf; i += 16) my_cnt[i] = 0;
+    for (int c0 = s0; c0 < s1; c0 += kBucketChunk) {
+      const int n = min(kBucketChunk, s1 - c0);
+      if (t < kBucketRows) rcnt[t] = 0;
+      __syncthreads();
+      for (int i = t; i < n; i += 256) atomicAdd(&rcnt[rec[c0 + i].y & kBucketMask], 1);
+      __syncthreads();
+      if (t < 64) {
+        const int v = t < kBucketRows ? rcnt[t] : 0;
+        int incl = v;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+          const int a = __shfl_up(incl, o);
+          if (t >= o) incl += a;
+        }
+        if (t < kBucketRows) {
+          rst[t] = incl - v;
+          rcur[t] = incl - v;
+        }
+      }
+      __syncthreads();
+      for (int i = t; i < n; i += 256) {
+        const uint2 q = rec[c0 + i];
+        const int d = atomicAdd(&rcur[q.y & kBucketMask], 1);
+        soff[d] = q.x;
+        sidx[d] = (uint16_t)i;
+      }
+      __syncthreads();
+      const int cnt = rcnt[grp];
+      if (cnt > 0)
+        gather_row<DT, AGG, AT, U>(m, in, dec, gc, (int64_t)b * kBucketRows + grp, cnt,
+                                   RowObs{soff + rst[grp], sidx + rst[grp], c0, fc + grp * nf}, gl, act);
+      __syncthreads();                                 // the chunk's LDS is reused next
     }
   }
 }
@@ -564,36 +714,38 @@ bool seg_pixels_dense_ok(const MeshDev& m, const ProbIn& in, int nf, int H, int 
   return in.sy == (int64_t)W * in.sx && (nf == 1 || in.sf == (int64_t)H * W * in.sx);
 }
 
-hipError_t launch_seg_gather(const MeshDev& m, const ProbIn& in, int f_first, int H, int W, const int32_t* start,
-                             const int32_t* rows, const int32_t* nrows, const uint32_t* ent, const float* ent_w,
-                             const float* ent_s, int nf, int frame_w, float mix, const float* wpix,
-                             hipStream_t s) {
-  if (m.n_rows == 0) return hipSuccess;
+bool seg_grouped_ok(const MeshDev& m, const ProbIn& in) { return grouped_ok(m, in); }
+
+hipError_t launch_bucket_gather(const MeshDev& m, const ProbIn& in, int f_first, int H, int W, int64_t n_buckets,
+                                const int32_t* bstart, const int32_t* blist, const int32_t* nblist, const uint2* rec,
+                                const float* rec_w, const float* rec_s, int nf, int frame_w, float mix,
+                                const float* wpix, hipStream_t s) {
+  if (m.n_rows == 0 || n_buckets <= 0) return hipSuccess;
+  if (!grouped_ok(m, in)) return hipErrorInvalidValue;
   if (frame_w && ((frame_w != 1 && frame_w != 3) || !seg_frame_counts_ok(m, in, nf, H, W)))
     return hipErrorInvalidValue;
-  // E4M3 without per-entry scales, or per-pixel weights: read by pixel index
-  const bool direct = (in.dtype == 3 && !ent_s) || wpix;
+  // E4M3 without per-observation scales, or per-pixel weights: read by pixel index
+  const bool direct = (in.dtype == 3 && !rec_s) || wpix;
   if (direct && ((in.dtype == 3 && !in.scale) || (frame_w && wpix) || !seg_pixels_dense_ok(m, in, nf, H, W)))
     return hipErrorInvalidValue;
-  const uint32_t spix = direct ? (uint32_t)in.sx : 0u;
-  const int64_t sbase = (int64_t)f_first * H * W;
+  GatherCtx gc{frame_w,
+               mix,
+               nf > 1 ? (uint32_t)in.sf : 0xffffffffu,   // every stored offset is below 2^32 - 1
+               direct ? (uint32_t)in.sx : 0u,
+               (int64_t)f_first * H * W,
+               wpix,
+               rec_w,
+               rec_s};
   const PixDecode dec{(int64_t)f_first * in.sf};
-  const bool grouped = grouped_ok(m, in);
-  if (grouped) {
-    const uint32_t sfd = nf > 1 ? (uint32_t)in.sf : 0xffffffffu;   // every stored offset is below 2^32 - 1
-    const size_t lds = frame_w ? (size_t)16 * nf * 4 : 0;
-    // enough resident groups to cover the machine; each walks the row list
-    // grid: gather_waves resident waves (4 row groups each) on each of the 256 CUs
-    const int64_t groups = std::min<int64_t>(m.n_rows, (int64_t)256 * m.gather_waves * 4);
-    dim3 g((unsigned)((groups * 16 + 255) / 256));
-#define LF_R(DT, AGG, AT)                                                                                    \
-  do {                                                                                                       \
-    if (m.gather_unroll == 4)                                                                                \
-      k_seg_gather16<DT, AGG, AT, 4><<<g, 256, lds, s>>>(m, in, dec, start, rows, nrows, ent, ent_w, ent_s,  \
-                                                         sfd, nf, frame_w, mix, spix, sbase, wpix);         \
-    else                                                                                                     \
-      k_seg_gather16<DT, AGG, AT, 8><<<g, 256, lds, s>>>(m, in, dec, start, rows, nrows, ent, ent_w, ent_s,  \
-                                                         sfd, nf, frame_w, mix, spix, sbase, wpix);         \
+  const size_t lds = bucket_gather_lds(nf, frame_w);
+  // gather_waves resident waves (one workgroup = 4 waves) on each of the 256 CUs
+  const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>(n_buckets, (int64_t)64 * m.gather_waves));
+#define LF_R(DT, AGG, AT)                                                                                      \
+  do {                                                                                                         \
+    if (m.gather_unroll == 4)                                                                                  \
+      k_bucket_gather16<DT, AGG, AT, 4><<<g, 256, lds, s>>>(m, in, dec, gc, bstart, blist, nblist, rec, nf);   \
+    else                                                                                                       \
+      k_bucket_gather16<DT, AGG, AT, 8><<<g, 256, lds, s>>>(m, in, dec, gc, bstart, blist, nblist, rec, nf);   \
   } while (0)
 #define LF_R2(DT)                                                                                            \
   do {                                                                                                       \
@@ -602,15 +754,23 @@ hipError_t launch_seg_gather(const MeshDev& m, const ProbIn& in, int f_first, in
     else if (m.accum_dtype == 2) { if (m.aggregator == 0) LF_R(DT, 0, 2); else LF_R(DT, 2, 2); }            \
     else { if (m.aggregator == 0) LF_R(DT, 0, 0); else LF_R(DT, 2, 0); }                                     \
   } while (0)
-    if (in.dtype == 0) LF_R2(0);
-    else LF_R2(3);
+  if (in.dtype == 0) LF_R2(0);
+  else LF_R2(3);
 #undef LF_R2
 #undef LF_R
-    return hipGetLastError();
-  }
+  return hipGetLastError();
+}
+
+hipError_t launch_seg_gather(const MeshDev& m, const ProbIn& in, int f_first, const int4* spans,
+                             const int32_t* nspans, const uint32_t* ent, const float* ent_w, const float* ent_s,
+                             hipStream_t s) {
+  if (m.n_rows == 0) return hipSuccess;
+  if (in.dtype == 3 && !ent_s) return hipErrorInvalidValue;
+  const PixDecode dec{(int64_t)f_first * in.sf};
   const int64_t waves = (m.n_rows + 63) / 64;
   dim3 g((unsigned)((waves + 3) / 4));
-#define LF_G(NCH, DT, AGG, AT) k_seg_gather<NCH, DT, AGG, AT><<<g, 256, 0, s>>>(m, in, dec, start, ent, ent_w, ent_s)
+#define LF_G(NCH, DT, AGG, AT) \
+  k_seg_gather<NCH, DT, AGG, AT><<<g, 256, 0, s>>>(m, in, dec, spans, nspans, ent, ent_w, ent_s)
 #define LF_G2(NCH, DT)                                                                                       \
   do {                                                                                                       \
     if (m.aggregator == 1) LF_G(NCH, DT, 1, 0);                                                              \
@@ -648,14 +808,23 @@ hipError_t launch_planar_rows(const ProbIn& in, int f_first, int nf, int H, int 
 }
 
 hipError_t launch_seg_fill(const ProbIn& in, int f_first, int nf, int H, int W, const int32_t* l, const int32_t* rank,
-                           const int32_t* start, uint32_t* ent_pix, float* ent_w, float* ent_s, int weighting,
+                           const int32_t* bstart, uint2* rec, float* rec_w, float* rec_s, int weighting,
                            const int32_t* cnt, int64_t cnt_stride, const float* wpix, float mix, int64_t win_lo,
                            int64_t n_rows, hipStream_t s) {
   if (nf <= 0) return hipSuccess;
   const int64_t HW = (int64_t)H * W;
   const unsigned gx = (unsigned)(((HW + 1023) / 1024 + 7) / 8 * 8);   // chunks, rounded up to a multiple of 8
-  k_seg_fill<<<dim3(gx, (unsigned)nf), 256, 0, s>>>(in, f_first, H, W, l, rank, start, ent_pix, ent_w, ent_s, weighting,
+  k_seg_fill<<<dim3(gx, (unsigned)nf), 256, 0, s>>>(in, f_first, H, W, l, rank, bstart, rec, rec_w, rec_s, weighting,
                                                     cnt, cnt_stride, wpix, mix, win_lo, n_rows);
+  return hipGetLastError();
+}
+
+hipError_t launch_bucket_sort(int64_t n_buckets, const int32_t* bstart, const int32_t* blist, const int32_t* nblist,
+                              const uint2* rec, const float* rec_w, const float* rec_s, uint32_t* ent, float* ent_w,
+                              float* ent_s, int4* spans, int32_t* nspans, hipStream_t s) {
+  if (n_buckets <= 0) return hipSuccess;
+  const unsigned g = (unsigned)std::min<int64_t>(n_buckets, 4096);
+  k_bucket_sort<<<g, 256, 0, s>>>(bstart, blist, nblist, rec, rec_w, rec_s, ent, ent_w, ent_s, spans, nspans);
   return hipGetLastError();
 }
 

@@ -55,7 +55,7 @@ def test_descent_skips_gather_knobs_for_atomic_scatter():
 
 def _traffic_file(tmp_path, digest, records):
     path = tmp_path / "traffic.txt"
-    path.write_text(json.dumps({"kernel": "k_seg_gather16", "source_digest": digest, "records": records}) +
+    path.write_text(json.dumps({"kernel": "k_bucket_gather16", "source_digest": digest, "records": records}) +
                     "\n\nnotes\n")
     return str(path)
 
