@@ -55,19 +55,40 @@ __device__ __forceinline__ void load_tri(const MeshDev& m, const Cam& cam, int64
 }
 
 // Snapped polygon of the camera-space triangle (A, B, C) clipped by the five
-// planes; returns its vertex count (0..8).  Out of line: only triangles
-// that cross a plane take this path.  It reads the camera record itself, so
-// that callers need not keep their copy in (per-lane scratch) memory.
+// planes, written to px, py (0..8 vertices; the count is returned).  Out of
+// line, with its polygon arrays in per-lane memory: only triangles that
+// cross a plane take this path.  It reads the camera record itself, so that
+// callers need not keep their copy in memory.
 __device__ __noinline__ int clipped_polygon(const float* __restrict__ cam_rec, float z_near, V3 A, V3 B, V3 C,
-                                            int (&PX)[8], int (&PY)[8]) {
+                                            int* px, int* py) {
   const Cam cam = load_cam(cam_rec);
   V3 P[8];
   P[0] = A; P[1] = B; P[2] = C;
   const int n = clip_poly(P, 3, cam, z_near);
-#pragma unroll
-  for (int i = 0; i < 8; ++i)
-    if (i < n) snap(cam, P[i], &PX[i], &PY[i]);
+  for (int i = 0; i < n; ++i) snap(cam, P[i], &px[i], &py[i]);
   return n;
+}
+
+// Vertex count and pixel-unit bounds of the clipped, snapped polygon, and its
+// vertices when it is a triangle (returned in registers).
+struct ClipBox {
+  int n, xmin, xmax, ymin, ymax;
+  int ax, ay, bx, by, cx, cy;
+};
+
+__device__ __noinline__ ClipBox clipped_box(const float* __restrict__ cam_rec, float z_near, V3 A, V3 B, V3 C) {
+  int PX[8], PY[8];
+  ClipBox r{};
+  r.n = clipped_polygon(cam_rec, z_near, A, B, C, PX, PY);
+  if (r.n < 3) return r;
+  r.xmin = r.xmax = PX[0];
+  r.ymin = r.ymax = PY[0];
+  for (int i = 1; i < r.n; ++i) {
+    r.xmin = min(r.xmin, PX[i]); r.xmax = max(r.xmax, PX[i]);
+    r.ymin = min(r.ymin, PY[i]); r.ymax = max(r.ymax, PY[i]);
+  }
+  r.ax = PX[0]; r.ay = PY[0]; r.bx = PX[1]; r.by = PY[1]; r.cx = PX[2]; r.cy = PY[2];
+  return r;
 }
 
 __device__ __forceinline__ void setup_triangle(const MeshDev& m, const Cam& cam, const float* cam_rec, int64_t t, int H,
@@ -93,19 +114,13 @@ __device__ __forceinline__ void setup_triangle(const MeshDev& m, const Cam& cam,
     xmin = min(min(s.ax, s.bx), s.cx); xmax = max(max(s.ax, s.bx), s.cx);
     ymin = min(min(s.ay, s.by), s.cy); ymax = max(max(s.ay, s.by), s.cy);
   } else {
-    int PX[8], PY[8];
-    const int n = clipped_polygon(cam_rec, m.z_near, A, B, C, PX, PY);
-    if (n < 3) return;
-    s.n = n;
-    if (n == 3) {
-      s.ax = PX[0]; s.ay = PY[0]; s.bx = PX[1]; s.by = PY[1]; s.cx = PX[2]; s.cy = PY[2];
+    const ClipBox cb = clipped_box(cam_rec, m.z_near, A, B, C);
+    if (cb.n < 3) return;
+    s.n = cb.n;
+    if (cb.n == 3) {
+      s.ax = cb.ax; s.ay = cb.ay; s.bx = cb.bx; s.by = cb.by; s.cx = cb.cx; s.cy = cb.cy;
     }
-    xmin = xmax = PX[0];
-    ymin = ymax = PY[0];
-    for (int i = 1; i < n; ++i) {
-      xmin = min(xmin, PX[i]); xmax = max(xmax, PX[i]);
-      ymin = min(ymin, PY[i]); ymax = max(ymax, PY[i]);
-    }
+    xmin = cb.xmin; xmax = cb.xmax; ymin = cb.ymin; ymax = cb.ymax;
   }
   // pixel x is a candidate iff its centre 256x + 128 lies in [xmin, xmax]
   s.x0 = max((xmin + 127) >> 8, 0);
@@ -303,6 +318,7 @@ struct TileCtx {
   int ts;                    // tile edge
   int small_px;              // boxes up to this area: one lane per triangle
   const float* cam_rec;      // the frame's camera record (global memory)
+  int* poly;                 // LDS [4 waves][16]: a clipped polygon's snapped x, then y
 };
 
 __device__ __forceinline__ void emit_lds(const TileCtx& c, const RayK& rk, int x, int y, uint32_t tri) {
@@ -312,22 +328,22 @@ __device__ __forceinline__ void emit_lds(const TileCtx& c, const RayK& rk, int x
   atomicMin(c.key + (y - c.ty0) * c.ts + (x - c.tx0), k);
 }
 
-// One thread rasterizes one sub-triangle over a small pixel box, stepping
-// the three edge functions incrementally.  When every coordinate difference
-// of the snapped triangle is below 2^14 (64 px) all edge values fit in int32
-// exactly, so the narrower arithmetic gives the same decisions.
-template <typename T>
-__device__ __forceinline__ void raster_thread_t(const TileCtx& c, const RayK& rk, uint32_t tri, const Edge3& e, int x0,
-                                                int x1, int y0, int y1) {
+// One thread rasterizes one triangle over a small pixel box, stepping the
+// three edge functions incrementally.  Only triangles whose coordinate
+// differences are all below 2^14 (64 px) take this path: then every edge
+// value fits in int32 exactly, so the narrow arithmetic gives the same
+// decisions as the int64 edge functions.
+__device__ __forceinline__ void raster_thread(const TileCtx& c, const RayK& rk, uint32_t tri, const Edge3& e, int x0,
+                                              int x1, int y0, int y1) {
   const int px0 = 256 * x0 + 128, py0 = 256 * y0 + 128;
-  T r01 = (T)(e.x1 - e.x0) * (T)(py0 - e.y0) - (T)(e.y1 - e.y0) * (T)(px0 - e.x0) - (T)e.b01;
-  T r12 = (T)(e.x2 - e.x1) * (T)(py0 - e.y1) - (T)(e.y2 - e.y1) * (T)(px0 - e.x1) - (T)e.b12;
-  T r20 = (T)(e.x0 - e.x2) * (T)(py0 - e.y2) - (T)(e.y0 - e.y2) * (T)(px0 - e.x2) - (T)e.b20;
-  const T sx01 = (T)-256 * (T)(e.y1 - e.y0), sy01 = (T)256 * (T)(e.x1 - e.x0);
-  const T sx12 = (T)-256 * (T)(e.y2 - e.y1), sy12 = (T)256 * (T)(e.x2 - e.x1);
-  const T sx20 = (T)-256 * (T)(e.y0 - e.y2), sy20 = (T)256 * (T)(e.x0 - e.x2);
+  int r01 = (e.x1 - e.x0) * (py0 - e.y0) - (e.y1 - e.y0) * (px0 - e.x0) - e.b01;
+  int r12 = (e.x2 - e.x1) * (py0 - e.y1) - (e.y2 - e.y1) * (px0 - e.x1) - e.b12;
+  int r20 = (e.x0 - e.x2) * (py0 - e.y2) - (e.y0 - e.y2) * (px0 - e.x2) - e.b20;
+  const int sx01 = -256 * (e.y1 - e.y0), sy01 = 256 * (e.x1 - e.x0);
+  const int sx12 = -256 * (e.y2 - e.y1), sy12 = 256 * (e.x2 - e.x1);
+  const int sx20 = -256 * (e.y0 - e.y2), sy20 = 256 * (e.x0 - e.x2);
   for (int y = y0; y <= y1; ++y) {
-    T a = r01, b = r12, d = r20;
+    int a = r01, b = r12, d = r20;
     for (int x = x0; x <= x1; ++x) {
       if ((a | b | d) >= 0) emit_lds(c, rk, x, y, tri);
       a += sx01; b += sx12; d += sx20;
@@ -336,80 +352,86 @@ __device__ __forceinline__ void raster_thread_t(const TileCtx& c, const RayK& rk
   }
 }
 
-__device__ __forceinline__ void raster_thread(const TileCtx& c, const RayK& rk, uint32_t tri, const Edge3& e, int x0,
-                                              int x1, int y0, int y1) {
-  const int ex = max(max(e.x0, e.x1), e.x2) - min(min(e.x0, e.x1), e.x2);
-  const int ey = max(max(e.y0, e.y1), e.y2) - min(min(e.y0, e.y1), e.y2);
-  if (ex < 16384 && ey < 16384) raster_thread_t<int>(c, rk, tri, e, x0, x1, y0, y1);
-  else raster_thread_t<long long>(c, rk, tri, e, x0, x1, y0, y1);
+// Whether the triangle this lane holds (box restricted to the tile) is drawn
+// by the lane itself; every other drawable triangle is queued for a wave.
+__device__ __forceinline__ bool lane_draws(const Setup& s, int x0, int x1, int y0, int y1, int small_px) {
+  const int ex = max(max(s.ax, s.bx), s.cx) - min(min(s.ax, s.bx), s.cx);
+  const int ey = max(max(s.ay, s.by), s.cy) - min(min(s.ay, s.by), s.cy);
+  return s.n == 3 && ex < 16384 && ey < 16384 && (x1 - x0 + 1) * (y1 - y0 + 1) <= small_px;
 }
 
-
-// Rasterize the triangle this lane holds (`s`, restricted to the pixel box
-// x0..x1 x y0..y1 of the tile); large boxes are done by the whole wave, one
-// triangle at a time, 8x8 pixels per step.  A clipped polygon is drawn as the
-// fan (v0, vi, vi+1).
-__device__ __forceinline__ void raster_entries(const TileCtx& c, const MeshDev& m, const Cam& cam, const Setup& s,
-                                               uint32_t tri, bool have, int x0, int x1, int y0, int y1) {
+// Draw one (sub-)triangle with the whole wave over the pixel box x0..x1 x
+// y0..y1, 8x8 pixels per step, with int64 edge functions.
+__device__ __forceinline__ void wave_triangle(const TileCtx& c, const RayK& rk, uint32_t t, int ax, int ay, int bx,
+                                              int by, int cx, int cy, int x0, int x1, int y0, int y1) {
+  const Edge3 e = orient(ax, ay, bx, by, cx, cy);
+  if (!e.ok) return;
   const int lane = threadIdx.x & 63;
-  const bool any = have && s.n >= 3 && x0 <= x1 && y0 <= y1;
-  const bool small = any && (x1 - x0 + 1) * (y1 - y0 + 1) <= c.small_px;
-  if (small) {
-    int PX[8], PY[8];
-    if (s.n > 3) {
-      V3 A, B, C;
-      load_tri(m, cam, tri, A, B, C);
-      clipped_polygon(c.cam_rec, m.z_near, A, B, C, PX, PY);
-    }
-    for (int i = 1; i + 1 < s.n; ++i) {
-      int ax, ay, bx, by, cx, cy;
-      if (s.n == 3) {
-        ax = s.ax; ay = s.ay; bx = s.bx; by = s.by; cx = s.cx; cy = s.cy;
-      } else {
-        ax = PX[0]; ay = PY[0]; bx = PX[i]; by = PY[i]; cx = PX[i + 1]; cy = PY[i + 1];
-      }
-      const Edge3 e = orient(ax, ay, bx, by, cx, cy);
-      if (e.ok) raster_thread(c, s.rk, tri, e, x0, x1, y0, y1);
+  const int ox = lane & 7, oy = lane >> 3;
+  for (int yb = y0; yb <= y1; yb += 8) {
+    for (int xb = x0; xb <= x1; xb += 8) {
+      const int x = xb + ox, y = yb + oy;
+      if (x > x1 || y > y1) continue;
+      if (covers(e, 256 * x + 128, 256 * y + 128)) emit_lds(c, rk, x, y, t);
     }
   }
-  unsigned long long big = __ballot(any && !small);
-  while (big) {
-    const int src = __ffsll(big) - 1;
-    big &= big - 1;
-    const int bn = __shfl(s.n, src);
-    RayK bk;
-    bk.n = V3{__shfl(s.rk.n.x, src), __shfl(s.rk.n.y, src), __shfl(s.rk.n.z, src)};
-    bk.d = __shfl(s.rk.d, src);
-    const int bx0 = __shfl(x0, src), bx1 = __shfl(x1, src), by0 = __shfl(y0, src), by1 = __shfl(y1, src);
-    const uint32_t btri = (uint32_t)__shfl((int)tri, src);
-    const int sax = __shfl(s.ax, src), say = __shfl(s.ay, src), sbx = __shfl(s.bx, src), sby = __shfl(s.by, src),
-              scx = __shfl(s.cx, src), scy = __shfl(s.cy, src);
-    int PX[8], PY[8];
-    if (bn > 3) {
-      // every lane clips the same (broadcast) triangle
-      V3 A, B, C;
-      load_tri(m, cam, btri, A, B, C);
-      clipped_polygon(c.cam_rec, m.z_near, A, B, C, PX, PY);
-    }
-    const int ox = lane & 7, oy = lane >> 3;
-    for (int i = 1; i + 1 < bn; ++i) {
-      int ax, ay, bx, by, cx, cy;
-      if (bn == 3) {
-        ax = sax; ay = say; bx = sbx; by = sby; cx = scx; cy = scy;
+}
+
+// A clipped triangle (a polygon of more than three vertices) drawn by the
+// whole wave as the fan (v0, vi, vi+1).  The polygon's vertices go to the
+// wave's LDS slot (every lane writes the same values, then reads them back).
+__device__ __forceinline__ void wave_polygon(const TileCtx& c, const MeshDev& m, const Cam& cam, const RayK& rk,
+                                             uint32_t t, int x0, int x1, int y0, int y1) {
+  int* PX = c.poly + 16 * (threadIdx.x >> 6);
+  int* PY = PX + 8;
+  V3 A, B, C;
+  load_tri(m, cam, t, A, B, C);
+  const int n = clipped_polygon(c.cam_rec, m.z_near, A, B, C, PX, PY);
+  for (int i = 1; i + 1 < n; ++i)
+    wave_triangle(c, rk, t, PX[0], PY[0], PX[i], PY[i], PX[i + 1], PY[i + 1], x0, x1, y0, y1);
+}
+
+// The whole wave draws triangle t (wave-uniform) over its box restricted to
+// the tile.
+__device__ __forceinline__ void raster_wave(const TileCtx& c, const MeshDev& m, const Cam& cam, uint32_t t, int H,
+                                            int W, int tx1, int ty1) {
+  Setup s;
+  setup_triangle(m, cam, c.cam_rec, t, H, W, s);
+  const int x0 = max(s.x0, c.tx0), x1 = min(s.x1, tx1), y0 = max(s.y0, c.ty0), y1 = min(s.y1, ty1);
+  if (s.n < 3 || x0 > x1 || y0 > y1) return;
+  if (s.n == 3) wave_triangle(c, s.rk, t, s.ax, s.ay, s.bx, s.by, s.cx, s.cy, x0, x1, y0, y1);
+  else wave_polygon(c, m, cam, s.rk, t, x0, x1, y0, y1);
+}
+
+// One round of up to 256 triangles (one per thread, `have` = this thread
+// holds triangle t): small ones are drawn by their lane, the rest queued in
+// LDS and drawn by the block's four waves in turn.  Every thread of the
+// block must call it.
+__device__ __forceinline__ void raster_round(const TileCtx& c, const MeshDev& m, const Cam& cam, bool have,
+                                             uint32_t t, int H, int W, int tx1, int ty1, uint32_t* queue,
+                                             int* queue_n) {
+  bool queued = false;
+  if (have) {
+    Setup s;
+    setup_triangle(m, cam, c.cam_rec, t, H, W, s);
+    const int x0 = max(s.x0, c.tx0), x1 = min(s.x1, tx1), y0 = max(s.y0, c.ty0), y1 = min(s.y1, ty1);
+    if (s.n >= 3 && x0 <= x1 && y0 <= y1) {
+      if (lane_draws(s, x0, x1, y0, y1, c.small_px)) {
+        const Edge3 e = orient(s.ax, s.ay, s.bx, s.by, s.cx, s.cy);
+        if (e.ok) raster_thread(c, s.rk, t, e, x0, x1, y0, y1);
       } else {
-        ax = PX[0]; ay = PY[0]; bx = PX[i]; by = PY[i]; cx = PX[i + 1]; cy = PY[i + 1];
-      }
-      const Edge3 e = orient(ax, ay, bx, by, cx, cy);
-      if (!e.ok) continue;
-      for (int yb = by0; yb <= by1; yb += 8) {
-        for (int xb = bx0; xb <= bx1; xb += 8) {
-          const int x = xb + ox, y = yb + oy;
-          if (x > bx1 || y > by1) continue;
-          if (covers(e, 256 * x + 128, 256 * y + 128)) emit_lds(c, bk, x, y, btri);
-        }
+        queued = true;
       }
     }
   }
+  if (queued) queue[atomicAdd(queue_n, 1)] = t;
+  __syncthreads();
+  const int nq = *queue_n;
+  __syncthreads();
+  if (threadIdx.x == 0) *queue_n = 0;
+  for (int i = threadIdx.x >> 6; i < nq; i += 4)
+    raster_wave(c, m, cam, (uint32_t)__builtin_amdgcn_readfirstlane((int)queue[i]), H, W, tx1, ty1);
+  __syncthreads();
 }
 
 }  // namespace
@@ -422,6 +444,9 @@ __global__ __launch_bounds__(256) void k_tile_raster(MeshDev m, const float* __r
   __shared__ unsigned long long key[TS * TS];
   __shared__ float rxs[TS], rys[TS];
   __shared__ int hkey[kTileSlots], hcnt[kTileSlots], hbase[kTileSlots];   // the tile's bucket table
+  __shared__ uint32_t queue[256];                                          // triangles a wave draws
+  __shared__ int queue_n;
+  __shared__ int poly[4 * 16];
   const int fb = blockIdx.y;
   const Cam cam = load_cam(cams + 16 * (int64_t)fb);
   const int ntx = (W + TS - 1) / TS, nty = (H + TS - 1) / TS;
@@ -435,26 +460,18 @@ __global__ __launch_bounds__(256) void k_tile_raster(MeshDev m, const float* __r
   for (int i = threadIdx.x; i < TS * TS; i += 256) key[i] = ~0ull;
   if (threadIdx.x < TS) rxs[threadIdx.x] = ray_x(cam, tx0 + threadIdx.x);
   else if (threadIdx.x < 2 * TS) rys[threadIdx.x - TS] = ray_y(cam, ty0 + threadIdx.x - TS);
+  if (threadIdx.x == 0) queue_n = 0;
   __syncthreads();
   if (threadIdx.x == 0) *tc = 0;
-  const TileCtx c{key, rxs, rys, tx0, ty0, TS, m.small_px, cams + 16 * (int64_t)fb};
+  const TileCtx c{key, rxs, rys, tx0, ty0, TS, m.small_px, cams + 16 * (int64_t)fb, poly};
   const int64_t HW = (int64_t)H * W;
 
   if (n_ent <= cap) {
-    const int e0 = 0, e1 = n_ent;
     const int32_t* lst = tlist + (int64_t)fb * list_cap + (int64_t)tile * cap;
-    for (int base = e0; base < e1; base += 256) {   // same trip count for the whole block
+    for (int base = 0; base < n_ent; base += 256) {   // same trip count for the whole block
       const int e = base + threadIdx.x;
-      const bool have = e < e1;
-      Setup s;
-      s.n = 0;
-      s.x0 = 0; s.x1 = -1; s.y0 = 0; s.y1 = -1;
-      uint32_t tri = 0;
-      if (have) {
-        tri = (uint32_t)lst[e];
-        setup_triangle(m, cam, c.cam_rec, tri, H, W, s);
-      }
-      raster_entries(c, m, cam, s, tri, have, max(s.x0, tx0), min(s.x1, tx1), max(s.y0, ty0), min(s.y1, ty1));
+      const bool have = e < n_ent;
+      raster_round(c, m, cam, have, have ? (uint32_t)lst[e] : 0u, H, W, tx1, ty1, queue, &queue_n);
     }
   } else {
     // the tile's list overflowed its capacity: walk every triangle of every
@@ -464,66 +481,78 @@ __global__ __launch_bounds__(256) void k_tile_raster(MeshDev m, const float* __r
       const int w = w0 + (threadIdx.x >> 6);
       const int64_t t = w < nvis ? (int64_t)vis[(int64_t)fb * m.n_clusters + w] * kClusterTris + (threadIdx.x & 63)
                                  : m.T;
-      Setup s;
-      s.n = 0;
-      s.x0 = 0; s.x1 = -1; s.y0 = 0; s.y1 = -1;
-      const bool have = t < m.T;
-      if (have) setup_triangle(m, cam, c.cam_rec, t, H, W, s);
-      raster_entries(c, m, cam, s, (uint32_t)t, have, max(s.x0, tx0), min(s.x1, tx1), max(s.y0, ty0), min(s.y1, ty1));
+      raster_round(c, m, cam, t < m.T, (uint32_t)t, H, W, tx1, ty1, queue, &queue_n);
     }
   }
-  __syncthreads();
-
-  // ---- resolve every pixel of the tile: 4 pixels per thread, each phase
-  // issued for all 4 before the next so the memory round trips overlap ----
+  // (every round ends at a barrier: the tile's depth keys are final here)
+  // ---- resolve every pixel of the tile: PPT pixels per thread, in groups of
+  // G whose memory round trips overlap; triangle, depth and feature outputs
+  // are written as soon as they are known ----
   constexpr int PPT = TS * TS / 256;
   int32_t tri[PPT], l[PPT];
-  float z[PPT];
-  int64_t pix[PPT];
-  bool in[PPT], use[PPT];
-  float4 tv[PPT][3];
-  float4 geo[PPT];
-#pragma unroll
-  for (int r = 0; r < PPT; ++r) {
-    geo[r] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  bool use[PPT];
+  auto pix_of = [&](int r) {
     const int i = threadIdx.x + 256 * r;
-    const int x = tx0 + (i % TS), y = ty0 + (i / TS);
-    in[r] = x <= tx1 && y <= ty1;
-    pix[r] = (int64_t)fb * HW + (int64_t)y * W + x;
-    const unsigned long long k = key[i];
-    tri[r] = (in[r] && k != ~0ull) ? (int32_t)(uint32_t)(k & 0xffffffffull) : -1;
+    return (int64_t)fb * HW + (int64_t)(ty0 + i / TS) * W + (tx0 + i % TS);
+  };
+  auto in_of = [&](int r) {
+    const int i = threadIdx.x + 256 * r;
+    return tx0 + (i % TS) <= tx1 && ty0 + (i / TS) <= ty1;
+  };
+#pragma unroll
+  for (int r = 0; r < PPT; ++r) {
+    const unsigned long long k = key[threadIdx.x + 256 * r];
+    tri[r] = (in_of(r) && k != ~0ull) ? (int32_t)(uint32_t)(k & 0xffffffffull) : -1;
     l[r] = -1;
-    z[r] = __builtin_nanf("");
   }
+  constexpr int G = PPT < 2 ? PPT : 2;   // pixels whose loads are in flight together (16-pixel tiles: 1)
+  static_assert(PPT % G == 0, "pixel groups divide the pixels per thread");
 #pragma unroll
-  for (int r = 0; r < PPT; ++r) {
-    if (tri[r] >= 0) {
-      tv[r][0] = m.tri_v[3 * (int64_t)tri[r]];
-      tv[r][1] = m.tri_v[3 * (int64_t)tri[r] + 1];
-      tv[r][2] = m.tri_v[3 * (int64_t)tri[r] + 2];
+  for (int h = 0; h < PPT; h += G) {
+    float4 tv[G][3];
+    bool vis[G];
+#pragma unroll
+    for (int q = 0; q < G; ++q) {
+      const int r = h + q;
+      if (tri[r] >= 0) {
+        tv[q][0] = m.tri_v[3 * (int64_t)tri[r]];
+        tv[q][1] = m.tri_v[3 * (int64_t)tri[r] + 1];
+        tv[q][2] = m.tri_v[3 * (int64_t)tri[r] + 2];
+      }
+      vis[q] = !out.valid || (tri[r] >= 0 && out.valid[pix_of(r)]);
     }
-    use[r] = tri[r] >= 0 && (!out.valid || out.valid[pix[r]]);
-  }
 #pragma unroll
-  for (int r = 0; r < PPT; ++r) {
-    if (tri[r] >= 0) {
-      const int i = threadIdx.x + 256 * r;
-      const float4 p = tv[r][0], q = tv[r][1], t3 = tv[r][2];
-      const RayK rk = ray_consts(to_cam(cam, p.x, p.y, p.z), to_cam(cam, p.w, q.x, q.y), to_cam(cam, q.z, q.w, t3.x));
-      const float rx = rxs[i % TS], ry = rys[i / TS];
-      const float den = rdot(rx, ry, rk.n);
-      z[r] = rk.d / den;
-      const float u = rdot(rx, ry, rk.nu) / den;
-      const float v = rdot(rx, ry, rk.nv) / den;
-      l[r] = (int32_t)(row_offset(m, tri[r]) + texel_id(tri_s(m, tri[r]), m.split, u, v));
-      if (out.geo) {
-        // |cos| of the angle between the ray and the triangle normal, depth
-        // squashed to [0, 1), 3 * smallest barycentric clamped to [0, 1]
-        const float rl = sqrtf(rx * rx + ry * ry + 1.0f);
-        const float nl = sqrtf(rk.n.x * rk.n.x + rk.n.y * rk.n.y + rk.n.z * rk.n.z);
-        const float cs = nl > 0.0f ? fabsf(den) / (rl * nl) : 0.0f;
-        const float b = 3.0f * fminf(fminf(u, v), 1.0f - u - v);
-        geo[r] = make_float4(cs, z[r] / (1.0f + z[r]), fminf(fmaxf(b, 0.0f), 1.0f), 0.0f);
+    for (int q = 0; q < G; ++q) {
+      const int r = h + q;
+      use[r] = tri[r] >= 0 && vis[q];
+      float z = __builtin_nanf("");
+      float4 geo = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      if (tri[r] >= 0) {
+        const int i = threadIdx.x + 256 * r;
+        const float4 p = tv[q][0], qq = tv[q][1], t3 = tv[q][2];
+        const RayK rk = ray_consts(to_cam(cam, p.x, p.y, p.z), to_cam(cam, p.w, qq.x, qq.y),
+                                   to_cam(cam, qq.z, qq.w, t3.x));
+        const float rx = rxs[i % TS], ry = rys[i / TS];
+        const float den = rdot(rx, ry, rk.n);
+        z = rk.d / den;
+        const float u = rdot(rx, ry, rk.nu) / den;
+        const float v = rdot(rx, ry, rk.nv) / den;
+        l[r] = (int32_t)(row_offset(m, tri[r]) + texel_id(tri_s(m, tri[r]), m.split, u, v));
+        if (out.geo) {
+          // |cos| of the angle between the ray and the triangle normal, depth
+          // squashed to [0, 1), 3 * smallest barycentric clamped to [0, 1]
+          const float rl = sqrtf(rx * rx + ry * ry + 1.0f);
+          const float nl = sqrtf(rk.n.x * rk.n.x + rk.n.y * rk.n.y + rk.n.z * rk.n.z);
+          const float cs = nl > 0.0f ? fabsf(den) / (rl * nl) : 0.0f;
+          const float b = 3.0f * fminf(fminf(u, v), 1.0f - u - v);
+          geo = make_float4(cs, z / (1.0f + z), fminf(fmaxf(b, 0.0f), 1.0f), 0.0f);
+        }
+      }
+      if (in_of(r)) {
+        const int64_t px = pix_of(r);
+        if (out.tri) out.tri[px] = tri[r];
+        if (out.z) out.z[px] = z;
+        if (out.geo) out.geo[px] = geo;
       }
     }
   }
@@ -607,18 +636,13 @@ __global__ __launch_bounds__(256) void k_tile_raster(MeshDev m, const float* __r
       for (int r = 0; r < PPT; ++r) {
         const int s = __shfl(slot[r], head[r]);
         const int base = __shfl(rb[r], head[r]) + (s >= 0 ? hbase[s] : 0);
-        if (win[r]) out.rank[pix[r]] = base + (lane - head[r]);
+        if (win[r]) out.rank[pix_of(r)] = base + (lane - head[r]);
       }
     }
   }
 #pragma unroll
-  for (int r = 0; r < PPT; ++r) {
-    if (!in[r]) continue;
-    if (out.l) out.l[pix[r]] = l[r];
-    if (out.tri) out.tri[pix[r]] = tri[r];
-    if (out.z) out.z[pix[r]] = z[r];
-    if (out.geo) out.geo[pix[r]] = geo[r];
-  }
+  for (int r = 0; r < PPT; ++r)
+    if (out.l && in_of(r)) out.l[pix_of(r)] = l[r];
 }
 
 // ---- launcher ---------------------------------------------------------------
