@@ -255,8 +255,15 @@ lf_status lf_set_overlap(lf_mesh mesh, int32_t enabled);
  *  d_l_out   [F][H][W] rows or NULL (required when d_images is set);
  *  d_tex_out [n_texels][c] in tex_dtype or NULL;  d_labels [n_texels]
  *            (required);  d_images [F][H][W] uint8 or NULL.
- * Jobs run one after another on `stream` and share one frame workspace of
- * lf_batch_ws_bytes bytes (the largest any job needs). */
+ * The jobs run on up to four scene lanes at once: streams of the library
+ * (one set per device) forked from `stream` and joined back into it with
+ * events, so that small scenes' kernels fill the compute units a large
+ * scene's latency-bound kernels leave idle.  Jobs on one mesh run in one
+ * lane, in call order; meshes are dealt to lanes largest first (frames x
+ * pixels).  Each lane has its own slice of the workspace:
+ * lf_batch_ws_bytes = lanes x the largest frame workspace a job needs.
+ * Batched calls on one device enqueue one at a time (a library lock); their
+ * work is ordered on the lane streams. */
 typedef struct {
     lf_mesh mesh;
     const float* d_cams;
@@ -283,9 +290,10 @@ lf_status lf_batch_ws_bytes(const lf_scene_job* jobs, int32_t n_jobs, int64_t* b
 lf_status lf_fuse_batch(const lf_scene_job* jobs, int32_t n_jobs, void* d_ws, int64_t ws_bytes,
                         hipStream_t stream);
 
-/* Capture the jobs' whole launch sequence on `stream` (not the legacy
- * default stream) into an executable HIP graph; lf_graph_launch replays it
- * on any stream.  The sequence holds kernels only (buffers are cleared by
+/* Capture the jobs' whole launch sequence into executable HIP graphs, one per
+ * scene lane (on one lane, captured on `stream`, which must not be the
+ * legacy default stream); lf_graph_launch replays them on any stream,
+ * forking it into the lanes and joining them back.  The sequence holds kernels only (buffers are cleared by
  * kernels, no host synchronisation, no allocation), so replays are
  * independent.  Every buffer the jobs name is baked into the graph: keep them
  * alive and in place while the graph exists; new input values in those

@@ -632,12 +632,30 @@ FuseArgs job_args(const lf_scene_job& j) {
                   j.pool, j.weighting, j.d_l_out, j.batch, j.scatter_mode};
 }
 
+// Lane of every job, the number of lanes used and one lane's workspace bytes.
+struct BatchPlan {
+  std::vector<int> lane;
+  int lanes = 1;
+  int64_t lane_bytes = 256;
+};
+
+BatchPlan plan_batch(const lf_scene_job* jobs, int32_t n);
+
 lf_status check_jobs(const lf_scene_job* jobs, int32_t n, const void* ws, int64_t ws_bytes) {
   if (n < 0) return fail(LF_EINVAL, "negative job count");
   if (n > 0 && !jobs) return fail(LF_EINVAL, "NULL jobs");
   for (int i = 0; i < n; ++i) {
+    lf_status st = check_mesh(jobs[i].mesh);
+    if (st != LF_OK) return fail(st, "job %d: invalid mesh handle", i);
+  }
+  // every lane of the call has its own slice of the workspace
+  const BatchPlan plan = plan_batch(jobs, n);
+  if (n > 0 && ws_bytes < plan.lanes * plan.lane_bytes)
+    return fail(LF_ESIZE, "batch workspace %lld < %lld bytes (%d scene lanes)", (long long)ws_bytes,
+                (long long)(plan.lanes * plan.lane_bytes), plan.lanes);
+  for (int i = 0; i < n; ++i) {
     const lf_scene_job& j = jobs[i];
-    lf_status st = check_fuse(job_args(j), ws, ws_bytes);
+    lf_status st = check_fuse(job_args(j), ws, plan.lane_bytes);
     if (st != LF_OK) return fail(st, "job %d: %s", i, std::string(g_err).c_str());
     if (!j.d_labels) return fail(LF_EINVAL, "job %d: labels buffer is NULL", i);
     if (j.d_tex_out && j.tex_dtype != LF_F32 && j.tex_dtype != LF_BF16 && j.tex_dtype != LF_F16)
@@ -647,42 +665,138 @@ lf_status check_jobs(const lf_scene_job* jobs, int32_t n, const void* ws, int64_
   return LF_OK;
 }
 
-lf_status run_jobs(const lf_scene_job* jobs, int32_t n, void* d_ws, hipStream_t stream) {
+// One job, complete, on `stream` with workspace d_ws.
+lf_status run_job(const lf_scene_job& j, void* d_ws, hipStream_t stream) {
+  lf_mesh m = j.mesh;
+  {
+    StageTimer tm(m, 6, stream);
+    LF_TRY(launch_zero(m->d.accum, m->d.n_rows * m->d.c * (m->d.accum_dtype == LF_F32 ? 4 : 2), stream),
+           "clear accumulator");
+    if (m->d.wsum) LF_TRY(launch_zero(m->d.wsum, m->d.n_rows * 4, stream), "clear weights");
+  }
+  lf_status st = fuse_impl(job_args(j), d_ws, stream);
+  if (st != LF_OK) return st;
+  {
+    StageTimer tm(m, 4, stream);
+    LF_TRY(launch_finalize(m->d, j.d_tex_out, j.tex_dtype, j.d_labels, stream), "finalize");
+  }
+  if (j.d_images) {
+    StageTimer tm(m, 5, stream);
+    const int64_t HW = (int64_t)j.H * j.W;
+    // with an input pool, frame f's validity is input frame f % pool's
+    const int chunk = j.pool > 0 ? j.pool : j.F;
+    for (int f0 = 0; f0 < j.F; f0 += chunk) {
+      const int nf = std::min(chunk, j.F - f0);
+      LF_TRY(launch_render(j.d_l_out + f0 * HW, j.d_valid, j.d_labels, nf * HW, j.d_images + f0 * HW, stream),
+             "render");
+    }
+  }
+  return LF_OK;
+}
+
+// ---- many scenes at once: scene lanes ---------------------------------------------
+// The jobs of one batched call run on up to kBatchLanes streams of the
+// library at once (forked from and joined back into the caller's stream with
+// events, so that a captured graph holds the lanes as parallel branches):
+// the kernels of small scenes then fill the compute units that a large
+// scene's latency-bound kernels leave idle.  Jobs on one mesh share a lane
+// (in call order); meshes are dealt to lanes largest first, each to the lane
+// with the least work (frames x pixels).  Every lane has its own slice of the
+// workspace.
+constexpr int kBatchLanes = 4;
+
+struct LanePool {
+  hipStream_t s[kBatchLanes] = {};
+  hipEvent_t fork = nullptr;
+  hipEvent_t join[kBatchLanes] = {};
+};
+std::mutex g_lane_mu;                 // held while a batched call enqueues its work
+LanePool g_lanes[64];                 // per device
+
+lf_status lane_pool(LanePool** out) {
+  int dev = -1;
+  LF_TRY(hipGetDevice(&dev), "current device");
+  if (dev < 0 || dev >= 64) return fail(LF_EINVAL, "device ordinal %d beyond the lane table", dev);
+  LanePool& p = g_lanes[dev];
+  if (!p.fork) {
+    for (int l = 0; l < kBatchLanes; ++l) {
+      LF_TRY(hipStreamCreateWithFlags(&p.s[l], hipStreamNonBlocking), "lane stream");
+      LF_TRY(hipEventCreateWithFlags(&p.join[l], hipEventDisableTiming), "lane event");
+    }
+    LF_TRY(hipEventCreateWithFlags(&p.fork, hipEventDisableTiming), "lane event");
+  }
+  *out = &p;
+  return LF_OK;
+}
+
+BatchPlan plan_batch(const lf_scene_job* jobs, int32_t n) {
+  BatchPlan p;
+  p.lane.assign(n, 0);
+  std::vector<lf_mesh> meshes;
+  std::vector<double> work;
+  std::vector<int> mesh_of(n);
   for (int i = 0; i < n; ++i) {
-    const lf_scene_job& j = jobs[i];
-    lf_mesh m = j.mesh;
-    {
-      StageTimer tm(m, 6, stream);
-      LF_TRY(launch_zero(m->d.accum, m->d.n_rows * m->d.c * (m->d.accum_dtype == LF_F32 ? 4 : 2), stream),
-             "clear accumulator");
-      if (m->d.wsum) LF_TRY(launch_zero(m->d.wsum, m->d.n_rows * 4, stream), "clear weights");
+    int k = 0;
+    while (k < (int)meshes.size() && meshes[k] != jobs[i].mesh) ++k;
+    if (k == (int)meshes.size()) {
+      meshes.push_back(jobs[i].mesh);
+      work.push_back(0.0);
     }
-    lf_status st = fuse_impl(job_args(j), d_ws, stream);
-    if (st != LF_OK) return st;
-    {
-      StageTimer tm(m, 4, stream);
-      LF_TRY(launch_finalize(m->d, j.d_tex_out, j.tex_dtype, j.d_labels, stream), "finalize");
+    mesh_of[i] = k;
+    work[k] += (double)jobs[i].F * jobs[i].H * jobs[i].W;
+    p.lane_bytes = std::max(p.lane_bytes, align256(fuse_layout(job_args(jobs[i])).total));
+  }
+  p.lanes = std::max(1, std::min<int>(kBatchLanes, (int)meshes.size()));
+  std::vector<int> order(meshes.size());
+  for (size_t k = 0; k < order.size(); ++k) order[k] = (int)k;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work[a] > work[b]; });
+  std::vector<double> load(p.lanes, 0.0);
+  std::vector<int> lane_of_mesh(meshes.size(), 0);
+  for (int k : order) {
+    const int l = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    lane_of_mesh[k] = l;
+    load[l] += work[k];
+  }
+  for (int i = 0; i < n; ++i) p.lane[i] = lane_of_mesh[mesh_of[i]];
+  return p;
+}
+
+lf_status run_jobs(const lf_scene_job* jobs, int32_t n, void* d_ws, hipStream_t stream) {
+  if (n <= 0) return LF_OK;
+  const BatchPlan plan = plan_batch(jobs, n);
+  char* ws = reinterpret_cast<char*>(d_ws);
+  if (plan.lanes == 1) {
+    for (int i = 0; i < n; ++i) {
+      lf_status st = run_job(jobs[i], ws, stream);
+      if (st != LF_OK) return st;
     }
-    if (j.d_images) {
-      StageTimer tm(m, 5, stream);
-      const int64_t HW = (int64_t)j.H * j.W;
-      // with an input pool, frame f's validity is input frame f % pool's
-      const int chunk = j.pool > 0 ? j.pool : j.F;
-      for (int f0 = 0; f0 < j.F; f0 += chunk) {
-        const int nf = std::min(chunk, j.F - f0);
-        LF_TRY(launch_render(j.d_l_out + f0 * HW, j.d_valid, j.d_labels, nf * HW, j.d_images + f0 * HW, stream),
-               "render");
-      }
-    }
+    return LF_OK;
+  }
+  std::lock_guard<std::mutex> lock(g_lane_mu);
+  LanePool* lp = nullptr;
+  lf_status st = lane_pool(&lp);
+  if (st != LF_OK) return st;
+  LF_TRY(hipEventRecord(lp->fork, stream), "fork");
+  for (int l = 0; l < plan.lanes; ++l) LF_TRY(hipStreamWaitEvent(lp->s[l], lp->fork, 0), "lane start");
+  for (int i = 0; i < n; ++i) {
+    const int l = plan.lane[i];
+    if ((st = run_job(jobs[i], ws + (int64_t)l * plan.lane_bytes, lp->s[l])) != LF_OK) return st;
+  }
+  for (int l = 0; l < plan.lanes; ++l) {
+    LF_TRY(hipEventRecord(lp->join[l], lp->s[l]), "lane end");
+    LF_TRY(hipStreamWaitEvent(stream, lp->join[l], 0), "join");
   }
   return LF_OK;
 }
 
 }  // namespace
 
+// One executable graph per scene lane: a launch forks the caller's stream
+// into the lane streams, replays every lane's graph on its own lane, and
+// joins them back.
 struct lf_graph_s {
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
+  std::vector<hipGraph_t> graph;
+  std::vector<hipGraphExec_t> exec;
 };
 
 extern "C" {
@@ -821,15 +935,14 @@ lf_status lf_fuse_ws_bytes(lf_mesh mesh, int32_t H, int32_t W, int32_t batch, in
 lf_status lf_batch_ws_bytes(const lf_scene_job* jobs, int32_t n, int64_t* bytes) {
   g_err[0] = 0;
   if (n < 0 || (n > 0 && !jobs)) return fail(LF_EINVAL, "bad job list");
-  int64_t mx = 256;
   for (int i = 0; i < n; ++i) {
     lf_status st = check_mesh(jobs[i].mesh);
     if (st != LF_OK) return fail(st, "job %d: invalid mesh handle", i);
     if ((st = check_frames(jobs[i].F, jobs[i].H, jobs[i].W)) != LF_OK) return st;
     if (jobs[i].batch < 1) return fail(LF_EINVAL, "job %d: batch must be >= 1", i);
-    mx = std::max(mx, fuse_layout(job_args(jobs[i])).total);
   }
-  if (bytes) *bytes = mx;
+  const BatchPlan plan = plan_batch(jobs, n);
+  if (bytes) *bytes = plan.lanes * plan.lane_bytes;
   return LF_OK;
 }
 
@@ -850,47 +963,75 @@ lf_status lf_graph_capture_batch(const lf_scene_job* jobs, int32_t n, void* d_ws
   if (st != LF_OK) return st;
   for (int i = 0; i < n; ++i)
     if (jobs[i].mesh->prof.on) return fail(LF_ESTATE, "job %d: turn profiling off before capturing", i);
-  LF_TRY(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal), "begin capture");
-  st = run_jobs(jobs, n, d_ws, stream);
-  hipGraph_t g = nullptr;
-  const hipError_t e = hipStreamEndCapture(stream, &g);
+  const BatchPlan plan = plan_batch(jobs, n);
+  lf_graph h = new (std::nothrow) lf_graph_s;
+  if (!h) return fail(LF_EINVAL, "out of host memory");
+  // on one lane the caller's stream is captured; with several, every lane's
+  // jobs on its own lane stream
+  std::unique_lock<std::mutex> lock(g_lane_mu, std::defer_lock);
+  LanePool* lp = nullptr;
+  if (plan.lanes > 1) {
+    lock.lock();
+    if ((st = lane_pool(&lp)) != LF_OK) {
+      delete h;
+      return st;
+    }
+  }
+  char* ws = reinterpret_cast<char*>(d_ws);
+  for (int l = 0; l < plan.lanes && st == LF_OK; ++l) {
+    hipStream_t ls = plan.lanes > 1 ? lp->s[l] : stream;
+    hipError_t e = hipStreamBeginCapture(ls, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+      st = fail(LF_EHIP, "begin capture: %s", hipGetErrorString(e));
+      break;
+    }
+    for (int i = 0; i < n && st == LF_OK; ++i)
+      if (plan.lane[i] == l) st = run_job(jobs[i], ws + (int64_t)l * plan.lane_bytes, ls);
+    hipGraph_t lg = nullptr;
+    e = hipStreamEndCapture(ls, &lg);
+    if (st == LF_OK && e != hipSuccess) st = fail(LF_EHIP, "end capture: %s", hipGetErrorString(e));
+    if (lg) h->graph.push_back(lg);
+    if (st == LF_OK) {
+      hipGraphExec_t x = nullptr;
+      e = hipGraphInstantiate(&x, lg, nullptr, nullptr, 0);
+      if (e != hipSuccess) st = fail(LF_EHIP, "instantiate: %s", hipGetErrorString(e));
+      else h->exec.push_back(x);
+    }
+  }
+  if (lock.owns_lock()) lock.unlock();
   if (st != LF_OK) {
-    if (g) (void)hipGraphDestroy(g);
+    lf_graph_free(h);
     return st;
   }
-  if (e != hipSuccess) {
-    if (g) (void)hipGraphDestroy(g);
-    return fail(LF_EHIP, "end capture: %s", hipGetErrorString(e));
-  }
-  hipGraphExec_t x = nullptr;
-  const hipError_t ei = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
-  if (ei != hipSuccess) {
-    (void)hipGraphDestroy(g);
-    return fail(LF_EHIP, "instantiate: %s", hipGetErrorString(ei));
-  }
-  lf_graph h = new (std::nothrow) lf_graph_s;
-  if (!h) {
-    (void)hipGraphExecDestroy(x);
-    (void)hipGraphDestroy(g);
-    return fail(LF_EINVAL, "out of host memory");
-  }
-  h->graph = g;
-  h->exec = x;
   *out = h;
   return LF_OK;
 }
 
 lf_status lf_graph_launch(lf_graph g, hipStream_t stream) {
   g_err[0] = 0;
-  if (!g || !g->exec) return fail(LF_ESTATE, "invalid graph handle");
-  LF_TRY(hipGraphLaunch(g->exec, stream), "graph launch");
+  if (!g || g->exec.empty()) return fail(LF_ESTATE, "invalid graph handle");
+  if (g->exec.size() == 1) {
+    LF_TRY(hipGraphLaunch(g->exec[0], stream), "graph launch");
+    return LF_OK;
+  }
+  std::lock_guard<std::mutex> lock(g_lane_mu);
+  LanePool* lp = nullptr;
+  lf_status st = lane_pool(&lp);
+  if (st != LF_OK) return st;
+  LF_TRY(hipEventRecord(lp->fork, stream), "fork");
+  for (size_t l = 0; l < g->exec.size(); ++l) {
+    LF_TRY(hipStreamWaitEvent(lp->s[l], lp->fork, 0), "lane start");
+    LF_TRY(hipGraphLaunch(g->exec[l], lp->s[l]), "graph launch");
+    LF_TRY(hipEventRecord(lp->join[l], lp->s[l]), "lane end");
+    LF_TRY(hipStreamWaitEvent(stream, lp->join[l], 0), "join");
+  }
   return LF_OK;
 }
 
 void lf_graph_free(lf_graph g) {
   if (!g) return;
-  if (g->exec) (void)hipGraphExecDestroy(g->exec);
-  if (g->graph) (void)hipGraphDestroy(g->graph);
+  for (hipGraphExec_t x : g->exec) (void)hipGraphExecDestroy(x);
+  for (hipGraph_t x : g->graph) (void)hipGraphDestroy(x);
   delete g;
 }
 
