@@ -269,8 +269,9 @@ def weight_and_frame_sweeps(log_fn, seeds=range(200, 210)):
 def learned_scale_report(mlp, log_fn, n_frames=1000, pool=16):
     """Learned weight at scale: a 2M-triangle room, SPLIT s = 4 (32M texels),
     1000 frames of 1296x968 (inputs cycled from a pool of 16), c = 40.
-    Throughput of plain w^(P) vs the learned weight (inference fused into the
-    fusion pass), and pixel accuracy of both on the pool's own 16 frames."""
+    Throughput of plain w^(P) vs the learned weight (network evaluated inside
+    the gather, and in a separate pass first), and pixel accuracy of both on
+    the pool's own 16 frames."""
     import torch
     from paper_2111_11103_amd import scenes as S
     from paper_2111_11103_amd import semfuse as sf
@@ -289,7 +290,10 @@ def learned_scale_report(mlp, log_fn, n_frames=1000, pool=16):
     log_fn(f"[bench] learned at scale: T={sc.n_faces} texels={mesh.n_texels} ready in {time.time() - t0:.0f} s")
     res = {"workload": f"room mesh {sc.n_faces} triangles, SPLIT s=4 ({mesh.n_texels} texels), {n_frames} frames "
                        f"{W}x{H} (input pool of {pool}), c=40"}
-    for name, wt in (("plain", sf.W_PIXEL), ("learned", sf.W_LEARNED)):
+    tuning = mesh.get_tuning()
+    for name, wt, site in (("plain", sf.W_PIXEL, 1), ("learned", sf.W_LEARNED, 1),
+                           ("learned_separate_pass", sf.W_LEARNED, 0)):
+        mesh.set_tuning(**dict(tuning, learned_in_gather=site))
         job = mesh.job(cams, probs, valid=valid, pool=pool, weighting=wt, batch=pool, scatter_mode=sf.SCATTER_SORTED)
         ws = sf.batch_ws([job])
         sf.fuse_batch([job], ws)
@@ -300,16 +304,19 @@ def learned_scale_report(mlp, log_fn, n_frames=1000, pool=16):
         dt = time.perf_counter() - tt
         res[f"{name}_value"] = n_frames * H * W / dt
         res[f"{name}_ms"] = dt * 1e3
-        # accuracy on the pool's own frames (their cameras, their ground truth)
-        acc_job = mesh.job(cams[:pool], probs, valid=valid, weighting=wt, batch=pool, images=True)
-        sf.fuse_batch([acc_job])
-        torch.cuda.synchronize()
-        seen = (acc_job.l >= 0) & (valid != 0)
-        res[f"{name}_pixel_acc"] = float((acc_job.images[seen].long() == gt[seen]).float().mean())
-        if "input_pixel_acc" not in res:
-            res["input_pixel_acc"] = float((probs.argmax(1)[seen] == gt[seen]).float().mean())
-        del job, acc_job, ws
+        if site == 1:
+            # accuracy on the pool's own frames (their cameras, their ground truth)
+            acc_job = mesh.job(cams[:pool], probs, valid=valid, weighting=wt, batch=pool, images=True)
+            sf.fuse_batch([acc_job])
+            torch.cuda.synchronize()
+            seen = (acc_job.l >= 0) & (valid != 0)
+            res[f"{name}_pixel_acc"] = float((acc_job.images[seen].long() == gt[seen]).float().mean())
+            if "input_pixel_acc" not in res:
+                res["input_pixel_acc"] = float((probs.argmax(1)[seen] == gt[seen]).float().mean())
+            del acc_job
+        del job, ws
         torch.cuda.empty_cache()
+    mesh.set_tuning(**tuning)
     mesh.bind_mlp(None)
     log_fn(f"[bench] learned at scale: {res}")
     return res
@@ -590,13 +597,25 @@ def main():
         def learned_step():
             mlp_holder["mlp"] = sf.WeightMLP("cuda", seed=0)
             mesh.bind_mlp(mlp_holder["mlp"])
-            return make_step(probs, sf.W_LEARNED)[0]
+            if tuning is None:
+                return make_step(probs, sf.W_LEARNED)[0]
+            # the learned weight's gather is the longer stream: its own tuning
+            from paper_2111_11103_amd import tune
+            mlp_holder["saved"] = mesh.get_tuning()
+            t = tune.autotune(mesh, cams, probs, valid=valid, weighting=sf.W_LEARNED, probe_frames=64, log=log)
+            mlp_holder["tuning"] = t
+            return make_step(probs, sf.W_LEARNED, batch=int(t["batch"]), scatter=int(t["scatter_mode"]))[0]
         legs.append(("learned", learned_step, None))
         for name, mk, _ in legs:
             st = mk()
             tt, pr = timed(st, 2, 1, name)
             forms[name] = {"value": 2 * npx / tt, "ms_per_step": 1000 * tt / 2,
                            "stage_ms_per_step": {STAGES[k]: pr.ms[k] / 2 for k in range(8) if pr.launches[k]}}
+        if "tuning" in mlp_holder:
+            forms["learned"]["tuning"] = {k: mlp_holder["tuning"][k] for k in
+                                          ("batch", "scatter_mode", "tile", "small_px", "gather_unroll", "gather_waves",
+                                           "learned_in_gather")}
+            mesh.set_tuning(**mlp_holder["saved"])
         mesh.bind_mlp(None)
         # the paper's texture resolution: a_t from the worst-case frame, s_t =
         # max(1, ceil(0.2 sqrt(a_t))), SQUARE texels (Section 3.1)

@@ -224,7 +224,10 @@ lf_status lf_rasterize(lf_mesh mesh, const float* d_cams, int32_t F, int32_t H, 
  * 48), and the resident waves per compute unit the gather's grid is sized
  * for (1..1024; default 8: fewer leave room for the next batch's raster,
  * which runs concurrently on a second stream; more than fit at once, e.g.
- * 512, balance rows of uneven length when the gather has the device alone).
+ * 512, balance rows of uneven length when the gather has the device alone),
+ * and where LF_W_LEARNED evaluates the network (0, default: in a separate
+ * pass over the batch's pixels first; 1: inside the texel-sorted gather
+ * where it can).
  * Frame batch size and scatter mode are per-call arguments.
  * lf_frame_ws_bytes depends on the tile: query it after lf_set_tuning. */
 typedef struct {
@@ -232,6 +235,7 @@ typedef struct {
     int32_t gather_unroll;
     int32_t small_px;
     int32_t gather_waves;
+    int32_t learned_in_gather;
 } lf_tuning;
 lf_status lf_set_tuning(lf_mesh mesh, const lf_tuning* tuning);
 lf_status lf_get_tuning(lf_mesh mesh, lf_tuning* tuning);
@@ -320,7 +324,14 @@ void lf_graph_free(lf_graph graph);
  * W2 ([64][64]), b2, w3, b3 (n_params floats); the packed form holds W1, W2,
  * w3 in bfloat16 and the biases in binary32 (packed_bytes, 16-byte aligned).
  * Training target: y_k = 1 when the observation's own argmax equals the
- * label plain fusion gives its texel; loss = mean binary cross-entropy. */
+ * label plain fusion gives its texel; loss = mean binary cross-entropy.
+ * Where the network runs (lf_tuning.learned_in_gather): a separate pass
+ * writes per-pixel weights first, from a per-frame count array; or, on the
+ * texel-sorted path with contiguous classes (c % 4 == 0, c <= 64,
+ * channels-last or staged planar input) and batches of at most 128 frames,
+ * the gather evaluates the network for every observation of a texel bucket
+ * just before summing them (n from its own per-frame counters).  Both give
+ * the same weights. */
 
 /* Number of master parameters and bytes of the packed form. */
 lf_status lf_mlp_sizes(int32_t* n_params, int64_t* packed_bytes);

@@ -188,7 +188,8 @@ FrameLayout frame_layout(const MeshDev& m, int H, int W, int B, int weighting, i
   L.tlist = o; o += align256(B * L.list_cap * 4);
   L.l = o; o += align256(B * HW * 4);
   L.cnt = o; if (weighting != LF_W_PIXEL) o += align256(B * m.n_rows * 4);
-  L.geo = o; if (weighting == LF_W_LEARNED) o += align256(B * HW * 16);
+  // learned-weight geometry: two sets on the sorted path, whose gather may read them in place
+  L.geo = o; if (weighting == LF_W_LEARNED) o += align256((L.sorted ? 2 : 1) * B * HW * 16);
   // learned weights: two sets on the sorted path, whose gather reads them in place
   L.wpix = o; if (weighting == LF_W_LEARNED) o += align256((L.sorted ? 2 : 1) * B * HW * 4);
   // first level of the sorted path, used on the caller's stream only: bucket
@@ -330,6 +331,7 @@ lf_status lf_load_mesh(const lf_mesh_opts* opts, const float* d_vertices, int64_
   d.gather_unroll = 8;
   d.small_px = 48;
   d.gather_waves = 8;
+  d.learned_in_gather = 0;
   d.mix = 0.5f;
 
   LF_TRY(launch_zero(d.err, 4, stream), "clear flag");
@@ -488,7 +490,7 @@ lf_status fuse_impl(const FuseArgs& a, void* d_ws, hipStream_t stream) {
   const int64_t* st = a.strides;
   ProbIn in{a.probs, a.scale, a.valid, st[0], st[1], st[2], st[3], a.dtype};
   const bool learned = a.weighting == LF_W_LEARNED;
-  float4* geo = learned ? reinterpret_cast<float4*>(ws + L.geo) : nullptr;
+  float4* geo_sets = learned ? reinterpret_cast<float4*>(ws + L.geo) : nullptr;   // [1 or 2][B][H][W]
   float* wpix_sets = learned ? reinterpret_cast<float*>(ws + L.wpix) : nullptr;   // [1 or 2][B][H][W]
   // the sorted path stores batch-relative element offsets in 32 bits
   const bool staged = mode == LF_SCATTER_STAGED && (int64_t)B * HW * d.c < ((int64_t)1 << 32);
@@ -503,13 +505,20 @@ lf_status fuse_impl(const FuseArgs& a, void* d_ws, hipStream_t stream) {
   // observations per frame itself, so no per-frame count array is kept
   const bool frame_counts = sorted && (a.weighting == LF_W_IMAGE || a.weighting == LF_W_MIX) &&
                             seg_frame_counts_ok(d, staged ? staged_in(ws + L.stage[0], nullptr) : in, B, H, W);
-  int32_t* cnt = (a.weighting != LF_W_PIXEL && !frame_counts) ? reinterpret_cast<int32_t*>(ws + L.cnt) : nullptr;
   // pixels dense in the gather's input: it reads E4M3 scales and the learned
   // weight by pixel index itself, and the fill copies neither
   const bool pix_direct =
       sorted && seg_pixels_dense_ok(d, staged ? staged_in(ws + L.stage[0], nullptr) : in, B, H, W);
   // the grouped gather reads the bucket records; any other layout is sorted by row through memory first
   const bool grouped = sorted && (staged || seg_grouped_ok(d, in));
+  // the learned weight inside the grouped gather: features from the
+  // observations it streams, n from its per-frame counters, geometry from
+  // the resolve (set k of batch k); no count array and no inference pass
+  const bool learn_in_gather =
+      learned && d.learned_in_gather && grouped && seg_learned_ok(d, staged ? staged_in(ws + L.stage[0], nullptr) : in, B, H, W);
+  int32_t* cnt = (a.weighting != LF_W_PIXEL && !frame_counts && !learn_in_gather)
+                     ? reinterpret_cast<int32_t*>(ws + L.cnt)
+                     : nullptr;
   int32_t* seg = sorted ? reinterpret_cast<int32_t*>(ws + L.seg) : nullptr;
   LF_TRY(launch_zero(ws + L.tcnt, B * L.ntiles * 4, stream), "clear tile counts");
   if (cnt) LF_TRY(launch_zero(cnt, (int64_t)B * d.n_rows * 4, stream), "clear counts");
@@ -551,12 +560,16 @@ lf_status fuse_impl(const FuseArgs& a, void* d_ws, hipStream_t stream) {
     const float* cams_in = a.cams + 16 * (int64_t)(f0 - fi);  // camera of input index fi + k is f0 + k
     int32_t* lb = a.l_out ? a.l_out + (int64_t)f0 * HW : reinterpret_cast<int32_t*>(ws + L.l);
     const uint8_t* vb = a.valid ? a.valid + (int64_t)fi * HW : nullptr;
+    const int k = nbatch & 1;   // sorted path: buffer set of this batch
+    float4* geo = learned ? geo_sets + (sorted ? (int64_t)k * B * HW : 0) : nullptr;
+    // geometry set k may still be read by the gather two batches back
+    if (learn_in_gather && nbatch >= 2)
+      LF_TRY(hipStreamWaitEvent(stream, mesh->gathered_ev[k], 0), "wait for gather");
     if (seg) LF_TRY(launch_zero(seg, L.n_buckets * 4, stream), "clear bucket counts");
     RasterOut out{lb, nullptr, nullptr, vb, cnt, d.n_rows, seg, rank, geo};
     if ((status = render_batch(mesh, a.cams, f0, nb, H, W, L, ws, out, stream)) != LF_OK) return status;
-    const int k = nbatch & 1;   // sorted path: buffer set of this batch
-    float* wpix = learned ? wpix_sets + (sorted ? (int64_t)k * B * HW : 0) : nullptr;
-    if (learned) {
+    float* wpix = (learned && !learn_in_gather) ? wpix_sets + (sorted ? (int64_t)k * B * HW : 0) : nullptr;
+    if (learned && !learn_in_gather) {
       // weight set k may still be read by the gather two batches back
       if (sorted && nbatch >= 2) LF_TRY(hipStreamWaitEvent(stream, mesh->gathered_ev[k], 0), "wait for gather");
       StageTimer tm(mesh, 7, stream);
@@ -605,7 +618,10 @@ lf_status fuse_impl(const FuseArgs& a, void* d_ws, hipStream_t stream) {
         if (grouped)
           LF_TRY(launch_bucket_gather(d, staged ? staged_in(stg, nullptr) : in, staged ? 0 : fi, H, W, L.n_buckets,
                                       bstart, blist, counts + 1, rec, rw, rs, nb, frame_counts ? a.weighting : 0,
-                                      d.mix, (learned && pix_direct) ? wpix : nullptr, side),
+                                      d.mix, (learned && pix_direct) ? wpix : nullptr,
+                                      GatherLearn{learn_in_gather ? mesh->mlp : nullptr, geo,
+                                                  a.cams + 16 * (int64_t)f0},
+                                      side),
                  "bucket gather");
         else
           LF_TRY(launch_seg_gather(d, in, fi, spans, counts, eo, ew, es, side), "segment gather");
@@ -1147,7 +1163,10 @@ lf_status lf_set_tuning(lf_mesh mesh, const lf_tuning* t) {
   if (t->small_px < 1 || t->small_px > 1024) return fail(LF_EINVAL, "small_px must be in [1, 1024], got %d", t->small_px);
   if (t->gather_waves < 1 || t->gather_waves > 1024)
     return fail(LF_EINVAL, "gather_waves must be in [1, 1024], got %d", t->gather_waves);
+  if (t->learned_in_gather != 0 && t->learned_in_gather != 1)
+    return fail(LF_EINVAL, "learned_in_gather must be 0 or 1, got %d", t->learned_in_gather);
   mesh->d.small_px = t->small_px;
+  mesh->d.learned_in_gather = t->learned_in_gather;
   mesh->d.gather_waves = t->gather_waves;
   mesh->d.tile = t->tile;
   mesh->d.gather_unroll = t->gather_unroll;
@@ -1206,6 +1225,7 @@ lf_status lf_get_tuning(lf_mesh mesh, lf_tuning* t) {
   t->gather_unroll = mesh->d.gather_unroll;
   t->small_px = mesh->d.small_px;
   t->gather_waves = mesh->d.gather_waves;
+  t->learned_in_gather = mesh->d.learned_in_gather;
   return LF_OK;
 }
 

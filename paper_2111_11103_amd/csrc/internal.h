@@ -28,6 +28,7 @@ struct MeshDev {
   int32_t small_px;          // pixel boxes up to this area are rasterized by one lane
   int32_t gather_waves;      // resident waves per CU the sorted gather's grid is sized for
   float mix;                 // alpha of the mixed weight (1 - alpha) w^(P) + alpha w^(I)
+  int32_t learned_in_gather; // the learned weight evaluated inside the sorted gather where it can (1) or never (0)
 };
 
 __device__ __forceinline__ int64_t row_offset(const MeshDev& m, int64_t t) {
@@ -126,16 +127,51 @@ hipError_t launch_planar_rows(const ProbIn& in, int f_first, int nf, int H, int 
 // Whether the input's classes are contiguous 4-class chunks the grouped
 // gather reads (c <= 64, c % 4 == 0, aligned).
 bool seg_grouped_ok(const MeshDev& m, const ProbIn& in);
+// n / d for every 32-bit unsigned n, with d (>= 1) fixed at launch: the
+// round-up multiplier method (Granlund & Montgomery, "Division by invariant
+// integers using multiplication", 1994): t = mulhi(m, n),
+// q = (t + ((n - t) >> s1)) >> s2.
+struct Udiv {
+  uint32_t m = 1, s1 = 0, s2 = 0;
+  static Udiv make(uint32_t d) {
+    Udiv u;
+    uint32_t l = 0;
+    while (l < 32 && ((uint64_t)1 << l) < d) ++l;   // l = ceil(log2 d)
+    u.m = (uint32_t)((((unsigned __int128)1 << 32) * (((uint64_t)1 << l) - d)) / d + 1);
+    u.s1 = l < 1 ? l : 1;
+    u.s2 = l > 1 ? l - 1 : 0;
+    return u;
+  }
+  __host__ __device__ __forceinline__ uint32_t operator()(uint32_t n) const {
+    const uint32_t t = (uint32_t)(((uint64_t)n * m) >> 32);   // v_mul_hi_u32
+    return (t + ((n - t) >> s1)) >> s2;
+  }
+};
+
+// What the grouped gather needs to evaluate the learned weight itself
+// (mlp = nullptr: it does not): the packed network, the resolve's per-pixel
+// geometry of the batch ([nf][H][W]) and the batch's cameras ([nf][16]).
+// The launcher fills in the image size and its dividers.
+struct GatherLearn {
+  const void* mlp;
+  const float4* geo;
+  const float* cams;
+  uint32_t hw = 0, w = 0;
+  Udiv dhw, dw;
+};
 // Grouped gather from the bucket-ordered records of a batch of nf frames.
-// Weights: from rec_w (or 1) when frame_w is 0 and wpix is null; with
-// frame_w = LF_W_IMAGE or LF_W_MIX the gather counts every row's observations
-// per frame itself (only where seg_frame_counts_ok holds); with wpix
-// ([nf][H][W] per-pixel weights) it reads them by pixel index, as it reads
-// E4M3 scales when rec_s is null (only where seg_pixels_dense_ok holds).
+// Weights: from rec_w (or 1) when frame_w is 0, wpix is null and learn.mlp
+// is null; with frame_w = LF_W_IMAGE or LF_W_MIX the gather counts every
+// row's observations per frame itself (only where seg_frame_counts_ok
+// holds); with wpix ([nf][H][W] per-pixel weights) it reads them by pixel
+// index, as it reads E4M3 scales when rec_s is null (only where
+// seg_pixels_dense_ok holds); with learn.mlp it computes every
+// observation's learned weight from the observation itself (where both
+// hold).
 hipError_t launch_bucket_gather(const MeshDev& m, const ProbIn& in, int f_first, int H, int W, int64_t n_buckets,
                                 const int32_t* bstart, const int32_t* blist, const int32_t* nblist, const uint2* rec,
                                 const float* rec_w, const float* rec_s, int nf, int frame_w, float mix,
-                                const float* wpix, hipStream_t s);
+                                const float* wpix, const GatherLearn& learn, hipStream_t s);
 // Per-class gather over the spans of k_bucket_sort (any strides; weights and
 // E4M3 scales per entry).
 hipError_t launch_seg_gather(const MeshDev& m, const ProbIn& in, int f_first, const int4* spans,
@@ -149,6 +185,10 @@ bool seg_frame_counts_ok(const MeshDev& m, const ProbIn& in, int nf, int H, int 
 // index from its stored offset, to read E4M3 scales and per-pixel weights by
 // it (then the fill stores neither).
 bool seg_pixels_dense_ok(const MeshDev& m, const ProbIn& in, int nf, int H, int W);
+// Whether the grouped gather can evaluate the learned weight itself for
+// input `in` in batches of at most nf frames (frame counts and pixel
+// indices recoverable, nf <= 128, its LDS within 64 KB).
+bool seg_learned_ok(const MeshDev& m, const ProbIn& in, int nf, int H, int W);
 // counts[0] += labelled valid pixels of the label images img [F][H][W],
 // counts[1] += those whose label is the argmax of the pixel's own input.
 hipError_t launch_agreement(const ProbIn& in, int c, int F, int H, int W, const uint8_t* img,

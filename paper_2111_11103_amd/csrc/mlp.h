@@ -13,6 +13,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "internal.h"
+
 namespace lf {
 
 typedef short s4 __attribute__((ext_vector_type(4)));
@@ -50,106 +52,218 @@ __host__ __device__ inline MlpW mlp_view(const void* packed) {
 }
 
 // ---- inference on the matrix cores ---------------------------------------------
-constexpr int H1S = 68;   // LDS row stride of q(h1) in halfwords (conflict-free fragment reads)
+// Both layers are computed transposed (hidden unit x observation), so that a
+// layer's output fragment is, lane for lane, the next layer's B operand: in
+// a 16x16x16 product lane (col, grp) holds D[4 grp + r][col], r = 0..3, and
+// takes B[4 grp + r][col]; q(h1) never leaves the registers.  The input
+// fragments take q(phi) of observation 16 t + col from that lane by
+// permutes.  No LDS is used, so waves do not wait for each other.
 
-struct WaveLds {
-  uint16_t* phi;   // [64][8]
-  uint16_t* h1;    // [64][H1S]
-  float* logit;    // [64]
-};
-
-// Orders the LDS exchanges between the lanes of one wave: the LDS performs a
-// wave's operations in issue order, so only the compiler has to keep them in
-// program order (fences and a wave-level scheduling barrier).
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+__device__ __forceinline__ s4 pack_s4(uint32_t lo, uint32_t hi) {
+  return s4{(short)(lo & 0xffffu), (short)(lo >> 16), (short)(hi & 0xffffu), (short)(hi >> 16)};
 }
 
-// Evaluate the network for the 64 observations of a wave (lane = observation).
-// Every lane of the wave must reach it; L is the wave's own LDS, so waves do
-// not wait for each other.
-__device__ inline float mlp_wave(const float (&phi)[NI], const MlpW& W, const WaveLds& L) {
+// Evaluate the network for the observations of a wave (lane = observation).
+// Every lane of the wave must reach it.  Only the first nt (wave-uniform,
+// 1..4) groups of 16 lanes are evaluated; lanes from 16 nt on get an
+// unspecified value.
+__device__ inline float mlp_wave(const float (&phi)[NI], const MlpW& W, int nt = 4) {
   const int lane = threadIdx.x & 63;
   const int col = lane & 15, grp = lane >> 4;
+  // q(phi) of this lane, two features per word
+  uint32_t qp[NI / 2];
 #pragma unroll
-  for (int k = 0; k < NI; ++k) L.phi[lane * NI + k] = bf16_bits(phi[k]);
-  // B fragments: lane holds B[k = 4*grp + r][j = col] of each 16x16 tile
-  s4 bw1[4];
+  for (int k = 0; k < NI / 2; ++k) qp[k] = (uint32_t)bf16_bits(phi[2 * k]) | ((uint32_t)bf16_bits(phi[2 * k + 1]) << 16);
+  // layer 1: A = W1 tile n (unit 16 n + col, inputs 4 grp .. 4 grp + 3; K padded 8 -> 16)
+  s4 aw1[4];
 #pragma unroll
   for (int n = 0; n < 4; ++n) {
-    s4 t = {0, 0, 0, 0};
+    s4 v = {0, 0, 0, 0};
     if (grp < 2) {
       const uint16_t* w = W.W1 + (n * 16 + col) * NI + 4 * grp;
-      t = s4{(short)w[0], (short)w[1], (short)w[2], (short)w[3]};
+      v = s4{(short)w[0], (short)w[1], (short)w[2], (short)w[3]};
     }
-    bw1[n] = t;
+    aw1[n] = v;
   }
-  wave_lds_sync();
-  // layer 1: h1[sample][unit] for 4 sample tiles x 4 unit tiles
+  float b1v[4][4];
+#pragma unroll
+  for (int n = 0; n < 4; ++n)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) b1v[n][r] = W.b1[n * 16 + 4 * grp + r];
+  s4 h1[4][4];   // [unit tile][observation tile]: q(h1) of units 16 n + 4 grp + r, observation 16 t + col
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
-    s4 a = {0, 0, 0, 0};
-    if (grp < 2) {
-      const uint16_t* x = L.phi + (t * 16 + col) * NI + 4 * grp;
-      a = s4{(short)x[0], (short)x[1], (short)x[2], (short)x[3]};
-    }
+    if (t < nt) {
+      const int src = t * 16 + col;
+      uint32_t q[NI / 2];
 #pragma unroll
-    for (int n = 0; n < 4; ++n) {
-      f4 d = {0.f, 0.f, 0.f, 0.f};
-      d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bw1[n], d, 0, 0, 0);
-      const float bias = W.b1[n * 16 + col];
+      for (int k = 0; k < NI / 2; ++k) q[k] = (uint32_t)__shfl((int)qp[k], src);
+      const s4 bphi = grp == 0 ? pack_s4(q[0], q[1]) : grp == 1 ? pack_s4(q[2], q[3]) : s4{0, 0, 0, 0};
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const float h = fmaxf(d[r] + bias, 0.0f);
-        L.h1[(t * 16 + 4 * grp + r) * H1S + n * 16 + col] = bf16_bits(h);
+      for (int n = 0; n < 4; ++n) {
+        f4 d = {0.f, 0.f, 0.f, 0.f};
+        d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(aw1[n], bphi, d, 0, 0, 0);
+        uint32_t lo = (uint32_t)bf16_bits(fmaxf(d[0] + b1v[n][0], 0.0f)) |
+                      ((uint32_t)bf16_bits(fmaxf(d[1] + b1v[n][1], 0.0f)) << 16);
+        uint32_t hi = (uint32_t)bf16_bits(fmaxf(d[2] + b1v[n][2], 0.0f)) |
+                      ((uint32_t)bf16_bits(fmaxf(d[3] + b1v[n][3], 0.0f)) << 16);
+        h1[n][t] = pack_s4(lo, hi);
       }
     }
   }
-  wave_lds_sync();
-  // layer 2 + output layer
-  float part[4][4];
+  // layer 2 + output layer: A = W2 tile (n2, ks), B = q(h1) tile (ks, t)
+  float part[4] = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-  for (int t = 0; t < 4; ++t)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) part[t][r] = 0.0f;
-#pragma unroll
-  for (int n = 0; n < 4; ++n) {
-    s4 bw2[4];
+  for (int n2 = 0; n2 < 4; ++n2) {
+    s4 aw2[4];
 #pragma unroll
     for (int ks = 0; ks < 4; ++ks) {
-      const uint16_t* w = W.W2 + (n * 16 + col) * NH + ks * 16 + 4 * grp;
-      bw2[ks] = s4{(short)w[0], (short)w[1], (short)w[2], (short)w[3]};
+      const uint16_t* w = W.W2 + (n2 * 16 + col) * NH + ks * 16 + 4 * grp;
+      aw2[ks] = s4{(short)w[0], (short)w[1], (short)w[2], (short)w[3]};
     }
-    const float bias = W.b2[n * 16 + col];
-    const float w3 = bf16_val(W.w3[n * 16 + col]);
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      f4 d = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int ks = 0; ks < 4; ++ks) {
-        const uint16_t* x = L.h1 + (t * 16 + col) * H1S + ks * 16 + 4 * grp;
-        const s4 a = s4{(short)x[0], (short)x[1], (short)x[2], (short)x[3]};
-        d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bw2[ks], d, 0, 0, 0);
-      }
-#pragma unroll
-      for (int r = 0; r < 4; ++r) part[t][r] += w3 * fmaxf(d[r] + bias, 0.0f);
-    }
-  }
-  // sum over the 16 units a lane group holds, per sample row
-#pragma unroll
-  for (int t = 0; t < 4; ++t)
+    float b2v[4], w3v[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      float v = part[t][r];
-#pragma unroll
-      for (int o = 8; o > 0; o >>= 1) v += __shfl_xor(v, o, 16);
-      if (col == 0) L.logit[t * 16 + 4 * grp + r] = v + W.b3[0];
+      b2v[r] = W.b2[n2 * 16 + 4 * grp + r];
+      w3v[r] = bf16_val(W.w3[n2 * 16 + 4 * grp + r]);
     }
-  wave_lds_sync();
-  const float z = L.logit[lane];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      if (t < nt) {
+        f4 d = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(aw2[ks], h1[ks][t], d, 0, 0, 0);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) part[t] = fmaf(w3v[r], fmaxf(d[r] + b2v[r], 0.0f), part[t]);
+      }
+    }
+  }
+  // sum over the four lane groups (units 4 grp + r of every tile); lane
+  // 16 grp + col is observation 16 t + col with t = grp
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    part[t] += __shfl_xor(part[t], 16);
+    part[t] += __shfl_xor(part[t], 32);
+  }
+  const float z = (grp == 0 ? part[0] : grp == 1 ? part[1] : grp == 2 ? part[2] : part[3]) + W.b3[0];
   return 1.0f / (1.0f + expf(-z));
+}
+
+// ---- features ---------------------------------------------------------------------
+// Probability features of pixel (frame f, y, x): normalised entropy, top-1,
+// top-1 minus top-2.  Also returns the first maximal class (BEST).
+// Running entropy / top-2 / first-argmax update with class j's probability,
+// without branches.  The entropy is accumulated in bits with the hardware
+// base-2 logarithm (normalised by log2 c below, the same value as nats /
+// ln c); a probability below the smallest normal binary32 enters the
+// logarithm at that bound (its term is under 1.5e-36, and 0 for p = 0).
+// Top-2 counts a repeated maximum twice: p2 = median(p2, p1, p) is the
+// second largest of {p2 <= p1, p}.
+template <bool BEST>
+__device__ __forceinline__ void prob_step(float p, int j, float& h, float& p1, float& p2, int& best) {
+  h -= p * __log2f(fmaxf(p, 1.17549435e-38f));
+  if constexpr (BEST) best = p > p1 ? j : best;
+  p2 = __builtin_amdgcn_fmed3f(p2, p1, p);
+  p1 = fmaxf(p1, p);
+}
+
+// Entropy sum, top-2 and first argmax over a contiguous class vector of c
+// (c % 4 == 0, c <= 64) values: FP32, or E4M3 codes times `scale`, four per
+// 32-bit word.  `src` may point to global memory or LDS; every load of the
+// vector is issued first.
+template <int DT, bool BEST, typename P>
+__device__ __forceinline__ void vector_features(const P* src, float scale, int c, float& h, float& p1, float& p2,
+                                                int& best) {
+  if constexpr (DT == 0) {
+    const float4* s4p = reinterpret_cast<const float4*>(src);
+    float4 v[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q)
+      if (4 * q < c) v[q] = s4p[q];
+#pragma unroll
+    for (int q = 0; q < 16; ++q)
+      if (4 * q < c) {
+        prob_step<BEST>(v[q].x, 4 * q, h, p1, p2, best);
+        prob_step<BEST>(v[q].y, 4 * q + 1, h, p1, p2, best);
+        prob_step<BEST>(v[q].z, 4 * q + 2, h, p1, p2, best);
+        prob_step<BEST>(v[q].w, 4 * q + 3, h, p1, p2, best);
+      }
+  } else {
+    const uint32_t* s1p = reinterpret_cast<const uint32_t*>(src);
+    uint32_t v[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q)
+      if (4 * q < c) v[q] = s1p[q];
+#pragma unroll
+    for (int q = 0; q < 16; ++q)
+      if (4 * q < c) {
+        prob_step<BEST>(fp8_e4m3_byte<0>(v[q]) * scale, 4 * q, h, p1, p2, best);
+        prob_step<BEST>(fp8_e4m3_byte<1>(v[q]) * scale, 4 * q + 1, h, p1, p2, best);
+        prob_step<BEST>(fp8_e4m3_byte<2>(v[q]) * scale, 4 * q + 2, h, p1, p2, best);
+        prob_step<BEST>(fp8_e4m3_byte<3>(v[q]) * scale, 4 * q + 3, h, p1, p2, best);
+      }
+  }
+}
+
+// Normalised entropy from the entropy sum h (bits); top-2 is 0 for c < 2.
+// Hardware logarithm and reciprocal (about one unit in the last place each).
+__device__ __forceinline__ void finish_prob_features(float h, int c, float& ent, float& p2) {
+  if (c < 2) p2 = 0.0f;
+  ent = c > 1 ? h * __builtin_amdgcn_rcpf(__log2f((float)c)) : 0.0f;
+}
+
+template <int DT, bool BEST>
+__device__ __forceinline__ void prob_features(const ProbIn& in, int64_t base, float scale, int c, float& ent, float& p1,
+                                              float& p2, int& best) {
+  float h = 0.0f;
+  p1 = -__builtin_inff();
+  p2 = -__builtin_inff();
+  best = 0;
+  const int64_t esz = DT == 0 ? 4 : 1;
+  const bool vec = in.sc == 1 && (c & 3) == 0 && c <= 64 &&
+                   ((reinterpret_cast<uintptr_t>(in.p) + base * esz) & (4 * esz - 1)) == 0;
+  if (vec) {
+    vector_features<DT, BEST>(reinterpret_cast<const uint8_t*>(in.p) + base * esz, scale, c, h, p1, p2, best);
+  } else {
+    for (int j = 0; j < c; ++j) {
+      float p;
+      if constexpr (DT == 0) {
+        p = reinterpret_cast<const float*>(in.p)[base + (int64_t)j * in.sc];
+      } else {
+        p = fp8_e4m3(reinterpret_cast<const uint8_t*>(in.p)[base + (int64_t)j * in.sc]) * scale;
+      }
+      prob_step<BEST>(p, j, h, p1, p2, best);
+    }
+  }
+  finish_prob_features(h, c, ent, p2);
+}
+
+// phi of one observation from the renderer's per-pixel geometry (cos of the
+// viewing angle, z/(1+z), centroid closeness), its frame count, its pixel
+// position and the probability features (normalised entropy, top-1, top-2).
+// ln n / ln 64 = log2 n / 6; the radial distance with the hardware square
+// root and reciprocal (about one unit in the last place each).
+__device__ __forceinline__ void observation_phi(float ent, float p1, float p2, float4 geo, int n_same, int x, int y,
+                                                const float* cam, float (&phi)[NI]) {
+  phi[0] = geo.x;
+  phi[1] = geo.y;
+  phi[2] = ent;
+  phi[3] = p1;
+  phi[4] = p1 - p2;
+  phi[5] = geo.z;
+  phi[6] = fminf(__log2f((float)max(n_same, 1)) * (1.0f / 6.0f), 2.0f);
+  const float cx = cam[2], cy = cam[3];
+  const float dx = (float)x + 0.5f - cx, dy = (float)y + 0.5f - cy;
+  phi[7] = __builtin_amdgcn_sqrtf(dx * dx + dy * dy) * __builtin_amdgcn_rsqf(cx * cx + cy * cy);
+}
+
+template <int DT, bool BEST = true>
+__device__ __forceinline__ void observation_features(const ProbIn& in, int64_t base, float scale, int c, float4 geo,
+                                                     int n_same, int x, int y, const float* cam, float (&phi)[NI],
+                                                     int& best) {
+  float ent, p1, p2;
+  prob_features<DT, BEST>(in, base, scale, c, ent, p1, p2, best);
+  observation_phi(ent, p1, p2, geo, n_same, x, y, cam, phi);
 }
 
 }  // namespace lf

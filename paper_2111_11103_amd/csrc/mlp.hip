@@ -7,7 +7,7 @@
 // q = round to bfloat16; W1, W2, w3 are bfloat16, biases and accumulation
 // binary32.  Inference runs both matrix products on the matrix cores
 // (v_mfma_f32_16x16x16_bf16): a wave evaluates 64 observations as four
-// 16-row tiles, staging q(phi) and q(h1) through LDS between the layers.
+// 16-column tiles of the transposed layers, q(h1) kept in registers.
 // Training gradients are accumulated on the vector ALUs in binary32 (one
 // wave per chunk of observations, one lane per hidden unit) and applied
 // with Adam on binary32 master parameters.
@@ -47,125 +47,24 @@ __global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, float* __re
 
 __global__ __launch_bounds__(256) void k_mlp_forward(const void* __restrict__ packed, const float* __restrict__ phi,
                                                      int64_t n, float* __restrict__ w_out) {
-  __shared__ uint16_t sphi[4][64 * NI];
-  __shared__ uint16_t sh1[4][64 * H1S];
-  __shared__ float slog[4][64];
-  const int wv = threadIdx.x >> 6;
-  const WaveLds L{sphi[wv], sh1[wv], slog[wv]};
   const MlpW W = mlp_view(packed);
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   float x[NI];
 #pragma unroll
   for (int k = 0; k < NI; ++k) x[k] = i < n ? phi[i * NI + k] : 0.0f;
-  const float w = mlp_wave(x, W, L);
+  const float w = mlp_wave(x, W);
   if (i < n) w_out[i] = w;
 }
 
-// ---- features ---------------------------------------------------------------------
-// Probability features of pixel (frame f, y, x): normalised entropy, top-1,
-// top-1 minus top-2.  Also returns the first maximal class.
-// Running entropy / top-2 / first-argmax update with class j's probability.
-// The entropy is accumulated in bits with the hardware base-2 logarithm
-// (normalised by log2 c below, the same value as nats / ln c); terms of
-// probabilities below the smallest normal binary32 (each under 1e-36) are
-// left out.
-__device__ __forceinline__ void prob_step(float p, int j, float& h, float& p1, float& p2, int& best) {
-  if (p >= 1.17549435e-38f) h -= p * __log2f(p);
-  if (p > p1) { p2 = p1; p1 = p; best = j; }
-  else if (p > p2) p2 = p;
-}
-
+// Inference as a pass of its own (layouts the grouped gather does not take):
+// weight of every valid covered pixel of the batch (0 elsewhere), from the
+// per-frame count array.
 template <int DT>
-__device__ __forceinline__ void prob_features(const ProbIn& in, int64_t base, float scale, int c, float& ent, float& p1,
-                                              float& p2, int& best) {
-  float h = 0.0f;
-  p1 = -__builtin_inff();
-  p2 = -__builtin_inff();
-  best = 0;
-  const int64_t esz = DT == 0 ? 4 : 1;
-  const bool vec = in.sc == 1 && (c & 3) == 0 && c <= 64 &&
-                   ((reinterpret_cast<uintptr_t>(in.p) + base * esz) & (4 * esz - 1)) == 0;
-  if (vec) {
-    // contiguous classes: issue every load of the vector first, then reduce
-    if constexpr (DT == 0) {
-      const float4* src = reinterpret_cast<const float4*>(reinterpret_cast<const float*>(in.p) + base);
-      float4 v[16];
-#pragma unroll
-      for (int q = 0; q < 16; ++q)
-        if (4 * q < c) v[q] = src[q];
-#pragma unroll
-      for (int q = 0; q < 16; ++q)
-        if (4 * q < c) {
-          prob_step(v[q].x, 4 * q, h, p1, p2, best);
-          prob_step(v[q].y, 4 * q + 1, h, p1, p2, best);
-          prob_step(v[q].z, 4 * q + 2, h, p1, p2, best);
-          prob_step(v[q].w, 4 * q + 3, h, p1, p2, best);
-        }
-    } else {
-      const uint32_t* src = reinterpret_cast<const uint32_t*>(reinterpret_cast<const uint8_t*>(in.p) + base);
-      uint32_t v[16];
-#pragma unroll
-      for (int q = 0; q < 16; ++q)
-        if (4 * q < c) v[q] = src[q];
-#pragma unroll
-      for (int q = 0; q < 16; ++q)
-        if (4 * q < c) {
-          prob_step(fp8_e4m3_byte<0>(v[q]) * scale, 4 * q, h, p1, p2, best);
-          prob_step(fp8_e4m3_byte<1>(v[q]) * scale, 4 * q + 1, h, p1, p2, best);
-          prob_step(fp8_e4m3_byte<2>(v[q]) * scale, 4 * q + 2, h, p1, p2, best);
-          prob_step(fp8_e4m3_byte<3>(v[q]) * scale, 4 * q + 3, h, p1, p2, best);
-        }
-    }
-  } else {
-    for (int j = 0; j < c; ++j) {
-      float p;
-      if constexpr (DT == 0) {
-        p = reinterpret_cast<const float*>(in.p)[base + (int64_t)j * in.sc];
-      } else {
-        p = fp8_e4m3(reinterpret_cast<const uint8_t*>(in.p)[base + (int64_t)j * in.sc]) * scale;
-      }
-      prob_step(p, j, h, p1, p2, best);
-    }
-  }
-  if (c < 2) p2 = 0.0f;
-  ent = c > 1 ? h / log2f((float)c) : 0.0f;
-}
-
-// phi of one observation from the renderer's per-pixel geometry (cos of the
-// viewing angle, z/(1+z), centroid closeness), its frame count, its pixel
-// position and its probabilities.
-template <int DT>
-__device__ __forceinline__ void observation_features(const ProbIn& in, int64_t base, float scale, int c, float4 geo,
-                                                     int n_same, int x, int y, const float* cam, float (&phi)[NI],
-                                                     int& best) {
-  float ent, p1, p2;
-  prob_features<DT>(in, base, scale, c, ent, p1, p2, best);
-  phi[0] = geo.x;
-  phi[1] = geo.y;
-  phi[2] = ent;
-  phi[3] = p1;
-  phi[4] = p1 - p2;
-  phi[5] = geo.z;
-  phi[6] = fminf(logf((float)max(n_same, 1)) / logf(64.0f), 2.0f);
-  const float cx = cam[2], cy = cam[3];
-  const float dx = (float)x + 0.5f - cx, dy = (float)y + 0.5f - cy;
-  phi[7] = sqrtf(dx * dx + dy * dy) / sqrtf(cx * cx + cy * cy);
-}
-
-// Fused inference during fusion: weight of every valid covered pixel of the
-// batch (0 elsewhere).  The LDS of a block admits four waves per SIMD; the
-// register budget is held to that occupancy (no AGPR overflow, no spills).
-template <int DT>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_mlp_weights(const void* __restrict__ packed, ProbIn in, int f_first, int H,
+__global__ __launch_bounds__(256) void k_mlp_weights(const void* __restrict__ packed, ProbIn in, int f_first, int H,
                                                      int W, const float* __restrict__ cams,
                                                      const int32_t* __restrict__ lbuf, const float4* __restrict__ geo,
                                                      const int32_t* __restrict__ cnt, int64_t cnt_stride, int c,
                                                      float* __restrict__ wpix) {
-  __shared__ uint16_t sphi[4][64 * NI];
-  __shared__ uint16_t sh1[4][64 * H1S];
-  __shared__ float slog[4][64];
-  const int wv = threadIdx.x >> 6;
-  const WaveLds L{sphi[wv], sh1[wv], slog[wv]};
   const MlpW Wt = mlp_view(packed);
   const int fb = blockIdx.y;
   const int64_t HW = (int64_t)H * W;
@@ -184,11 +83,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
       const int64_t base = (int64_t)(f_first + fb) * in.sf + (int64_t)y * in.sy + (int64_t)xx * in.sx;
       const float sc = DT == 3 ? in.scale[gi] : 1.0f;
       int best;
-      observation_features<DT>(in, base, sc, c, geo[pi], cnt[(int64_t)fb * cnt_stride + l], xx, y,
+      observation_features<DT, false>(in, base, sc, c, geo[pi], cnt[(int64_t)fb * cnt_stride + l], xx, y,
                                cams + 16 * (int64_t)(f_first + fb), x, best);
     }
   }
-  const float w = mlp_wave(x, Wt, L);
+  const float w = mlp_wave(x, Wt);
   if (p < HW) wpix[pi] = use ? w : 0.0f;
 }
 

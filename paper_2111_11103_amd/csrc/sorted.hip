@@ -18,7 +18,8 @@
 //                 workgroup per bucket sorts its records by row in LDS, then
 //                 16 lanes per row (4 classes each) stream the row's
 //                 observations, sum w * f(p) in registers and update the row
-//                 once;
+//                 once (with the learned weight, the workgroup first
+//                 evaluates the network for every record of the bucket);
 //   k_bucket_sort + k_seg_gather  any other layout: the buckets' records
 //                 sorted by row through memory (one span (row, start, end)
 //                 per touched row), then one wave per 64 touched rows,
@@ -30,6 +31,7 @@
 
 #include "accum.h"
 #include "internal.h"
+#include "mlp.h"
 #include "spec.h"
 
 namespace lf {
@@ -476,16 +478,19 @@ struct GatherCtx {
   const float* wpix;
   const float* ew;   // per-observation weights, or nullptr
   const float* es;   // per-observation E4M3 scales, or nullptr
+  Udiv dsfd, dspix;  // division by sfd and by spix (1 where spix = 0)
 };
 
 // The observations of one row: element offsets off[0 .. n); observation k's
 // weight and scale sit at ibase + (idx ? idx[k] : k) of ew / es; fcnt = the
-// row's per-frame counts (frame weights).
+// row's per-frame counts (frame weights); sw[k] = observation k's learned
+// weight when the gather evaluated the network itself.
 struct RowObs {
   const uint32_t* off;
   const uint16_t* idx;
   int64_t ibase;
   const int* fcnt;
+  const float* sw;
 };
 
 // One group (16 lanes) adds the row's observations to texel row x: up to 16
@@ -515,11 +520,13 @@ __device__ __forceinline__ void gather_row(const MeshDev& m, const ProbIn& in, c
     const int kk = k0 + gl;
     const bool okl = kk < n;
     const uint32_t my_e = okl ? ro.off[kk] : 0u;
-    const uint32_t my_p = gc.spix ? my_e / gc.spix : 0u;   // batch-relative pixel index
+    const uint32_t my_p = gc.spix ? gc.dspix(my_e) : 0u;   // batch-relative pixel index
     const int64_t ei = ro.ibase + (ro.idx ? (int64_t)ro.idx[okl ? kk : 0] : (int64_t)kk);
     float my_w;
-    if (gc.frame_w) {
-      const float nn = okl ? (float)ro.fcnt[my_e / gc.sfd] : 1.0f;
+    if (ro.sw) {
+      my_w = okl ? ro.sw[kk] : 0.0f;
+    } else if (gc.frame_w) {
+      const float nn = okl ? (float)ro.fcnt[gc.dsfd(my_e)] : 1.0f;
       my_w = okl ? (gc.frame_w == 1 ? 1.0f / nn : (1.0f - gc.mix) + gc.mix / nn) : 0.0f;
     } else if (gc.wpix) {
       my_w = okl ? gc.wpix[my_p] : 0.0f;
@@ -614,47 +621,98 @@ __device__ __forceinline__ void gather_row(const MeshDev& m, const ProbIn& in, c
 // The grouped gather straight from the bucket-ordered records: one workgroup
 // per non-empty bucket (walking the list), one group per row of the bucket
 // (kBucketRows = 16 groups).  The bucket's records are counted per row and
-// frame in LDS (frame weights), then taken kBucketChunk at a time: counted
-// per row, scanned, and moved into LDS in row order, and every group adds its
-// row's observations of the chunk (a row split over chunks is read and
-// written once per chunk, by the same workgroup, in order).
+// frame in LDS (frame weights, learned weight), then taken a chunk at a
+// time: counted per row, scanned, and moved into LDS in row order, and every
+// group adds its row's observations of the chunk (a row split over chunks is
+// read and written once per chunk, by the same workgroup, in order).
 constexpr int kBucketChunk = 2048;
+constexpr int kLearnChunk = 1024;   // records per chunk with the learned weight
 
-size_t bucket_gather_lds(int nf, int frame_w) {
-  return (size_t)kBucketChunk * 4 + (size_t)kBucketChunk * 2 + 3 * kBucketRows * 4 +
-         (frame_w ? (size_t)kBucketRows * nf * 4 : 0);
+__host__ __device__ inline size_t bucket_gather_lds(int nf, bool frame_counts, bool learned) {
+  const size_t ch = learned ? kLearnChunk : kBucketChunk;
+  return ch * 4 + (learned ? ch * 4 : 0) + ch * 2 + 3 * kBucketRows * 4 +
+         (frame_counts ? (size_t)kBucketRows * nf * 4 : 0);
 }
 
-template <int DT, int AGG, int AT, int U>
-__global__ __launch_bounds__(256) void k_bucket_gather16(MeshDev m, ProbIn in, PixDecode dec, GatherCtx gc,
-                                                         const int32_t* __restrict__ bstart,
-                                                         const int32_t* __restrict__ blist,
-                                                         const int32_t* __restrict__ nblist,
-                                                         const uint2* __restrict__ rec, int nf) {
+// The learned weight of every record of a chunk (row order, d = 0 .. n):
+// wave w takes records 64 (w + 4 i) .. + 63, one per lane: features as the
+// separate inference pass computes them (probabilities from the record's
+// class vector, geometry from the resolve's per-pixel copy, n from the
+// bucket's frame counters), the network on the matrix cores for the
+// 16-record tiles the records fill, weights into LDS.  Pixels are dense in
+// the input (offset = spix * batch-relative pixel index).
+template <int DT>
+__device__ __forceinline__ void chunk_learned_weights(const MeshDev& m, const ProbIn& in, const PixDecode& dec,
+                                                      const GatherCtx& gc, const GatherLearn& lc,
+                                                      const uint32_t* soff, const uint16_t* srow, const int* fc,
+                                                      int nf, int n, float* sw) {
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int c = m.c;
+  for (int base = wv * 64; base < n; base += 256) {
+    // the network's parameters are read where they are used (from cache),
+    // not held in registers across records
+    const void* wp = lc.mlp;
+    asm volatile("" : "+s"(wp));
+    const MlpW Wt = mlp_view(wp);
+    const int d = base + lane;
+    const bool ok = d < n;
+    float phi[NI];
+#pragma unroll
+    for (int k = 0; k < NI; ++k) phi[k] = 0.0f;
+    if (ok) {
+      const uint32_t e = soff[d];
+      const uint32_t p = gc.dspix(e);            // batch-relative pixel index
+      const uint32_t fb = lc.dhw(p);
+      const uint32_t rem = p - fb * lc.hw;
+      const uint32_t y = lc.dw(rem), x = rem - y * lc.w;
+      const float sc = DT == 3 ? in.scale[gc.sbase + p] : 1.0f;
+      float h = 0.0f, p1 = -__builtin_inff(), p2 = -__builtin_inff(), ent;
+      int best = 0;
+      vector_features<DT, false>(reinterpret_cast<const uint8_t*>(in.p) + dec(in, e) * (DT == 0 ? 4 : 1), sc, c, h,
+                                 p1, p2, best);
+      finish_prob_features(h, c, ent, p2);
+      observation_phi(ent, p1, p2, lc.geo[p], fc[srow[d] * nf + gc.dsfd(e)], (int)x, (int)y,
+                      lc.cams + 16 * (int64_t)fb, phi);
+    }
+    const float w = mlp_wave(phi, Wt, min(4, (n - base + 15) >> 4));
+    if (ok) sw[d] = w;
+  }
+}
+
+template <int DT, int AGG, int AT, int U, bool LW>
+__device__ __forceinline__ void bucket_gather16(const MeshDev& m, const ProbIn& in, const PixDecode& dec,
+                                                const GatherCtx& gc, const GatherLearn& lc, int H, int W,
+                                                const int32_t* __restrict__ bstart, const int32_t* __restrict__ blist,
+                                                const int32_t* __restrict__ nblist, const uint2* __restrict__ rec,
+                                                int nf) {
   static_assert(kBucketRows == 16, "one group of 16 lanes per row of a bucket");
+  constexpr int CH = LW ? kLearnChunk : kBucketChunk;
   extern __shared__ int lds[];
-  uint32_t* soff = reinterpret_cast<uint32_t*>(lds);                    // [kBucketChunk] offsets, row order
-  uint16_t* sidx = reinterpret_cast<uint16_t*>(soff + kBucketChunk);    // [kBucketChunk] chunk index of each
-  int* rcnt = reinterpret_cast<int*>(sidx + kBucketChunk);              // [16] the chunk's count per row
+  uint32_t* soff = reinterpret_cast<uint32_t*>(lds);                    // [CH] offsets, row order
+  float* sw = reinterpret_cast<float*>(soff + CH);                      // LW: [CH] learned weights
+  uint16_t* sidx = reinterpret_cast<uint16_t*>(LW ? reinterpret_cast<uint32_t*>(sw + CH) : soff + CH);
+                                                                        // [CH] chunk index (LW: row) of each
+  int* rcnt = reinterpret_cast<int*>(sidx + CH);                        // [16] the chunk's count per row
   int* rst = rcnt + kBucketRows;                                        // [16] start per row
   int* rcur = rst + kBucketRows;                                        // [16] cursor per row
   int* fc = rcur + kBucketRows;                                         // [16][nf] frame counts
   const int t = threadIdx.x, gl = t & 15, grp = t >> 4;
   const bool act = gl < (m.c >> 2);
+  const bool counts = LW || gc.frame_w;
   const int nb = *nblist;
   for (int g = blockIdx.x; g < nb; g += gridDim.x) {
     const int b = blist[g];
     const int s0 = bstart[b], s1 = bstart[b + 1];
-    if (gc.frame_w) {
+    if (counts) {
       for (int i = t; i < kBucketRows * nf; i += 256) fc[i] = 0;
       __syncthreads();
       for (int i = s0 + t; i < s1; i += 256) {
         const uint2 q = rec[i];
-        atomicAdd(&fc[(q.y & kBucketMask) * nf + q.x / gc.sfd], 1);
+        atomicAdd(&fc[(q.y & kBucketMask) * nf + gc.dsfd(q.x)], 1);
       }
     }
-    for (int c0 = s0; c0 < s1; c0 += kBucketChunk) {
-      const int n = min(kBucketChunk, s1 - c0);
+    for (int c0 = s0; c0 < s1; c0 += CH) {
+      const int n = min(CH, s1 - c0);
       if (t < kBucketRows) rcnt[t] = 0;
       __syncthreads();
       for (int i = t; i < n; i += 256) atomicAdd(&rcnt[rec[c0 + i].y & kBucketMask], 1);
@@ -675,18 +733,44 @@ __global__ __launch_bounds__(256) void k_bucket_gather16(MeshDev m, ProbIn in, P
       __syncthreads();
       for (int i = t; i < n; i += 256) {
         const uint2 q = rec[c0 + i];
-        const int d = atomicAdd(&rcur[q.y & kBucketMask], 1);
+        const int r = q.y & kBucketMask;
+        const int d = atomicAdd(&rcur[r], 1);
         soff[d] = q.x;
-        sidx[d] = (uint16_t)i;
+        sidx[d] = (uint16_t)(LW ? r : i);
       }
       __syncthreads();
+      if constexpr (LW) {
+        chunk_learned_weights<DT>(m, in, dec, gc, lc, soff, sidx, fc, nf, n, sw);
+        __syncthreads();
+      }
       const int cnt = rcnt[grp];
       if (cnt > 0)
         gather_row<DT, AGG, AT, U>(m, in, dec, gc, (int64_t)b * kBucketRows + grp, cnt,
-                                   RowObs{soff + rst[grp], sidx + rst[grp], c0, fc + grp * nf}, gl, act);
+                                   RowObs{soff + rst[grp], LW ? nullptr : sidx + rst[grp], c0, fc + grp * nf,
+                                          LW ? sw + rst[grp] : nullptr},
+                                   gl, act);
       __syncthreads();                                 // the chunk's LDS is reused next
     }
   }
+}
+
+template <int DT, int AGG, int AT, int U>
+__global__ __launch_bounds__(256) void k_bucket_gather16(MeshDev m, ProbIn in, PixDecode dec, GatherCtx gc,
+                                                         GatherLearn lc, int H, int W,
+                                                         const int32_t* __restrict__ bstart,
+                                                         const int32_t* __restrict__ blist,
+                                                         const int32_t* __restrict__ nblist,
+                                                         const uint2* __restrict__ rec, int nf) {
+  bucket_gather16<DT, AGG, AT, U, false>(m, in, dec, gc, lc, H, W, bstart, blist, nblist, rec, nf);
+}
+
+// With the learned weight: registers for four waves per SIMD (no spills).
+template <int DT, int AGG, int AT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_bucket_gather16_learned(
+    MeshDev m, ProbIn in, PixDecode dec, GatherCtx gc, GatherLearn lc, int H, int W,
+    const int32_t* __restrict__ bstart, const int32_t* __restrict__ blist, const int32_t* __restrict__ nblist,
+    const uint2* __restrict__ rec, int nf) {
+  bucket_gather16<DT, AGG, AT, 8, true>(m, in, dec, gc, lc, H, W, bstart, blist, nblist, rec, nf);
 }
 
 constexpr int kCountFrames = 256;   // frames per batch the gather's frame counters cover (16 KB of LDS)
@@ -716,36 +800,51 @@ bool seg_pixels_dense_ok(const MeshDev& m, const ProbIn& in, int nf, int H, int 
 
 bool seg_grouped_ok(const MeshDev& m, const ProbIn& in) { return grouped_ok(m, in); }
 
+constexpr int kLearnFrames = 128;   // frames per batch of the learned gather (per-wave frame counters)
+
+bool seg_learned_ok(const MeshDev& m, const ProbIn& in, int nf, int H, int W) {
+  return nf <= kLearnFrames && seg_frame_counts_ok(m, in, nf, H, W) && seg_pixels_dense_ok(m, in, nf, H, W) &&
+         bucket_gather_lds(nf, true, true) <= 65536;
+}
+
 hipError_t launch_bucket_gather(const MeshDev& m, const ProbIn& in, int f_first, int H, int W, int64_t n_buckets,
                                 const int32_t* bstart, const int32_t* blist, const int32_t* nblist, const uint2* rec,
                                 const float* rec_w, const float* rec_s, int nf, int frame_w, float mix,
-                                const float* wpix, hipStream_t s) {
+                                const float* wpix, const GatherLearn& learn, hipStream_t s) {
   if (m.n_rows == 0 || n_buckets <= 0) return hipSuccess;
   if (!grouped_ok(m, in)) return hipErrorInvalidValue;
-  if (frame_w && ((frame_w != 1 && frame_w != 3) || !seg_frame_counts_ok(m, in, nf, H, W)))
+  const bool learned = learn.mlp != nullptr;
+  if ((frame_w || learned) && !seg_frame_counts_ok(m, in, nf, H, W)) return hipErrorInvalidValue;
+  if (frame_w && frame_w != 1 && frame_w != 3) return hipErrorInvalidValue;
+  if (learned && (frame_w || wpix || rec_w || !learn.geo || !learn.cams || !seg_learned_ok(m, in, nf, H, W)))
     return hipErrorInvalidValue;
-  // E4M3 without per-observation scales, or per-pixel weights: read by pixel index
-  const bool direct = (in.dtype == 3 && !rec_s) || wpix;
+  // E4M3 without per-observation scales, per-pixel weights or the learned
+  // weight: read by pixel index
+  const bool direct = (in.dtype == 3 && !rec_s) || wpix || learned;
   if (direct && ((in.dtype == 3 && !in.scale) || (frame_w && wpix) || !seg_pixels_dense_ok(m, in, nf, H, W)))
     return hipErrorInvalidValue;
-  GatherCtx gc{frame_w,
-               mix,
-               nf > 1 ? (uint32_t)in.sf : 0xffffffffu,   // every stored offset is below 2^32 - 1
-               direct ? (uint32_t)in.sx : 0u,
-               (int64_t)f_first * H * W,
-               wpix,
-               rec_w,
-               rec_s};
+  const uint32_t sfd = nf > 1 ? (uint32_t)in.sf : 0xffffffffu;   // every stored offset is below 2^32 - 1
+  const uint32_t spix = direct ? (uint32_t)in.sx : 0u;
+  GatherCtx gc{frame_w, mix, sfd, spix, (int64_t)f_first * H * W, wpix, rec_w, rec_s, Udiv::make(sfd),
+               Udiv::make(spix ? spix : 1u)};
+  GatherLearn lc = learn;
+  lc.hw = (uint32_t)H * (uint32_t)W;
+  lc.w = (uint32_t)W;
+  lc.dhw = Udiv::make(lc.hw);
+  lc.dw = Udiv::make(lc.w);
   const PixDecode dec{(int64_t)f_first * in.sf};
-  const size_t lds = bucket_gather_lds(nf, frame_w);
+  const size_t lds = bucket_gather_lds(nf, frame_w || learned, learned);
   // gather_waves resident waves (one workgroup = 4 waves) on each of the 256 CUs
   const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>(n_buckets, (int64_t)64 * m.gather_waves));
-#define LF_R(DT, AGG, AT)                                                                                      \
-  do {                                                                                                         \
-    if (m.gather_unroll == 4)                                                                                  \
-      k_bucket_gather16<DT, AGG, AT, 4><<<g, 256, lds, s>>>(m, in, dec, gc, bstart, blist, nblist, rec, nf);   \
-    else                                                                                                       \
-      k_bucket_gather16<DT, AGG, AT, 8><<<g, 256, lds, s>>>(m, in, dec, gc, bstart, blist, nblist, rec, nf);   \
+#define LF_ARGS m, in, dec, gc, lc, H, W, bstart, blist, nblist, rec, nf
+#define LF_R(DT, AGG, AT)                                                                   \
+  do {                                                                                      \
+    if (learned)                                                                            \
+      k_bucket_gather16_learned<DT, AGG, AT><<<g, 256, lds, s>>>(LF_ARGS);                  \
+    else if (m.gather_unroll == 4)                                                          \
+      k_bucket_gather16<DT, AGG, AT, 4><<<g, 256, lds, s>>>(LF_ARGS);                       \
+    else                                                                                    \
+      k_bucket_gather16<DT, AGG, AT, 8><<<g, 256, lds, s>>>(LF_ARGS);                       \
   } while (0)
 #define LF_R2(DT)                                                                                            \
   do {                                                                                                       \
@@ -758,6 +857,7 @@ hipError_t launch_bucket_gather(const MeshDev& m, const ProbIn& in, int f_first,
   else LF_R2(3);
 #undef LF_R2
 #undef LF_R
+#undef LF_ARGS
   return hipGetLastError();
 }
 

@@ -41,7 +41,7 @@ class _MeshOpts(C.Structure):
 
 class _Tuning(C.Structure):
     _fields_ = [("tile", C.c_int32), ("gather_unroll", C.c_int32), ("small_px", C.c_int32),
-                ("gather_waves", C.c_int32)]
+                ("gather_waves", C.c_int32), ("learned_in_gather", C.c_int32)]
 
 
 class _SceneJob(C.Structure):
@@ -396,9 +396,10 @@ class Mesh:
         return area
 
     # -- tuning and jobs ----------------------------------------------------------------
-    def set_tuning(self, tile=32, gather_unroll=8, small_px=48, gather_waves=8):
+    def set_tuning(self, tile=32, gather_unroll=8, small_px=48, gather_waves=8, learned_in_gather=0):
         """lf_set_tuning (results do not depend on it)."""
-        _check(lib().lf_set_tuning(self._h, C.byref(_Tuning(tile, gather_unroll, small_px, gather_waves))))
+        _check(lib().lf_set_tuning(self._h, C.byref(_Tuning(tile, gather_unroll, small_px, gather_waves,
+                                                            1 if learned_in_gather else 0))))
         self._fws.clear()
 
     def set_overlap(self, enabled=True):
@@ -410,7 +411,7 @@ class Mesh:
         t = _Tuning()
         _check(lib().lf_get_tuning(self._h, C.byref(t)))
         return {"tile": t.tile, "gather_unroll": t.gather_unroll, "small_px": t.small_px,
-                "gather_waves": t.gather_waves}
+                "gather_waves": t.gather_waves, "learned_in_gather": t.learned_in_gather}
 
     def job(self, cams, probs, *, scale=None, valid=None, pool=0, weighting=W_PIXEL, batch=16,
             scatter_mode=SCATTER_AUTO, l_out=None, tex_dtype=None, images=False):

@@ -104,7 +104,8 @@ def _ws_bytes(mesh, H, W, batch, weighting, mode, probs):
 
 
 def _apply(mesh, cfg):
-    mesh.set_tuning(cfg["tile"], cfg["gather_unroll"], cfg["small_px"], cfg["gather_waves"])
+    mesh.set_tuning(cfg["tile"], cfg["gather_unroll"], cfg["small_px"], cfg["gather_waves"],
+                    cfg.get("learned_in_gather", 0))
 
 
 def autotune(mesh: sf.Mesh, cams: torch.Tensor, probs: torch.Tensor, *, scale=None, valid=None,
@@ -160,6 +161,10 @@ def autotune(mesh: sf.Mesh, cams: torch.Tensor, probs: torch.Tensor, *, scale=No
              "gather_unroll": 8, "gather_waves": 8}
     sweeps = [("batch", batches), ("scatter_mode", modes), ("tile", TILES), ("small_px", SMALL),
               ("gather_unroll", UNROLLS), ("gather_waves", GATHER_WAVES)]
+    if weighting == sf.W_LEARNED:
+        # where the network runs: inside the gather, or a separate pass first
+        start["learned_in_gather"] = 0
+        sweeps.append(("learned_in_gather", (0, 1)))
     best, best_ms = coordinate_descent(trial, start, sweeps)
     mesh.reset()
     mesh._fws.clear()

@@ -89,7 +89,7 @@ def test_tunings_do_not_change_results(scenes):
     for tile, unroll, small, gw in ((16, 4, 12, 8), (16, 8, 1, 1), (32, 4, 96, 32), (32, 8, 48, 512)):
         t = {"tile": tile, "gather_unroll": unroll, "small_px": small, "gather_waves": gw}
         jobs, meshes = _jobs(scenes[:1], tunings=[t])
-        assert meshes[0].get_tuning() == t
+        assert meshes[0].get_tuning() == dict(t, learned_in_gather=0)
         sf.fuse_batch(jobs)
         _check(jobs, scenes[:1], f"tile {tile} unroll {unroll}")
         r = meshes[0].rasterize(to_dev(d["cams"], torch.float32), d["H"], d["W"])
@@ -141,7 +141,9 @@ def test_autotuner_picks_and_caches(scenes, tmp_path):
     path = str(tmp_path / "tune.json")
     r1 = tune.autotune(m, cams, probs, valid=d["valid"].cuda(), probe_frames=8, cache_path=path, log=say)
     assert not r1["cached"] and r1["n_candidates"] >= 6
-    assert m.get_tuning() == {k: r1[k] for k in ("tile", "gather_unroll", "small_px", "gather_waves")}
+    got = m.get_tuning()
+    assert {k: got[k] for k in ("tile", "gather_unroll", "small_px", "gather_waves")} == \
+        {k: r1[k] for k in ("tile", "gather_unroll", "small_px", "gather_waves")}
     with open(path) as fh:
         table = json.load(fh)
     assert len(table) == 1
