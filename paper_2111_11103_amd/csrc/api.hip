@@ -412,6 +412,7 @@ struct FuseArgs {
   int32_t weighting;
   int32_t* l_out;
   int32_t batch, scatter_mode;
+  bool one_stream = false;   // gathers (and staging) on the call's stream even when the mesh overlaps
 };
 
 // Resolved scatter mode (AUTO -> SORTED iff classes are contiguous) and the
@@ -525,7 +526,7 @@ lf_status fuse_impl(const FuseArgs& a, void* d_ws, hipStream_t stream) {
   int32_t* rank = sorted ? reinterpret_cast<int32_t*>(ws + L.rank) : nullptr;
   lf_status status;
   int nbatch = 0;      // sorted batches issued: batch k's gather runs on `side`
-  hipStream_t side = mesh->overlap ? mesh->side : stream;
+  hipStream_t side = (mesh->overlap && !a.one_stream) ? mesh->side : stream;
   // batches: frames [f0, f0 + nb) read input frames [fi, fi + nb)
   struct Batch {
     int f0, nb, fi;
@@ -682,7 +683,9 @@ lf_status check_jobs(const lf_scene_job* jobs, int32_t n, const void* ws, int64_
 }
 
 // One job, complete, on `stream` with workspace d_ws.
-lf_status run_job(const lf_scene_job& j, void* d_ws, hipStream_t stream) {
+// one_stream: the scene runs entirely on `stream` (no side-stream overlap
+// within the scene: several scene lanes already fill the device).
+lf_status run_job(const lf_scene_job& j, void* d_ws, hipStream_t stream, bool one_stream = false) {
   lf_mesh m = j.mesh;
   {
     StageTimer tm(m, 6, stream);
@@ -690,7 +693,9 @@ lf_status run_job(const lf_scene_job& j, void* d_ws, hipStream_t stream) {
            "clear accumulator");
     if (m->d.wsum) LF_TRY(launch_zero(m->d.wsum, m->d.n_rows * 4, stream), "clear weights");
   }
-  lf_status st = fuse_impl(job_args(j), d_ws, stream);
+  FuseArgs a = job_args(j);
+  a.one_stream = one_stream;
+  lf_status st = fuse_impl(a, d_ws, stream);
   if (st != LF_OK) return st;
   {
     StageTimer tm(m, 4, stream);
@@ -713,12 +718,14 @@ lf_status run_job(const lf_scene_job& j, void* d_ws, hipStream_t stream) {
 // ---- many scenes at once: scene lanes ---------------------------------------------
 // The jobs of one batched call run on up to kBatchLanes streams of the
 // library at once (forked from and joined back into the caller's stream with
-// events, so that a captured graph holds the lanes as parallel branches):
-// the kernels of small scenes then fill the compute units that a large
-// scene's latency-bound kernels leave idle.  Jobs on one mesh share a lane
-// (in call order); meshes are dealt to lanes largest first, each to the lane
-// with the least work (frames x pixels).  Every lane has its own slice of the
-// workspace.
+// events): the kernels of small scenes then fill the compute units that a
+// large scene's latency-bound kernels leave idle.  With several lanes a
+// scene runs on its lane's stream alone (no second stream per scene for the
+// gathers: the lanes already overlap one scene's gathers with another's
+// raster, and the extra streams cost more than they hide).  Jobs on one mesh
+// share a lane (in call order); meshes are dealt to lanes largest first,
+// each to the lane with the least work (frames x pixels).  Every lane has
+// its own slice of the workspace.
 constexpr int kBatchLanes = 4;
 
 struct LanePool {
@@ -796,7 +803,7 @@ lf_status run_jobs(const lf_scene_job* jobs, int32_t n, void* d_ws, hipStream_t 
   for (int l = 0; l < plan.lanes; ++l) LF_TRY(hipStreamWaitEvent(lp->s[l], lp->fork, 0), "lane start");
   for (int i = 0; i < n; ++i) {
     const int l = plan.lane[i];
-    if ((st = run_job(jobs[i], ws + (int64_t)l * plan.lane_bytes, lp->s[l])) != LF_OK) return st;
+    if ((st = run_job(jobs[i], ws + (int64_t)l * plan.lane_bytes, lp->s[l], true)) != LF_OK) return st;
   }
   for (int l = 0; l < plan.lanes; ++l) {
     LF_TRY(hipEventRecord(lp->join[l], lp->s[l]), "lane end");
@@ -1002,7 +1009,7 @@ lf_status lf_graph_capture_batch(const lf_scene_job* jobs, int32_t n, void* d_ws
       break;
     }
     for (int i = 0; i < n && st == LF_OK; ++i)
-      if (plan.lane[i] == l) st = run_job(jobs[i], ws + (int64_t)l * plan.lane_bytes, ls);
+      if (plan.lane[i] == l) st = run_job(jobs[i], ws + (int64_t)l * plan.lane_bytes, ls, plan.lanes > 1);
     hipGraph_t lg = nullptr;
     e = hipStreamEndCapture(ls, &lg);
     if (st == LF_OK && e != hipSuccess) st = fail(LF_EHIP, "end capture: %s", hipGetErrorString(e));
