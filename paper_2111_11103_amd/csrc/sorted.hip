@@ -630,7 +630,7 @@ constexpr int kLearnChunk = 1024;   // records per chunk with the learned weight
 
 __host__ __device__ inline size_t bucket_gather_lds(int nf, bool frame_counts, bool learned) {
   const size_t ch = learned ? kLearnChunk : kBucketChunk;
-  return ch * 4 + (learned ? ch * 4 : 0) + ch * 2 + 3 * kBucketRows * 4 +
+  return ch * 4 + (learned ? ch * 4 : 0) + ch * 2 + 4 * kBucketRows * 4 +
          (frame_counts ? (size_t)kBucketRows * nf * 4 : 0);
 }
 
@@ -692,17 +692,34 @@ __device__ __forceinline__ void bucket_gather16(const MeshDev& m, const ProbIn& 
   float* sw = reinterpret_cast<float*>(soff + CH);                      // LW: [CH] learned weights
   uint16_t* sidx = reinterpret_cast<uint16_t*>(LW ? reinterpret_cast<uint32_t*>(sw + CH) : soff + CH);
                                                                         // [CH] chunk index (LW: row) of each
-  int* rcnt = reinterpret_cast<int*>(sidx + CH);                        // [16] the chunk's count per row
-  int* rst = rcnt + kBucketRows;                                        // [16] start per row
+  int* rcnt2 = reinterpret_cast<int*>(sidx + CH);                       // [2][16] the chunk's count per row
+                                                                        // (chunk j uses half j % 2)
+  int* rst = rcnt2 + 2 * kBucketRows;                                   // [16] start per row
   int* rcur = rst + kBucketRows;                                        // [16] cursor per row
   int* fc = rcur + kBucketRows;                                         // [16][nf] frame counts
   const int t = threadIdx.x, gl = t & 15, grp = t >> 4;
   const bool act = gl < (m.c >> 2);
   const bool counts = LW || gc.frame_w;
   const int nb = *nblist;
-  for (int g = blockIdx.x; g < nb; g += gridDim.x) {
-    const int b = blist[g];
-    const int s0 = bstart[b], s1 = bstart[b + 1];
+  int g = blockIdx.x;
+  int b = 0, s0 = 0, s1 = 0;
+  if (g < nb) {
+    b = blist[g];
+    s0 = bstart[b];
+    s1 = bstart[b + 1];
+  }
+  if (t < 2 * kBucketRows) rcnt2[t] = 0;
+  __syncthreads();
+  int j = 0;                                           // chunks done by this workgroup
+  while (g < nb) {
+    // the next bucket's place, read while this one is summed
+    const int gn = g + (int)gridDim.x;
+    int bn = 0, s0n = 0, s1n = 0;
+    if (gn < nb) {
+      bn = blist[gn];
+      s0n = bstart[bn];
+      s1n = bstart[bn + 1];
+    }
     if (counts) {
       for (int i = t; i < kBucketRows * nf; i += 256) fc[i] = 0;
       __syncthreads();
@@ -711,11 +728,20 @@ __device__ __forceinline__ void bucket_gather16(const MeshDev& m, const ProbIn& 
         atomicAdd(&fc[(q.y & kBucketMask) * nf + gc.dsfd(q.x)], 1);
       }
     }
-    for (int c0 = s0; c0 < s1; c0 += CH) {
+    for (int c0 = s0; c0 < s1; c0 += CH, ++j) {
       const int n = min(CH, s1 - c0);
-      if (t < kBucketRows) rcnt[t] = 0;
-      __syncthreads();
-      for (int i = t; i < n; i += 256) atomicAdd(&rcnt[rec[c0 + i].y & kBucketMask], 1);
+      int* rcnt = rcnt2 + (j & 1) * kBucketRows;
+      // the chunk's records, read once: counted per row, then placed in row order
+      constexpr int PER = CH / 256;
+      uint2 q[PER];
+#pragma unroll
+      for (int k = 0; k < PER; ++k) {
+        const int i = t + 256 * k;
+        q[k] = i < n ? rec[c0 + i] : make_uint2(0u, 0u);
+      }
+#pragma unroll
+      for (int k = 0; k < PER; ++k)
+        if (t + 256 * k < n) atomicAdd(&rcnt[q[k].y & kBucketMask], 1);
       __syncthreads();
       if (t < 64) {
         const int v = t < kBucketRows ? rcnt[t] : 0;
@@ -731,13 +757,18 @@ __device__ __forceinline__ void bucket_gather16(const MeshDev& m, const ProbIn& 
         }
       }
       __syncthreads();
-      for (int i = t; i < n; i += 256) {
-        const uint2 q = rec[c0 + i];
-        const int r = q.y & kBucketMask;
-        const int d = atomicAdd(&rcur[r], 1);
-        soff[d] = q.x;
-        sidx[d] = (uint16_t)(LW ? r : i);
+#pragma unroll
+      for (int k = 0; k < PER; ++k) {
+        const int i = t + 256 * k;
+        if (i < n) {
+          const int r = q[k].y & kBucketMask;
+          const int d = atomicAdd(&rcur[r], 1);
+          soff[d] = q[k].x;
+          sidx[d] = (uint16_t)(LW ? r : i);
+        }
       }
+      // the other half of the row counts is free: clear it for the next chunk
+      if (t < kBucketRows) rcnt2[((j + 1) & 1) * kBucketRows + t] = 0;
       __syncthreads();
       if constexpr (LW) {
         chunk_learned_weights<DT>(m, in, dec, gc, lc, soff, sidx, fc, nf, n, sw);
@@ -751,6 +782,10 @@ __device__ __forceinline__ void bucket_gather16(const MeshDev& m, const ProbIn& 
                                    gl, act);
       __syncthreads();                                 // the chunk's LDS is reused next
     }
+    g = gn;
+    b = bn;
+    s0 = s0n;
+    s1 = s1n;
   }
 }
 
