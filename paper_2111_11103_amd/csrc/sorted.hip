@@ -260,54 +260,69 @@ __global__ __launch_bounds__(256) void k_bucket_sort(const int32_t* __restrict__
 // For inputs whose classes are far apart in memory (NCHW), frames are first
 // transposed into a staging array of contiguous class vectors (pixel-major,
 // c floats per pixel), which the fill and gather then treat like
-// channels-last input.  A block takes 256 consecutive pixels of one frame:
-// each class plane is read coalesced into LDS (padded rows, no bank
-// conflicts), then the block's 256 x c floats are written out as contiguous
-// float4 runs (c % 4 == 0, c <= 60, FP32; LDS sized by c).
+// channels-last input.  A block takes 128 consecutive pixels of one frame:
+// each class plane is read coalesced into LDS (padded rows; every load of a
+// thread issued before its LDS stores), then the block's 128 x c floats are
+// written out as contiguous float4 runs (c % 4 == 0, c <= 60, FP32; LDS
+// sized by c).
 constexpr int kStageMaxC = 60;
-constexpr int kStageRow = 257;     // padded LDS row of one class (256 pixels)
+constexpr int kStagePixels = 128;   // pixels per block (LDS c x 129 floats: several blocks per CU)
 
+template <int PB>
 __global__ __launch_bounds__(256) void k_planar_rows(ProbIn in, int f_first, int H, int W, int c,
                                                      float* __restrict__ staging) {
-  extern __shared__ float sv[];                             // [c][kStageRow]
+  constexpr int ROW = PB + 1;                               // padded LDS row of one class
+  constexpr int K4 = PB / 4;                                // float4 of a plane per block
+  constexpr int JS = 256 / K4;                              // planes read per pass of the block
+  extern __shared__ float sv[];                             // [c][ROW]
   const int fb = blockIdx.y;
   const int64_t HW = (int64_t)H * W;
   const int t = threadIdx.x;
-  const int64_t p0 = (int64_t)blockIdx.x * 256;
-  const int64_t p = p0 + t;
+  const int64_t p0 = (int64_t)blockIdx.x * PB;
   const float* base = reinterpret_cast<const float*>(in.p) + (int64_t)(f_first + fb) * in.sf;
   if (in.sx == 1 && in.sy == W && (HW & 3) == 0 && (in.sc & 3) == 0 && (in.sf & 3) == 0 &&
       (reinterpret_cast<uintptr_t>(in.p) & 15) == 0) {
-    // dense planes: float4 loads of 4 consecutive pixels, every load of the block independent
-    const int n4 = (int)min<int64_t>(64, (HW - p0) >> 2);
-    for (int i = t; i < c * 64; i += 256) {
-      const int j = i >> 6, k = i & 63;
-      if (k < n4) {
-        const float4 v = *reinterpret_cast<const float4*>(base + (int64_t)j * in.sc + p0 + 4 * k);
-        float* d = sv + j * kStageRow + 4 * k;
-        d[0] = v.x; d[1] = v.y; d[2] = v.z; d[3] = v.w;
+    // dense planes: float4 loads of 4 consecutive pixels (thread t: pixels
+    // 4 (t % K4) .. + 3 of planes t / K4 + JS i), all issued before the LDS
+    // stores
+    const int n4 = (int)min<int64_t>(K4, (HW - p0) >> 2);
+    const int k = t % K4, j0 = t / K4;
+    constexpr int NV = (kStageMaxC + JS - 1) / JS;
+    float4 v[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      const int j = j0 + JS * i;
+      if (j < c && k < n4) v[i] = *reinterpret_cast<const float4*>(base + (int64_t)j * in.sc + p0 + 4 * k);
+    }
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      const int j = j0 + JS * i;
+      if (j < c && k < n4) {
+        float* d = sv + j * ROW + 4 * k;
+        d[0] = v[i].x; d[1] = v[i].y; d[2] = v[i].z; d[3] = v[i].w;
       }
     }
-  } else if (p < HW) {
+  } else if (t < PB && p0 + t < HW) {
+    const int64_t p = p0 + t;
     const int y = (int)(p / W), x = (int)(p - (int64_t)y * W);
     const float* src = base + (int64_t)y * in.sy + (int64_t)x * in.sx;
     float* dst = sv + t;
 #pragma unroll 4
     for (int j = 0; j < c; ++j) {
-      dst[j * kStageRow] = *src;
+      dst[j * ROW] = *src;
       src += in.sc;
     }
   }
   __syncthreads();
   // output element i (in float4 units) of the block is (row, q) = (i / nq, i % nq): walk it incrementally
   const int nq = c >> 2;
-  const int n = (int)min<int64_t>(256, HW - p0);
+  const int n = (int)min<int64_t>(PB, HW - p0);
   const int drow = 256 / nq, dq = 256 - drow * nq;
   int row = t / nq, q = t - (t / nq) * nq;
   float4* out = reinterpret_cast<float4*>(staging + ((int64_t)fb * HW + p0) * c);
   for (int i = t; i < n * nq; i += 256) {
-    const float* col = sv + 4 * q * kStageRow + row;
-    out[i] = make_float4(col[0], col[kStageRow], col[2 * kStageRow], col[3 * kStageRow]);
+    const float* col = sv + 4 * q * ROW + row;
+    out[i] = make_float4(col[0], col[ROW], col[2 * ROW], col[3 * ROW]);
     row += drow;
     q += dq;
     if (q >= nq) { q -= nq; ++row; }
@@ -937,8 +952,9 @@ hipError_t launch_planar_rows(const ProbIn& in, int f_first, int nf, int H, int 
   if (nf <= 0) return hipSuccess;
   if (c > kStageMaxC || (c & 3) || in.dtype != 0) return hipErrorInvalidValue;
   const int64_t HW = (int64_t)H * W;
-  const size_t lds = (size_t)c * kStageRow * 4;
-  k_planar_rows<<<dim3((unsigned)((HW + 255) / 256), (unsigned)nf), 256, lds, s>>>(in, f_first, H, W, c, staging);
+  const size_t lds = (size_t)c * (kStagePixels + 1) * 4;
+  k_planar_rows<kStagePixels><<<dim3((unsigned)((HW + kStagePixels - 1) / kStagePixels), (unsigned)nf), 256, lds, s>>>(
+      in, f_first, H, W, c, staging);
   return hipGetLastError();
 }
 
