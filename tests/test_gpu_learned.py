@@ -276,6 +276,45 @@ def test_learned_fusion_on_grouped_gather(scene, layout):
         assert np.all(np.abs(A0 - A) <= 1e-5 * np.abs(A) + 1e-30)
 
 
+def test_learned_in_gather_at_forty_classes():
+    """The in-gather network at the launch shape the tuner takes at scale:
+    c = 40 (ten active lanes of a row group), batches of 64 and 26 frames
+    (per-frame counters for 64 frames), SPLIT s = 3 texels: fusion against
+    the oracle chain, same bound as above."""
+    say("[case] learned weight inside the gather, c = 40, 90 frames of 160x120, batch 64")
+    w = S.config1(device="cpu", structured=True, n_frames=90)
+    sc = w.scene
+    om = oracle_mesh(sc.vertices, sc.faces, 3, oracle.SPLIT)
+    _, l_o = om.raster_frames(w.cams, w.H, w.W)
+    c = 40
+    g = torch.Generator().manual_seed(5)
+    probs = torch.softmax(2.5 * torch.randn((len(w.cams), c, w.H, w.W), generator=g), 1)
+    A_p, W_p = oracle.fuse(om.n_texels, c, l_o, probs.numpy(), w.valid.numpy())
+    _, lab = oracle.finalize(A_p, W_p)
+    p = _params(11)
+    phi_o, _, pix_o = _oracle_features(w, om, lab, probs=probs.numpy())
+    wts = omlp.forward(p, phi_o).astype(np.float32)
+    wpix = np.zeros(l_o.shape, np.float32).reshape(-1)
+    wpix[pix_o] = wts
+    A_o, W_o = oracle.fuse(om.n_texels, c, l_o, probs.numpy(), w.valid.numpy(), weighting=oracle.W_GIVEN,
+                           wpix=wpix.reshape(l_o.shape))
+    gm = gpu_mesh((sc.vertices, sc.faces), 3, oracle.SPLIT, c)
+    gm.bind_mlp(sf.WeightMLP("cuda", torch.from_numpy(p)))
+    gm.set_tuning(32, 8, 96, 8, learned_in_gather=1)
+    x = probs.to(memory_format=torch.channels_last).cuda()
+    gm.fuse_frames(to_dev(w.cams, torch.float32), x, valid=w.valid.cuda(), weighting=sf.W_LEARNED,
+                   scatter_mode=sf.SCATTER_SORTED, batch=64)
+    A = gm.accum.cpu().numpy().astype(np.float64)
+    delta = 5e-3
+    err = np.abs(A - A_o)
+    assert np.all(err <= 1e-5 * np.abs(A_o) + delta * A_p + 1e-30)
+    rel_row = (err / np.maximum(np.abs(A_o), 1e-30)).max(1)
+    seen = W_o > 0
+    frac = float((rel_row[seen] <= 1e-5).mean())
+    say(f"  texels within 1e-5: {frac:.4f} of {int(seen.sum())}")
+    assert frac >= 0.99
+
+
 def test_training_and_heldout_gain():
     """Train on 50 seeded scenes (seeds 100-149, view-dependent noise) with the
     project's kernels, then fuse 10 held-out scenes (seeds 200-209) with the
