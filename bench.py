@@ -527,8 +527,14 @@ def main():
     tpx = measured_traffic({"batch": args.batch, "scatter_mode": args.scatter, **mesh.get_tuning()})
     traffic = None if tpx is None else tpx * px_per_launch     # HBM bytes per launch (counters, calibrated)
     b_min = npx * per_px + mesh.n_texels * c * 4
+    # B_alg: B_min plus the per-frame read-modify-write of every texel row a
+    # frame touches (D_f distinct valid rows of frame f), as the update loop
+    # of Section 3.3.2 states it frame by frame
+    d_f = [int(torch.unique(l_out[f][(l_out[f] >= 0) & (valid[f] != 0)]).numel()) for f in range(F)]
+    b_alg = b_min + sum(d_f) * 2 * c * 4
     log(f"[bench] gather {scat_ms:.3f} ms/launch; {rows_per_launch:.0f} rows per launch; "
-        f"B_min {b_min / 1e9:.2f} GB -> {b_min / (t_total / args.steps) / 1e9:.0f} GB/s whole step")
+        f"B_min {b_min / 1e9:.2f} GB -> {b_min / (t_total / args.steps) / 1e9:.0f} GB/s whole step; "
+        f"B_alg {b_alg / 1e9:.2f} GB (mean D_f {sum(d_f) / F:.0f})")
     result = {
         "metric": METRIC,
         "value": value,
@@ -557,6 +563,9 @@ def main():
                      "row_rmw_bytes_per_launch": rmw_bytes,
                      "achieved_incl_row_rmw": (px_per_launch * per_px + rmw_bytes) / (scat_ms * 1e-3) / 1e9},
         "step_hbm_frac": b_min / (t_total / args.steps) / 1e9 / HBM_PEAK_GBS,
+        "step_bytes": {"b_min": b_min, "b_alg": b_alg, "distinct_rows_per_frame": sum(d_f) / F,
+                       "b_min_frac": b_min / (t_total / args.steps) / 1e9 / HBM_PEAK_GBS,
+                       "b_alg_frac": b_alg / (t_total / args.steps) / 1e9 / HBM_PEAK_GBS},
         "stage_ms_per_step": stage_ms,
     }
 
