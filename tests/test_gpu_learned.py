@@ -277,11 +277,12 @@ def test_learned_fusion_on_grouped_gather(scene, layout):
 
 
 def test_learned_in_gather_at_forty_classes():
-    """The in-gather network at the launch shape the tuner takes at scale:
-    c = 40 (ten active lanes of a row group), batches of 64 and 26 frames
-    (per-frame counters for 64 frames), SPLIT s = 3 texels: fusion against
-    the oracle chain, same bound as above."""
-    say("[case] learned weight inside the gather, c = 40, 90 frames of 160x120, batch 64")
+    """Both sites of the network at c = 40 (ten active lanes of a row
+    group), in batches of 64 (per-frame counters for 64 frames) and of 32
+    (three batches: a buffer set reused), SPLIT s = 3 texels: inside the
+    gather, and in its own pass; fusion against the oracle chain, same
+    bound as above."""
+    say("[case] learned weight at c = 40, 90 frames of 160x120, batches 64 and 32, both sites")
     w = S.config1(device="cpu", structured=True, n_frames=90)
     sc = w.scene
     om = oracle_mesh(sc.vertices, sc.faces, 3, oracle.SPLIT)
@@ -300,19 +301,22 @@ def test_learned_in_gather_at_forty_classes():
                            wpix=wpix.reshape(l_o.shape))
     gm = gpu_mesh((sc.vertices, sc.faces), 3, oracle.SPLIT, c)
     gm.bind_mlp(sf.WeightMLP("cuda", torch.from_numpy(p)))
-    gm.set_tuning(32, 8, 96, 8, learned_in_gather=1)
     x = probs.to(memory_format=torch.channels_last).cuda()
-    gm.fuse_frames(to_dev(w.cams, torch.float32), x, valid=w.valid.cuda(), weighting=sf.W_LEARNED,
-                   scatter_mode=sf.SCATTER_SORTED, batch=64)
-    A = gm.accum.cpu().numpy().astype(np.float64)
-    delta = 5e-3
-    err = np.abs(A - A_o)
-    assert np.all(err <= 1e-5 * np.abs(A_o) + delta * A_p + 1e-30)
-    rel_row = (err / np.maximum(np.abs(A_o), 1e-30)).max(1)
-    seen = W_o > 0
-    frac = float((rel_row[seen] <= 1e-5).mean())
-    say(f"  texels within 1e-5: {frac:.4f} of {int(seen.sum())}")
-    assert frac >= 0.99
+    # inside the gather, then the separate pass
+    for site, batch in ((1, 64), (1, 32), (0, 64), (0, 32)):
+        gm.set_tuning(32, 8, 96, 8, learned_in_gather=site)
+        gm.reset()
+        gm.fuse_frames(to_dev(w.cams, torch.float32), x, valid=w.valid.cuda(), weighting=sf.W_LEARNED,
+                       scatter_mode=sf.SCATTER_SORTED, batch=batch)
+        A = gm.accum.cpu().numpy().astype(np.float64)
+        delta = 5e-3
+        err = np.abs(A - A_o)
+        assert np.all(err <= 1e-5 * np.abs(A_o) + delta * A_p + 1e-30)
+        rel_row = (err / np.maximum(np.abs(A_o), 1e-30)).max(1)
+        seen = W_o > 0
+        frac = float((rel_row[seen] <= 1e-5).mean())
+        say(f"  site {site}, batch {batch}: texels within 1e-5: {frac:.4f} of {int(seen.sum())}")
+        assert frac >= 0.99
 
 
 def test_training_and_heldout_gain():
