@@ -392,6 +392,8 @@ def main():
     ap.add_argument("--unroll", type=int, default=8, help="sorted-gather unroll (with an explicit --batch)")
     ap.add_argument("--small", type=int, default=48, help="single-lane triangle box area (with an explicit --batch)")
     ap.add_argument("--gwaves", type=int, default=8, help="gather grid waves per CU (with an explicit --batch)")
+    ap.add_argument("--learned-site", type=int, default=0, choices=[0, 1],
+                    help="learned weight: 0 its own pass, 1 inside the gather (with an explicit --batch)")
     ap.add_argument("--weighting", type=int, default=0,
                     help="0 w^(P), 1 w^(I), 2 learned (a seeded, untrained network), 3 mixed w^(P)/w^(I)")
     ap.add_argument("--layout", default="nhwc", choices=["nchw", "nhwc"])
@@ -468,7 +470,7 @@ def main():
                                probe_frames=64, log=log)
         args.batch, args.scatter = int(tuning["batch"]), int(tuning["scatter_mode"])
     else:
-        mesh.set_tuning(args.tile, args.unroll, args.small, args.gwaves)
+        mesh.set_tuning(args.tile, args.unroll, args.small, args.gwaves, args.learned_site)
 
     def make_step(p, weighting, scale=None, batch=args.batch, scatter=args.scatter):
         ws = mesh.frame_ws(H, W, batch, weighting, scatter, probs=p)
