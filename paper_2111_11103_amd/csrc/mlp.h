@@ -18,6 +18,8 @@
 namespace lf {
 
 typedef short s4 __attribute__((ext_vector_type(4)));
+typedef short s8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
 constexpr int NI = 8, NH = 64;
@@ -55,12 +57,20 @@ __host__ __device__ inline MlpW mlp_view(const void* packed) {
 // Both layers are computed transposed (hidden unit x observation), so that a
 // layer's output fragment is, lane for lane, the next layer's B operand: in
 // a 16x16x16 product lane (col, grp) holds D[4 grp + r][col], r = 0..3, and
-// takes B[4 grp + r][col]; q(h1) never leaves the registers.  The input
-// fragments take q(phi) of observation 16 t + col from that lane by
-// permutes.  No LDS is used, so waves do not wait for each other.
+// takes B[4 grp + r][col]; q(h1) never leaves the registers.  The hidden
+// layer contracts 32 units per 16x16x32 product: a lane's eight B values are
+// its fragments of two unit tiles, and its eight A values are the weights of
+// those same eight units (a contraction does not depend on the order in
+// which its index is laid over lanes and slots, as long as A and B agree).
+// The input fragments take q(phi) of observation 16 t + col from that lane
+// by permutes.  No LDS is used, so waves do not wait for each other.
 
 __device__ __forceinline__ s4 pack_s4(uint32_t lo, uint32_t hi) {
   return s4{(short)(lo & 0xffffu), (short)(lo >> 16), (short)(hi & 0xffffu), (short)(hi >> 16)};
+}
+// eight bfloat16 operands of a 16x16x32 product: tile a's four, then tile b's
+__device__ __forceinline__ bf8 join_bf8(s4 a, s4 b) {
+  return __builtin_bit_cast(bf8, (s8)__builtin_shufflevector(a, b, 0, 1, 2, 3, 4, 5, 6, 7));
 }
 
 // Evaluate the network for the observations of a wave (lane = observation).
@@ -101,25 +111,26 @@ __device__ inline float mlp_wave(const float (&phi)[NI], const MlpW& W, int nt =
       const s4 bphi = grp == 0 ? pack_s4(q[0], q[1]) : grp == 1 ? pack_s4(q[2], q[3]) : s4{0, 0, 0, 0};
 #pragma unroll
       for (int n = 0; n < 4; ++n) {
-        f4 d = {0.f, 0.f, 0.f, 0.f};
+        f4 d = {b1v[n][0], b1v[n][1], b1v[n][2], b1v[n][3]};   // bias enters as the accumulator
         d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(aw1[n], bphi, d, 0, 0, 0);
-        uint32_t lo = (uint32_t)bf16_bits(fmaxf(d[0] + b1v[n][0], 0.0f)) |
-                      ((uint32_t)bf16_bits(fmaxf(d[1] + b1v[n][1], 0.0f)) << 16);
-        uint32_t hi = (uint32_t)bf16_bits(fmaxf(d[2] + b1v[n][2], 0.0f)) |
-                      ((uint32_t)bf16_bits(fmaxf(d[3] + b1v[n][3], 0.0f)) << 16);
+        uint32_t lo = (uint32_t)bf16_bits(fmaxf(d[0], 0.0f)) | ((uint32_t)bf16_bits(fmaxf(d[1], 0.0f)) << 16);
+        uint32_t hi = (uint32_t)bf16_bits(fmaxf(d[2], 0.0f)) | ((uint32_t)bf16_bits(fmaxf(d[3], 0.0f)) << 16);
         h1[n][t] = pack_s4(lo, hi);
       }
     }
   }
-  // layer 2 + output layer: A = W2 tile (n2, ks), B = q(h1) tile (ks, t)
+  // layer 2 + output layer: A = W2 tiles (n2, 2 k2), (n2, 2 k2 + 1), B = q(h1)
+  // tiles (2 k2, t), (2 k2 + 1, t): units 32 k2 + 4 grp + r and
+  // 32 k2 + 16 + 4 grp + r of output unit 16 n2 + col
   float part[4] = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
   for (int n2 = 0; n2 < 4; ++n2) {
-    s4 aw2[4];
+    bf8 aw2[2];
 #pragma unroll
-    for (int ks = 0; ks < 4; ++ks) {
-      const uint16_t* w = W.W2 + (n2 * 16 + col) * NH + ks * 16 + 4 * grp;
-      aw2[ks] = s4{(short)w[0], (short)w[1], (short)w[2], (short)w[3]};
+    for (int k2 = 0; k2 < 2; ++k2) {
+      const uint16_t* w = W.W2 + (n2 * 16 + col) * NH + k2 * 32 + 4 * grp;
+      aw2[k2] = join_bf8(s4{(short)w[0], (short)w[1], (short)w[2], (short)w[3]},
+                         s4{(short)w[16], (short)w[17], (short)w[18], (short)w[19]});
     }
     float b2v[4], w3v[4];
 #pragma unroll
@@ -130,11 +141,12 @@ __device__ inline float mlp_wave(const float (&phi)[NI], const MlpW& W, int nt =
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       if (t < nt) {
-        f4 d = {0.f, 0.f, 0.f, 0.f};
+        f4 d = {b2v[0], b2v[1], b2v[2], b2v[3]};
 #pragma unroll
-        for (int ks = 0; ks < 4; ++ks) d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(aw2[ks], h1[ks][t], d, 0, 0, 0);
+        for (int k2 = 0; k2 < 2; ++k2)
+          d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aw2[k2], join_bf8(h1[2 * k2][t], h1[2 * k2 + 1][t]), d, 0, 0, 0);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) part[t] = fmaf(w3v[r], fmaxf(d[r] + b2v[r], 0.0f), part[t]);
+        for (int r = 0; r < 4; ++r) part[t] = fmaf(w3v[r], fmaxf(d[r], 0.0f), part[t]);
       }
     }
   }
@@ -161,19 +173,46 @@ __device__ inline float mlp_wave(const float (&phi)[NI], const MlpW& W, int nt =
 // second largest of {p2 <= p1, p}.
 template <bool BEST>
 __device__ __forceinline__ void prob_step(float p, int j, float& h, float& p1, float& p2, int& best) {
-  h -= p * __log2f(fmaxf(p, 1.17549435e-38f));
+  h = fmaf(-p, __log2f(fmaxf(p, 1.17549435e-38f)), h);
   if constexpr (BEST) best = p > p1 ? j : best;
   p2 = __builtin_amdgcn_fmed3f(p2, p1, p);
   p1 = fmaxf(p1, p);
 }
 
-// Entropy sum, top-2 and first argmax over a contiguous class vector of c
+// Entropy partial of four consecutive classes j .. j + 3, summed in class
+// order from 0, with the running top-2 and first argmax.
+template <bool BEST>
+__device__ __forceinline__ float chunk_entropy(float a, float b, float cc, float d, int j, float& p1, float& p2,
+                                               int& best) {
+  float s = 0.0f;
+  prob_step<BEST>(a, j, s, p1, p2, best);
+  prob_step<BEST>(b, j + 1, s, p1, p2, best);
+  prob_step<BEST>(cc, j + 2, s, p1, p2, best);
+  prob_step<BEST>(d, j + 3, s, p1, p2, best);
+  return s;
+}
+
+// The order in which a class vector's entropy is summed (c % 4 == 0,
+// c <= 64): partials of the four-class chunks, then a binary tree over 16
+// chunk slots (slots past the vector hold 0).  It is the order that a
+// butterfly over 16 lanes holding one chunk each produces, so a vector read
+// by one lane and a vector read by 16 lanes give the same bits.
+__device__ __forceinline__ float tree16(float (&s)[16]) {
+#pragma unroll
+  for (int w = 1; w < 16; w *= 2)
+#pragma unroll
+    for (int i = 0; i < 16; i += 2 * w) s[i] = s[i] + s[i + w];
+  return s[0];
+}
+
+// Entropy sum h, top-2 and first argmax over a contiguous class vector of c
 // (c % 4 == 0, c <= 64) values: FP32, or E4M3 codes times `scale`, four per
 // 32-bit word.  `src` may point to global memory or LDS; every load of the
 // vector is issued first.
 template <int DT, bool BEST, typename P>
 __device__ __forceinline__ void vector_features(const P* src, float scale, int c, float& h, float& p1, float& p2,
                                                 int& best) {
+  float s[16];
   if constexpr (DT == 0) {
     const float4* s4p = reinterpret_cast<const float4*>(src);
     float4 v[16];
@@ -182,12 +221,7 @@ __device__ __forceinline__ void vector_features(const P* src, float scale, int c
       if (4 * q < c) v[q] = s4p[q];
 #pragma unroll
     for (int q = 0; q < 16; ++q)
-      if (4 * q < c) {
-        prob_step<BEST>(v[q].x, 4 * q, h, p1, p2, best);
-        prob_step<BEST>(v[q].y, 4 * q + 1, h, p1, p2, best);
-        prob_step<BEST>(v[q].z, 4 * q + 2, h, p1, p2, best);
-        prob_step<BEST>(v[q].w, 4 * q + 3, h, p1, p2, best);
-      }
+      s[q] = 4 * q < c ? chunk_entropy<BEST>(v[q].x, v[q].y, v[q].z, v[q].w, 4 * q, p1, p2, best) : 0.0f;
   } else {
     const uint32_t* s1p = reinterpret_cast<const uint32_t*>(src);
     uint32_t v[16];
@@ -196,13 +230,36 @@ __device__ __forceinline__ void vector_features(const P* src, float scale, int c
       if (4 * q < c) v[q] = s1p[q];
 #pragma unroll
     for (int q = 0; q < 16; ++q)
-      if (4 * q < c) {
-        prob_step<BEST>(fp8_e4m3_byte<0>(v[q]) * scale, 4 * q, h, p1, p2, best);
-        prob_step<BEST>(fp8_e4m3_byte<1>(v[q]) * scale, 4 * q + 1, h, p1, p2, best);
-        prob_step<BEST>(fp8_e4m3_byte<2>(v[q]) * scale, 4 * q + 2, h, p1, p2, best);
-        prob_step<BEST>(fp8_e4m3_byte<3>(v[q]) * scale, 4 * q + 3, h, p1, p2, best);
-      }
+      s[q] = 4 * q < c ? chunk_entropy<BEST>(fp8_e4m3_byte<0>(v[q]) * scale, fp8_e4m3_byte<1>(v[q]) * scale,
+                                             fp8_e4m3_byte<2>(v[q]) * scale, fp8_e4m3_byte<3>(v[q]) * scale, 4 * q,
+                                             p1, p2, best)
+                       : 0.0f;
   }
+  h = tree16(s);
+}
+
+// One step of the 16-lane butterfly of the chunked order above: this lane's
+// entropy partial and top-2 merged with those of the lane DPP control CTRL
+// names (xor 1, xor 2 within a quad, then the half-row and row mirrors).
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xf, 0xf, false));
+}
+template <int CTRL>
+__device__ __forceinline__ void butterfly_step(float& h, float& p1, float& p2) {
+  const float oh = dpp_f<CTRL>(h), o1 = dpp_f<CTRL>(p1), o2 = dpp_f<CTRL>(p2);
+  h = h + oh;
+  const float lo = fminf(p1, o1);
+  p1 = fmaxf(p1, o1);
+  p2 = fmaxf(lo, fmaxf(p2, o2));
+}
+// Every lane of a wave must take part; afterwards each lane holds its 16-lane
+// group's entropy sum (in tree16's order) and top-2.
+__device__ __forceinline__ void butterfly16(float& h, float& p1, float& p2) {
+  butterfly_step<0xb1>(h, p1, p2);    // quad_perm [1, 0, 3, 2]
+  butterfly_step<0x4e>(h, p1, p2);    // quad_perm [2, 3, 0, 1]
+  butterfly_step<0x141>(h, p1, p2);   // row_half_mirror
+  butterfly_step<0x140>(h, p1, p2);   // row_mirror
 }
 
 // Normalised entropy from the entropy sum h (bits); top-2 is 0 for c < 2.
@@ -224,6 +281,23 @@ __device__ __forceinline__ void prob_features(const ProbIn& in, int64_t base, fl
                    ((reinterpret_cast<uintptr_t>(in.p) + base * esz) & (4 * esz - 1)) == 0;
   if (vec) {
     vector_features<DT, BEST>(reinterpret_cast<const uint8_t*>(in.p) + base * esz, scale, c, h, p1, p2, best);
+  } else if ((c & 3) == 0 && c <= 64) {
+    // strided classes, summed in the chunked order of the vector path
+    float s[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      float v[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+      if (4 * q < c) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int64_t o = base + (int64_t)(4 * q + k) * in.sc;
+          if constexpr (DT == 0) v[k] = reinterpret_cast<const float*>(in.p)[o];
+          else v[k] = fp8_e4m3(reinterpret_cast<const uint8_t*>(in.p)[o]) * scale;
+        }
+      }
+      s[q] = 4 * q < c ? chunk_entropy<BEST>(v[0], v[1], v[2], v[3], 4 * q, p1, p2, best) : 0.0f;
+    }
+    h = tree16(s);
   } else {
     for (int j = 0; j < c; ++j) {
       float p;

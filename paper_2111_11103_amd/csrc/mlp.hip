@@ -6,8 +6,9 @@
 //   w  = sigmoid(w3 . h2 + b3)
 // q = round to bfloat16; W1, W2, w3 are bfloat16, biases and accumulation
 // binary32.  Inference runs both matrix products on the matrix cores
-// (v_mfma_f32_16x16x16_bf16): a wave evaluates 64 observations as four
-// 16-column tiles of the transposed layers, q(h1) kept in registers.
+// (v_mfma_f32_16x16x16_bf16 for the 8-input layer, v_mfma_f32_16x16x32_bf16
+// for the hidden layer): a wave evaluates 64 observations as four 16-column
+// tiles of the transposed layers, q(h1) kept in registers.
 // Training gradients are accumulated on the vector ALUs in binary32 (one
 // wave per chunk of observations, one lane per hidden unit) and applied
 // with Adam on binary32 master parameters.
@@ -58,17 +59,19 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const void* __restrict__ pa
 
 // Inference as a pass of its own (layouts the grouped gather does not take):
 // weight of every valid covered pixel of the batch (0 elsewhere), from the
-// per-frame count array.
+// per-frame count array.  A pixel's class vector, geometry and validity are
+// read before its coverage is known (they exist for every pixel of the
+// frame), so only the frame count waits for the texel row.
 template <int DT>
 __global__ __launch_bounds__(256) void k_mlp_weights(const void* __restrict__ packed, ProbIn in, int f_first, int H,
-                                                     int W, const float* __restrict__ cams,
+                                                     int W, Udiv dw, const float* __restrict__ cams,
                                                      const int32_t* __restrict__ lbuf, const float4* __restrict__ geo,
                                                      const int32_t* __restrict__ cnt, int64_t cnt_stride, int c,
                                                      float* __restrict__ wpix) {
   const MlpW Wt = mlp_view(packed);
   const int fb = blockIdx.y;
-  const int64_t HW = (int64_t)H * W;
-  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const uint32_t HW = (uint32_t)H * (uint32_t)W;
+  const uint32_t p = blockIdx.x * 256u + threadIdx.x;
   const int64_t pi = (int64_t)fb * HW + p;
   const int64_t gi = (int64_t)(f_first + fb) * HW + p;
   float x[NI];
@@ -76,19 +79,91 @@ __global__ __launch_bounds__(256) void k_mlp_weights(const void* __restrict__ pa
   for (int k = 0; k < NI; ++k) x[k] = 0.0f;
   bool use = false;
   if (p < HW) {
+    const int y = (int)dw(p), xx = (int)(p - (uint32_t)y * (uint32_t)W);
     const int l = lbuf[pi];
-    use = l >= 0 && (!in.valid || in.valid[gi]);
-    if (use) {
-      const int y = (int)(p / W), xx = (int)(p - (int64_t)y * W);
-      const int64_t base = (int64_t)(f_first + fb) * in.sf + (int64_t)y * in.sy + (int64_t)xx * in.sx;
-      const float sc = DT == 3 ? in.scale[gi] : 1.0f;
-      int best;
-      observation_features<DT, false>(in, base, sc, c, geo[pi], cnt[(int64_t)fb * cnt_stride + l], xx, y,
-                               cams + 16 * (int64_t)(f_first + fb), x, best);
-    }
+    const bool ok = !in.valid || in.valid[gi];
+    const float4 g = geo[pi];
+    const int64_t base = (int64_t)(f_first + fb) * in.sf + (int64_t)y * in.sy + (int64_t)xx * in.sx;
+    const float sc = DT == 3 ? in.scale[gi] : 1.0f;
+    float ent, p1, p2;
+    int best;
+    prob_features<DT, false>(in, base, sc, c, ent, p1, p2, best);
+    use = l >= 0 && ok;
+    if (use)
+      observation_phi(ent, p1, p2, g, cnt[(int64_t)fb * cnt_stride + l], xx, y, cams + 16 * (int64_t)(f_first + fb),
+                      x);
   }
   const float w = mlp_wave(x, Wt);
   if (p < HW) wpix[pi] = use ? w : 0.0f;
+}
+
+// The same pass for pixel-dense class vectors (channels-last, rows and
+// frames contiguous, c % 4 == 0, c <= 64): one wave per 64 consecutive
+// pixels copies their class vectors -- one contiguous byte range -- into LDS
+// with 16-byte loads in address order, then each lane reads its own vector
+// from LDS.  Read lane by lane from global memory instead, every load
+// instruction of the wave would touch a cache line per lane and each line
+// would be requested again by the next load instructions.
+__device__ const uint8_t kValidAll = 1;   // validity of every pixel when no mask is given
+
+template <int DT>
+__global__ __launch_bounds__(64) void k_mlp_weights_staged(const void* __restrict__ packed, ProbIn in, int f_first,
+                                                           int H, int W, Udiv dw, const float* __restrict__ cams,
+                                                           const int32_t* __restrict__ lbuf,
+                                                           const float4* __restrict__ geo,
+                                                           const int32_t* __restrict__ cnt, int64_t cnt_stride, int c,
+                                                           float* __restrict__ wpix) {
+  extern __shared__ float4 stage[];   // [64 * c * esz / 16]
+  constexpr int esz = DT == 0 ? 4 : 1;
+  const MlpW Wt = mlp_view(packed);
+  const int fb = blockIdx.y;
+  const int lane = threadIdx.x;
+  const uint32_t HW = (uint32_t)H * (uint32_t)W;
+  const uint32_t p0 = blockIdx.x * 64u, p = p0 + lane;
+  const int n_px = (int)min(64u, HW - p0);
+  const int64_t pi = (int64_t)fb * HW + p;
+  const int64_t gi = (int64_t)(f_first + fb) * HW + p;
+  // the wave's class vectors: bytes [0, n_px c esz) from the first pixel on
+  const uint8_t* src8 = reinterpret_cast<const uint8_t*>(in.p) + ((int64_t)(f_first + fb) * in.sf + (int64_t)p0 * c) * esz;
+  const int nbytes = n_px * c * esz, n16 = nbytes >> 4;
+  const float4* src = reinterpret_cast<const float4*>(src8);
+  // global -> LDS without registers: load i puts lane's 16 bytes at
+  // stage[64 i + lane]
+#pragma unroll
+  for (int i = 0; i < 16; ++i)
+    if (lane + 64 * i < n16)
+      __builtin_amdgcn_global_load_lds(src + lane + 64 * i, (__attribute__((address_space(3))) void*)(stage + 64 * i),
+                                       16, 0, 0);
+  // a ragged last wave may end in 4-byte words (c esz is a multiple of 4)
+  const int tail = (nbytes - 16 * n16) >> 2;
+  if (lane < tail)
+    reinterpret_cast<uint32_t*>(stage)[4 * n16 + lane] = reinterpret_cast<const uint32_t*>(src8)[4 * n16 + lane];
+  // loads whose addresses do not depend on the texel row, issued behind them
+  // without branches (lanes past the last pixel read the last pixel's)
+  const int64_t back = lane < n_px ? 0 : lane - (n_px - 1);
+  const int l = lbuf[pi - back];
+  const uint8_t ok = *(in.valid ? in.valid + (gi - back) : &kValidAll);
+  const float4 g = geo[pi - back];
+  const float sc = DT == 3 ? in.scale[gi - back] : 1.0f;
+  __builtin_amdgcn_s_waitcnt(0x0f70);   // vmcnt(0): the LDS loads have landed
+  __syncthreads();
+  // features of every lane without branches (the frame count load then
+  // overlaps the class loop); lanes that are not a valid covered pixel
+  // enter the network with phi = 0 and write weight 0
+  const bool use = lane < n_px && l >= 0 && ok != 0;
+  const int n_same = cnt[(int64_t)fb * cnt_stride + max(l, 0)];
+  float h = 0.0f, p1 = -__builtin_inff(), p2 = -__builtin_inff(), ent;
+  int best = 0;
+  vector_features<DT, false>(reinterpret_cast<const uint8_t*>(stage) + min(lane, n_px - 1) * c * esz, sc, c, h, p1,
+                             p2, best);
+  finish_prob_features(h, c, ent, p2);
+  const int y = (int)dw(p), xx = (int)(p - (uint32_t)y * (uint32_t)W);
+  float x[NI];
+  observation_phi(ent, p1, p2, g, n_same, xx, y, cams + 16 * (int64_t)(f_first + fb), x);
+#pragma unroll
+  for (int k = 0; k < NI; ++k) x[k] = use ? x[k] : 0.0f;
+  const float w = mlp_wave(x, Wt);
+  if (lane < n_px) wpix[pi] = use ? w : 0.0f;
 }
 
 // Training data: features and targets (own argmax == the texel's fused label)
@@ -275,9 +350,24 @@ hipError_t launch_mlp_weights(const void* packed, const ProbIn& in, int f_first,
                               int64_t cnt_stride, int c, float* wpix, hipStream_t s) {
   if (nf <= 0) return hipSuccess;
   const int64_t HW = (int64_t)H * W;
+  if (HW >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
+  const Udiv dw = Udiv::make((uint32_t)W);
+  const int64_t esz = in.dtype == 0 ? 4 : 1;
+  const bool dense = in.sc == 1 && in.sx == c && in.sy == (int64_t)W * c && (c & 3) == 0 && c <= 64 &&
+                     (reinterpret_cast<uintptr_t>(in.p) & 15) == 0 && ((in.sf * esz) & 15) == 0;
+  if (dense) {
+    dim3 g((unsigned)((HW + 63) / 64), (unsigned)nf);
+    const size_t lds = (size_t)64 * c * esz;
+    if (in.dtype == 0)
+      k_mlp_weights_staged<0><<<g, 64, lds, s>>>(packed, in, f_first, H, W, dw, cams, l, g4, cnt, cnt_stride, c, wpix);
+    else
+      k_mlp_weights_staged<3><<<g, 64, lds, s>>>(packed, in, f_first, H, W, dw, cams, l, g4, cnt, cnt_stride, c, wpix);
+    return hipGetLastError();
+  }
   dim3 g((unsigned)((HW + 255) / 256), (unsigned)nf);
-  if (in.dtype == 0) k_mlp_weights<0><<<g, 256, 0, s>>>(packed, in, f_first, H, W, cams, l, g4, cnt, cnt_stride, c, wpix);
-  else k_mlp_weights<3><<<g, 256, 0, s>>>(packed, in, f_first, H, W, cams, l, g4, cnt, cnt_stride, c, wpix);
+  if (in.dtype == 0)
+    k_mlp_weights<0><<<g, 256, 0, s>>>(packed, in, f_first, H, W, dw, cams, l, g4, cnt, cnt_stride, c, wpix);
+  else k_mlp_weights<3><<<g, 256, 0, s>>>(packed, in, f_first, H, W, dw, cams, l, g4, cnt, cnt_stride, c, wpix);
   return hipGetLastError();
 }
 

@@ -30,6 +30,8 @@
 #include <algorithm>
 
 #include "accum.h"
+#include <type_traits>
+
 #include "internal.h"
 #include "mlp.h"
 #include "spec.h"
@@ -650,10 +652,13 @@ __host__ __device__ inline size_t bucket_gather_lds(int nf, bool frame_counts, b
 }
 
 // The learned weight of every record of a chunk (row order, d = 0 .. n):
-// wave w takes records 64 (w + 4 i) .. + 63, one per lane: features as the
-// separate inference pass computes them (probabilities from the record's
-// class vector, geometry from the resolve's per-pixel copy, n from the
-// bucket's frame counters), the network on the matrix cores for the
+// wave w takes records 64 (w + 4 i) .. + 63.  Each record's class vector is
+// read by 16 lanes, four classes a lane (one 16-byte or 4-byte load of a
+// contiguous vector, four records per load instruction), and reduced over
+// the group by a butterfly in the separate pass's summation order; the lane
+// whose index is the record's place in the wave keeps its entropy sum and
+// top-2.  Then lane = record: geometry from the resolve's per-pixel copy, n
+// from the bucket's frame counters, the network on the matrix cores for the
 // 16-record tiles the records fill, weights into LDS.  Pixels are dense in
 // the input (offset = spix * batch-relative pixel index).
 template <int DT>
@@ -662,13 +667,58 @@ __device__ __forceinline__ void chunk_learned_weights(const MeshDev& m, const Pr
                                                       const uint32_t* soff, const uint16_t* srow, const int* fc,
                                                       int nf, int n, float* sw) {
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int gl = lane & 15, gq = lane >> 4;
   const int c = m.c;
+  const bool act = gl < (c >> 2);
+  const uint8_t* pb = reinterpret_cast<const uint8_t*>(in.p);
   for (int base = wv * 64; base < n; base += 256) {
     // the network's parameters are read where they are used (from cache),
     // not held in registers across records
     const void* wp = lc.mlp;
     asm volatile("" : "+s"(wp));
     const MlpW Wt = mlp_view(wp);
+    // round r: group gq reduces record base + 16 gq + r.  Eight rounds' loads
+    // are issued before their sums; loads take no branch (lanes past the
+    // chunk or the vector read an in-bounds chunk and drop it).
+    float hk = 0.0f, p1k = -__builtin_inff(), p2k = -__builtin_inff();
+    const int q = act ? gl : 0;
+#pragma unroll 1
+    for (int r0 = 0; r0 < 16; r0 += 8) {
+      typename std::conditional<DT == 0, float4, uint32_t>::type v[8];
+      float sc[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const uint32_t e = soff[min(base + 16 * gq + r0 + i, n - 1)];
+        if constexpr (DT == 0) {
+          v[i] = reinterpret_cast<const float4*>(pb + dec(in, e) * 4)[q];
+          sc[i] = 1.0f;
+        } else {
+          v[i] = reinterpret_cast<const uint32_t*>(pb + dec(in, e))[q];
+          sc[i] = in.scale[gc.sbase + gc.dspix(e)];
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int r = r0 + i;
+        const bool use = act && base + 16 * gq + r < n;
+        float h, p1 = -__builtin_inff(), p2 = -__builtin_inff();
+        int best = 0;
+        if constexpr (DT == 0) {
+          h = chunk_entropy<false>(v[i].x, v[i].y, v[i].z, v[i].w, 4 * q, p1, p2, best);
+        } else {
+          h = chunk_entropy<false>(fp8_e4m3_byte<0>(v[i]) * sc[i], fp8_e4m3_byte<1>(v[i]) * sc[i],
+                                   fp8_e4m3_byte<2>(v[i]) * sc[i], fp8_e4m3_byte<3>(v[i]) * sc[i], 4 * q, p1, p2,
+                                   best);
+        }
+        h = use ? h : 0.0f;
+        p1 = use ? p1 : -__builtin_inff();
+        p2 = use ? p2 : -__builtin_inff();
+        butterfly16(h, p1, p2);
+        hk = gl == r ? h : hk;
+        p1k = gl == r ? p1 : p1k;
+        p2k = gl == r ? p2 : p2k;
+      }
+    }
     const int d = base + lane;
     const bool ok = d < n;
     float phi[NI];
@@ -680,13 +730,9 @@ __device__ __forceinline__ void chunk_learned_weights(const MeshDev& m, const Pr
       const uint32_t fb = lc.dhw(p);
       const uint32_t rem = p - fb * lc.hw;
       const uint32_t y = lc.dw(rem), x = rem - y * lc.w;
-      const float sc = DT == 3 ? in.scale[gc.sbase + p] : 1.0f;
-      float h = 0.0f, p1 = -__builtin_inff(), p2 = -__builtin_inff(), ent;
-      int best = 0;
-      vector_features<DT, false>(reinterpret_cast<const uint8_t*>(in.p) + dec(in, e) * (DT == 0 ? 4 : 1), sc, c, h,
-                                 p1, p2, best);
-      finish_prob_features(h, c, ent, p2);
-      observation_phi(ent, p1, p2, lc.geo[p], fc[srow[d] * nf + gc.dsfd(e)], (int)x, (int)y,
+      float ent;
+      finish_prob_features(hk, c, ent, p2k);
+      observation_phi(ent, p1k, p2k, lc.geo[p], fc[srow[d] * nf + gc.dsfd(e)], (int)x, (int)y,
                       lc.cams + 16 * (int64_t)fb, phi);
     }
     const float w = mlp_wave(phi, Wt, min(4, (n - base + 15) >> 4));

@@ -319,6 +319,60 @@ def test_learned_in_gather_at_forty_classes():
         assert frac >= 0.99
 
 
+@pytest.mark.parametrize("dtype,c", [("f32", 40), ("fp8", 20)])
+def test_separate_pass_on_ragged_frames(dtype, c):
+    """The network in its own pass for pixel-dense channels-last input, whose
+    class vectors are copied to LDS a wave (64 pixels) at a time: 157x113
+    frames end in a partial wave of 13 pixels (at c = 20 in E4M3 that wave's
+    bytes end in a 4-byte word), 10 % of the pixels invalid.  Fusion against
+    the oracle chain, same bound as above."""
+    say(f"[case] learned weight in its own pass, {dtype} c = {c}, 6 frames of 157x113 (ragged last wave)")
+    w = S.config1(device="cpu", structured=True, n_frames=6, H=113, W=157)
+    g = torch.Generator().manual_seed(31)
+    valid = w.valid.clone()
+    valid[torch.rand(valid.shape, generator=g) < 0.1] = 0
+    w.valid = valid
+    sc = w.scene
+    om = oracle_mesh(sc.vertices, sc.faces, 1, oracle.SPLIT)
+    _, l_o = om.raster_frames(w.cams, w.H, w.W)
+    probs = torch.softmax(2.0 * torch.randn((len(w.cams), c, w.H, w.W), generator=g), 1)
+    scale = None
+    if dtype == "fp8":
+        q, scale = S.quantize_fp8(probs)
+        deq = np.vectorize(oracle.e4m3_decode)(np.arange(256)).astype(np.float32)[q.numpy()]
+        probs_o = (deq * scale.numpy()[:, None]).astype(np.float32)
+        x = q.permute(0, 2, 3, 1).contiguous().cuda().permute(0, 3, 1, 2)
+        scale = scale.cuda()
+    else:
+        probs_o = probs.numpy()
+        x = probs.to(memory_format=torch.channels_last).cuda()
+    A_p, W_p = oracle.fuse(om.n_texels, c, l_o, probs_o, w.valid.numpy())
+    _, lab = oracle.finalize(A_p, W_p)
+    p = _params(13)
+    phi_o, _, pix_o = _oracle_features(w, om, lab, probs=probs_o)
+    wts = omlp.forward(p, phi_o).astype(np.float32)
+    wpix = np.zeros(l_o.shape, np.float32).reshape(-1)
+    wpix[pix_o] = wts
+    A_o, W_o = oracle.fuse(om.n_texels, c, l_o, probs_o, w.valid.numpy(), weighting=oracle.W_GIVEN,
+                           wpix=wpix.reshape(l_o.shape))
+    gm = gpu_mesh((sc.vertices, sc.faces), 1, oracle.SPLIT, c)
+    gm.bind_mlp(sf.WeightMLP("cuda", torch.from_numpy(p)))
+    gm.set_tuning(learned_in_gather=0)
+    for batch in (2, 6):
+        gm.reset()
+        gm.fuse_frames(to_dev(w.cams, torch.float32), x, scale=scale, valid=w.valid.cuda(), weighting=sf.W_LEARNED,
+                       scatter_mode=sf.SCATTER_SORTED, batch=batch)
+        A = gm.accum.cpu().numpy().astype(np.float64)
+        delta = 5e-3
+        err = np.abs(A - A_o)
+        assert np.all(err <= 1e-5 * np.abs(A_o) + delta * A_p + 1e-30)
+        rel_row = (err / np.maximum(np.abs(A_o), 1e-30)).max(1)
+        seen = W_o > 0
+        frac = float((rel_row[seen] <= 1e-5).mean())
+        say(f"  batch {batch}: texels within 1e-5: {frac:.4f} of {int(seen.sum())}")
+        assert frac >= 0.99
+
+
 def test_training_and_heldout_gain():
     """Train on 50 seeded scenes (seeds 100-149, view-dependent noise) with the
     project's kernels, then fuse 10 held-out scenes (seeds 200-209) with the
