@@ -193,16 +193,16 @@ __device__ __forceinline__ float chunk_entropy(float a, float b, float cc, float
 }
 
 // The order in which a class vector's entropy is summed (c % 4 == 0,
-// c <= 64): partials of the four-class chunks, then a binary tree over 16
-// chunk slots (slots past the vector hold 0).  It is the order that a
-// butterfly over 16 lanes holding one chunk each produces, so a vector read
-// by one lane and a vector read by 16 lanes give the same bits.
-__device__ __forceinline__ float tree16(float (&s)[16]) {
+// c <= 64): partials s[q] of the four-class chunks (slots past the vector
+// hold 0); lane sums t_j = ((s[j] + s[j + 4]) + s[j + 8]) + s[j + 12],
+// j = 0..3; then (t_0 + t_1) + (t_2 + t_3).  It is the order of four lanes
+// each summing chunks j, j + 4, ... of a vector and reducing by a butterfly,
+// so a vector read by one lane and a vector read by four give the same bits.
+__device__ __forceinline__ float chunk_order_sum(const float (&s)[16]) {
+  float t[4];
 #pragma unroll
-  for (int w = 1; w < 16; w *= 2)
-#pragma unroll
-    for (int i = 0; i < 16; i += 2 * w) s[i] = s[i] + s[i + w];
-  return s[0];
+  for (int j = 0; j < 4; ++j) t[j] = ((s[j] + s[j + 4]) + s[j + 8]) + s[j + 12];
+  return (t[0] + t[1]) + (t[2] + t[3]);
 }
 
 // Entropy sum h, top-2 and first argmax over a contiguous class vector of c
@@ -235,12 +235,13 @@ __device__ __forceinline__ void vector_features(const P* src, float scale, int c
                                              p1, p2, best)
                        : 0.0f;
   }
-  h = tree16(s);
+  h = chunk_order_sum(s);
 }
 
-// One step of the 16-lane butterfly of the chunked order above: this lane's
-// entropy partial and top-2 merged with those of the lane DPP control CTRL
-// names (xor 1, xor 2 within a quad, then the half-row and row mirrors).
+// One step of the four-lane butterfly of the chunked order above: this
+// lane's entropy partial and top-2 merged with those of the lane DPP control
+// CTRL names.  With p1 >= p2 and o1 >= o2 the second largest of the four is
+// max(min(p1, o1), max(p2, o2)) = median(p1, o1, max(p2, o2)).
 template <int CTRL>
 __device__ __forceinline__ float dpp_f(float x) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xf, 0xf, false));
@@ -249,17 +250,14 @@ template <int CTRL>
 __device__ __forceinline__ void butterfly_step(float& h, float& p1, float& p2) {
   const float oh = dpp_f<CTRL>(h), o1 = dpp_f<CTRL>(p1), o2 = dpp_f<CTRL>(p2);
   h = h + oh;
-  const float lo = fminf(p1, o1);
+  p2 = __builtin_amdgcn_fmed3f(p1, o1, fmaxf(p2, o2));
   p1 = fmaxf(p1, o1);
-  p2 = fmaxf(lo, fmaxf(p2, o2));
 }
-// Every lane of a wave must take part; afterwards each lane holds its 16-lane
-// group's entropy sum (in tree16's order) and top-2.
-__device__ __forceinline__ void butterfly16(float& h, float& p1, float& p2) {
-  butterfly_step<0xb1>(h, p1, p2);    // quad_perm [1, 0, 3, 2]
-  butterfly_step<0x4e>(h, p1, p2);    // quad_perm [2, 3, 0, 1]
-  butterfly_step<0x141>(h, p1, p2);   // row_half_mirror
-  butterfly_step<0x140>(h, p1, p2);   // row_mirror
+// Every lane of a wave must take part; afterwards each lane holds its quad's
+// entropy sum (lane sums t_j added as (t_0 + t_1) + (t_2 + t_3)) and top-2.
+__device__ __forceinline__ void butterfly4(float& h, float& p1, float& p2) {
+  butterfly_step<0xb1>(h, p1, p2);   // quad_perm [1, 0, 3, 2]
+  butterfly_step<0x4e>(h, p1, p2);   // quad_perm [2, 3, 0, 1]
 }
 
 // Normalised entropy from the entropy sum h (bits); top-2 is 0 for c < 2.
@@ -297,7 +295,7 @@ __device__ __forceinline__ void prob_features(const ProbIn& in, int64_t base, fl
       }
       s[q] = 4 * q < c ? chunk_entropy<BEST>(v[0], v[1], v[2], v[3], 4 * q, p1, p2, best) : 0.0f;
     }
-    h = tree16(s);
+    h = chunk_order_sum(s);
   } else {
     for (int j = 0; j < c; ++j) {
       float p;

@@ -653,9 +653,9 @@ __host__ __device__ inline size_t bucket_gather_lds(int nf, bool frame_counts, b
 
 // The learned weight of every record of a chunk (row order, d = 0 .. n):
 // wave w takes records 64 (w + 4 i) .. + 63.  Each record's class vector is
-// read by 16 lanes, four classes a lane (one 16-byte or 4-byte load of a
-// contiguous vector, four records per load instruction), and reduced over
-// the group by a butterfly in the separate pass's summation order; the lane
+// read by four lanes, lane j taking the four-class chunks j, j + 4, ...
+// (16 records a load instruction, 64 contiguous bytes each), summed in the
+// separate pass's order and reduced by a butterfly over the quad; the lane
 // whose index is the record's place in the wave keeps its entropy sum and
 // top-2.  Then lane = record: geometry from the resolve's per-pixel copy, n
 // from the bucket's frame counters, the network on the matrix cores for the
@@ -667,9 +667,8 @@ __device__ __forceinline__ void chunk_learned_weights(const MeshDev& m, const Pr
                                                       const uint32_t* soff, const uint16_t* srow, const int* fc,
                                                       int nf, int n, float* sw) {
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int gl = lane & 15, gq = lane >> 4;
-  const int c = m.c;
-  const bool act = gl < (c >> 2);
+  const int j = lane & 3, g4 = lane >> 2;
+  const int c = m.c, nq = c >> 2, kmax = (nq + 3) >> 2;   // chunks; chunks per lane
   const uint8_t* pb = reinterpret_cast<const uint8_t*>(in.p);
   for (int base = wv * 64; base < n; base += 256) {
     // the network's parameters are read where they are used (from cache),
@@ -677,46 +676,50 @@ __device__ __forceinline__ void chunk_learned_weights(const MeshDev& m, const Pr
     const void* wp = lc.mlp;
     asm volatile("" : "+s"(wp));
     const MlpW Wt = mlp_view(wp);
-    // round r: group gq reduces record base + 16 gq + r.  Eight rounds' loads
-    // are issued before their sums; loads take no branch (lanes past the
-    // chunk or the vector read an in-bounds chunk and drop it).
+    // round r: quad g4 reduces record base + 4 g4 + r.  Two rounds' loads
+    // are issued before their sums; loads take no branch (past the chunk or
+    // the vector a lane reads an in-bounds chunk and drops it).
     float hk = 0.0f, p1k = -__builtin_inff(), p2k = -__builtin_inff();
-    const int q = act ? gl : 0;
 #pragma unroll 1
-    for (int r0 = 0; r0 < 16; r0 += 8) {
-      typename std::conditional<DT == 0, float4, uint32_t>::type v[8];
-      float sc[8];
+    for (int r0 = 0; r0 < 4; r0 += 2) {
+      typename std::conditional<DT == 0, float4, uint32_t>::type v[2][4];
+      float sc[2];
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const uint32_t e = soff[min(base + 16 * gq + r0 + i, n - 1)];
-        if constexpr (DT == 0) {
-          v[i] = reinterpret_cast<const float4*>(pb + dec(in, e) * 4)[q];
-          sc[i] = 1.0f;
-        } else {
-          v[i] = reinterpret_cast<const uint32_t*>(pb + dec(in, e))[q];
-          sc[i] = in.scale[gc.sbase + gc.dspix(e)];
+      for (int i = 0; i < 2; ++i) {
+        const uint32_t e = soff[min(base + 4 * g4 + r0 + i, n - 1)];
+        const int64_t o = dec(in, e);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int q = min(j + 4 * k, nq - 1);
+          if constexpr (DT == 0) v[i][k] = reinterpret_cast<const float4*>(pb + o * 4)[q];
+          else v[i][k] = reinterpret_cast<const uint32_t*>(pb + o)[q];
         }
+        sc[i] = DT == 3 ? in.scale[gc.sbase + gc.dspix(e)] : 1.0f;
       }
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
+      for (int i = 0; i < 2; ++i) {
         const int r = r0 + i;
-        const bool use = act && base + 16 * gq + r < n;
-        float h, p1 = -__builtin_inff(), p2 = -__builtin_inff();
+        float h = 0.0f, p1 = -__builtin_inff(), p2 = -__builtin_inff();
         int best = 0;
-        if constexpr (DT == 0) {
-          h = chunk_entropy<false>(v[i].x, v[i].y, v[i].z, v[i].w, 4 * q, p1, p2, best);
-        } else {
-          h = chunk_entropy<false>(fp8_e4m3_byte<0>(v[i]) * sc[i], fp8_e4m3_byte<1>(v[i]) * sc[i],
-                                   fp8_e4m3_byte<2>(v[i]) * sc[i], fp8_e4m3_byte<3>(v[i]) * sc[i], 4 * q, p1, p2,
-                                   best);
+        if (base + 4 * g4 + r < n) {
+#pragma unroll
+          for (int k = 0; k < 4; ++k)
+            if (k < kmax && j + 4 * k < nq) {
+              if constexpr (DT == 0) {
+                h = h + chunk_entropy<false>(v[i][k].x, v[i][k].y, v[i][k].z, v[i][k].w, 4 * (j + 4 * k), p1, p2,
+                                             best);
+              } else {
+                const float t = sc[i];
+                h = h + chunk_entropy<false>(fp8_e4m3_byte<0>(v[i][k]) * t, fp8_e4m3_byte<1>(v[i][k]) * t,
+                                             fp8_e4m3_byte<2>(v[i][k]) * t, fp8_e4m3_byte<3>(v[i][k]) * t,
+                                             4 * (j + 4 * k), p1, p2, best);
+              }
+            }
         }
-        h = use ? h : 0.0f;
-        p1 = use ? p1 : -__builtin_inff();
-        p2 = use ? p2 : -__builtin_inff();
-        butterfly16(h, p1, p2);
-        hk = gl == r ? h : hk;
-        p1k = gl == r ? p1 : p1k;
-        p2k = gl == r ? p2 : p2k;
+        butterfly4(h, p1, p2);
+        hk = j == r ? h : hk;
+        p1k = j == r ? p1 : p1k;
+        p2k = j == r ? p2 : p2k;
       }
     }
     const int d = base + lane;
