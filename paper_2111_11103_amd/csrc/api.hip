@@ -562,6 +562,7 @@ lf_status fuse_impl(const FuseArgs& a, void* d_ws, hipStream_t stream) {
     int32_t* lb = a.l_out ? a.l_out + (int64_t)f0 * HW : reinterpret_cast<int32_t*>(ws + L.l);
     const uint8_t* vb = a.valid ? a.valid + (int64_t)fi * HW : nullptr;
     const int k = nbatch & 1;   // sorted path: buffer set of this batch
+    bool cnt_zeroed = false;    // the per-frame counts cleared by the fill
     float4* geo = learned ? geo_sets + (sorted ? (int64_t)k * B * HW : 0) : nullptr;
     // geometry set k may still be read by the gather two batches back
     if (learn_in_gather && nbatch >= 2)
@@ -592,6 +593,9 @@ lf_status fuse_impl(const FuseArgs& a, void* d_ws, hipStream_t stream) {
       uint32_t* eo = grouped ? nullptr : reinterpret_cast<uint32_t*>(ws + L.ent_off[k]);
       float* ew = (!grouped && need_w) ? reinterpret_cast<float*>(ws + L.ent_w[k]) : nullptr;
       float* es = (!grouped && need_s) ? reinterpret_cast<float*>(ws + L.ent_s[k]) : nullptr;
+      // the fill sets the per-frame counts back to zero where it does not
+      // read them itself (nothing after it does)
+      cnt_zeroed = cnt && !(rw && (a.weighting == LF_W_IMAGE || a.weighting == LF_W_MIX));
       // set k was last read by the gather two batches ago
       if (nbatch >= 2) LF_TRY(hipStreamWaitEvent(stream, mesh->gathered_ev[k], 0), "wait for gather");
       {
@@ -603,10 +607,12 @@ lf_status fuse_impl(const FuseArgs& a, void* d_ws, hipStream_t stream) {
         const ProbIn sin = staged_in(stg, a.valid ? a.valid + (int64_t)fi * HW : nullptr);
         if (staged)
           LF_TRY(launch_seg_fill(sin, 0, nb, H, W, lb, rank, bstart, rec, rw, nullptr, a.weighting, cnt, d.n_rows,
-                                 wpix, d.mix, d.win_lo, d.n_rows, stream), "bucket fill");
+                                 wpix, d.mix, d.win_lo, d.n_rows, cnt_zeroed ? cnt : nullptr, stream),
+                 "bucket fill");
         else
           LF_TRY(launch_seg_fill(in, fi, nb, H, W, lb, rank, bstart, rec, rw, rs, a.weighting, cnt, d.n_rows, wpix,
-                                 d.mix, d.win_lo, d.n_rows, stream), "bucket fill");
+                                 d.mix, d.win_lo, d.n_rows, cnt_zeroed ? cnt : nullptr, stream),
+                 "bucket fill");
         if (!grouped)
           LF_TRY(launch_bucket_sort(L.n_buckets, bstart, blist, counts + 1, rec, rw, rs, eo, ew, es, spans, counts,
                                     stream), "bucket sort");
@@ -634,7 +640,7 @@ lf_status fuse_impl(const FuseArgs& a, void* d_ws, hipStream_t stream) {
       LF_TRY(launch_scatter_atomic(d, in, fi, nb, H, W, lb, a.weighting, cnt, d.n_rows, wpix, d.mix, stream),
              "scatter");
     }
-    if (cnt) {
+    if (cnt && !cnt_zeroed) {
       StageTimer tm(mesh, 3, stream);
       LF_TRY(launch_clear_counts(lb, vb, nb, H, W, cnt, d.n_rows, d.win_lo, stream), "clear counts");
     }

@@ -107,11 +107,14 @@ hipError_t launch_seg_scan(const int32_t* seg, int64_t n, int32_t* sums, int32_t
 // buckets and cnt are indexed by window-relative rows.  Every other valid
 // covered pixel writes rec[bstart[bucket] + rank] = (element offset of its
 // class-0 value relative to frame f_first, row within the bucket), and its
-// weight / E4M3 scale into rec_w / rec_s where those are given.
+// weight / E4M3 scale into rec_w / rec_s where those are given.  With
+// cnt_zero (the per-frame count array, [nf][cnt_stride], when nothing after
+// the fill reads it and the fill's own weights do not) every covered pixel
+// in the window also sets its row's count back to zero.
 hipError_t launch_seg_fill(const ProbIn& in, int f_first, int nf, int H, int W, const int32_t* l, const int32_t* rank,
                            const int32_t* bstart, uint2* rec, float* rec_w, float* rec_s, int weighting,
                            const int32_t* cnt, int64_t cnt_stride, const float* wpix, float mix, int64_t win_lo,
-                           int64_t n_rows, hipStream_t s);
+                           int64_t n_rows, int32_t* cnt_zero, hipStream_t s);
 // Second level of the sort through memory (layouts the grouped gather does
 // not take): every non-empty bucket's records ordered by row into ent (and
 // ent_w / ent_s) within the bucket's range, with one span (window-relative

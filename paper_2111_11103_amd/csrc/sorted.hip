@@ -162,7 +162,7 @@ __global__ __launch_bounds__(256) void k_seg_fill(ProbIn in, int f_first, int H,
                                                   float* __restrict__ rec_s, int weighting,
                                                   const int32_t* __restrict__ cnt, int64_t cnt_stride,
                                                   const float* __restrict__ wpix, float mix, int64_t win_lo,
-                                                  int64_t n_rows) {
+                                                  int64_t n_rows, int32_t* __restrict__ cnt_zero) {
   constexpr int P = 4;
   const int fb = blockIdx.y;
   const int64_t HW = (int64_t)H * W;
@@ -177,6 +177,8 @@ __global__ __launch_bounds__(256) void k_seg_fill(ProbIn in, int f_first, int H,
     // window-relative row (-1: no triangle, invalid, or outside the window)
     const int64_t lw = ok[k] ? (int64_t)lbuf[(int64_t)fb * HW + p[k]] - win_lo : -1;
     l[k] = (lw >= 0 && lw < n_rows) ? (int)lw : -1;
+    // the per-frame count of the row is no longer needed: back to zero
+    if (cnt_zero && l[k] >= 0) cnt_zero[(int64_t)fb * cnt_stride + l[k]] = 0;
     if (l[k] >= 0 && in.valid && !in.valid[(int64_t)(f_first + fb) * HW + p[k]]) l[k] = -1;
   }
 #pragma unroll
@@ -1010,12 +1012,14 @@ hipError_t launch_planar_rows(const ProbIn& in, int f_first, int nf, int H, int 
 hipError_t launch_seg_fill(const ProbIn& in, int f_first, int nf, int H, int W, const int32_t* l, const int32_t* rank,
                            const int32_t* bstart, uint2* rec, float* rec_w, float* rec_s, int weighting,
                            const int32_t* cnt, int64_t cnt_stride, const float* wpix, float mix, int64_t win_lo,
-                           int64_t n_rows, hipStream_t s) {
+                           int64_t n_rows, int32_t* cnt_zero, hipStream_t s) {
   if (nf <= 0) return hipSuccess;
+  // the count array is either read here (w^(I), mixed) or cleared here
+  if (cnt_zero && rec_w && (weighting == 1 || weighting == 3)) return hipErrorInvalidValue;
   const int64_t HW = (int64_t)H * W;
   const unsigned gx = (unsigned)(((HW + 1023) / 1024 + 7) / 8 * 8);   // chunks, rounded up to a multiple of 8
   k_seg_fill<<<dim3(gx, (unsigned)nf), 256, 0, s>>>(in, f_first, H, W, l, rank, bstart, rec, rec_w, rec_s, weighting,
-                                                    cnt, cnt_stride, wpix, mix, win_lo, n_rows);
+                                                    cnt, cnt_stride, wpix, mix, win_lo, n_rows, cnt_zero);
   return hipGetLastError();
 }
 
