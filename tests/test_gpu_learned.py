@@ -319,14 +319,19 @@ def test_learned_in_gather_at_forty_classes():
         assert frac >= 0.99
 
 
-@pytest.mark.parametrize("dtype,c", [("f32", 40), ("fp8", 20)])
-def test_separate_pass_on_ragged_frames(dtype, c):
-    """The network in its own pass for pixel-dense channels-last input, whose
-    class vectors are copied to LDS a wave (64 pixels) at a time: 157x113
-    frames end in a partial wave of 13 pixels (at c = 20 in E4M3 that wave's
-    bytes end in a 4-byte word), 10 % of the pixels invalid.  Fusion against
-    the oracle chain, same bound as above."""
-    say(f"[case] learned weight in its own pass, {dtype} c = {c}, 6 frames of 157x113 (ragged last wave)")
+@pytest.mark.parametrize("dtype,c", [("f32", 40), ("fp8", 20), ("f32", 4), ("f32", 64)])
+def test_learned_sites_on_ragged_frames(dtype, c):
+    """Both sites of the network for pixel-dense channels-last input.  In its
+    own pass the class vectors are copied to LDS a wave (64 pixels) at a
+    time: 157x113 frames end in a partial wave of 13 pixels (for that pass
+    the E4M3 input, c = 20, has its frames padded to a 16-byte stride, so
+    that wave's bytes end in a 4-byte word; the gather takes dense frames
+    only and gets them unpadded).  Inside the gather four
+    lanes read a vector, lane j its chunks j, j + 4, ...: c = 4 (one chunk),
+    20 (lane 0 two chunks, the others one), 40 (up to three), 64 (four each).
+    10 % of the pixels invalid.  Fusion against the oracle chain, same bound
+    as above."""
+    say(f"[case] learned weight, both sites, {dtype} c = {c}, 6 frames of 157x113 (ragged last wave)")
     w = S.config1(device="cpu", structured=True, n_frames=6, H=113, W=157)
     g = torch.Generator().manual_seed(31)
     valid = w.valid.clone()
@@ -341,11 +346,18 @@ def test_separate_pass_on_ragged_frames(dtype, c):
         q, scale = S.quantize_fp8(probs)
         deq = np.vectorize(oracle.e4m3_decode)(np.arange(256)).astype(np.float32)[q.numpy()]
         probs_o = (deq * scale.numpy()[:, None]).astype(np.float32)
-        x = q.permute(0, 2, 3, 1).contiguous().cuda().permute(0, 3, 1, 2)
+        F, n = len(w.cams), w.H * w.W * c
+        fstride = (n + 15) // 16 * 16
+        assert fstride != n and (13 * c) % 16 != 0
+        buf = torch.zeros((F, fstride), dtype=torch.uint8)
+        buf[:, :n] = q.permute(0, 2, 3, 1).reshape(F, n)
+        xs = {0: buf.cuda().as_strided((F, c, w.H, w.W), (fstride, 1, w.W * c, c)),
+              1: q.permute(0, 2, 3, 1).contiguous().cuda().permute(0, 3, 1, 2)}
         scale = scale.cuda()
     else:
         probs_o = probs.numpy()
         x = probs.to(memory_format=torch.channels_last).cuda()
+        xs = {0: x, 1: x}
     A_p, W_p = oracle.fuse(om.n_texels, c, l_o, probs_o, w.valid.numpy())
     _, lab = oracle.finalize(A_p, W_p)
     p = _params(13)
@@ -357,11 +369,11 @@ def test_separate_pass_on_ragged_frames(dtype, c):
                            wpix=wpix.reshape(l_o.shape))
     gm = gpu_mesh((sc.vertices, sc.faces), 1, oracle.SPLIT, c)
     gm.bind_mlp(sf.WeightMLP("cuda", torch.from_numpy(p)))
-    gm.set_tuning(learned_in_gather=0)
-    for batch in (2, 6):
+    for site, batch in ((0, 2), (0, 6), (1, 2), (1, 6)):
+        gm.set_tuning(learned_in_gather=site)
         gm.reset()
-        gm.fuse_frames(to_dev(w.cams, torch.float32), x, scale=scale, valid=w.valid.cuda(), weighting=sf.W_LEARNED,
-                       scatter_mode=sf.SCATTER_SORTED, batch=batch)
+        gm.fuse_frames(to_dev(w.cams, torch.float32), xs[site], scale=scale, valid=w.valid.cuda(),
+                       weighting=sf.W_LEARNED, scatter_mode=sf.SCATTER_SORTED, batch=batch)
         A = gm.accum.cpu().numpy().astype(np.float64)
         delta = 5e-3
         err = np.abs(A - A_o)
@@ -369,7 +381,7 @@ def test_separate_pass_on_ragged_frames(dtype, c):
         rel_row = (err / np.maximum(np.abs(A_o), 1e-30)).max(1)
         seen = W_o > 0
         frac = float((rel_row[seen] <= 1e-5).mean())
-        say(f"  batch {batch}: texels within 1e-5: {frac:.4f} of {int(seen.sum())}")
+        say(f"  site {site}, batch {batch}: texels within 1e-5: {frac:.4f} of {int(seen.sum())}")
         assert frac >= 0.99
 
 
