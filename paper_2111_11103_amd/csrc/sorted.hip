@@ -656,7 +656,8 @@ __host__ __device__ inline size_t bucket_gather_lds(int nf, bool frame_counts, b
 // The learned weight of every record of a chunk (row order, d = 0 .. n):
 // wave w takes records 64 (w + 4 i) .. + 63.  Each record's class vector is
 // read by four lanes, lane j taking the four-class chunks j, j + 4, ...
-// (16 records a load instruction, 64 contiguous bytes each), summed in the
+// (a load instruction reads four consecutive chunks of each of 16 records:
+// 64 contiguous bytes in FP32, 16 in E4M3), summed in the
 // separate pass's order and reduced by a butterfly over the quad; the lane
 // whose index is the record's place in the wave keeps its entropy sum and
 // top-2.  Then lane = record: geometry from the resolve's per-pixel copy, n
