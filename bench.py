@@ -411,8 +411,8 @@ def main():
                     help="only run a plain device copy of MIB MiB (counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU frame sharding is a design "
-                                   "(reduce-scatter of the texel array), not part of this build",
+        print(json.dumps({"error": "this benchmark runs on one GPU only; sharding frames across GPUs (a "
+                                   "reduce-scatter of the texel array) is designed but not implemented",
                           "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
 
