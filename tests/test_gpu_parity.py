@@ -201,11 +201,13 @@ def test_nhwc_and_fp8_inputs(cfg1):
 
 
 @pytest.mark.parametrize("shape,valid_mode", [((3, 16, 32), "none"), ((3, 16, 32), "aligned"),
-                                              ((3, 16, 32), "offset"), ((3, 17, 33), "aligned")])
+                                              ((3, 16, 32), "offset"), ((3, 17, 33), "aligned"),
+                                              ((2, 97, 131), "aligned"), ((2, 97, 131), "none")])
 def test_render_back_paths(cfg1, shape, valid_mode):
     """Label render-back over stored rows against the oracle, for pixel
-    counts that are and are not multiples of 4 and a validity array at an odd
-    address; random rows include -1 (no texel) and labels include 255."""
+    counts that are and are not multiples of 4, one and several workgroups,
+    and a validity array at an odd address; random rows include -1 (no
+    texel) and labels include 255."""
     say(f"[case] render-back {shape} valid={valid_mode}")
     sc = cfg1.scene
     gm = gpu_mesh((sc.vertices, sc.faces), 1, oracle.SPLIT, 13)
